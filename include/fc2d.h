@@ -1,0 +1,166 @@
+/*
+ * fc2d.h -- C ABI of the MI355X (gfx950) two-dimensional Fourier Continuation
+ * library (libfc2d.so).
+ *
+ * Method: O. P. Bruno and J. Paul, "Two-dimensional Fourier Continuation and
+ * applications", arXiv 2010.03901.  Section numbers below refer to that paper.
+ *
+ * Conventions shared by every entry point
+ *  - Status: 0 (FC2D_OK) on success, a negative FC2D_E_* code on failure;
+ *    fc2d_last_error() returns a message for the calling thread's last failure.
+ *  - Grid arrays are row-major [field][i][j] <-> (x_i, y_j) = (x0 + i h, y0 + j h)
+ *    with j (the y index) fastest, float64 (eq. cart_grid).  The box is periodic
+ *    with period N h; the right edge is excluded.
+ *  - Half spectra are [field][i][j'] with j' = 0..N_y/2, interleaved complex128
+ *    (re, im), the real-to-complex convention along y then a complex transform
+ *    along x (the layout of numpy.fft.rfft2).
+ *  - Device pointers are hipMalloc'ed (or torch) memory on the current device;
+ *    host pointers are ordinary memory.  The library never frees caller memory.
+ *  - Calls taking a stream enqueue work asynchronously on it (NULL = the null
+ *    stream); enqueue-time errors are returned, kernel faults surface at the
+ *    next synchronisation.
+ */
+#ifndef FC2D_H
+#define FC2D_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FC2D_VERSION 100
+
+enum {
+    FC2D_OK = 0,
+    FC2D_E_ARG = -1,          /* invalid argument (NULL, size, unsupported combination) */
+    FC2D_E_TABLE = -2,        /* FC-Gram table could not be built for the parameters */
+    FC2D_E_GEOMETRY = -3,     /* domain/grid inadmissible (reach, box, matching stencils) */
+    FC2D_E_NEWTON = -4,       /* foot-of-normal solve did not converge */
+    FC2D_E_HIP = -5,          /* a HIP runtime call failed */
+    FC2D_E_NOMEM = -6         /* device or host allocation failed */
+};
+
+enum { FC2D_CURVE_POLAR = 1, FC2D_CURVE_CARTESIAN = 2 };
+enum { FC2D_FORWARD = -1, FC2D_INVERSE = 1 };
+enum { FC2D_LAPLACE_INV = 1, FC2D_DX = 2, FC2D_DY = 3 };
+
+/* Boundary Gamma as a smooth 2 pi-periodic counter-clockwise curve q(theta)
+ * (eq. param).  Series s(t) = s0 + sum_{m=1..nmodes} (s_{2m-1} cos mt + s_{2m} sin mt),
+ * arrays of 1 + 2 nmodes doubles:
+ *   POLAR      q = r(t) (cos t, sin t) with r = series a; b unused;
+ *   CARTESIAN  x(t) = series a, y(t) = series b.
+ * The outward normal is n = (y', -x') / |q'| (Sec. 3.1).  Host memory; copied. */
+typedef struct {
+    int kind;
+    int nmodes;
+    const double* a;
+    const double* b;
+} fc2d_curve;
+
+/* Cartesian grid H of eq. cart_grid: x_i = x0 + i h (0 <= i < nx), y_j = y0 + j h. */
+typedef struct {
+    double x0, y0, h;
+    int nx, ny;
+} fc2d_grid;
+
+/* Plan options; fc2d_opts_default() fills the paper's choices (Remark 3.3):
+ * n_r = 6, Z = 12, n_os = 20, M = d + 3, k1 = h, B = nearest power of two to
+ * 2 pi / h, trigonometric band limit mf = 20. */
+typedef struct {
+    int B;             /* boundary points, k2 = 2 pi / B (eq. bdry_grid) */
+    double k1;         /* normal step (eq. vnbj_m, eq. vnbj_p); 0 -> h */
+    int M;             /* interpolation nodes (degree M - 1); 0 -> d + 3 */
+    int n_r;           /* refinement factor, C_r = n_r C (Remark 2.2) */
+    int Z;             /* zero-matching points (eq. min_prob) */
+    int n_os;          /* oversampling factor (eq. q_over) */
+    int mf;            /* band limit of the trigonometric fit (eq. auxi_trig_poly) */
+    int newton_maxit;  /* cap on foot-of-normal iterations (failure testing); 0 -> 60 */
+} fc2d_opts;
+
+typedef struct fc2d_plan fc2d_plan;
+
+typedef struct {
+    int d, C, M, n_r, Cr, B;
+    double k1, k2;
+    int64_t n_bdry;     /* B feet + squares: length of f_bdry */
+    int64_t n_strip;    /* grid points with 0 < eta <= C k1 */
+    int64_t n_in, n_far;
+    int newton_max_iters;
+} fc2d_plan_info;
+
+void fc2d_opts_default(const fc2d_grid* grid, fc2d_opts* opts);
+
+/* Geometrical Setup (Sec. 3.5 steps 1-4): boundary grid and normals,
+ * admissibility (C k1 <= 0.9 exterior reach; Omega u V+ inside the box),
+ * classification of H into IN / STRIP / FAR with the foot of the normal
+ * (theta^Q, eta_Q) of every STRIP point (Sec. 3.3, 3.4), the matching stencils
+ * of Sec. 3.2 and the FC-Gram tables of Sec. 2.2 / Remark 2.2.  Runs kernels on
+ * `stream` and synchronises it.  *out owns its device memory; immutable after
+ * creation; release with fc2d_plan_destroy.  Errors: FC2D_E_ARG, FC2D_E_TABLE,
+ * FC2D_E_GEOMETRY, FC2D_E_NEWTON, FC2D_E_HIP, FC2D_E_NOMEM. */
+int fc2d_plan_create(const fc2d_curve* curve, const fc2d_grid* grid, int d, int C,
+                     const fc2d_opts* opts, hipStream_t stream, fc2d_plan** out);
+int fc2d_plan_destroy(fc2d_plan* plan);
+int fc2d_plan_get_info(const fc2d_plan* plan, fc2d_plan_info* info);
+
+/* Boundary points whose values f_bdry must hold (host memory): the B feet
+ * q(theta_p) first, then the crossings of the matching-stencil grid lines with
+ * Gamma (the "squares" of Fig. 3).  *n receives the count; xy (2 n doubles,
+ * x then y per point) may be NULL to query n. */
+int fc2d_boundary_points(const fc2d_plan* plan, int64_t* n, double* xy);
+
+/* Plan contents for checking (host memory).  classes: nx*ny int8 with
+ * 0 = FAR, 1 = IN, 2 = STRIP.  strip arrays: n_strip entries in row-major order
+ * of the flat grid index; theta in [0, 2 pi), eta in (0, C k1]; seed = the
+ * proximity-map normal index used to start the foot solve.  Any pointer may be NULL. */
+int fc2d_plan_classes(const fc2d_plan* plan, int8_t* classes);
+int fc2d_plan_strip(const fc2d_plan* plan, int64_t* index, double* theta, double* eta, int32_t* seed);
+
+/* Matching values f_{D_p} (Sec. 3.2): fD [nf][B][d] device float64, from
+ * f_grid [nf][nx][ny] (device; only IN entries read) and f_bdry [nf][n_bdry]
+ * (device).  Sums are carried in double-double and rounded once. */
+int fc2d_matching(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
+                  double* fD, int nf, hipStream_t stream);
+
+/* Blending to zero on V+_{B,C_r} (eq. b_to_z, Remark 2.2): F [nf][C_r+1][B]
+ * device float64 with F[0][p] = f_bdry[p] and F[l][p] = (A_r Q^T f_{D_p})_{l-1}.
+ * A materialised check of the blend; fc2d_extend never forms F. */
+int fc2d_blend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
+               double* F, int nf, hipStream_t stream);
+
+/* 2D-FC extension f^c on H (Sec. 3.5 steps 5-6): out [nf][nx][ny] device with
+ * IN points = f (bitwise), STRIP points = interpolated continuation, FAR = 0.
+ * out may alias f_grid (in place: then only STRIP and FAR entries are written). */
+int fc2d_extend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
+                double* out, int nf, hipStream_t stream);
+
+/* 2D FFT (Sec. 3.5 step 7), nx and ny powers of two in [16, 8192].
+ * FC2D_FORWARD: in = real [nf][nx][ny], out = half spectrum, unnormalised.
+ * FC2D_INVERSE: in = half spectrum (overwritten as work space), out = real,
+ * scaled by 1/(nx ny).  in and out must not overlap. */
+int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStream_t stream);
+
+/* Spectral operators on half spectra (in place allowed): FC2D_LAPLACE_INV
+ * multiplies by -1/|k|^2 with the (0,0) mode set to 0 (eq. poisson_ps_coeffs);
+ * FC2D_DX / FC2D_DY multiply by i k_x / i k_y with the Nyquist mode zeroed;
+ * k = (2 pi l / (nx h), 2 pi m / (ny h)), l in (-nx/2, nx/2]. */
+int fc2d_spectral_apply(const fc2d_grid* grid, int op, const void* in, void* out, int nf,
+                        hipStream_t stream);
+
+/* Fourier Forwarding modal propagation (eq. wave_2d_ff_modal, eq. wave_2d_ff):
+ * uh = cos(w t) u0h + sin(w t)/w u1h and uth = -w sin(w t) u0h + cos(w t) u1h with
+ * w = 2 pi c |(l/(nx h), m/(ny h))|; the (0,0) mode gets u0h + t u1h and u1h.
+ * Half spectra, device; outputs may alias inputs. */
+int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, const void* u1h,
+                 void* uh, void* uth, int nf, hipStream_t stream);
+
+const char* fc2d_strerror(int status);
+const char* fc2d_last_error(void);
+int fc2d_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FC2D_H */

@@ -24,7 +24,8 @@ Readings of the paper taken here (the paper leaves them open):
 * Foot of the normal (Sec. 3.4).  Seed theta^(0) by interpolating
   theta = T(tau) over the M normals of S_{theta_p} at tau = 0 (eq. param_tau),
   then safeguarded Newton on g(theta) = (q(theta) - Q).q'(theta) inside a
-  bracket around theta_p, to |d theta| <= 4e-16 * 2 pi.
+  bracket around theta_p, to |d theta| <= 4e-16 * 2 pi or until the bracket
+  is within 8 units in the last place.
 * Matching stencils (Sec. 3.2, Fig. 3).  Candidate red stars are the
   crossings, at depth >= 0 and in order of depth, of the inward normal with
   the grid lines x = x_i (when |n_x| >= |n_y|) or y = y_j.  A star's nodes are
@@ -52,6 +53,7 @@ from .interp import lagrange_weights
 FAR, IN, STRIP = 0, 1, 2
 LD = np.longdouble
 TWO_PI = 2.0 * math.pi
+EPS = 2.0 ** -52
 
 
 class GeometryError(Exception):
@@ -156,7 +158,9 @@ def foot_solve(curve, bd, X, Y, p, M, tol=4e-16 * TWO_PI, maxit=60):
         new = np.where(g == 0, t, new)
         iters[idx] += 1
         th[idx] = new
-        done = np.abs(new - t) <= tol
+        # converged: a step below tol, or the bracket around the root collapsed
+        # to within tol (near the reach, rounding noise in g can exceed tol * g')
+        done = (np.abs(new - t) <= tol) | (hi[idx] - lo[idx] <= 8 * EPS * np.maximum(1.0, np.abs(hi[idx])))
         active[idx[done]] = False
     else:
         if active.any():

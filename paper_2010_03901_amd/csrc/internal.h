@@ -1,0 +1,105 @@
+// Internal declarations shared by the host plan code (g++) and the HIP
+// kernel translation units (hipcc).  Not part of the public ABI.
+#pragma once
+
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include <hip/hip_runtime_api.h>
+
+#include "../../include/fc2d.h"
+#include "geom.h"
+
+namespace fc2d {
+
+// FC-Gram tables (fcgram_quad.cpp): Q [d][d], A [C][d], Ar [n_r C][d], row-major.
+int gram_tables(int d, int C, int Z, int n_os, int n_r, int mf, double* Q, double* A, double* Ar);
+
+void set_error(const std::string& msg);
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace fc2d
+
+// The plan: host copies needed by the host-side queries plus device arrays
+// used by the extension kernels.
+struct fc2d_plan {
+    fc2d_grid grid;
+    int d, C, M, n_r, Cr, B;
+    double k1, k2;
+    fc2d::CurveC curve;
+    // host
+    std::vector<double> Q, A, Ar;                // tables
+    std::vector<double> bx, by, bnx, bny;        // boundary samples and normals
+    std::vector<double> squares;                 // 2 per square (x, y)
+    std::vector<int8_t> cls;                     // nx * ny
+    std::vector<int32_t> strip_idx, strip_seed;  // row-major STRIP list
+    std::vector<double> strip_theta, strip_eta;
+    int newton_max_iters = 0;
+    int64_t n_in = 0, n_far = 0;
+    // device
+    double* d_Q = nullptr;          // [d][d]
+    double* d_Ar = nullptr;         // [Cr][d]
+    int32_t* d_mref = nullptr;      // [B][M][M] grid flat index (>= 0) or -(1 + square)
+    double* d_mwv = nullptr;        // [B][M][M][2] double-double weights along the grid line
+    double* d_mwn = nullptr;        // [B][d-1][M][2] double-double weights along the normal
+    int32_t* d_sidx = nullptr;      // [S] STRIP flat index
+    double* d_sth = nullptr;        // [S] theta^Q
+    double* d_seta = nullptr;       // [S] eta_Q
+    int32_t* d_run_ptr = nullptr;   // [nx + 1] row runs
+    int32_t* d_run = nullptr;       // [nruns][3] (start, end, class)
+    int nruns = 0;
+    double* d_c = nullptr;          // [nf_cap][B][d] Gram coefficients (work)
+    int nf_cap = 0;
+};
+
+namespace fc2d {
+
+// ---- plan kernels (kernels_plan.hip) ----
+struct ClassifyArgs {
+    CurveC curve;
+    double x0, y0, h;
+    int nx, ny;
+    const double *bx, *by, *bnx, *bny;
+    int B, M;
+    double k2, r_out, r_in, width;   // width = C k1
+    const int32_t* col_ptr;          // [nx + 1]
+    const double* col_y;             // crossings of column x_i with the polygon, sorted
+    int maxit;
+};
+struct StripRec {
+    int32_t idx;
+    int32_t seed;
+    int32_t iters;
+    int32_t pad;
+    double theta;
+    double eta;
+};
+// Runs nearest-sample scatter + classification; fills cls (device, nx*ny),
+// strip records (device, capacity cap) and counters[0] = count, counters[1] =
+// foot failures, counters[2] = max iterations.
+int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64_t cap,
+                    uint64_t* d_near, int* d_counters, hipStream_t s);
+
+// ---- extension kernels (kernels_extend.hip) ----
+int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry,
+                 double* c_out, double* fD_out, int nf, hipStream_t s);
+int launch_blend(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry,
+                 double* F, int nf, hipStream_t s);
+int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry,
+                 double* out, int nf, hipStream_t s);
+int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, hipStream_t s);
+
+// ---- FFT and spectral kernels (kernels_fft.hip) ----
+int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s);
+int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s);
+int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
+int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,
+             double* uth, int nf, hipStream_t s);
+
+}  // namespace fc2d

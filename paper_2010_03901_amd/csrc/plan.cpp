@@ -1,0 +1,776 @@
+// Host side of the Geometrical Setup (Sec. 3.5 steps 1-4) and the C ABI.
+//
+// Boundary-sized work (boundary grid, admissibility, matching stencils and the
+// squares of Fig. 3) runs here on the host in C++; grid-sized and
+// strip-sized work (classification of H, foot of the normal) runs in the
+// device kernels of kernels_plan.hip.
+//
+// Readings of the paper (the same rules the checking code follows; they are
+// stated in the paper's terms):
+//  * Classification: IN / FAR by the parity of crossings of each grid column
+//    with a 16 B-vertex polygon of Gamma; every point whose nearest boundary
+//    sample is within C k1 + ds/2 (outside) or h + ds/2 (inside), ds the
+//    largest sample spacing, is reclassified by the signed normal distance eta
+//    of its foot: IN (eta <= 0), STRIP (0 < eta <= C k1) or FAR.
+//  * Matching stencils (Sec. 3.2): candidate red stars are the crossings at
+//    depth >= 0 of the inward normal with grid lines x = x_i (|n_x| >= |n_y|)
+//    or y = y_j, in order of depth.  A star's nodes are the IN points of the
+//    run of IN points holding it (at most M + 1 grid steps away) and the
+//    crossings of its line with Gamma bounding the run (squares); a square
+//    closer than h/2 to the IN node next to it is dropped.  The first M
+//    candidates with at least M nodes are the red stars; each uses its M
+//    nearest nodes.  Weights are formed in x87 extended precision and stored
+//    as double-double.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace fc2d {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+static int hip_fail(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return FC2D_E_HIP;
+}
+
+#define HIPCHK(call)                                          \
+    do {                                                      \
+        hipError_t e_ = (call);                               \
+        if (e_ != hipSuccess) return hip_fail(e_, #call);    \
+    } while (0)
+
+template <typename T>
+static int dev_upload(T** dst, const T* src, size_t n) {
+    *dst = nullptr;
+    if (n == 0) return FC2D_OK;
+    hipError_t e = hipMalloc((void**)dst, n * sizeof(T));
+    if (e != hipSuccess) {
+        set_error("hipMalloc failed");
+        return FC2D_E_NOMEM;
+    }
+    e = hipMemcpy(*dst, src, n * sizeof(T), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy H2D");
+    return FC2D_OK;
+}
+
+// ----------------------------------------------------------------------------
+// FC-Gram table cache
+// ----------------------------------------------------------------------------
+struct TableKey {
+    int d, C, Z, n_os, n_r, mf;
+    bool operator==(const TableKey& o) const {
+        return d == o.d && C == o.C && Z == o.Z && n_os == o.n_os && n_r == o.n_r && mf == o.mf;
+    }
+};
+struct TableEntry {
+    TableKey k;
+    std::vector<double> Q, A, Ar;
+};
+static std::mutex g_tab_mu;
+static std::vector<TableEntry> g_tabs;
+
+static int get_tables(const TableKey& k, std::vector<double>& Q, std::vector<double>& A,
+                      std::vector<double>& Ar) {
+    std::lock_guard<std::mutex> lk(g_tab_mu);
+    for (auto& e : g_tabs)
+        if (e.k == k) {
+            Q = e.Q; A = e.A; Ar = e.Ar;
+            return FC2D_OK;
+        }
+    TableEntry e;
+    e.k = k;
+    e.Q.resize(k.d * k.d);
+    e.A.resize(k.C * k.d);
+    e.Ar.resize(k.C * k.n_r * k.d);
+    if (gram_tables(k.d, k.C, k.Z, k.n_os, k.n_r, k.mf, e.Q.data(), e.A.data(), e.Ar.data()) != 0) {
+        set_error("FC-Gram table construction failed for these parameters");
+        return FC2D_E_TABLE;
+    }
+    g_tabs.push_back(e);
+    Q = e.Q; A = e.A; Ar = e.Ar;
+    return FC2D_OK;
+}
+
+// ----------------------------------------------------------------------------
+// host foot solve dispatch
+// ----------------------------------------------------------------------------
+static int foot_host(int M, const CurveC& cv, const BndView& bd, double X, double Y, int p, int maxit,
+                     double* th, double* eta, int* it) {
+    switch (M) {
+        case 4: return foot_solve<4>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 5: return foot_solve<5>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 6: return foot_solve<6>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 7: return foot_solve<7>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 8: return foot_solve<8>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 9: return foot_solve<9>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 10: return foot_solve<10>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 11: return foot_solve<11>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 12: return foot_solve<12>(cv, bd, X, Y, p, maxit, th, eta, it);
+    }
+    return FOOT_NO_BRACKET;
+}
+
+// nearest boundary sample by discrete descent from p
+static int nearest_sample(const fc2d_plan* pl, double X, double Y, int p) {
+    auto d2 = [&](int q) {
+        const int r = imod(q, pl->B);
+        const double dx = pl->bx[r] - X, dy = pl->by[r] - Y;
+        return dx * dx + dy * dy;
+    };
+    double best = d2(p);
+    for (int dir = -1; dir <= 1; dir += 2) {
+        for (;;) {
+            const double v = d2(p + dir);
+            if (v < best) {
+                best = v;
+                p += dir;
+            } else {
+                break;
+            }
+        }
+    }
+    return imod(p, pl->B);
+}
+
+// ----------------------------------------------------------------------------
+// matching stencils (Sec. 3.2)
+// ----------------------------------------------------------------------------
+struct StarRec {
+    int p;
+    bool vertical;
+    int line;            // grid line index i_s
+    long double delta;   // depth along the inward normal
+    long double bstar;   // coordinate of the star along its line
+    std::vector<int> lower, upper;   // IN node indices along the line
+    bool sq_has[2] = {false, false};
+    double sq_b[2] = {0, 0};
+};
+struct SqReq {
+    int rid, side;
+    bool vertical;
+    double a_line, b_in, b_out, result;
+    int seed;
+};
+
+static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
+                          std::vector<double>& mwv, std::vector<double>& mwn) {
+    const fc2d_grid& g = pl->grid;
+    const int M = pl->M, d = pl->d, B = pl->B;
+    const double h = g.h;
+    std::vector<StarRec> stars;
+    stars.reserve((size_t)B * 2 * M);
+    std::vector<SqReq> reqs;
+    for (int p = 0; p < B; ++p) {
+        const double nx = pl->bnx[p], ny = pl->bny[p];
+        const bool vertical = fabs(nx) >= fabs(ny);
+        double na, nb, qa, qb, a0, b0;
+        int Nb;
+        if (vertical) {
+            na = nx; nb = ny; qa = pl->bx[p]; qb = pl->by[p]; a0 = g.x0; b0 = g.y0; Nb = g.ny;
+        } else {
+            na = ny; nb = nx; qa = pl->by[p]; qb = pl->bx[p]; a0 = g.y0; b0 = g.x0; Nb = g.nx;
+        }
+        const double u = (qa - a0) / h;
+        int i_first, step;
+        if (na > 0) { i_first = (int)floor(u); step = -1; }
+        else { i_first = (int)ceil(u); step = 1; }
+        for (int s = 0; s < 2 * M; ++s) {
+            StarRec r;
+            r.p = p;
+            r.vertical = vertical;
+            r.line = i_first + step * s;
+            const double a_s = a0 + r.line * h;
+            r.delta = ((long double)qa - (long double)a_s) / (long double)na;
+            r.bstar = (long double)qb - r.delta * (long double)nb;
+            const int jb = (int)floor(((double)r.bstar - b0) / h);
+            auto c_at = [&](int j) -> int {
+                if (j < 0 || j >= Nb) return 0;
+                if (r.line < 0 || r.line >= (vertical ? g.nx : g.ny)) return 0;
+                return vertical ? pl->cls[(size_t)r.line * g.ny + j] : pl->cls[(size_t)j * g.ny + r.line];
+            };
+            int j = jb;
+            while (j >= jb - M && c_at(j) == 1) { r.lower.push_back(j); --j; }
+            const bool lo_stop = j >= jb - M;
+            const int jlo = j;
+            j = jb + 1;
+            while (j <= jb + 1 + M && c_at(j) == 1) { r.upper.push_back(j); ++j; }
+            const bool hi_stop = j <= jb + 1 + M;
+            const int jhi = j;
+            const int rid = (int)stars.size();
+            if (lo_stop) {
+                SqReq q{rid, 0, vertical, a_s,
+                        r.lower.empty() ? (double)r.bstar : b0 + (jlo + 1) * h, b0 + jlo * h, 0.0, p};
+                reqs.push_back(q);
+            }
+            if (hi_stop) {
+                SqReq q{rid, 1, vertical, a_s,
+                        r.upper.empty() ? (double)r.bstar : b0 + (jhi - 1) * h, b0 + jhi * h, 0.0, p};
+                reqs.push_back(q);
+            }
+            stars.push_back(std::move(r));
+        }
+    }
+    // squares: bisection on the sign of eta along each segment
+    const BndView bd{pl->bx.data(), pl->by.data(), pl->bnx.data(), pl->bny.data(), B, pl->k2};
+    int fail = 0;
+#pragma omp parallel for schedule(dynamic, 64) reduction(+ : fail)
+    for (long k = 0; k < (long)reqs.size(); ++k) {
+        SqReq& q = reqs[k];
+        double lo = q.b_in, hi = q.b_out;
+        int seed = q.seed;
+        for (int it = 0; it < 64; ++it) {
+            const double mid = 0.5 * (lo + hi);
+            const double X = q.vertical ? q.a_line : mid;
+            const double Y = q.vertical ? mid : q.a_line;
+            seed = nearest_sample(pl, X, Y, seed);
+            double th, eta;
+            int its;
+            if (foot_host(M, pl->curve, bd, X, Y, seed, maxit, &th, &eta, &its) != FOOT_OK) {
+                ++fail;
+                break;
+            }
+            if (eta <= 0) lo = mid;
+            else hi = mid;
+        }
+        q.result = 0.5 * (lo + hi);
+    }
+    if (fail) {
+        set_error("foot of the normal failed while locating grid-line crossings with the boundary");
+        return FC2D_E_NEWTON;
+    }
+    for (const SqReq& q : reqs) {
+        StarRec& r = stars[q.rid];
+        const std::vector<int>& run = q.side == 0 ? r.lower : r.upper;
+        if (!run.empty()) {
+            const double gb = (r.vertical ? g.y0 : g.x0) + run.back() * h;
+            if (fabs(q.result - gb) < 0.5 * h) continue;   // dropped: too close to the run's end
+        }
+        r.sq_has[q.side] = true;
+        r.sq_b[q.side] = q.result;
+    }
+    // select stars and nodes, form weights
+    mref.assign((size_t)B * M * M, 0);
+    mwv.assign((size_t)B * M * M * 2, 0.0);
+    mwn.assign((size_t)B * (d - 1) * M * 2, 0.0);
+    pl->squares.clear();
+    std::vector<long double> deltas(M);
+    for (int p = 0; p < B; ++p) {
+        int used = 0;
+        for (int s = 0; s < 2 * M && used < M; ++s) {
+            const StarRec& r = stars[(size_t)p * 2 * M + s];
+            const int ncand = (int)r.lower.size() + (int)r.upper.size() + r.sq_has[0] + r.sq_has[1];
+            if (ncand < M) continue;
+            const double b0 = r.vertical ? g.y0 : g.x0;
+            struct Node { bool sq; int j; double b; };
+            std::vector<Node> lo, hi;
+            for (int j : r.lower) lo.push_back({false, j, b0 + j * h});
+            if (r.sq_has[0]) lo.push_back({true, -1, r.sq_b[0]});
+            for (int j : r.upper) hi.push_back({false, j, b0 + j * h});
+            if (r.sq_has[1]) hi.push_back({true, -1, r.sq_b[1]});
+            std::vector<Node> chosen;
+            size_t a = 0, b = 0;
+            const double bs = (double)r.bstar;
+            while ((int)chosen.size() < M) {
+                if (a < lo.size() && b < hi.size()) {
+                    const double dl = bs - lo[a].b, du = hi[b].b - bs;
+                    if (dl < du || (dl == du && !(lo[a].sq && !hi[b].sq))) chosen.push_back(lo[a++]);
+                    else chosen.push_back(hi[b++]);
+                } else if (a < lo.size()) {
+                    chosen.push_back(lo[a++]);
+                } else {
+                    chosen.push_back(hi[b++]);
+                }
+            }
+            for (int k = 0; k < M; ++k) {
+                long double w = 1.0L;
+                for (int m = 0; m < M; ++m)
+                    if (m != k)
+                        w *= (r.bstar - (long double)chosen[m].b) / ((long double)chosen[k].b - (long double)chosen[m].b);
+                const size_t o = (((size_t)p * M + used) * M + k);
+                const double whi = (double)w;
+                mwv[2 * o] = whi;
+                mwv[2 * o + 1] = (double)(w - (long double)whi);
+                if (!chosen[k].sq) {
+                    mref[o] = r.vertical ? (int32_t)((size_t)r.line * g.ny + chosen[k].j)
+                                         : (int32_t)((size_t)chosen[k].j * g.ny + r.line);
+                } else {
+                    mref[o] = -(1 + (int32_t)(pl->squares.size() / 2));
+                    const double a_s = (r.vertical ? g.x0 : g.y0) + r.line * h;
+                    if (r.vertical) { pl->squares.push_back(a_s); pl->squares.push_back(chosen[k].b); }
+                    else { pl->squares.push_back(chosen[k].b); pl->squares.push_back(a_s); }
+                }
+            }
+            deltas[used] = r.delta;
+            ++used;
+        }
+        if (used < M) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "matching stencil: fewer than M usable red stars at normal %d", p);
+            set_error(buf);
+            return FC2D_E_GEOMETRY;
+        }
+        for (int q = 0; q < d - 1; ++q) {
+            const long double x = (long double)(d - 1 - q) * (long double)pl->k1;
+            for (int s = 0; s < M; ++s) {
+                long double w = 1.0L;
+                for (int m = 0; m < M; ++m)
+                    if (m != s) w *= (x - deltas[m]) / (deltas[s] - deltas[m]);
+                const size_t o = ((size_t)p * (d - 1) + q) * M + s;
+                const double whi = (double)w;
+                mwn[2 * o] = whi;
+                mwn[2 * o + 1] = (double)(w - (long double)whi);
+            }
+        }
+    }
+    return FC2D_OK;
+}
+
+// ----------------------------------------------------------------------------
+// plan creation
+// ----------------------------------------------------------------------------
+static void free_plan(fc2d_plan* pl) {
+    if (!pl) return;
+    void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_sidx,
+                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete pl;
+}
+
+static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, int C,
+                       const fc2d_opts* opts_in, hipStream_t stream, fc2d_plan** out) {
+    if (!curve || !grid || !out) { set_error("NULL argument"); return FC2D_E_ARG; }
+    *out = nullptr;
+    fc2d_opts o;
+    fc2d_opts_default(grid, &o);
+    if (opts_in) {
+        if (opts_in->B > 0) o.B = opts_in->B;
+        if (opts_in->k1 > 0) o.k1 = opts_in->k1;
+        if (opts_in->M > 0) o.M = opts_in->M;
+        if (opts_in->n_r > 0) o.n_r = opts_in->n_r;
+        if (opts_in->Z > 0) o.Z = opts_in->Z;
+        if (opts_in->n_os > 0) o.n_os = opts_in->n_os;
+        if (opts_in->mf > 0) o.mf = opts_in->mf;
+        if (opts_in->newton_maxit > 0) o.newton_maxit = opts_in->newton_maxit;
+    }
+    if (o.M <= 0) o.M = d + 3;
+    if (d < 2 || d > 12 || C < 2 || o.M < 4 || o.M > 8 || o.M < d - 1 || grid->h <= 0 || grid->nx < 8 ||
+        grid->ny < 8 || (int64_t)grid->nx * grid->ny >= (int64_t)1 << 31 || o.B < 16 ||
+        curve->nmodes < 0 || curve->nmodes > kMaxModes || !curve->a ||
+        (curve->kind == FC2D_CURVE_CARTESIAN && !curve->b) ||
+        (curve->kind != FC2D_CURVE_POLAR && curve->kind != FC2D_CURVE_CARTESIAN)) {
+        set_error("invalid plan arguments (supported: 2 <= d <= 12, 4 <= M <= 8, M >= d - 1, B >= 16)");
+        return FC2D_E_ARG;
+    }
+    fc2d_plan* pl = new (std::nothrow) fc2d_plan();
+    if (!pl) { set_error("out of host memory"); return FC2D_E_NOMEM; }
+    pl->grid = *grid;
+    pl->d = d; pl->C = C; pl->M = o.M; pl->n_r = o.n_r; pl->Cr = C * o.n_r; pl->B = o.B;
+    pl->k1 = o.k1;
+    pl->k2 = 2.0 * M_PI / o.B;
+    memset(&pl->curve, 0, sizeof pl->curve);
+    pl->curve.kind = curve->kind;
+    pl->curve.nmodes = curve->nmodes;
+    for (int i = 0; i < 1 + 2 * curve->nmodes; ++i) {
+        pl->curve.a[i] = curve->a[i];
+        if (curve->kind == FC2D_CURVE_CARTESIAN) pl->curve.b[i] = curve->b[i];
+    }
+    int st = get_tables(TableKey{d, C, o.Z, o.n_os, o.n_r, o.mf}, pl->Q, pl->A, pl->Ar);
+    if (st) { free_plan(pl); return st; }
+
+    // step 1: boundary discretisation and normals (eq. bdry_grid)
+    const int B = pl->B;
+    pl->bx.resize(B); pl->by.resize(B); pl->bnx.resize(B); pl->bny.resize(B);
+    double spmax = 0.0;
+    for (int p = 0; p < B; ++p) {
+        double v[6];
+        curve_eval(pl->curve, p * pl->k2, v);
+        const double sp = sqrt(v[2] * v[2] + v[3] * v[3]);
+        pl->bx[p] = v[0]; pl->by[p] = v[1];
+        pl->bnx[p] = v[3] / sp; pl->bny[p] = -v[2] / sp;
+        spmax = std::max(spmax, sp);
+    }
+    // admissibility: exterior reach and the box
+    {
+        const int ns = 16 * B;
+        double kmin = 0.0;   // most negative curvature
+        for (int k = 0; k < ns; ++k) {
+            double v[6];
+            curve_eval(pl->curve, k * (2.0 * M_PI / ns), v);
+            const double s2 = v[2] * v[2] + v[3] * v[3];
+            const double kap = (v[2] * v[5] - v[3] * v[4]) / (s2 * sqrt(s2));
+            kmin = std::min(kmin, kap);
+        }
+        const double reach_ext = kmin < 0 ? 1.0 / -kmin : INFINITY;
+        if (C * pl->k1 > 0.9 * reach_ext) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "C k1 = %.4g exceeds 0.9 x exterior reach %.4g", C * pl->k1, reach_ext);
+            set_error(buf);
+            free_plan(pl);
+            return FC2D_E_GEOMETRY;
+        }
+        const double xlo = grid->x0, xhi = grid->x0 + (grid->nx - 1) * grid->h;
+        const double ylo = grid->y0, yhi = grid->y0 + (grid->ny - 1) * grid->h;
+        for (int p = 0; p < B; ++p) {
+            const double ox = pl->bx[p] + pl->bnx[p] * (C * pl->k1);
+            const double oy = pl->by[p] + pl->bny[p] * (C * pl->k1);
+            const double xs[2] = {pl->bx[p], ox}, ys[2] = {pl->by[p], oy};
+            for (int k = 0; k < 2; ++k)
+                if (xs[k] < xlo || xs[k] > xhi || ys[k] < ylo || ys[k] > yhi) {
+                    set_error("Omega u V+ is not inside the box");
+                    free_plan(pl);
+                    return FC2D_E_GEOMETRY;
+                }
+        }
+    }
+    // column crossings of the 16 B-vertex polygon (parity test)
+    std::vector<int32_t> col_ptr(grid->nx + 1, 0);
+    std::vector<double> col_y;
+    {
+        const int nv = 16 * B;
+        std::vector<double> px(nv), py(nv);
+        for (int k = 0; k < nv; ++k) {
+            double v[6];
+            curve_eval(pl->curve, k * (2.0 * M_PI / nv), v);
+            px[k] = v[0]; py[k] = v[1];
+        }
+        std::vector<std::vector<double>> cols(grid->nx);
+        for (int k = 0; k < nv; ++k) {
+            const int k1 = (k + 1) % nv;
+            const double ax = px[k], ay = py[k], bx = px[k1], by = py[k1];
+            const double xmin = std::min(ax, bx), xmax = std::max(ax, bx);
+            const long i0 = (long)ceil((xmin - grid->x0) / grid->h);
+            const long i1 = (long)ceil((xmax - grid->x0) / grid->h);
+            for (long i = i0; i < i1; ++i) {
+                if (i < 0 || i >= grid->nx) continue;
+                const double xc = grid->x0 + i * grid->h;
+                const double s = (xc - ax) / (bx - ax);
+                cols[i].push_back(ay + s * (by - ay));
+            }
+        }
+        for (int i = 0; i < grid->nx; ++i) {
+            std::sort(cols[i].begin(), cols[i].end());
+            col_ptr[i + 1] = col_ptr[i] + (int32_t)cols[i].size();
+            col_y.insert(col_y.end(), cols[i].begin(), cols[i].end());
+        }
+    }
+    // steps 3-4 on the device: classification and foot of the normal
+    const int64_t npts = (int64_t)grid->nx * grid->ny;
+    const double ds = pl->k2 * spmax;
+    ClassifyArgs ca;
+    ca.curve = pl->curve;
+    ca.x0 = grid->x0; ca.y0 = grid->y0; ca.h = grid->h; ca.nx = grid->nx; ca.ny = grid->ny;
+    ca.B = B; ca.M = pl->M; ca.k2 = pl->k2;
+    ca.r_out = C * pl->k1 + 0.5 * ds + 1e-12;
+    ca.r_in = 0.5 * ds + grid->h;
+    ca.width = C * pl->k1;
+    ca.maxit = o.newton_maxit;
+    double *d_bx = nullptr, *d_by = nullptr, *d_bnx = nullptr, *d_bny = nullptr, *d_coly = nullptr;
+    int32_t* d_colptr = nullptr;
+    int8_t* d_cls = nullptr;
+    StripRec* d_rec = nullptr;
+    uint64_t* d_near = nullptr;
+    int* d_cnt = nullptr;
+    // capacity for STRIP records: twice the area of a band of width r_out
+    // along the boundary, plus a margin of a few grid rows
+    double perim = 0.0;
+    for (int p = 0; p < B; ++p) {
+        double v[6];
+        curve_eval(pl->curve, p * pl->k2, v);
+        perim += sqrt(v[2] * v[2] + v[3] * v[3]) * pl->k2;
+    }
+    const double hh = grid->h;
+    int64_t cap = std::min<int64_t>(
+        npts, (int64_t)(2.0 * perim * ca.r_out / (hh * hh) + 4.0 * perim / hh) + 4096);
+    std::vector<StripRec> rec;
+    int cnt[3] = {0, 0, 0};
+    auto cleanup = [&]() {
+        void* ps[] = {d_bx, d_by, d_bnx, d_bny, d_coly, d_colptr, d_cls, d_rec, d_near, d_cnt};
+        for (void* q : ps)
+            if (q) (void)hipFree(q);
+    };
+    st = FC2D_OK;
+    do {
+        if ((st = dev_upload(&d_bx, pl->bx.data(), B))) break;
+        if ((st = dev_upload(&d_by, pl->by.data(), B))) break;
+        if ((st = dev_upload(&d_bnx, pl->bnx.data(), B))) break;
+        if ((st = dev_upload(&d_bny, pl->bny.data(), B))) break;
+        if ((st = dev_upload(&d_colptr, col_ptr.data(), col_ptr.size()))) break;
+        if (!col_y.empty() && (st = dev_upload(&d_coly, col_y.data(), col_y.size()))) break;
+        if (hipMalloc((void**)&d_cls, npts) != hipSuccess || hipMalloc((void**)&d_rec, cap * sizeof(StripRec)) != hipSuccess ||
+            hipMalloc((void**)&d_near, npts * sizeof(uint64_t)) != hipSuccess ||
+            hipMalloc((void**)&d_cnt, 4 * sizeof(int)) != hipSuccess) {
+            set_error("hipMalloc failed (classification work space)");
+            st = FC2D_E_NOMEM;
+            break;
+        }
+        ca.bx = d_bx; ca.by = d_by; ca.bnx = d_bnx; ca.bny = d_bny;
+        ca.col_ptr = d_colptr; ca.col_y = d_coly;
+        if ((st = launch_classify(ca, d_cls, d_rec, cap, d_near, d_cnt, stream))) break;
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) { st = hip_fail(e, "classification kernels"); break; }
+        if ((e = hipMemcpy(cnt, d_cnt, 3 * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
+        if (cnt[1] > 0) {
+            char buf[128];
+            snprintf(buf, sizeof buf, "foot of the normal failed at %d grid points", cnt[1]);
+            set_error(buf);
+            st = FC2D_E_NEWTON;
+            break;
+        }
+        if (cnt[0] > cap) { set_error("STRIP capacity exceeded"); st = FC2D_E_GEOMETRY; break; }
+        pl->cls.resize(npts);
+        rec.resize(cnt[0]);
+        if ((e = hipMemcpy(pl->cls.data(), d_cls, npts, hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
+        if (cnt[0] && (e = hipMemcpy(rec.data(), d_rec, cnt[0] * sizeof(StripRec), hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
+    } while (0);
+    cleanup();
+    if (st) { free_plan(pl); return st; }
+    std::sort(rec.begin(), rec.end(), [](const StripRec& a, const StripRec& b) { return a.idx < b.idx; });
+    pl->newton_max_iters = cnt[2];
+    pl->strip_idx.resize(rec.size()); pl->strip_seed.resize(rec.size());
+    pl->strip_theta.resize(rec.size()); pl->strip_eta.resize(rec.size());
+    for (size_t k = 0; k < rec.size(); ++k) {
+        pl->strip_idx[k] = rec[k].idx; pl->strip_seed[k] = rec[k].seed;
+        pl->strip_theta[k] = rec[k].theta; pl->strip_eta[k] = rec[k].eta;
+    }
+    for (int8_t c : pl->cls) {
+        if (c == 1) ++pl->n_in;
+        else if (c == 0) ++pl->n_far;
+    }
+    // matching stencils
+    std::vector<int32_t> mref;
+    std::vector<double> mwv, mwn;
+    st = build_matching(pl, o.newton_maxit, mref, mwv, mwn);
+    if (st) { free_plan(pl); return st; }
+    // row runs of equal class
+    std::vector<int32_t> run_ptr(grid->nx + 1, 0), runs;
+    for (int i = 0; i < grid->nx; ++i) {
+        const int8_t* row = &pl->cls[(size_t)i * grid->ny];
+        int j = 0;
+        while (j < grid->ny) {
+            int k = j;
+            while (k < grid->ny && row[k] == row[j]) ++k;
+            runs.push_back(j); runs.push_back(k); runs.push_back(row[j]);
+            j = k;
+        }
+        run_ptr[i + 1] = (int32_t)(runs.size() / 3);
+    }
+    pl->nruns = (int)(runs.size() / 3);
+    // uploads
+    do {
+        if ((st = dev_upload(&pl->d_Q, pl->Q.data(), pl->Q.size()))) break;
+        if ((st = dev_upload(&pl->d_Ar, pl->Ar.data(), pl->Ar.size()))) break;
+        if ((st = dev_upload(&pl->d_mref, mref.data(), mref.size()))) break;
+        if ((st = dev_upload(&pl->d_mwv, mwv.data(), mwv.size()))) break;
+        if ((st = dev_upload(&pl->d_mwn, mwn.data(), mwn.size()))) break;
+        if ((st = dev_upload(&pl->d_sidx, pl->strip_idx.data(), pl->strip_idx.size()))) break;
+        if ((st = dev_upload(&pl->d_sth, pl->strip_theta.data(), pl->strip_theta.size()))) break;
+        if ((st = dev_upload(&pl->d_seta, pl->strip_eta.data(), pl->strip_eta.size()))) break;
+        if ((st = dev_upload(&pl->d_run_ptr, run_ptr.data(), run_ptr.size()))) break;
+        if ((st = dev_upload(&pl->d_run, runs.data(), runs.size()))) break;
+    } while (0);
+    if (st) { free_plan(pl); return st; }
+    *out = pl;
+    return FC2D_OK;
+}
+
+int ensure_work(const fc2d_plan* cpl, int nf) {
+    fc2d_plan* pl = const_cast<fc2d_plan*>(cpl);
+    if (nf <= pl->nf_cap) return FC2D_OK;
+    if (pl->d_c) (void)hipFree(pl->d_c);
+    pl->d_c = nullptr;
+    pl->nf_cap = 0;
+    if (hipMalloc((void**)&pl->d_c, (size_t)nf * pl->B * pl->d * sizeof(double)) != hipSuccess) {
+        set_error("hipMalloc failed (Gram coefficient work space)");
+        return FC2D_E_NOMEM;
+    }
+    pl->nf_cap = nf;
+    return FC2D_OK;
+}
+
+static std::mutex g_work_mu;
+
+}  // namespace fc2d
+
+using namespace fc2d;
+
+extern "C" {
+
+void fc2d_opts_default(const fc2d_grid* grid, fc2d_opts* o) {
+    if (!o) return;
+    memset(o, 0, sizeof *o);
+    o->n_r = 6; o->Z = 12; o->n_os = 20; o->mf = 20; o->newton_maxit = 60;
+    o->M = 0;
+    o->k1 = grid ? grid->h : 0.0;
+    int B = 256;
+    if (grid && grid->h > 0) {
+        const double t = 2.0 * M_PI / grid->h;
+        B = 1 << (int)lround(log2(t));
+    }
+    o->B = B;
+}
+
+int fc2d_plan_create(const fc2d_curve* curve, const fc2d_grid* grid, int d, int C, const fc2d_opts* opts,
+                     hipStream_t stream, fc2d_plan** out) {
+    try {
+        return create_plan(curve, grid, d, C, opts, stream, out);
+    } catch (const std::bad_alloc&) {
+        set_error("out of host memory");
+        return FC2D_E_NOMEM;
+    }
+}
+
+int fc2d_plan_destroy(fc2d_plan* plan) {
+    free_plan(plan);
+    return FC2D_OK;
+}
+
+int fc2d_plan_get_info(const fc2d_plan* pl, fc2d_plan_info* info) {
+    if (!pl || !info) { set_error("NULL argument"); return FC2D_E_ARG; }
+    info->d = pl->d; info->C = pl->C; info->M = pl->M; info->n_r = pl->n_r; info->Cr = pl->Cr; info->B = pl->B;
+    info->k1 = pl->k1; info->k2 = pl->k2;
+    info->n_bdry = pl->B + (int64_t)pl->squares.size() / 2;
+    info->n_strip = (int64_t)pl->strip_idx.size();
+    info->n_in = pl->n_in; info->n_far = pl->n_far;
+    info->newton_max_iters = pl->newton_max_iters;
+    return FC2D_OK;
+}
+
+int fc2d_boundary_points(const fc2d_plan* pl, int64_t* n, double* xy) {
+    if (!pl || !n) { set_error("NULL argument"); return FC2D_E_ARG; }
+    const int64_t ns = (int64_t)pl->squares.size() / 2;
+    *n = pl->B + ns;
+    if (xy) {
+        for (int p = 0; p < pl->B; ++p) { xy[2 * p] = pl->bx[p]; xy[2 * p + 1] = pl->by[p]; }
+        memcpy(xy + 2 * pl->B, pl->squares.data(), pl->squares.size() * sizeof(double));
+    }
+    return FC2D_OK;
+}
+
+int fc2d_plan_classes(const fc2d_plan* pl, int8_t* classes) {
+    if (!pl) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (classes) memcpy(classes, pl->cls.data(), pl->cls.size());
+    return FC2D_OK;
+}
+
+int fc2d_plan_strip(const fc2d_plan* pl, int64_t* index, double* theta, double* eta, int32_t* seed) {
+    if (!pl) { set_error("NULL argument"); return FC2D_E_ARG; }
+    const size_t S = pl->strip_idx.size();
+    for (size_t k = 0; k < S; ++k) {
+        if (index) index[k] = pl->strip_idx[k];
+        if (theta) theta[k] = pl->strip_theta[k];
+        if (eta) eta[k] = pl->strip_eta[k];
+        if (seed) seed[k] = pl->strip_seed[k];
+    }
+    return FC2D_OK;
+}
+
+static int check_fields(const fc2d_plan* pl, int nf) {
+    if (!pl || nf < 0) { set_error("invalid plan or field count"); return FC2D_E_ARG; }
+    return FC2D_OK;
+}
+
+int fc2d_matching(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* fD, int nf,
+                  hipStream_t s) {
+    int st = check_fields(pl, nf);
+    if (st) return st;
+    if (nf == 0) return FC2D_OK;
+    if (!f_grid || !f_bdry || !fD) { set_error("NULL argument"); return FC2D_E_ARG; }
+    std::lock_guard<std::mutex> lk(g_work_mu);
+    if ((st = ensure_work(pl, nf))) return st;
+    const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
+    return launch_match(pl, f_grid, f_bdry, nb, pl->d_c, fD, nf, s);
+}
+
+int fc2d_blend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* F, int nf,
+               hipStream_t s) {
+    int st = check_fields(pl, nf);
+    if (st) return st;
+    if (nf == 0) return FC2D_OK;
+    if (!f_grid || !f_bdry || !F) { set_error("NULL argument"); return FC2D_E_ARG; }
+    std::lock_guard<std::mutex> lk(g_work_mu);
+    if ((st = ensure_work(pl, nf))) return st;
+    const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
+    if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
+    return launch_blend(pl, pl->d_c, f_bdry, nb, F, nf, s);
+}
+
+int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* out, int nf,
+                hipStream_t s) {
+    int st = check_fields(pl, nf);
+    if (st) return st;
+    if (nf == 0) return FC2D_OK;
+    if (!f_grid || !f_bdry || !out) { set_error("NULL argument"); return FC2D_E_ARG; }
+    std::lock_guard<std::mutex> lk(g_work_mu);
+    if ((st = ensure_work(pl, nf))) return st;
+    const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
+    if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
+    if ((st = launch_mask(pl, f_grid, out, nf, s))) return st;
+    return launch_strip(pl, pl->d_c, f_bdry, nb, out, nf, s);
+}
+
+static bool pow2_ok(int n) { return n >= 16 && n <= 8192 && (n & (n - 1)) == 0; }
+
+int fc2d_fft(const fc2d_grid* g, void* in, void* out, int dir, int nf, hipStream_t s) {
+    if (!g || !pow2_ok(g->nx) || !pow2_ok(g->ny) || nf < 0) {
+        set_error("fc2d_fft: nx and ny must be powers of two in [16, 8192]");
+        return FC2D_E_ARG;
+    }
+    if (nf == 0) return FC2D_OK;
+    if (!in || !out || in == out) { set_error("fc2d_fft: NULL or aliased buffers"); return FC2D_E_ARG; }
+    if (dir == FC2D_FORWARD) return fft2_r2c(g, (const double*)in, (double*)out, nf, s);
+    if (dir == FC2D_INVERSE) return fft2_c2r(g, (double*)in, (double*)out, nf, s);
+    set_error("fc2d_fft: dir must be FC2D_FORWARD or FC2D_INVERSE");
+    return FC2D_E_ARG;
+}
+
+int fc2d_spectral_apply(const fc2d_grid* g, int op, const void* in, void* out, int nf, hipStream_t s) {
+    if (!g || g->nx < 2 || g->ny < 2 || g->h <= 0 || nf < 0 ||
+        (op != FC2D_LAPLACE_INV && op != FC2D_DX && op != FC2D_DY)) {
+        set_error("fc2d_spectral_apply: invalid arguments");
+        return FC2D_E_ARG;
+    }
+    if (nf == 0) return FC2D_OK;
+    if (!in || !out) { set_error("NULL argument"); return FC2D_E_ARG; }
+    return spectral_apply(g, op, (const double*)in, (double*)out, nf, s);
+}
+
+int ff_propagate(const fc2d_grid* g, double c, double t, const void* u0h, const void* u1h, void* uh, void* uth,
+                 int nf, hipStream_t s) {
+    if (!g || g->nx < 2 || g->ny < 2 || g->h <= 0 || nf < 0) {
+        set_error("ff_propagate: invalid arguments");
+        return FC2D_E_ARG;
+    }
+    if (nf == 0) return FC2D_OK;
+    if (!u0h || !u1h || !uh || !uth) { set_error("NULL argument"); return FC2D_E_ARG; }
+    return ff_apply(g, c, t, (const double*)u0h, (const double*)u1h, (double*)uh, (double*)uth, nf, s);
+}
+
+const char* fc2d_strerror(int status) {
+    switch (status) {
+        case FC2D_OK: return "ok";
+        case FC2D_E_ARG: return "invalid argument";
+        case FC2D_E_TABLE: return "FC-Gram table unavailable";
+        case FC2D_E_GEOMETRY: return "inadmissible geometry";
+        case FC2D_E_NEWTON: return "foot-of-normal solve failed";
+        case FC2D_E_HIP: return "HIP runtime error";
+        case FC2D_E_NOMEM: return "out of memory";
+    }
+    return "unknown status";
+}
+
+const char* fc2d_last_error(void) { return g_last_error.c_str(); }
+
+int fc2d_version(void) { return FC2D_VERSION; }
+
+}  // extern "C"

@@ -1,0 +1,265 @@
+"""ctypes binding of libfc2d.so (argument marshalling only; every step runs in
+the library's HIP kernels).  Names follow include/fc2d.h.
+
+Device buffers are torch tensors (float64, contiguous, on the current HIP
+device); streams default to torch's current stream.  The library must have
+been built (``python -m paper_2010_03901_amd.build``); nothing here computes
+a fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libfc2d.so")
+
+FC2D_OK = 0
+FC2D_E_ARG, FC2D_E_TABLE, FC2D_E_GEOMETRY, FC2D_E_NEWTON, FC2D_E_HIP, FC2D_E_NOMEM = -1, -2, -3, -4, -5, -6
+FC2D_CURVE_POLAR, FC2D_CURVE_CARTESIAN = 1, 2
+FC2D_FORWARD, FC2D_INVERSE = -1, 1
+FC2D_LAPLACE_INV, FC2D_DX, FC2D_DY = 1, 2, 3
+
+FAR, IN, STRIP = 0, 1, 2
+
+
+class Fc2dError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s (%d): %s" % (_lib().fc2d_strerror(status).decode(), status, msg))
+        self.status = status
+
+
+class fc2d_curve(C.Structure):
+    _fields_ = [("kind", C.c_int), ("nmodes", C.c_int), ("a", C.POINTER(C.c_double)), ("b", C.POINTER(C.c_double))]
+
+
+class fc2d_grid(C.Structure):
+    _fields_ = [("x0", C.c_double), ("y0", C.c_double), ("h", C.c_double), ("nx", C.c_int), ("ny", C.c_int)]
+
+
+class fc2d_opts(C.Structure):
+    _fields_ = [("B", C.c_int), ("k1", C.c_double), ("M", C.c_int), ("n_r", C.c_int), ("Z", C.c_int),
+                ("n_os", C.c_int), ("mf", C.c_int), ("newton_maxit", C.c_int)]
+
+
+class fc2d_plan_info(C.Structure):
+    _fields_ = [("d", C.c_int), ("C", C.c_int), ("M", C.c_int), ("n_r", C.c_int), ("Cr", C.c_int), ("B", C.c_int),
+                ("k1", C.c_double), ("k2", C.c_double), ("n_bdry", C.c_int64), ("n_strip", C.c_int64),
+                ("n_in", C.c_int64), ("n_far", C.c_int64), ("newton_max_iters", C.c_int)]
+
+
+_LIB = None
+_P = C.c_void_p
+
+
+def _lib():
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libfc2d.so is not built; run `python -m paper_2010_03901_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        sig = {
+            "fc2d_opts_default": (None, [C.POINTER(fc2d_grid), C.POINTER(fc2d_opts)]),
+            "fc2d_plan_create": (C.c_int, [C.POINTER(fc2d_curve), C.POINTER(fc2d_grid), C.c_int, C.c_int,
+                                           C.POINTER(fc2d_opts), _P, C.POINTER(_P)]),
+            "fc2d_plan_destroy": (C.c_int, [_P]),
+            "fc2d_plan_get_info": (C.c_int, [_P, C.POINTER(fc2d_plan_info)]),
+            "fc2d_boundary_points": (C.c_int, [_P, C.POINTER(C.c_int64), _P]),
+            "fc2d_plan_classes": (C.c_int, [_P, _P]),
+            "fc2d_plan_strip": (C.c_int, [_P, _P, _P, _P, _P]),
+            "fc2d_matching": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_blend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_extend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
+            "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
+            "ff_propagate": (C.c_int, [C.POINTER(fc2d_grid), C.c_double, C.c_double, _P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_strerror": (C.c_char_p, [C.c_int]),
+            "fc2d_last_error": (C.c_char_p, []),
+            "fc2d_version": (C.c_int, []),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = lib
+    return _LIB
+
+
+def _check(status):
+    if status != FC2D_OK:
+        raise Fc2dError(status, _lib().fc2d_last_error().decode())
+
+
+def _stream(stream):
+    if stream is not None:
+        return C.c_void_p(stream)
+    import torch
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dptr(t, name, dtype=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("%s must be a device tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError("%s must be %s" % (name, dtype))
+    return C.c_void_p(t.data_ptr())
+
+
+def make_grid(x0, y0, h, nx, ny):
+    return fc2d_grid(float(x0), float(y0), float(h), int(nx), int(ny))
+
+
+def make_curve(kind, coef):
+    """kind 'polar' with coef [c0, a1, b1, ...] or 'cartesian' with ([x...], [y...])."""
+    if kind == "polar":
+        a = np.ascontiguousarray(coef, dtype=np.float64)
+        b = None
+        k = FC2D_CURVE_POLAR
+    else:
+        xa, ya = coef
+        n = max(len(xa), len(ya))
+        a = np.zeros(n)
+        b = np.zeros(n)
+        a[: len(xa)] = xa
+        b[: len(ya)] = ya
+        k = FC2D_CURVE_CARTESIAN
+    if a.size % 2 == 0:
+        a = np.concatenate([a, [0.0]])
+        if b is not None:
+            b = np.concatenate([b, [0.0]])
+    nm = (a.size - 1) // 2
+    cv = fc2d_curve(k, nm, a.ctypes.data_as(C.POINTER(C.c_double)),
+                    b.ctypes.data_as(C.POINTER(C.c_double)) if b is not None else None)
+    cv._keep = (a, b)
+    return cv
+
+
+class Plan:
+    """Owning wrapper of fc2d_plan*."""
+
+    def __init__(self, curve, grid, d=5, C_=27, B=None, k1=None, M=None, n_r=None, Z=None, n_os=None, mf=None,
+                 newton_maxit=None, stream=None):
+        lib = _lib()
+        self.grid = grid
+        opts = fc2d_opts()
+        lib.fc2d_opts_default(C.byref(grid), C.byref(opts))
+        for name, v in (("B", B), ("k1", k1), ("M", M), ("n_r", n_r), ("Z", Z), ("n_os", n_os), ("mf", mf),
+                        ("newton_maxit", newton_maxit)):
+            if v is not None:
+                setattr(opts, name, v)
+        h = C.c_void_p()
+        _check(lib.fc2d_plan_create(C.byref(curve), C.byref(grid), int(d), int(C_), C.byref(opts),
+                                    _stream(stream), C.byref(h)))
+        self._h = h
+        info = fc2d_plan_info()
+        _check(lib.fc2d_plan_get_info(h, C.byref(info)))
+        self.info = info
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib().fc2d_plan_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def fc2d_plan_create(curve, grid, d=5, C_=27, **kw):
+    return Plan(curve, grid, d, C_, **kw)
+
+
+def fc2d_plan_destroy(plan):
+    plan.close()
+
+
+def fc2d_boundary_points(plan):
+    n = C.c_int64()
+    _check(_lib().fc2d_boundary_points(plan.handle, C.byref(n), None))
+    xy = np.zeros((n.value, 2))
+    _check(_lib().fc2d_boundary_points(plan.handle, C.byref(n), C.c_void_p(xy.ctypes.data)))
+    return xy
+
+
+def fc2d_plan_classes(plan):
+    g = plan.grid
+    out = np.zeros((g.nx, g.ny), dtype=np.int8)
+    _check(_lib().fc2d_plan_classes(plan.handle, C.c_void_p(out.ctypes.data)))
+    return out
+
+
+def fc2d_plan_strip(plan):
+    S = plan.info.n_strip
+    idx = np.zeros(S, dtype=np.int64)
+    th = np.zeros(S)
+    eta = np.zeros(S)
+    seed = np.zeros(S, dtype=np.int32)
+    _check(_lib().fc2d_plan_strip(plan.handle, C.c_void_p(idx.ctypes.data), C.c_void_p(th.ctypes.data),
+                                  C.c_void_p(eta.ctypes.data), C.c_void_p(seed.ctypes.data)))
+    return idx, th, eta, seed
+
+
+def _nf(f_grid, grid):
+    n = f_grid.numel() // (grid.nx * grid.ny)
+    if n * grid.nx * grid.ny != f_grid.numel():
+        raise ValueError("f_grid size is not a multiple of nx*ny")
+    return n
+
+
+def fc2d_matching(plan, f_grid, f_bdry, fD, stream=None):
+    import torch
+    nf = _nf(f_grid, plan.grid)
+    _check(_lib().fc2d_matching(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+                                _dptr(fD, "fD", torch.float64), nf, _stream(stream)))
+
+
+def fc2d_blend(plan, f_grid, f_bdry, F, stream=None):
+    import torch
+    nf = _nf(f_grid, plan.grid)
+    _check(_lib().fc2d_blend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+                             _dptr(F, "F", torch.float64), nf, _stream(stream)))
+
+
+def fc2d_extend(plan, f_grid, f_bdry, out, stream=None):
+    import torch
+    nf = _nf(f_grid, plan.grid)
+    if f_bdry.numel() != nf * plan.info.n_bdry or out.numel() != f_grid.numel():
+        raise ValueError("f_bdry / out sizes do not match the plan")
+    _check(_lib().fc2d_extend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+                              _dptr(out, "out", torch.float64), nf, _stream(stream)))
+
+
+def fc2d_fft(grid, inp, out, direction, stream=None):
+    import torch
+    real = inp if direction == FC2D_FORWARD else out
+    nf = _nf(real, grid)
+    spec = out if direction == FC2D_FORWARD else inp
+    if spec.dtype != torch.complex128 or spec.numel() != nf * grid.nx * (grid.ny // 2 + 1):
+        raise ValueError("spectrum must be complex128 [nf][nx][ny/2+1]")
+    _check(_lib().fc2d_fft(C.byref(grid), _dptr(inp, "in"), _dptr(out, "out"), int(direction), nf, _stream(stream)))
+
+
+def fc2d_spectral_apply(grid, op, inp, out, stream=None):
+    nf = inp.numel() // (grid.nx * (grid.ny // 2 + 1))
+    _check(_lib().fc2d_spectral_apply(C.byref(grid), int(op), _dptr(inp, "in"), _dptr(out, "out"), nf, _stream(stream)))
+
+
+def ff_propagate(grid, c, t, u0h, u1h, uh, uth, stream=None):
+    nf = u0h.numel() // (grid.nx * (grid.ny // 2 + 1))
+    _check(_lib().ff_propagate(C.byref(grid), float(c), float(t), _dptr(u0h, "u0h"), _dptr(u1h, "u1h"),
+                               _dptr(uh, "uh"), _dptr(uth, "uth"), nf, _stream(stream)))
+
+
+def fc2d_version():
+    return _lib().fc2d_version()

@@ -1,0 +1,70 @@
+"""Host-side checks of the C-ABI library: it loads, exports every entry point
+that include/fc2d.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fc2d.h")
+LIB = os.path.join(ROOT, "paper_2010_03901_amd", "libfc2d.so")
+
+pytestmark = pytest.mark.skipif(not os.path.exists(LIB), reason="libfc2d.so not built (run __graft_entry__.build())")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(n for n in names if n.startswith(("fc2d_", "ff_"))))
+
+
+def test_header_declares_the_path():
+    names = declared_functions()
+    for must in ("fc2d_plan_create", "fc2d_extend", "fc2d_fft", "ff_propagate", "fc2d_spectral_apply"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported():
+    lib = C.CDLL(LIB)
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_version_and_strerror():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    assert lib.fc2d_version() == 100
+    assert lib.fc2d_strerror(fc2d.FC2D_E_GEOMETRY) == b"inadmissible geometry"
+
+
+def test_argument_errors_without_gpu():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    g = fc2d.make_grid(0, 0, 0.1, 100, 64)          # 100 is not a power of two
+    assert lib.fc2d_fft(C.byref(g), C.c_void_p(8), C.c_void_p(16), fc2d.FC2D_FORWARD, 1, None) == fc2d.FC2D_E_ARG
+    assert b"powers of two" in lib.fc2d_last_error()
+    g2 = fc2d.make_grid(0, 0, 0.1, 64, 64)
+    assert lib.fc2d_fft(C.byref(g2), C.c_void_p(8), C.c_void_p(8), fc2d.FC2D_FORWARD, 1, None) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_fft(C.byref(g2), C.c_void_p(8), C.c_void_p(16), 7, 1, None) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_fft(C.byref(g2), None, None, fc2d.FC2D_FORWARD, 0, None) == fc2d.FC2D_OK   # empty batch
+    h = C.c_void_p()
+    assert lib.fc2d_plan_create(None, C.byref(g2), 5, 27, None, None, C.byref(h)) == fc2d.FC2D_E_ARG
+    cv = fc2d.make_curve("polar", [1.0])
+    assert lib.fc2d_plan_create(C.byref(cv), C.byref(g2), 5, 27, None, None, None) == fc2d.FC2D_E_ARG
+    o = fc2d.fc2d_opts()
+    lib.fc2d_opts_default(C.byref(g2), C.byref(o))
+    o.M = 20                                           # beyond the supported interpolation size
+    assert lib.fc2d_plan_create(C.byref(cv), C.byref(g2), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_spectral_apply(C.byref(g2), 99, C.c_void_p(8), C.c_void_p(8), 1, None) == fc2d.FC2D_E_ARG
+
+
+def test_opts_default_follows_the_paper():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    g = fc2d.make_grid(-1.5, -1.5, 3.0 / 128, 128, 128)
+    o = fc2d.fc2d_opts()
+    lib.fc2d_opts_default(C.byref(g), C.byref(o))
+    assert (o.n_r, o.Z, o.n_os, o.mf) == (6, 12, 20, 20)
+    assert o.k1 == g.h and o.B == 256

@@ -1,0 +1,150 @@
+"""GPU parity of the HIP 2D-FC path against the CPU oracle, through the C ABI.
+
+Bars (floating point): matching values, blend and extension within 1e-11 of
+the oracle relative to the field's largest magnitude, IN points bitwise equal
+to f, FAR points exactly 0; spectra within 1e-12 relative; integer work
+(classification, STRIP index list) bit-exact."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_common import fields, gpu_plan, oracle_plan, rel_err
+from oracle import extend as OE
+from oracle import plan as OP
+from oracle import spectral as OS
+
+pytestmark = pytest.mark.gpu
+
+CASES = {
+    "disc128": (W.cfg_disc128,),
+    "star320": (W.cfg_star, 320),
+    "kite256": (W.cfg_kite, 256),
+    "star1024": (W.cfg_star, 1024),
+}
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _funcs(name):
+    if name.startswith("star"):
+        return [W.f_star(s) for s in range(3)]
+    if name.startswith("kite"):
+        return [W.poisson_rhs(0), W.f_cfg1]
+    return [W.f_cfg1, W.f_paper_disc]
+
+
+@pytest.fixture(scope="module", params=list(CASES))
+def both(request, torch_mod):
+    name = request.param
+    case, opl = oracle_plan(name, *CASES[name])
+    print("\n[parity] case", name, "n", case.n, "B", case.B, flush=True)
+    gpl = gpu_plan(case)
+    return name, case, opl, gpl
+
+
+def test_classification_bit_exact(both):
+    from paper_2010_03901_amd import fc2d
+    name, case, opl, gpl = both
+    cls = fc2d.fc2d_plan_classes(gpl)
+    assert np.array_equal(cls, opl.cls), (name, np.argwhere(cls != opl.cls)[:5])
+    idx, th, eta, seed = fc2d.fc2d_plan_strip(gpl)
+    assert np.array_equal(idx, opl.strip_idx)
+    dth = np.abs((th - opl.strip_theta + math.pi) % (2 * math.pi) - math.pi)
+    assert dth.max() < 1e-13
+    assert np.abs(eta - opl.strip_eta).max() < 1e-14
+    # seeds are valid: within two normals of the foot
+    dp = np.abs(((seed - th / opl.k2) + case.B / 2) % case.B - case.B / 2)
+    assert dp.max() < 2.0
+
+
+def test_boundary_points_agree(both):
+    from paper_2010_03901_amd import fc2d
+    name, case, opl, gpl = both
+    g = fc2d.fc2d_boundary_points(gpl)
+    o = OP.boundary_points(opl)
+    assert g.shape == o.shape
+    assert np.array_equal(g[: case.B], o[: case.B])          # feet: same formula, same libm
+    assert np.abs(g - o).max() < 1e-14
+
+
+def _device(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+
+
+def test_matching_and_blend(both, torch_mod):
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    name, case, opl, gpl = both
+    funcs = _funcs(name)
+    fg, fbo = fields(case, funcs, OP.boundary_points(opl))
+    _, fbg = fields(case, funcs, fc2d.fc2d_boundary_points(gpl))
+    nf = len(funcs)
+    fD = torch.zeros((nf, case.B, case.d), dtype=torch.float64, device="cuda:0")
+    fc2d.fc2d_matching(gpl, _device(torch, fg), _device(torch, fbg), fD)
+    F = torch.zeros((nf, opl.Cr + 1, case.B), dtype=torch.float64, device="cuda:0")
+    fc2d.fc2d_blend(gpl, _device(torch, fg), _device(torch, fbg), F)
+    torch.cuda.synchronize()
+    for k in range(nf):
+        fDo = OE.matching_values(opl, fg[k], fbo[k])
+        assert rel_err(fD[k].cpu().numpy(), fDo.astype(np.float64)) < 1e-13
+        Fo = OE.blend(opl, fDo)
+        assert rel_err(F[k].cpu().numpy(), Fo) < 1e-11
+
+
+def test_extend_parity(both, torch_mod):
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    name, case, opl, gpl = both
+    funcs = _funcs(name)
+    fg, fbo = fields(case, funcs, OP.boundary_points(opl))
+    _, fbg = fields(case, funcs, fc2d.fc2d_boundary_points(gpl))
+    nf = len(funcs)
+    fg_garbage = fg.copy()
+    fg_garbage[:, opl.cls != OP.IN] = 1e300           # only IN entries may be read
+    dfg = _device(torch, fg_garbage)
+    out = torch.full_like(dfg, float("nan"))
+    fc2d.fc2d_extend(gpl, dfg, _device(torch, fbg), out)
+    # in place
+    inplace = dfg.clone()
+    fc2d.fc2d_extend(gpl, inplace, _device(torch, fbg), inplace)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    inplace = inplace.cpu().numpy()
+    assert np.array_equal(out, inplace)
+    for k in range(nf):
+        ref = OE.extend(opl, fg[k], fbo[k])
+        inm = opl.cls == OP.IN
+        assert np.array_equal(out[k][inm], fg[k][inm])
+        assert np.all(out[k][opl.cls == OP.FAR] == 0.0)
+        e = rel_err(out[k], ref)
+        print("[parity] extend", name, "field", k, "rel err %.3e" % e)
+        assert e < 1e-11
+
+
+def test_fft_forward_inverse(both, torch_mod):
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    name, case, opl, gpl = both
+    if case.n & (case.n - 1):
+        pytest.skip("FFT sizes are powers of two")
+    rng = np.random.default_rng(7)
+    u = rng.standard_normal((2, case.n, case.n))
+    grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+    du = _device(torch, u)
+    spec = torch.zeros((2, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    fc2d.fc2d_fft(grid, du, spec, fc2d.FC2D_FORWARD)
+    back = torch.zeros_like(du)
+    spec2 = spec.clone()
+    fc2d.fc2d_fft(grid, spec2, back, fc2d.FC2D_INVERSE)
+    torch.cuda.synchronize()
+    for k in range(2):
+        assert rel_err(spec[k].cpu().numpy(), np.fft.rfft2(u[k])) < 1e-12
+    assert rel_err(back.cpu().numpy(), u) < 1e-13

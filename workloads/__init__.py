@@ -116,12 +116,12 @@ def box_case(name, curve, lo, hi, n, B, k1=None, **kw):
 
 
 def fitted_case(name, curve, n, B=None, k1=None, C=27, **kw):
-    """Square box around the domain: side n h with h = D / (n - 2C - 2), D the
+    """Square box around the domain: side n h with h = D / (n - 2C - 4), D the
     larger extent of the domain, centred on its bounding box; B = the power of
     two nearest 2 pi / h when not given."""
     xmin, xmax, ymin, ymax = bbox(curve)
     D = max(xmax - xmin, ymax - ymin)
-    h = D / (n - 2 * C - 2)
+    h = D / (n - 2 * C - 4)
     cx, cy = 0.5 * (xmin + xmax), 0.5 * (ymin + ymax)
     x0 = cx - 0.5 * n * h
     y0 = cy - 0.5 * n * h

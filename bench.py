@@ -1,0 +1,176 @@
+"""Throughput of the 2D-FC hot path on one MI355X: extension + forward 2D FFT.
+
+Workload (the star domain of the paper-derived benchmark): r(t) = 1 + 0.3 cos 5t,
+B = 2048 boundary points, box [-1.6, 1.6]^2 on a 1024 x 1024 float64 grid, d = 5,
+C = 27, M = 8, normal step k1 = 0.0024 (0.9 x exterior reach / C).  A step
+extends nf fields f = sin(k1 x) cos(k2 y) + x^3 y ((k1, k2) drawn by seed) and
+takes their forward 2D FFT; inputs are resident in HBM before timing.
+
+Prints one JSON line (metric, value = extended grid points per second, roofline
+of the dominant kernel from HIP-event kernel times, cpu_baseline = the oracle
+timed on a bounded sample on the host).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--nf", type=int, default=128, help="fields per step")
+    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-fields", type=int, default=96)
+    return ap.parse_args()
+
+
+def algorithmic_bytes(name, n, nf, info):
+    """Bytes a kernel must move per launch (float64 / complex128 arrays)."""
+    npts = n * n
+    half = n * (n // 2 + 1)
+    if name == "k_rows_r2c":
+        return nf * (8 * npts + 16 * half)
+    if name == "k_cols":
+        return nf * 32 * half
+    if name == "k_mask":            # out of place: read IN, write IN and FAR
+        return nf * (8 * info.n_in + 8 * (info.n_in + info.n_far))
+    if name == "k_strip":           # write the STRIP values, read (index, theta, eta)
+        return nf * 8 * info.n_strip + 20 * info.n_strip
+    if name == "k_match":
+        return nf * 8 * (info.B * 8 * 8 + info.B * info.d)
+    return 0
+
+
+def cpu_baseline(case, nf_sample):
+    """The oracle (plain NumPy, one thread) on nf_sample fields of the same workload."""
+    from threadpoolctl import threadpool_limits
+    import numpy as np
+    import workloads as W
+    from oracle import extend as OE, fcgram, plan as OP, spectral as OS
+    from oracle.curves import Curve
+    with threadpool_limits(limits=1):
+        pl = OP.make_plan(Curve(*case.curve), OP.Grid(case.x0, case.y0, case.h, case.n, case.n),
+                          fcgram.load_tables(case.d), case.B, k1=case.k1, M=case.M)
+        bp = OP.boundary_points(pl)
+        fields = []
+        for s in range(nf_sample):
+            f = W.f_star(s)
+            fields.append((W.grid_values(case, f), f(bp[:, 0], bp[:, 1])))
+        t0 = time.perf_counter()
+        for fg, fb in fields:
+            ext = OE.extend(pl, fg, fb)
+            OS.fft2_forward(ext)
+        dt = time.perf_counter() - t0
+    return {"value": nf_sample * case.n * case.n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+            "sample": "%d fields of the %dx%d star workload (plan excluded), extend + rfft2, one thread"
+                      % (nf_sample, case.n, case.n)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2010_03901_amd import fc2d
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    case = W.cfg_star(args.n)
+    nf = args.nf
+    print("[bench] workload star%d nf=%d steps=%d warmup=%d" % (case.n, nf, args.steps, args.warmup),
+          file=sys.stderr, flush=True)
+    grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+    t0 = time.perf_counter()
+    plan = fc2d.Plan(fc2d.make_curve(*case.curve), grid, d=case.d, C_=case.C, B=case.B, k1=case.k1, M=case.M)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    info = plan.info
+    bp = fc2d.fc2d_boundary_points(plan)
+    # inputs: nf seeded fields, built on the host once and copied to HBM
+    x = case.x0 + np.arange(case.n) * case.h
+    fg = torch.empty((nf, case.n, case.n), dtype=torch.float64, device="cuda:0")
+    fb = torch.empty((nf, bp.shape[0]), dtype=torch.float64, device="cuda:0")
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    for s in range(nf):
+        f = W.f_star(s)
+        fg[s].copy_(torch.from_numpy(f(X, Y)))
+        fb[s].copy_(torch.from_numpy(f(bp[:, 0], bp[:, 1])))
+    ext = torch.empty_like(fg)
+    spec = torch.empty((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    torch.cuda.synchronize()
+    print("[bench] plan %.2fs, inputs ready" % plan_s, file=sys.stderr, flush=True)
+
+    def step():
+        fc2d.fc2d_extend(plan, fg, fb, ext)
+        fc2d.fc2d_fft(grid, ext, spec, fc2d.FC2D_FORWARD)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(args.steps):
+        step()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    value = nf * case.n * case.n / (ms * 1e-3)
+    print("[bench] %.3f ms/step, %.3e points/s" % (ms, value), file=sys.stderr, flush=True)
+
+    # per-kernel times from HIP events on the launch stream (library tracer)
+    fc2d.fc2d_trace_begin()
+    for _ in range(args.steps):
+        step()
+    tr = fc2d.fc2d_trace_end()
+    per = {}
+    for name, t in tr:
+        if name == "begin":
+            continue
+        per.setdefault(name, []).append(t)
+    kernels = {k: {"avg_ms": float(np.mean(v)), "launches": len(v),
+                   "alg_bytes": algorithmic_bytes(k, case.n, nf, info)} for k, v in per.items()}
+    for k, v in kernels.items():
+        v["GBs"] = v["alg_bytes"] / (v["avg_ms"] * 1e-3) / 1e9 if v["avg_ms"] > 0 else None
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    dk = kernels[dom]
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": dk["GBs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": dk["GBs"] / HBM_PEAK_GBS, "traffic": None,
+                "alg_bytes_per_launch": dk["alg_bytes"], "avg_ms": dk["avg_ms"]}
+    print("[bench] kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
+        cpu = cpu_baseline(case, args.cpu_sample_fields)
+
+    out = {
+        "metric": "2D-FC extended grid points/s at <=1e-11 err vs oracle; plain vs batched+MLP",
+        "value": value, "unit": "points/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "star r=1+0.3cos5t, B=%d, [-1.6,1.6]^2 on %dx%d, d=5, C=27, M=8, k1=%g; "
+                               "extend + forward FFT of %d fields per step" % (case.B, case.n, case.n, case.k1, nf),
+                   "fields_per_step": nf, "grid": case.n, "path": "plain"},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "kernels": kernels,
+        "plan_s": plan_s,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

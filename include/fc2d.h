@@ -136,7 +136,8 @@ int fc2d_blend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry
 int fc2d_extend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
                 double* out, int nf, hipStream_t stream);
 
-/* 2D FFT (Sec. 3.5 step 7), nx and ny powers of two in [16, 8192].
+/* 2D FFT (Sec. 3.5 step 7); nx a power of two in [16, 4096], ny a power of
+ * two in [16, 8192] (Remark 3.2: the grid is padded to FFT-friendly sizes).
  * FC2D_FORWARD: in = real [nf][nx][ny], out = half spectrum, unnormalised.
  * FC2D_INVERSE: in = half spectrum (overwritten as work space), out = real,
  * scaled by 1/(nx ny).  in and out must not overlap. */
@@ -155,6 +156,17 @@ int fc2d_spectral_apply(const fc2d_grid* grid, int op, const void* in, void* out
  * Half spectra, device; outputs may alias inputs. */
 int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, const void* u1h,
                  void* uh, void* uth, int nf, hipStream_t stream);
+
+/* Kernel tracing (a profiling aid, not needed for results).  fc2d_trace_begin
+ * opens a trace and records a HIP event on `stream`; until fc2d_trace_end every
+ * kernel the library launches records one more event after it on its own
+ * stream.  fc2d_trace_end synchronises, closes the trace and returns, in
+ * launch order, up to `cap` entries of kernel name (static strings owned by
+ * the library) and milliseconds since the previous event -- the kernel's
+ * duration when the traced calls share one stream.  *n receives the number
+ * of entries written.  Either output array may be NULL. */
+int fc2d_trace_begin(hipStream_t stream);
+int fc2d_trace_end(int* n, const char** names, float* ms, int cap);
 
 const char* fc2d_strerror(int status);
 const char* fc2d_last_error(void);

@@ -14,7 +14,9 @@ Readings of the paper taken here (the paper leaves them open):
   C k1 + ds/2 and inside points within h + ds/2 (ds = k2 max|q'|, the largest
   sample spacing) -- then get a foot of the normal, and their signed normal
   distance eta decides IN (eta <= 0), STRIP (0 < eta <= C k1) or FAR
-  (eta > C k1).  Every point with 0 < eta <= C k1 is a band point, since its
+  (eta > C k1).  A point with eta <= 1e-13 (1 + |x| + |y|) is taken to lie
+  on Gamma and is IN: this keeps grid points that sit exactly on Gamma (e.g.
+  (1.3, 0) on the star) out of the rounding noise of eta.  Every point with 0 < eta <= C k1 is a band point, since its
   nearest sample is at most sqrt((C k1)^2 + (ds/2)^2) away.
 * Proximity map.  The seed of every foot solve is the normal p of the
   nearest boundary point of V+_{B,C_r} (level q = 0) -- the index part of the
@@ -31,8 +33,8 @@ Readings of the paper taken here (the paper leaves them open):
   the grid lines x = x_i (when |n_x| >= |n_y|) or y = y_j.  A star's nodes are
   the IN points of the run of IN points on its line that holds the star (at
   most M + 1 grid steps away) and the crossings of that line with Gamma that
-  bound the run ("squares"); a square closer than h/2 to the IN node next to
-  it is dropped.  The red stars are the first M candidates offering at least
+  bound the run ("squares"); a square closer than h/2 to one of these IN
+  nodes is dropped.  The red stars are the first M candidates offering at least
   M nodes (a line nearly tangent to Gamma next to a shallow star offers too
   few), and each uses the M nodes nearest to it.  Squares are listed once per
   use, in the order normal, star, node.  Values at the
@@ -54,6 +56,7 @@ FAR, IN, STRIP = 0, 1, 2
 LD = np.longdouble
 TWO_PI = 2.0 * math.pi
 EPS = 2.0 ** -52
+ON_GAMMA_TOL = 1e-13
 
 
 class GeometryError(Exception):
@@ -263,7 +266,9 @@ def make_plan(curve, grid, tables, B, k1=None, M=None, n_r=None):
     # step 4: foot of the normal for band points
     th, eta, iters = foot_solve(curve, bd, XX.ravel()[bidx], YY.ravel()[bidx], near[bidx], M)
     cls = np.where(inside, IN, FAR).astype(np.int8)
-    bcls = np.where(eta <= 0, IN, np.where(eta <= C * k1, STRIP, FAR)).astype(np.int8)
+    # a point within rounding distance of Gamma counts as on Gamma, hence IN
+    on_tol = ON_GAMMA_TOL * (1.0 + np.abs(XX.ravel()[bidx]) + np.abs(YY.ravel()[bidx]))
+    bcls = np.where(eta <= on_tol, IN, np.where(eta <= C * k1, STRIP, FAR)).astype(np.int8)
     cls[bidx] = bcls
     pl.cls = cls.reshape(grid.nx, grid.ny)
     sel = bcls == STRIP
@@ -359,11 +364,10 @@ def _matching_stencils(pl):
     else:
         bsq = np.zeros(0)
     for (rid, side, vertical, a_s, b_in, b_out), b in zip(sq_req, bsq):
-        run = runs[rid][side]
-        if run:
-            grid_b = (grid.y0 if vertical else grid.x0) + run[-1] * h
-            if abs(b - grid_b) < 0.5 * h:
-                continue          # too close to the last IN node of the run: dropped
+        b0 = grid.y0 if vertical else grid.x0
+        nodes = runs[rid][0] + runs[rid][1]
+        if any(abs(b - (b0 + j * h)) < 0.5 * h for j in nodes):
+            continue              # closer than h/2 to an IN node: dropped
         runs[rid][2 + side] = b
     # phase 3: per normal, the first M stars whose line offers >= M nodes;
     # the M nodes nearest each star; weights in longdouble

@@ -26,7 +26,8 @@ HIPCC_FLAGS = [
     "-Wno-unused-result",
 ]
 GXX_FLAGS = [
-    "-O2", "-fPIC", "-std=gnu++17", "-ffp-contract=off", "-fopenmp", "-Wno-unknown-pragmas",
+    "-O2", "-fPIC", "-std=gnu++17", "-ffp-contract=off", "-fno-builtin-sin", "-fno-builtin-cos",
+    "-fopenmp", "-Wno-unknown-pragmas",
     "-D__HIP_PLATFORM_AMD__", "-I" + os.path.join(ROCM, "include"), "-Wall", "-Wno-unused-function",
 ]
 

@@ -19,6 +19,10 @@ int gram_tables(int d, int C, int Z, int n_os, int n_r, int mf, double* Q, doubl
 
 void set_error(const std::string& msg);
 
+// Kernel tracer: when a trace is open (fc2d_trace_begin), records a HIP event
+// on `s` after each launch so fc2d_trace_end can report per-kernel times.
+void trace_point(const char* name, hipStream_t s);
+
 struct DevBuf {
     void* p = nullptr;
     size_t bytes = 0;

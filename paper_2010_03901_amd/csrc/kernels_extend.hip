@@ -174,12 +174,13 @@ __global__ void k_mask(const int32_t* __restrict__ run_ptr, const int32_t* __res
     }
 }
 
-static int launch_check(const char* what) {
+static int launch_check(const char* what, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string(what) + ": " + hipGetErrorString(e));
         return FC2D_E_HIP;
     }
+    trace_point(what, s);
     return FC2D_OK;
 }
 
@@ -195,7 +196,7 @@ int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry
         case 8: k_match<8><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, c_out, fD_out); break;
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
-    return launch_check("k_match");
+    return launch_check("k_match", s);
 }
 
 int launch_blend(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry, double* F, int nf,
@@ -203,7 +204,7 @@ int launch_blend(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     const int64_t n = (int64_t)(pl->Cr + 1) * pl->B;
     dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 4096), nf);
     k_blend<<<grid, 256, 0, s>>>(c, f_bdry, nbdry, pl->d_Ar, pl->d, pl->B, pl->Cr, F);
-    return launch_check("k_blend");
+    return launch_check("k_blend", s);
 }
 
 int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry, double* out, int nf,
@@ -222,14 +223,14 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
         case 8: k_strip<8><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts); break;
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
-    return launch_check("k_strip");
+    return launch_check("k_strip", s);
 }
 
 int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, hipStream_t s) {
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
     dim3 grid(pl->grid.nx, nf);
     k_mask<<<grid, 256, 0, s>>>(pl->d_run_ptr, pl->d_run, pl->grid.ny, f_grid, out, npts, f_grid != out);
-    return launch_check("k_mask");
+    return launch_check("k_mask", s);
 }
 
 }  // namespace fc2d

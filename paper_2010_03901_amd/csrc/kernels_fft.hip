@@ -271,12 +271,13 @@ __global__ __launch_bounds__(256) void k_cols(double2* __restrict__ data, int nx
     }
 }
 
-static int check(const char* what) {
+static int check(const char* what, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
         set_error(std::string(what) + ": " + hipGetErrorString(e));
         return FC2D_E_HIP;
     }
+    trace_point(what, s);
     return FC2D_OK;
 }
 
@@ -294,13 +295,13 @@ int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStrea
     const RadixPlan rpy = radix_plan(L);
     dim3 gr((nx + rpb - 1) / rpb, nf);
     k_rows_r2c<<<gr, nthreads_for(rpb * L), rpb * L * sizeof(double2), s>>>(in, (double2*)out, nx, ny, rpb, rpy, twy);
-    int st = check("k_rows_r2c");
+    int st = check("k_rows_r2c", s);
     if (st) return st;
     const int T = col_tile(nx);
     const RadixPlan rpx = radix_plan(nx);
     dim3 gc((L + 1 + T - 1) / T, nf);
     k_cols<false><<<gc, nthreads_for(nx * T), nx * T * sizeof(double2), s>>>((double2*)out, nx, L + 1, T, rpx, twx);
-    return check("k_cols");
+    return check("k_cols", s);
 }
 
 int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s) {
@@ -313,14 +314,14 @@ int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s)
     const RadixPlan rpx = radix_plan(nx);
     dim3 gc((L + 1 + T - 1) / T, nf);
     k_cols<true><<<gc, nthreads_for(nx * T), nx * T * sizeof(double2), s>>>((double2*)in, nx, L + 1, T, rpx, twx);
-    int st = check("k_cols");
+    int st = check("k_cols", s);
     if (st) return st;
     const int rpb = rows_per_block(ny);
     const RadixPlan rpy = radix_plan(L);
     dim3 gr((nx + rpb - 1) / rpb, nf);
     k_rows_c2r<<<gr, nthreads_for(rpb * L), rpb * L * sizeof(double2), s>>>((const double2*)in, out, nx, ny, rpb, rpy,
                                                                            twy, 1.0 / ((double)nx * (double)ny));
-    return check("k_rows_c2r");
+    return check("k_rows_c2r", s);
 }
 
 // ---------------------------------------------------------------------------
@@ -361,7 +362,7 @@ int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, in
     const int64_t n = (int64_t)nf * g->nx * (g->ny / 2 + 1);
     const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
     k_spectral<<<nb, 256, 0, s>>>((const double2*)in, (double2*)out, n, g->nx, g->ny, g->h, op);
-    return check("k_spectral");
+    return check("k_spectral", s);
 }
 
 __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2* uth, int64_t n, int nx, int ny,
@@ -399,7 +400,7 @@ int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const dou
     const unsigned nb = (unsigned)std::min<int64_t>((n + 255) / 256, 65536);
     k_ff<<<nb, 256, 0, s>>>((const double2*)u0, (const double2*)u1, (double2*)uh, (double2*)uth, n, g->nx, g->ny, g->h,
                             c, t);
-    return check("k_ff");
+    return check("k_ff", s);
 }
 
 }  // namespace fc2d

@@ -76,7 +76,9 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a, const uint64_t
             if (stt != FOOT_OK) {
                 atomicAdd(&counters[1], 1);
             } else {
-                c = eta <= 0.0 ? 1 : (eta <= a.width ? 2 : 0);
+                // within rounding distance of Gamma counts as on Gamma: IN
+                const double on_tol = 1e-13 * (1.0 + fabs(X) + fabs(Y));
+                c = eta <= on_tol ? 1 : (eta <= a.width ? 2 : 0);
                 if (c == 2) {
                     const int slot = atomicAdd(&counters[0], 1);
                     if (slot < cap) {
@@ -121,6 +123,7 @@ int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64
         set_error(std::string("classification launch: ") + hipGetErrorString(e));
         return FC2D_E_HIP;
     }
+    trace_point("k_classify", s);
     return FC2D_OK;
 }
 

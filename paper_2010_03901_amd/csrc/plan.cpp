@@ -11,13 +11,14 @@
 //    with a 16 B-vertex polygon of Gamma; every point whose nearest boundary
 //    sample is within C k1 + ds/2 (outside) or h + ds/2 (inside), ds the
 //    largest sample spacing, is reclassified by the signed normal distance eta
-//    of its foot: IN (eta <= 0), STRIP (0 < eta <= C k1) or FAR.
+//    of its foot: IN (eta <= 0), STRIP (0 < eta <= C k1) or FAR; a point with
+//    eta <= 1e-13 (1 + |x| + |y|) lies on Gamma to rounding and is IN.
 //  * Matching stencils (Sec. 3.2): candidate red stars are the crossings at
 //    depth >= 0 of the inward normal with grid lines x = x_i (|n_x| >= |n_y|)
 //    or y = y_j, in order of depth.  A star's nodes are the IN points of the
 //    run of IN points holding it (at most M + 1 grid steps away) and the
 //    crossings of its line with Gamma bounding the run (squares); a square
-//    closer than h/2 to the IN node next to it is dropped.  The first M
+//    closer than h/2 to one of those IN nodes is dropped.  The first M
 //    candidates with at least M nodes are the red stars; each uses its M
 //    nearest nodes.  Weights are formed in x87 extended precision and stored
 //    as double-double.
@@ -37,6 +38,23 @@ namespace fc2d {
 
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
+
+// kernel tracer
+static std::mutex g_trace_mu;
+static bool g_trace_on = false;
+static std::vector<std::pair<const char*, hipEvent_t>> g_trace;
+
+void trace_point(const char* name, hipStream_t s) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    if (!g_trace_on) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return;
+    if (hipEventRecord(e, s) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return;
+    }
+    g_trace.push_back({name, e});
+}
 
 static int hip_fail(hipError_t e, const char* what) {
     set_error(std::string(what) + ": " + hipGetErrorString(e));
@@ -250,11 +268,11 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
     }
     for (const SqReq& q : reqs) {
         StarRec& r = stars[q.rid];
-        const std::vector<int>& run = q.side == 0 ? r.lower : r.upper;
-        if (!run.empty()) {
-            const double gb = (r.vertical ? g.y0 : g.x0) + run.back() * h;
-            if (fabs(q.result - gb) < 0.5 * h) continue;   // dropped: too close to the run's end
-        }
+        const double b0 = r.vertical ? g.y0 : g.x0;
+        bool near_node = false;
+        for (int j : r.lower) near_node = near_node || fabs(q.result - (b0 + j * h)) < 0.5 * h;
+        for (int j : r.upper) near_node = near_node || fabs(q.result - (b0 + j * h)) < 0.5 * h;
+        if (near_node) continue;   // dropped: closer than h/2 to an IN node
         r.sq_has[q.side] = true;
         r.sq_b[q.side] = q.result;
     }
@@ -719,11 +737,11 @@ int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry,
     return launch_strip(pl, pl->d_c, f_bdry, nb, out, nf, s);
 }
 
-static bool pow2_ok(int n) { return n >= 16 && n <= 8192 && (n & (n - 1)) == 0; }
+static bool pow2_ok(int n, int nmax) { return n >= 16 && n <= nmax && (n & (n - 1)) == 0; }
 
 int fc2d_fft(const fc2d_grid* g, void* in, void* out, int dir, int nf, hipStream_t s) {
-    if (!g || !pow2_ok(g->nx) || !pow2_ok(g->ny) || nf < 0) {
-        set_error("fc2d_fft: nx and ny must be powers of two in [16, 8192]");
+    if (!g || !pow2_ok(g->nx, 4096) || !pow2_ok(g->ny, 8192) || nf < 0) {
+        set_error("fc2d_fft: nx must be a power of two in [16, 4096] and ny one in [16, 8192]");
         return FC2D_E_ARG;
     }
     if (nf == 0) return FC2D_OK;
@@ -770,6 +788,41 @@ const char* fc2d_strerror(int status) {
 }
 
 const char* fc2d_last_error(void) { return g_last_error.c_str(); }
+
+int fc2d_trace_begin(hipStream_t stream) {
+    {
+        std::lock_guard<std::mutex> lk(g_trace_mu);
+        for (auto& t : g_trace) (void)hipEventDestroy(t.second);
+        g_trace.clear();
+        g_trace_on = true;
+    }
+    trace_point("begin", stream);
+    return FC2D_OK;
+}
+
+int fc2d_trace_end(int* n, const char** names, float* ms, int cap) {
+    std::lock_guard<std::mutex> lk(g_trace_mu);
+    g_trace_on = false;
+    int k = 0;
+    int st = FC2D_OK;
+    if (!g_trace.empty()) {
+        hipError_t e = hipEventSynchronize(g_trace.back().second);
+        if (e != hipSuccess) st = hip_fail(e, "fc2d_trace_end");
+        for (size_t i = 1; i < g_trace.size() && st == FC2D_OK; ++i) {
+            if (k < cap) {
+                float t = 0.0f;
+                if (hipEventElapsedTime(&t, g_trace[i - 1].second, g_trace[i].second) != hipSuccess) t = -1.0f;
+                if (names) names[k] = g_trace[i].first;
+                if (ms) ms[k] = t;
+            }
+            ++k;
+        }
+    }
+    for (auto& t : g_trace) (void)hipEventDestroy(t.second);
+    g_trace.clear();
+    if (n) *n = std::min(k, cap);
+    return st;
+}
 
 int fc2d_version(void) { return FC2D_VERSION; }
 

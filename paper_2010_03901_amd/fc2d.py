@@ -75,6 +75,8 @@ def _lib():
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
             "ff_propagate": (C.c_int, [C.POINTER(fc2d_grid), C.c_double, C.c_double, _P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_trace_begin": (C.c_int, [_P]),
+            "fc2d_trace_end": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.c_int]),
             "fc2d_strerror": (C.c_char_p, [C.c_int]),
             "fc2d_last_error": (C.c_char_p, []),
             "fc2d_version": (C.c_int, []),
@@ -259,6 +261,19 @@ def ff_propagate(grid, c, t, u0h, u1h, uh, uth, stream=None):
     nf = u0h.numel() // (grid.nx * (grid.ny // 2 + 1))
     _check(_lib().ff_propagate(C.byref(grid), float(c), float(t), _dptr(u0h, "u0h"), _dptr(u1h, "u1h"),
                                _dptr(uh, "uh"), _dptr(uth, "uth"), nf, _stream(stream)))
+
+
+def fc2d_trace_begin(stream=None):
+    _check(_lib().fc2d_trace_begin(_stream(stream)))
+
+
+def fc2d_trace_end(cap=4096):
+    """Close the trace; returns [(kernel name, milliseconds)] in launch order."""
+    n = C.c_int()
+    names = (C.c_char_p * cap)()
+    ms = (C.c_float * cap)()
+    _check(_lib().fc2d_trace_end(C.byref(n), names, ms, cap))
+    return [(names[i].decode(), float(ms[i])) for i in range(n.value)]
 
 
 def fc2d_version():

@@ -44,7 +44,7 @@ def test_argument_errors_without_gpu():
     lib = fc2d._lib()
     g = fc2d.make_grid(0, 0, 0.1, 100, 64)          # 100 is not a power of two
     assert lib.fc2d_fft(C.byref(g), C.c_void_p(8), C.c_void_p(16), fc2d.FC2D_FORWARD, 1, None) == fc2d.FC2D_E_ARG
-    assert b"powers of two" in lib.fc2d_last_error()
+    assert b"power of two" in lib.fc2d_last_error()
     g2 = fc2d.make_grid(0, 0, 0.1, 64, 64)
     assert lib.fc2d_fft(C.byref(g2), C.c_void_p(8), C.c_void_p(8), fc2d.FC2D_FORWARD, 1, None) == fc2d.FC2D_E_ARG
     assert lib.fc2d_fft(C.byref(g2), C.c_void_p(8), C.c_void_p(16), 7, 1, None) == fc2d.FC2D_E_ARG

@@ -25,27 +25,6 @@
 
 namespace fc2d {
 
-struct RadixPlan {
-    int nst;
-    int r[16];
-};
-
-static RadixPlan radix_plan(int L) {
-    RadixPlan p{};
-    int n = L;
-    std::vector<int> rs;
-    while (n % 8 == 0 && n > 1) { rs.push_back(8); n /= 8; }
-    if (n == 4) rs.push_back(4);
-    else if (n == 2) {
-        // replace one radix 8 by 4 x 4
-        if (!rs.empty()) { rs.pop_back(); rs.push_back(4); rs.push_back(4); }
-        else rs.push_back(2);
-    }
-    p.nst = (int)rs.size();
-    for (int i = 0; i < p.nst; ++i) p.r[i] = rs[i];
-    return p;
-}
-
 // ---------------------------------------------------------------------------
 // twiddle tables, cached per (device, N)
 // ---------------------------------------------------------------------------
@@ -124,151 +103,231 @@ __device__ __forceinline__ void dft8(double2* v) {
     v[3] = cadd(e3, o3); v[7] = csub(e3, o3);
 }
 
-// In-LDS Stockham FFT of nseq sequences of length L, element (q, n) at
-// buf[q * qs + n * ns].  Twiddle table of length NT (a multiple of L).
-// All threads of the block must call it.
-constexpr int kBPT = 4;   // butterflies per thread per stage (upper bound)
+template <bool INV>
+__device__ __forceinline__ double2 cmul_w(double2 a, double c, double s) {
+    // a * (c + i s) forward, a * (c - i s) inverse (s given for the forward sign)
+    return INV ? make_double2(a.x * c + a.y * s, a.y * c - a.x * s) : make_double2(a.x * c - a.y * s, a.x * s + a.y * c);
+}
+
+template <bool INV>
+__device__ __forceinline__ void dft16(double2* v) {
+    // 16 = 4 x 4: DFT4 over n1 for each n2, twiddle W16^(n2 k1), DFT4 over n2, transpose
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) dft4<INV>(v[n2], v[n2 + 4], v[n2 + 8], v[n2 + 12]);
+    const double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173, c2 = 0.70710678118654752440;
+    // forward W16^m = cos(2 pi m/16) - i sin(2 pi m/16)
+    v[1 + 4] = cmul_w<INV>(v[1 + 4], c1, -s1);    // m = 1
+    v[1 + 8] = cmul_w<INV>(v[1 + 8], c2, -c2);    // m = 2
+    v[1 + 12] = cmul_w<INV>(v[1 + 12], s1, -c1);  // m = 3
+    v[2 + 4] = cmul_w<INV>(v[2 + 4], c2, -c2);    // m = 2
+    v[2 + 8] = cmul_mi<INV>(v[2 + 8]);            // m = 4
+    v[2 + 12] = cmul_w<INV>(v[2 + 12], -c2, -c2); // m = 6
+    v[3 + 4] = cmul_w<INV>(v[3 + 4], s1, -c1);    // m = 3
+    v[3 + 8] = cmul_w<INV>(v[3 + 8], -c2, -c2);   // m = 6
+    v[3 + 12] = cmul_w<INV>(v[3 + 12], -c1, s1);  // m = 9
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) dft4<INV>(v[4 * k1], v[4 * k1 + 1], v[4 * k1 + 2], v[4 * k1 + 3]);
+    double2 o[16];
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1)
+#pragma unroll
+        for (int k2 = 0; k2 < 4; ++k2) o[k1 + 4 * k2] = v[4 * k1 + k2];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v[k] = o[k];
+}
 
 template <int R, bool INV>
-__device__ __forceinline__ void lds_stage(double2* buf, int L, int nseq, int qs, int ns, int Ns,
-                                          const double2* __restrict__ tw, int NT) {
-    const int nthr = blockDim.x;
-    const int nb = nseq * (L / R);
-    const int tstep = NT / (Ns * R);
-    double2 v[kBPT][R];
+__device__ __forceinline__ void dftR(double2* v) {
+    if constexpr (R == 16) dft16<INV>(v);
+    else if constexpr (R == 8) dft8<INV>(v);
+    else if constexpr (R == 4) dft4<INV>(v[0], v[1], v[2], v[3]);
+    else dft2<INV>(v[0], v[1]);
+}
+
+// largest radix in {16, 8, 4, 2} not above E that divides rem
+constexpr int pick_radix(int rem, int E) {
+    int r = 16;
+    while (r > E || rem % r != 0) r >>= 1;
+    return r;
+}
+
+// Register-resident Stockham FFT of length L, E elements per thread
+// (P = L / E threads per sequence).  Thread t owns butterflies b_i = t + i P;
+// v[i R + r] holds element b_i + r L/R of the current stage.  On entry v holds
+// the input in the first stage's read pattern (loaded by the caller); on exit
+// v[i R + r] = X[b_i + r L/R] for the last stage's radix R.  Intermediate
+// exchanges go through LDS at lds[n * NS + q * QS].
+template <int L, int E, int Ns, bool INV>
+struct StockhamFrom {
+    static constexpr int R = pick_radix(L / Ns, E);
+    static constexpr int NB = E / R;   // butterflies per thread
+    static constexpr int P = L / E;
+    static constexpr bool LAST = Ns * R == L;
+
+    __device__ static void run(double2* v, double2* lds, int QS, int NS, int q, int t,
+                               const double2* __restrict__ tw, int NT) {
+        if constexpr (Ns > 1) {
+            // read this stage's inputs from LDS
 #pragma unroll
-    for (int i = 0; i < kBPT; ++i) {
-        const int b = threadIdx.x + i * nthr;
-        if (b < nb) {
-            const int q = b % nseq;
-            const int t = b / nseq;
-            const int j = t % Ns;
+            for (int i = 0; i < NB; ++i) {
+                const int b = t + i * P;
 #pragma unroll
-            for (int r = 0; r < R; ++r) {
-                double2 x = buf[q * qs + (t + r * (L / R)) * ns];
-                if (r > 0 && j > 0) {
-                    double2 w = tw[j * r * tstep];
+                for (int r = 0; r < R; ++r) v[i * R + r] = lds[(b + r * (L / R)) * NS + q * QS];
+            }
+            // twiddles
+            constexpr int tstep_div = Ns * R;
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                const int b = t + i * P;
+                const int j = b % Ns;
+#pragma unroll
+                for (int r = 1; r < R; ++r) {
+                    double2 w = tw[(j * r) * (NT / tstep_div)];
                     if (INV) w = cconj(w);
-                    x = cmul(x, w);
+                    v[i * R + r] = cmul(v[i * R + r], w);
                 }
-                v[i][r] = x;
             }
         }
-    }
-    __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kBPT; ++i) {
-        const int b = threadIdx.x + i * nthr;
-        if (b < nb) {
-            const int q = b % nseq;
-            const int t = b / nseq;
-            const int j = t % Ns;
-            if constexpr (R == 8) dft8<INV>(v[i]);
-            else if constexpr (R == 4) dft4<INV>(v[i][0], v[i][1], v[i][2], v[i][3]);
-            else dft2<INV>(v[i][0], v[i][1]);
-            const int idxD = (t / Ns) * Ns * R + j;
+        for (int i = 0; i < NB; ++i) dftR<R, INV>(v + i * R);
+        if constexpr (!LAST) {
+            __syncthreads();   // every thread has read this stage's inputs
 #pragma unroll
-            for (int r = 0; r < R; ++r) buf[q * qs + (idxD + r * Ns) * ns] = v[i][r];
+            for (int i = 0; i < NB; ++i) {
+                const int b = t + i * P;
+                const int j = b % Ns;
+                const int base = (b / Ns) * Ns * R + j;
+#pragma unroll
+                for (int r = 0; r < R; ++r) lds[(base + r * Ns) * NS + q * QS] = v[i * R + r];
+            }
+            __syncthreads();
+            StockhamFrom<L, E, Ns * R, INV>::run(v, lds, QS, NS, q, t, tw, NT);
         }
     }
-    __syncthreads();
+};
+
+template <int L, int E>
+struct FirstStage {
+    static constexpr int R = pick_radix(L, E);
+};
+
+// first-stage index of register slot k (= i R1 + r)
+template <int L, int E>
+__device__ __forceinline__ int in_index(int k, int t) {
+    constexpr int R = FirstStage<L, E>::R;
+    constexpr int P = L / E;
+    return t + (k / R) * P + (k % R) * (L / R);
 }
 
-template <bool INV>
-__device__ void lds_fft(double2* buf, int L, int nseq, int qs, int ns, const RadixPlan& rp,
-                        const double2* __restrict__ tw, int NT) {
-    int Ns = 1;
-    for (int st = 0; st < rp.nst; ++st) {
-        const int R = rp.r[st];
-        if (R == 8) lds_stage<8, INV>(buf, L, nseq, qs, ns, Ns, tw, NT);
-        else if (R == 4) lds_stage<4, INV>(buf, L, nseq, qs, ns, Ns, tw, NT);
-        else lds_stage<2, INV>(buf, L, nseq, qs, ns, Ns, tw, NT);
-        Ns *= R;
-    }
+// last-stage index of register slot k
+template <int L, int E, int Ns>
+struct LastR {
+    static constexpr int R0 = pick_radix(L / Ns, E);
+    static constexpr int value = (Ns * R0 == L) ? R0 : LastR<L, E, (Ns * R0 == L ? L : Ns * R0)>::value;
+};
+template <int L, int E>
+struct LastR<L, E, L> {
+    static constexpr int value = 1;
+};
+template <int L, int E>
+__device__ __forceinline__ int out_index(int k, int t) {
+    constexpr int R = LastR<L, E, 1>::value;
+    constexpr int P = L / E;
+    return t + (k / R) * P + (k % R) * (L / R);
 }
 
 // ---------------------------------------------------------------------------
-// pass R: real rows -> half-spectrum rows
+// pass R: real rows -> half-spectrum rows (one row per P threads)
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_rows_r2c(const double* __restrict__ in, double2* __restrict__ out, int nx,
-                                                  int ny, int rpb, RadixPlan rp, const double2* __restrict__ tw) {
-    extern __shared__ double2 sbuf[];
-    const int L = ny / 2;
+template <int L, int E, int RPB>
+__global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __restrict__ in, double2* __restrict__ out,
+                                                            int nx, const double2* __restrict__ tw) {
+    constexpr int P = L / E;
+    constexpr int N = 2 * L;
+    __shared__ double2 lds[RPB * L];
+    const int q = threadIdx.x / P;
+    const int t = threadIdx.x % P;
+    const int row = blockIdx.x * RPB + q;
     const int f = blockIdx.y;
-    const int row0 = blockIdx.x * rpb;
-    const int nrows = min(rpb, nx - row0);
-    const double2* src = (const double2*)(in + ((int64_t)f * nx + row0) * ny);
-    for (int e = threadIdx.x; e < nrows * L; e += blockDim.x) sbuf[e] = src[e];
+    const bool live = row < nx;
+    const double2* src = (const double2*)(in + ((int64_t)f * nx + (live ? row : 0)) * N);
+    double2 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = src[in_index<L, E>(k, t)];
+    StockhamFrom<L, E, 1, false>::run(v, lds, L, 1, q, t, tw, N);
     __syncthreads();
-    lds_fft<false>(sbuf, L, nrows, L, 1, rp, tw, ny);
-    double2* dst = out + ((int64_t)f * nx + row0) * (L + 1);
-    for (int e = threadIdx.x; e < nrows * (L + 1); e += blockDim.x) {
-        const int q = e / (L + 1);
-        const int k = e - q * (L + 1);
-        const double2 zk = sbuf[q * L + (k == L ? 0 : k)];
-        const double2 zc = cconj(sbuf[q * L + (k == 0 ? 0 : L - k)]);
-        const double2 E = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[q * L + out_index<L, E>(k, t)] = v[k];
+    __syncthreads();
+    if (!live) return;
+    double2* dst = out + ((int64_t)f * nx + row) * (L + 1);
+    for (int k = t; k <= L; k += P) {
+        const double2 zk = lds[q * L + (k == L ? 0 : k)];
+        const double2 zc = cconj(lds[q * L + (k == 0 ? 0 : L - k)]);
+        const double2 Eh = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
         const double2 D = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y - zc.y));
-        // O = D / i = -i D
-        const double2 O = make_double2(D.y, -D.x);
-        const double2 w = tw[k % ny];
-        dst[e] = cadd(E, cmul(w, O));
+        const double2 O = make_double2(D.y, -D.x);   // D / i
+        dst[k] = cadd(Eh, cmul(tw[k], O));
     }
 }
 
-// pass R': half-spectrum rows -> real rows (scaled)
-__global__ __launch_bounds__(256) void k_rows_c2r(const double2* __restrict__ in, double* __restrict__ out, int nx,
-                                                  int ny, int rpb, RadixPlan rp, const double2* __restrict__ tw,
-                                                  double scale) {
-    extern __shared__ double2 sbuf[];
-    const int L = ny / 2;
+// pass R': half-spectrum rows -> real rows, scaled
+template <int L, int E, int RPB>
+__global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __restrict__ in, double* __restrict__ out,
+                                                            int nx, const double2* __restrict__ tw, double scale) {
+    constexpr int P = L / E;
+    constexpr int N = 2 * L;
+    __shared__ double2 lds[RPB * L];
+    const int q = threadIdx.x / P;
+    const int t = threadIdx.x % P;
+    const int row = blockIdx.x * RPB + q;
     const int f = blockIdx.y;
-    const int row0 = blockIdx.x * rpb;
-    const int nrows = min(rpb, nx - row0);
-    const double2* src = in + ((int64_t)f * nx + row0) * (L + 1);
-    for (int e = threadIdx.x; e < nrows * L; e += blockDim.x) {
-        const int q = e / L;
-        const int k = e - q * L;
-        const double2 xk = src[q * (L + 1) + k];
-        const double2 xc = cconj(src[q * (L + 1) + (L - k)]);
+    const bool live = row < nx;
+    const double2* src = in + ((int64_t)f * nx + (live ? row : 0)) * (L + 1);
+    double2 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int n = in_index<L, E>(k, t);
+        const double2 xk = src[n];
+        const double2 xc = cconj(src[L - n]);
         const double2 S = cadd(xk, xc);
-        const double2 D = csub(xk, xc);
-        const double2 w = cconj(tw[k]);   // exp(+2 pi i k / ny)
-        const double2 Dw = cmul(D, w);
-        // Z' = S + i Dw
-        sbuf[e] = make_double2(S.x - Dw.y, S.y + Dw.x);
+        const double2 Dw = cmul(csub(xk, xc), cconj(tw[n]));   // exp(+2 pi i n / N)
+        v[k] = make_double2(S.x - Dw.y, S.y + Dw.x);           // S + i Dw
     }
-    __syncthreads();
-    lds_fft<true>(sbuf, L, nrows, L, 1, rp, tw, ny);
-    double2* dst = (double2*)(out + ((int64_t)f * nx + row0) * ny);
-    for (int e = threadIdx.x; e < nrows * L; e += blockDim.x) {
-        const double2 z = sbuf[e];
-        dst[e] = make_double2(z.x * scale, z.y * scale);
-    }
+    StockhamFrom<L, E, 1, true>::run(v, lds, L, 1, q, t, tw, N);
+    if (!live) return;
+    double2* dst = (double2*)(out + ((int64_t)f * nx + row) * N);
+#pragma unroll
+    for (int k = 0; k < E; ++k) dst[out_index<L, E>(k, t)] = make_double2(v[k].x * scale, v[k].y * scale);
 }
 
 // ---------------------------------------------------------------------------
-// pass C: complex transform along x of T adjacent columns, in place
+// pass C: complex transform along x of T adjacent columns, in place.
+// Tiles are assigned so that consecutive tiles run on the same XCD (blocks
+// are dispatched round-robin over the 8 XCDs), letting the two halves of a
+// 128-byte line be served by one L2.
 // ---------------------------------------------------------------------------
-template <bool INV>
-__global__ __launch_bounds__(256) void k_cols(double2* __restrict__ data, int nx, int ncol, int T, RadixPlan rp,
-                                              const double2* __restrict__ tw) {
-    extern __shared__ double2 sbuf[];
-    const int f = blockIdx.y;
-    const int c0 = blockIdx.x * T;
-    double2* base = data + (int64_t)f * nx * ncol;
-    for (int e = threadIdx.x; e < nx * T; e += blockDim.x) {
-        const int n = e / T;
-        const int q = e - n * T;
-        sbuf[e] = (c0 + q < ncol) ? base[(int64_t)n * ncol + c0 + q] : make_double2(0.0, 0.0);
-    }
-    __syncthreads();
-    lds_fft<INV>(sbuf, nx, T, 1, T, rp, tw, nx);
-    for (int e = threadIdx.x; e < nx * T; e += blockDim.x) {
-        const int n = e / T;
-        const int q = e - n * T;
-        if (c0 + q < ncol) base[(int64_t)n * ncol + c0 + q] = sbuf[e];
-    }
+template <int L, int E, int T, bool INV>
+__global__ __launch_bounds__(T * (L / E)) void k_cols(double2* __restrict__ data, int ncol,
+                                                      const double2* __restrict__ tw) {
+    constexpr int P = L / E;
+    __shared__ double2 lds[L * T];
+    const int q = threadIdx.x % T;
+    const int t = threadIdx.x / T;
+    const int ntiles = (ncol + T - 1) / T;
+    const int per_xcd = (ntiles + 7) / 8;
+    const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tile >= ntiles) return;   // uniform per block
+    const int col = tile * T + q;
+    const bool live = col < ncol;
+    double2* base = data + (int64_t)blockIdx.y * L * ncol + (live ? col : 0);
+    double2 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, t) * ncol];
+    StockhamFrom<L, E, 1, INV>::run(v, lds, 1, T, q, t, tw, L);
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, t) * ncol] = v[k];
 }
 
 static int check(const char* what, hipStream_t s) {
@@ -281,46 +340,76 @@ static int check(const char* what, hipStream_t s) {
     return FC2D_OK;
 }
 
-static int col_tile(int nx) { return nx >= 4096 ? 1 : (nx >= 2048 ? 2 : 4); }
-static int rows_per_block(int ny) { return ny / 2 >= 256 ? 1 : 256 / (ny / 2); }
-static int nthreads_for(int elems) { return std::max(64, std::min(256, elems / 4)); }
+// row-pass configurations: (L, E, rows per block)
+template <bool FWD>
+static void launch_rows(int L, dim3 grid_rows_unused, int nx, int nf, const void* in, void* out, const double2* tw,
+                        double scale, hipStream_t s) {
+#define FC2D_ROWS(LL, EE, RR)                                                                              \
+    case LL: {                                                                                             \
+        dim3 g((nx + RR - 1) / RR, nf);                                                                    \
+        if (FWD) k_rows_r2c<LL, EE, RR><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw); \
+        else k_rows_c2r<LL, EE, RR><<<g, RR * (LL / EE), 0, s>>>((const double2*)in, (double*)out, nx, tw, scale); \
+        break;                                                                                             \
+    }
+    switch (L) {
+        FC2D_ROWS(8, 2, 32)
+        FC2D_ROWS(16, 2, 16)
+        FC2D_ROWS(32, 2, 8)
+        FC2D_ROWS(64, 2, 4)
+        FC2D_ROWS(128, 2, 2)
+        FC2D_ROWS(256, 4, 2)
+        FC2D_ROWS(512, 8, 1)
+        FC2D_ROWS(1024, 16, 1)
+        FC2D_ROWS(2048, 16, 1)
+        FC2D_ROWS(4096, 16, 1)
+    }
+#undef FC2D_ROWS
+}
+
+template <bool INV>
+static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* tw, hipStream_t s) {
+#define FC2D_COLS(LL, EE, TT)                                                                    \
+    case LL: {                                                                                   \
+        const int ntiles = (ncol + TT - 1) / TT;                                                 \
+        dim3 g(((ntiles + 7) / 8) * 8, nf);                                                      \
+        k_cols<LL, EE, TT, INV><<<g, TT * (LL / EE), 0, s>>>(data, ncol, tw);                    \
+        break;                                                                                   \
+    }
+    switch (nx) {
+        FC2D_COLS(16, 2, 16)
+        FC2D_COLS(32, 2, 8)
+        FC2D_COLS(64, 2, 8)
+        FC2D_COLS(128, 2, 4)
+        FC2D_COLS(256, 4, 4)
+        FC2D_COLS(512, 8, 4)
+        FC2D_COLS(1024, 16, 4)
+        FC2D_COLS(2048, 16, 2)
+        FC2D_COLS(4096, 16, 1)
+    }
+#undef FC2D_COLS
+}
 
 int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
     const int nx = g->nx, ny = g->ny, L = ny / 2;
-    if (nx > 4096 || ny > 8192) { set_error("fc2d_fft: sizes above 4096 x 8192 are not supported"); return FC2D_E_ARG; }
     const double2* twy = twiddles(ny);
     const double2* twx = twiddles(nx);
     if (!twy || !twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    const int rpb = rows_per_block(ny);
-    const RadixPlan rpy = radix_plan(L);
-    dim3 gr((nx + rpb - 1) / rpb, nf);
-    k_rows_r2c<<<gr, nthreads_for(rpb * L), rpb * L * sizeof(double2), s>>>(in, (double2*)out, nx, ny, rpb, rpy, twy);
+    launch_rows<true>(L, dim3(), nx, nf, in, out, twy, 1.0, s);
     int st = check("k_rows_r2c", s);
     if (st) return st;
-    const int T = col_tile(nx);
-    const RadixPlan rpx = radix_plan(nx);
-    dim3 gc((L + 1 + T - 1) / T, nf);
-    k_cols<false><<<gc, nthreads_for(nx * T), nx * T * sizeof(double2), s>>>((double2*)out, nx, L + 1, T, rpx, twx);
+    launch_cols<false>(nx, L + 1, nf, (double2*)out, twx, s);
     return check("k_cols", s);
 }
 
 int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s) {
     const int nx = g->nx, ny = g->ny, L = ny / 2;
-    if (nx > 4096 || ny > 8192) { set_error("fc2d_fft: sizes above 4096 x 8192 are not supported"); return FC2D_E_ARG; }
     const double2* twy = twiddles(ny);
     const double2* twx = twiddles(nx);
     if (!twy || !twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    const int T = col_tile(nx);
-    const RadixPlan rpx = radix_plan(nx);
-    dim3 gc((L + 1 + T - 1) / T, nf);
-    k_cols<true><<<gc, nthreads_for(nx * T), nx * T * sizeof(double2), s>>>((double2*)in, nx, L + 1, T, rpx, twx);
-    int st = check("k_cols", s);
+    launch_cols<true>(nx, L + 1, nf, (double2*)in, twx, s);
+    int st = check("k_cols_inv", s);
     if (st) return st;
-    const int rpb = rows_per_block(ny);
-    const RadixPlan rpy = radix_plan(L);
-    dim3 gr((nx + rpb - 1) / rpb, nf);
-    k_rows_c2r<<<gr, nthreads_for(rpb * L), rpb * L * sizeof(double2), s>>>((const double2*)in, out, nx, ny, rpb, rpy,
-                                                                           twy, 1.0 / ((double)nx * (double)ny));
+    launch_rows<false>(L, dim3(), nx, nf, in, out, twy, 1.0 / ((double)nx * (double)ny), s);
     return check("k_rows_c2r", s);
 }
 

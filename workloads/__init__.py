@@ -138,6 +138,11 @@ def cfg_disc128():
     return box_case("disc128", disc(), -1.5, 1.5, 128, 256, k1=0.2 / 27)
 
 
+def cfg_disc(n=256):
+    """Unit disc, B = 2n, box [-1.6, 1.6]^2 on n^2, k1 = h."""
+    return box_case("disc%d" % n, disc(), -1.6, 1.6, n, 2 * n)
+
+
 def cfg_star(n=1024):
     """Star r = 1 + 0.3 cos 5t, B = 2n, box [-1.6, 1.6]^2 on n^2."""
     h = 3.2 / n

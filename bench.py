@@ -40,6 +40,8 @@ def algorithmic_bytes(name, n, nf, info):
     half = n * (n // 2 + 1)
     if name == "k_rows_r2c":
         return nf * (8 * npts + 16 * half)
+    if name == "k_rows_r2c_ext":     # read f at IN points and the STRIP values, write the half spectrum
+        return nf * (8 * info.n_in + 8 * info.n_strip + 16 * half)
     if name == "k_cols":
         return nf * 32 * half
     if name == "k_mask":            # out of place: read IN, write IN and FAR
@@ -112,28 +114,37 @@ def main():
     torch.cuda.synchronize()
     print("[bench] plan %.2fs, inputs ready" % plan_s, file=sys.stderr, flush=True)
 
-    def step():
+    def step_plain():
         fc2d.fc2d_extend(plan, fg, fb, ext)
         fc2d.fc2d_fft(grid, ext, spec, fc2d.FC2D_FORWARD)
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(args.steps):
-        step()
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.steps
+    def step_fused():
+        fc2d.fc2d_extend_fft(plan, fg, fb, ext, spec)
+
+    def timed(step):
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(args.steps):
+            step()
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / args.steps
+
+    ms_plain = timed(step_plain)
+    ms = timed(step_fused)
     value = nf * case.n * case.n / (ms * 1e-3)
-    print("[bench] %.3f ms/step, %.3e points/s" % (ms, value), file=sys.stderr, flush=True)
+    value_plain = nf * case.n * case.n / (ms_plain * 1e-3)
+    print("[bench] plain %.3f ms/step (%.3e points/s); fused %.3f ms/step (%.3e points/s)"
+          % (ms_plain, value_plain, ms, value), file=sys.stderr, flush=True)
 
     # per-kernel times from HIP events on the launch stream (library tracer)
     fc2d.fc2d_trace_begin()
     for _ in range(args.steps):
-        step()
+        step_fused()
     tr = fc2d.fc2d_trace_end()
     per = {}
     for name, t in tr:
@@ -163,7 +174,8 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "star r=1+0.3cos5t, B=%d, [-1.6,1.6]^2 on %dx%d, d=5, C=27, M=8, k1=%g; "
                                "extend + forward FFT of %d fields per step" % (case.B, case.n, case.n, case.k1, nf),
-                   "fields_per_step": nf, "grid": case.n, "path": "plain"},
+                   "fields_per_step": nf, "grid": case.n, "path": "fused extend+FFT (fc2d_extend_fft)",
+                   "plain_points_per_s": value_plain, "plain_ms_per_step": ms_plain},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -136,6 +136,15 @@ int fc2d_blend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry
 int fc2d_extend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
                 double* out, int nf, hipStream_t stream);
 
+/* Extension fused with the forward 2D FFT (Sec. 3.5 steps 5-7): spec [nf][nx][ny/2+1]
+ * complex128 = the unnormalised forward transform of the grid fc2d_extend would
+ * produce, without materialising it: the STRIP values are written into `work`
+ * ([nf][nx][ny] float64, only STRIP entries are touched; it may alias f_grid)
+ * and the row transform assembles IN / STRIP / FAR values while loading.
+ * The plan's grid must have power-of-two sizes (nx <= 4096, ny <= 8192). */
+int fc2d_extend_fft(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, double* work,
+                    void* spec, int nf, hipStream_t stream);
+
 /* 2D FFT (Sec. 3.5 step 7); nx a power of two in [16, 4096], ny a power of
  * two in [16, 8192] (Remark 3.2: the grid is padded to FFT-friendly sizes).
  * FC2D_FORWARD: in = real [nf][nx][ny], out = half spectrum, unnormalised.

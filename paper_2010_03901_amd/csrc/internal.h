@@ -57,6 +57,7 @@ struct fc2d_plan {
     double* d_seta = nullptr;       // [S] eta_Q
     int32_t* d_run_ptr = nullptr;   // [nx + 1] row runs
     int32_t* d_run = nullptr;       // [nruns][3] (start, end, class)
+    uint8_t* d_cls2 = nullptr;      // [nx][ny/2] classes of the pair (2n, 2n+1), 2 bits each (ny even)
     int nruns = 0;
     double* d_c = nullptr;          // [nf_cap][B][d] Gram coefficients (work)
     int nf_cap = 0;
@@ -100,7 +101,10 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
 int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, hipStream_t s);
 
 // ---- FFT and spectral kernels (kernels_fft.hip) ----
-int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s);
+// strip / cls2 non-null: the rows are assembled on the fly from `in` (IN),
+// `strip` (STRIP) and zeros (FAR) using the per-pair class bytes cls2.
+int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s,
+             const double* strip = nullptr, const uint8_t* cls2 = nullptr);
 int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s);
 int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,

@@ -1,10 +1,12 @@
 // Cartesian Evaluation kernels (Sec. 3.5 steps 5-6).
 //
-//  k_match   one wave per (normal p, field): lane (s, k) multiplies the k-th
-//            grid-line node of red star s by its weight, the wave reduces to
-//            the M star values, then along the normal to f_{D_p} (Sec. 3.2),
-//            then c_p = Q^T f_{D_p} -- all in double-double, rounded once.
-//  k_strip   one thread per STRIP point and field: interpolation onto H n V+
+//  k_match   one thread per (normal p, field): the red-star values along the
+//            grid lines, the matching values along the normal (Sec. 3.2) and
+//            c_p = Q^T f_{D_p}, each a compensated dot product with
+//            double-double weights (rounded once); the normal's weights are
+//            uniform over the wave.
+//  k_strip   one thread per STRIP point looping over a chunk of fields:
+//            interpolation onto H n V+
 //            (Sec. 3.4).  Because every normal carries the same level weights
 //            v(eta_Q), the continuation values never need to be formed:
 //                ext(Q) = sum_j w_j(theta^Q) [ v_0 f_{D_j}[d-1] + u . c_j ],
@@ -23,52 +25,102 @@
 
 namespace fc2d {
 
+// Compensated dot product (Ogita, Rump & Oishi, "Accurate sum and dot product",
+// SIAM J. Sci. Comput. 26, 2005: Dot2) with a double-double left factor and
+// either a double or a double-double right factor.  Accumulates (s, e) with
+// s + e accurate as if computed in twice the working precision.
+struct Acc2 {
+    double s = 0.0, e = 0.0;
+    __device__ __forceinline__ void add(dd w, double v) {
+#pragma clang fp contract(off)
+        const double p = w.hi * v;
+        const double ep = fma(w.hi, v, -p);
+        const double t = s + p;
+        const double bb = t - s;
+        const double es = (s - (t - bb)) + (p - bb);
+        s = t;
+        e += ep + es + w.lo * v;
+    }
+    __device__ __forceinline__ void add(dd w, dd v) {
+#pragma clang fp contract(off)
+        const double p = w.hi * v.hi;
+        const double ep = fma(w.hi, v.hi, -p);
+        const double t = s + p;
+        const double bb = t - s;
+        const double es = (s - (t - bb)) + (p - bb);
+        s = t;
+        e += ep + es + (w.hi * v.lo + w.lo * v.hi);
+    }
+    __device__ __forceinline__ dd result() const {
+#pragma clang fp contract(off)
+        const double hi = s + e;
+        return dd{hi, e - (hi - s)};
+    }
+};
+
+// One thread per (normal p, field f): the weights of normal p are uniform
+// across the wave (scalar loads), each lane gathers its own field's values.
 template <int M>
 __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
                                               const double* __restrict__ mwn, const double* __restrict__ Q, int D,
                                               int B, const double* __restrict__ fg, int64_t npts,
-                                              const double* __restrict__ fb, int64_t nbdry, double* __restrict__ c_out,
-                                              double* __restrict__ fD_out) {
+                                              const double* __restrict__ fb, int64_t nbdry, int nf,
+                                              double* __restrict__ c_out, double* __restrict__ fD_out) {
     const int p = blockIdx.x;
-    const int f = blockIdx.y;
-    const int lane = threadIdx.x;
-    const int s = lane >> 3;
-    const int k = lane & 7;
+    const int f = blockIdx.y * 64 + threadIdx.x;
+    if (f >= nf) return;
     const double* g = fg + (int64_t)f * npts;
     const double* bv = fb + (int64_t)f * nbdry;
-    dd prod = {0.0, 0.0};
-    if (s < M && k < M) {
-        const int64_t o = ((int64_t)p * M + s) * M + k;
-        const int32_t r = mref[o];
-        const double val = r >= 0 ? g[r] : bv[B + (-r - 1)];
-        prod = dd_mul_d(dd{mwv[2 * o], mwv[2 * o + 1]}, val);
-    }
-    // star values: reduce over k within the 8-lane group of star s
-    prod = dd_add(prod, dd_shfl_xor(prod, 1));
-    prod = dd_add(prod, dd_shfl_xor(prod, 2));
-    prod = dd_add(prod, dd_shfl_xor(prod, 4));
-    // along the normal: lane (s, q) forms wn[q][s] * star_s, reduce over s
-    dd t = {0.0, 0.0};
-    if (s < M && k < D - 1) {
-        const int64_t o = ((int64_t)p * (D - 1) + k) * M + s;
-        t = dd_mul(dd{mwn[2 * o], mwn[2 * o + 1]}, prod);
-    }
-    t = dd_add(t, dd_shfl_xor(t, 8));
-    t = dd_add(t, dd_shfl_xor(t, 16));
-    t = dd_add(t, dd_shfl_xor(t, 32));
-    // lanes 0..D-2 now hold f_D[p][lane]; f_D[p][D-1] is the boundary sample
-    const double fb_p = bv[p];
-    dd fq[9];
+    const int32_t* ref = mref + (int64_t)p * M * M;
+    const double* wv = mwv + (int64_t)p * M * M * 2;
+    const double* wn = mwn + (int64_t)p * (D - 1) * M * 2;
+    // red-star values along the grid lines (Sec. 3.2, first interpolation)
+    dd star[M];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) fq[q] = dd_shfl(t, q < 8 ? q : 0);
-    if (lane < D) {
-        dd acc = {0.0, 0.0};
-        for (int q = 0; q < D; ++q) {
-            const dd v = (q < D - 1) ? fq[q] : dd{fb_p, 0.0};
-            acc = dd_add(acc, dd_mul_d(v, Q[q * D + lane]));
+    for (int s = 0; s < M; ++s) {
+        Acc2 a;
+#pragma unroll
+        for (int k = 0; k < M; ++k) {
+            const int o = s * M + k;
+            const int32_t r = ref[o];
+            const double val = r >= 0 ? g[r] : bv[B + (-r - 1)];
+            a.add(dd{wv[2 * o], wv[2 * o + 1]}, val);
         }
-        c_out[((int64_t)f * B + p) * D + lane] = acc.hi;
-        if (fD_out) fD_out[((int64_t)f * B + p) * D + lane] = (lane < D - 1) ? t.hi : fb_p;
+        star[s] = a.result();
+    }
+    // matching values along the normal (second interpolation), then Q^T f_D
+    const double fbp = bv[p];
+    dd fD[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        if (q < D - 1) {
+            Acc2 a;
+#pragma unroll
+            for (int s = 0; s < M; ++s) {
+                const int o = q * M + s;
+                a.add(dd{wn[2 * o], wn[2 * o + 1]}, star[s]);
+            }
+            fD[q] = a.result();
+        } else {
+            fD[q] = dd{fbp, 0.0};
+        }
+    }
+    double* co = c_out + ((int64_t)f * B + p) * D;
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        if (j < D) {
+            Acc2 a;
+#pragma unroll
+            for (int q = 0; q < 9; ++q)
+                if (q < D) a.add(fD[q], Q[q * D + j]);
+            co[j] = a.result().hi;
+        }
+    }
+    if (fD_out) {
+        double* fo = fD_out + ((int64_t)f * B + p) * D;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            if (q < D) fo[q] = fD[q].hi;
     }
 }
 
@@ -95,17 +147,18 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
                                                const double* __restrict__ seta, int64_t S, const double* __restrict__ Ar,
                                                int D, int Cr, int B, double k2, double lev_scale,
                                                const double* __restrict__ c, const double* __restrict__ fb,
-                                               int64_t nbdry, double* __restrict__ out, int64_t npts) {
+                                               int64_t nbdry, double* __restrict__ out, int64_t npts, int nf, int fpt) {
     extern __shared__ double sAr[];
     for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
     __syncthreads();
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S) return;
-    const int f = blockIdx.y;
     const double th = sth[k];
     const double eta = seta[k];
+    const int32_t idx = sidx[k];
     constexpr int kl = (M - 1) / 2;
     const int p0 = (M % 2 == 0) ? (int)floor(th / k2) : (int)rint(th / k2);
+    // theta weights over S_{theta^Q}
     double tn[M], w[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) tn[m] = (double)(p0 - kl + m) * k2;
@@ -117,6 +170,7 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
             if (q != m) v *= (th - tn[q]) / (tn[m] - tn[q]);
         w[m] = v;
     }
+    // level weights at s = eta n_r / k1 and u = A_r^T v (factored blend)
     const double s = eta * lev_scale;
     int l0 = (int)floor(s) - M / 2 + 1;
     l0 = l0 < 0 ? 0 : (l0 > Cr - M + 1 ? Cr - M + 1 : l0);
@@ -142,20 +196,28 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
         }
     }
     const double v0 = (l0 == 0) ? v[0] : 0.0;
-    const double* cf = c + (int64_t)f * B * D;
-    const double* bv = fb + (int64_t)f * nbdry;
-    double ext = 0.0;
+    int pj[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        int pj = (p0 - kl + m) % B;
-        pj = pj < 0 ? pj + B : pj;
-        double gsum = v0 * bv[pj];
-#pragma unroll
-        for (int j = 0; j < 9; ++j)
-            if (j < D) gsum += u[j] * cf[(int64_t)pj * D + j];
-        ext += w[m] * gsum;
+        int q = (p0 - kl + m) % B;
+        pj[m] = q < 0 ? q + B : q;
     }
-    out[(int64_t)f * npts + sidx[k]] = ext;
+    const int f0 = blockIdx.y * fpt;
+    const int f1 = min(nf, f0 + fpt);
+    for (int f = f0; f < f1; ++f) {
+        const double* cf = c + (int64_t)f * B * D;
+        const double* bv = fb + (int64_t)f * nbdry;
+        double ext = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) {
+            double gsum = v0 * bv[pj[m]];
+#pragma unroll
+            for (int j = 0; j < 9; ++j)
+                if (j < D) gsum += u[j] * cf[(int64_t)pj[m] * D + j];
+            ext += w[m] * gsum;
+        }
+        out[(int64_t)f * npts + idx] = ext;
+    }
 }
 
 __global__ void k_mask(const int32_t* __restrict__ run_ptr, const int32_t* __restrict__ runs, int ny,
@@ -187,13 +249,12 @@ static int launch_check(const char* what, hipStream_t s) {
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry, double* c_out,
                  double* fD_out, int nf, hipStream_t s) {
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
-    dim3 grid(pl->B, nf);
+    dim3 grid(pl->B, (nf + 63) / 64);
     switch (pl->M) {
-        case 4: k_match<4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, c_out, fD_out); break;
-        case 5: k_match<5><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, c_out, fD_out); break;
-        case 6: k_match<6><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, c_out, fD_out); break;
-        case 7: k_match<7><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, c_out, fD_out); break;
-        case 8: k_match<8><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, c_out, fD_out); break;
+#define FC2D_MATCH(MM) \
+        case MM: k_match<MM><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); break;
+        FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8)
+#undef FC2D_MATCH
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
     return launch_check("k_match", s);
@@ -212,15 +273,17 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     const int64_t S = (int64_t)pl->strip_idx.size();
     if (S == 0) return FC2D_OK;
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
-    dim3 grid((unsigned)((S + 255) / 256), nf);
+    // fields per thread: enough blocks to fill the chip, weights amortised over the rest
+    const int64_t pblocks = (S + 255) / 256;
+    int fpt = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nf * pblocks / 2048));
+    dim3 grid((unsigned)pblocks, (nf + fpt - 1) / fpt);
     const size_t lds = (size_t)pl->Cr * pl->d * sizeof(double);
     const double lev_scale = pl->n_r / pl->k1;
     switch (pl->M) {
-        case 4: k_strip<4><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts); break;
-        case 5: k_strip<5><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts); break;
-        case 6: k_strip<6><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts); break;
-        case 7: k_strip<7><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts); break;
-        case 8: k_strip<8><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts); break;
+#define FC2D_STRIP(MM) \
+        case MM: k_strip<MM><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts, nf, fpt); break;
+        FC2D_STRIP(4) FC2D_STRIP(5) FC2D_STRIP(6) FC2D_STRIP(7) FC2D_STRIP(8)
+#undef FC2D_STRIP
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
     return launch_check("k_strip", s);

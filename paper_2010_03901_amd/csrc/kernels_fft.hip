@@ -239,9 +239,33 @@ __device__ __forceinline__ int out_index(int k, int t) {
 // ---------------------------------------------------------------------------
 // pass R: real rows -> half-spectrum rows (one row per P threads)
 // ---------------------------------------------------------------------------
-template <int L, int E, int RPB>
+// Element n of a row is the pair (2n, 2n+1).  With an extension mask the row
+// is assembled on the fly (Sec. 3.5 step 6): cls2[n] holds the classes of the
+// pair (bits 0-1 and 2-3: 0 FAR, 1 IN, 2 STRIP); IN values come from `in`,
+// STRIP values from `strip` (same layout as `in`), FAR values are 0.
+template <bool MASKED>
+__device__ __forceinline__ double2 load_pair(const double* row, const double* srow, const uint8_t* crow, int n) {
+    if constexpr (!MASKED) {
+        return ((const double2*)row)[n];
+    } else {
+        const int c = crow[n];
+        const int c0 = c & 3, c1 = (c >> 2) & 3;
+        double2 z;
+        if (c0 == 1 && c1 == 1) {
+            z = ((const double2*)row)[n];
+        } else {
+            z.x = c0 == 1 ? row[2 * n] : (c0 == 2 ? srow[2 * n] : 0.0);
+            z.y = c1 == 1 ? row[2 * n + 1] : (c1 == 2 ? srow[2 * n + 1] : 0.0);
+        }
+        return z;
+    }
+}
+
+template <int L, int E, int RPB, bool MASKED>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __restrict__ in, double2* __restrict__ out,
-                                                            int nx, const double2* __restrict__ tw) {
+                                                            int nx, const double2* __restrict__ tw,
+                                                            const double* __restrict__ strip,
+                                                            const uint8_t* __restrict__ cls2) {
     constexpr int P = L / E;
     constexpr int N = 2 * L;
     __shared__ double2 lds[RPB * L];
@@ -250,10 +274,13 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
     const int row = blockIdx.x * RPB + q;
     const int f = blockIdx.y;
     const bool live = row < nx;
-    const double2* src = (const double2*)(in + ((int64_t)f * nx + (live ? row : 0)) * N);
+    const int64_t roff = ((int64_t)f * nx + (live ? row : 0)) * N;
+    const double* src = in + roff;
+    const double* ssrc = MASKED ? strip + roff : nullptr;
+    const uint8_t* crow = MASKED ? cls2 + (int64_t)(live ? row : 0) * L : nullptr;
     double2 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = src[in_index<L, E>(k, t)];
+    for (int k = 0; k < E; ++k) v[k] = load_pair<MASKED>(src, ssrc, crow, in_index<L, E>(k, t));
     StockhamFrom<L, E, 1, false>::run(v, lds, L, 1, q, t, tw, N);
     __syncthreads();
 #pragma unroll
@@ -342,12 +369,15 @@ static int check(const char* what, hipStream_t s) {
 
 // row-pass configurations: (L, E, rows per block)
 template <bool FWD>
-static void launch_rows(int L, dim3 grid_rows_unused, int nx, int nf, const void* in, void* out, const double2* tw,
-                        double scale, hipStream_t s) {
+static void launch_rows(int L, int nx, int nf, const void* in, void* out, const double2* tw, double scale,
+                        const double* strip, const uint8_t* cls2, hipStream_t s) {
 #define FC2D_ROWS(LL, EE, RR)                                                                              \
     case LL: {                                                                                             \
         dim3 g((nx + RR - 1) / RR, nf);                                                                    \
-        if (FWD) k_rows_r2c<LL, EE, RR><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw); \
+        if (FWD && cls2)                                                                                   \
+            k_rows_r2c<LL, EE, RR, true><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, strip, cls2); \
+        else if (FWD)                                                                                      \
+            k_rows_r2c<LL, EE, RR, false><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, nullptr, nullptr); \
         else k_rows_c2r<LL, EE, RR><<<g, RR * (LL / EE), 0, s>>>((const double2*)in, (double*)out, nx, tw, scale); \
         break;                                                                                             \
     }
@@ -389,13 +419,14 @@ static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* 
 #undef FC2D_COLS
 }
 
-int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
+int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
+             const uint8_t* cls2) {
     const int nx = g->nx, ny = g->ny, L = ny / 2;
     const double2* twy = twiddles(ny);
     const double2* twx = twiddles(nx);
     if (!twy || !twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_rows<true>(L, dim3(), nx, nf, in, out, twy, 1.0, s);
-    int st = check("k_rows_r2c", s);
+    launch_rows<true>(L, nx, nf, in, out, twy, 1.0, strip, cls2, s);
+    int st = check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
     if (st) return st;
     launch_cols<false>(nx, L + 1, nf, (double2*)out, twx, s);
     return check("k_cols", s);
@@ -409,7 +440,7 @@ int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s)
     launch_cols<true>(nx, L + 1, nf, (double2*)in, twx, s);
     int st = check("k_cols_inv", s);
     if (st) return st;
-    launch_rows<false>(L, dim3(), nx, nf, in, out, twy, 1.0 / ((double)nx * (double)ny), s);
+    launch_rows<false>(L, nx, nf, in, out, twy, 1.0 / ((double)nx * (double)ny), nullptr, nullptr, s);
     return check("k_rows_c2r", s);
 }
 

@@ -359,7 +359,7 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
 static void free_plan(fc2d_plan* pl) {
     if (!pl) return;
     void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_sidx,
-                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c};
+                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c, pl->d_cls2};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;
@@ -596,6 +596,12 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         if ((st = dev_upload(&pl->d_seta, pl->strip_eta.data(), pl->strip_eta.size()))) break;
         if ((st = dev_upload(&pl->d_run_ptr, run_ptr.data(), run_ptr.size()))) break;
         if ((st = dev_upload(&pl->d_run, runs.data(), runs.size()))) break;
+        if (grid->ny % 2 == 0) {
+            std::vector<uint8_t> cls2((size_t)grid->nx * (grid->ny / 2));
+            for (size_t e = 0; e < cls2.size(); ++e)
+                cls2[e] = (uint8_t)(pl->cls[2 * e] | (pl->cls[2 * e + 1] << 2));
+            if ((st = dev_upload(&pl->d_cls2, cls2.data(), cls2.size()))) break;
+        }
     } while (0);
     if (st) { free_plan(pl); return st; }
     *out = pl;
@@ -735,6 +741,26 @@ int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry,
     if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
     if ((st = launch_mask(pl, f_grid, out, nf, s))) return st;
     return launch_strip(pl, pl->d_c, f_bdry, nb, out, nf, s);
+}
+
+int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
+                    int nf, hipStream_t s) {
+    int st = check_fields(pl, nf);
+    if (st) return st;
+    if (nf == 0) return FC2D_OK;
+    const fc2d_grid* g = &pl->grid;
+    if (!f_grid || !f_bdry || !work || !spec) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (g->nx < 16 || g->nx > 4096 || (g->nx & (g->nx - 1)) || g->ny < 16 || g->ny > 8192 || (g->ny & (g->ny - 1)) ||
+        !pl->d_cls2) {
+        set_error("fc2d_extend_fft: the plan's grid must have power-of-two sizes (nx <= 4096, ny <= 8192)");
+        return FC2D_E_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_work_mu);
+    if ((st = ensure_work(pl, nf))) return st;
+    const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
+    if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
+    if ((st = launch_strip(pl, pl->d_c, f_bdry, nb, work, nf, s))) return st;
+    return fft2_r2c(g, f_grid, (double*)spec, nf, s, work, pl->d_cls2);
 }
 
 static bool pow2_ok(int n, int nmax) { return n >= 16 && n <= nmax && (n & (n - 1)) == 0; }

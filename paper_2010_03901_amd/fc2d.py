@@ -72,6 +72,7 @@ def _lib():
             "fc2d_matching": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
             "fc2d_blend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
             "fc2d_extend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_extend_fft": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P]),
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
             "ff_propagate": (C.c_int, [C.POINTER(fc2d_grid), C.c_double, C.c_double, _P, _P, _P, _P, C.c_int, _P]),
@@ -240,6 +241,19 @@ def fc2d_extend(plan, f_grid, f_bdry, out, stream=None):
         raise ValueError("f_bdry / out sizes do not match the plan")
     _check(_lib().fc2d_extend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
                               _dptr(out, "out", torch.float64), nf, _stream(stream)))
+
+
+def fc2d_extend_fft(plan, f_grid, f_bdry, work, spec, stream=None):
+    import torch
+    nf = _nf(f_grid, plan.grid)
+    g = plan.grid
+    if f_bdry.numel() != nf * plan.info.n_bdry or work.numel() != f_grid.numel():
+        raise ValueError("f_bdry / work sizes do not match the plan")
+    if spec.dtype != torch.complex128 or spec.numel() != nf * g.nx * (g.ny // 2 + 1):
+        raise ValueError("spec must be complex128 [nf][nx][ny/2+1]")
+    _check(_lib().fc2d_extend_fft(plan.handle, _dptr(f_grid, "f_grid", torch.float64),
+                                  _dptr(f_bdry, "f_bdry", torch.float64), _dptr(work, "work", torch.float64),
+                                  _dptr(spec, "spec"), nf, _stream(stream)))
 
 
 def fc2d_fft(grid, inp, out, direction, stream=None):

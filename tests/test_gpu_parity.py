@@ -148,3 +148,34 @@ def test_fft_forward_inverse(both, torch_mod):
     for k in range(2):
         assert rel_err(spec[k].cpu().numpy(), np.fft.rfft2(u[k])) < 1e-12
     assert rel_err(back.cpu().numpy(), u) < 1e-13
+
+
+def test_extend_fft_fused(both, torch_mod):
+    """fc2d_extend_fft equals the forward FFT of the oracle's extension, with a
+    separate work buffer and with work aliasing f_grid."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    name, case, opl, gpl = both
+    if case.n & (case.n - 1):
+        pytest.skip("fused path needs power-of-two grids")
+    funcs = _funcs(name)
+    fg, fbo = fields(case, funcs, OP.boundary_points(opl))
+    _, fbg = fields(case, funcs, fc2d.fc2d_boundary_points(gpl))
+    nf = len(funcs)
+    fg_garbage = fg.copy()
+    fg_garbage[:, opl.cls != OP.IN] = 1e300          # only IN entries may be read
+    dfg = _device(torch, fg_garbage)
+    dfb = _device(torch, fbg)
+    spec = torch.zeros((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    work = torch.full_like(dfg, float("nan"))
+    fc2d.fc2d_extend_fft(gpl, dfg, dfb, work, spec)
+    spec2 = torch.zeros_like(spec)
+    fc2d.fc2d_extend_fft(gpl, dfg, dfb, dfg, spec2)   # work aliases f_grid
+    torch.cuda.synchronize()
+    s1 = spec.cpu().numpy()
+    assert np.array_equal(s1, spec2.cpu().numpy())
+    for k in range(nf):
+        ref = np.fft.rfft2(OE.extend(opl, fg[k], fbo[k]))
+        e = rel_err(s1[k], ref)
+        print("[parity] extend_fft", name, "field", k, "rel err %.3e" % e)
+        assert e < 1e-11

@@ -31,6 +31,10 @@ def parse():
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-fields", type=int, default=96)
+    ap.add_argument("--col-tile", type=int, default=0, help="columns per block of the column FFT pass (0 = default)")
+    ap.add_argument("--strip-fields", type=int, default=-1, help="fields per thread of the strip kernel (-1 = default)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one 1 GiB device copy first (known-size kernel for counter calibration)")
     return ap.parse_args()
 
 
@@ -94,6 +98,10 @@ def main():
     print("[bench] workload star%d nf=%d steps=%d warmup=%d" % (case.n, nf, args.steps, args.warmup),
           file=sys.stderr, flush=True)
     grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+    if args.col_tile:
+        fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_COL_TILE, case.n, args.col_tile)
+    if args.strip_fields >= 0:
+        fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_STRIP_FIELDS, 0, args.strip_fields)
     t0 = time.perf_counter()
     plan = fc2d.Plan(fc2d.make_curve(*case.curve), grid, d=case.d, C_=case.C, B=case.B, k1=case.k1, M=case.M)
     torch.cuda.synchronize()
@@ -110,6 +118,13 @@ def main():
         fg[s].copy_(torch.from_numpy(f(X, Y)))
         fb[s].copy_(torch.from_numpy(f(bp[:, 0], bp[:, 1])))
     ext = torch.empty_like(fg)
+    if args.calib_copy:
+        a = torch.ones(1 << 27, dtype=torch.float64, device="cuda:0")
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     spec = torch.empty((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
     torch.cuda.synchronize()
     print("[bench] plan %.2fs, inputs ready" % plan_s, file=sys.stderr, flush=True)

@@ -45,6 +45,7 @@ enum {
 enum { FC2D_CURVE_POLAR = 1, FC2D_CURVE_CARTESIAN = 2 };
 enum { FC2D_FORWARD = -1, FC2D_INVERSE = 1 };
 enum { FC2D_LAPLACE_INV = 1, FC2D_DX = 2, FC2D_DY = 3 };
+enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2 };
 
 /* Boundary Gamma as a smooth 2 pi-periodic counter-clockwise curve q(theta)
  * (eq. param).  Series s(t) = s0 + sum_{m=1..nmodes} (s_{2m-1} cos mt + s_{2m} sin mt),
@@ -165,6 +166,15 @@ int fc2d_spectral_apply(const fc2d_grid* grid, int op, const void* in, void* out
  * Half spectra, device; outputs may alias inputs. */
 int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, const void* u1h,
                  void* uh, void* uth, int nf, hipStream_t stream);
+
+/* Launch-shape knobs, process-wide (set by the autotuner; results do not
+ * depend on them).  FC2D_TUNE_COL_TILE: columns per block of the column FFT
+ * pass for length n = nx (compiled choices: 4/8/16 for n <= 64, 4/8 up to 512,
+ * 2/4/8 for 1024, 1/2/4 for 2048, 1/2 for 4096).  FC2D_TUNE_STRIP_FIELDS:
+ * fields per thread of the strip interpolation (0 = automatic, n ignored).
+ * Not thread-safe against concurrent launches. */
+int fc2d_tune_set(int knob, int n, int value);
+int fc2d_tune_get(int knob, int n, int* value);
 
 /* Kernel tracing (a profiling aid, not needed for results).  fc2d_trace_begin
  * opens a trace and records a HIP event on `stream`; until fc2d_trace_end every

@@ -59,7 +59,7 @@ struct fc2d_plan {
     int32_t* d_run = nullptr;       // [nruns][3] (start, end, class)
     uint8_t* d_cls2 = nullptr;      // [nx][ny/2] classes of the pair (2n, 2n+1), 2 bits each (ny even)
     int nruns = 0;
-    double* d_c = nullptr;          // [nf_cap][B][d] Gram coefficients (work)
+    double* d_c = nullptr;          // [nf_cap][B][DP] Gram coefficients, boundary value, pad (DP = (d+2)&~1)
     int nf_cap = 0;
 };
 
@@ -109,5 +109,11 @@ int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s)
 int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,
              double* uth, int nf, hipStream_t s);
+
+// tuning knobs (autotuner)
+int col_tile_get(int nx);
+int col_tile_set(int nx, int T);
+int strip_fpt_get();
+int strip_fpt_set(int v);
 
 }  // namespace fc2d

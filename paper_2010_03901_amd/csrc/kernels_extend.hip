@@ -66,9 +66,12 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
                                               int B, const double* __restrict__ fg, int64_t npts,
                                               const double* __restrict__ fb, int64_t nbdry, int nf,
                                               double* __restrict__ c_out, double* __restrict__ fD_out) {
-    const int p = blockIdx.x;
+    // consecutive normals share grid lines: give each XCD (blocks are dealt
+    // round-robin to the 8 XCDs) a contiguous range of normals so they share an L2
+    const int per_xcd = (B + 7) / 8;
+    const int p = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
     const int f = blockIdx.y * 64 + threadIdx.x;
-    if (f >= nf) return;
+    if (p >= B || f >= nf) return;
     const double* g = fg + (int64_t)f * npts;
     const double* bv = fb + (int64_t)f * nbdry;
     const int32_t* ref = mref + (int64_t)p * M * M;
@@ -105,7 +108,9 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
             fD[q] = dd{fbp, 0.0};
         }
     }
-    double* co = c_out + ((int64_t)f * B + p) * D;
+    // c_p = Q^T f_{D_p}, stored with the boundary value appended: [c_0..c_{d-1}, f_{D_p}[d-1], 0 pad]
+    const int DP = (D + 2) & ~1;
+    double* co = c_out + ((int64_t)f * B + p) * DP;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         if (j < D) {
@@ -116,6 +121,8 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
             co[j] = a.result().hi;
         }
     }
+    co[D] = fbp;
+    if (DP > D + 1) co[D + 1] = 0.0;
     if (fD_out) {
         double* fo = fD_out + ((int64_t)f * B + p) * D;
 #pragma unroll
@@ -136,7 +143,8 @@ __global__ void k_blend(const double* __restrict__ c, const double* __restrict__
             v = fb[(int64_t)f * nbdry + p];
         } else {
             v = 0.0;
-            for (int j = 0; j < D; ++j) v += Ar[(l - 1) * D + j] * c[((int64_t)f * B + p) * D + j];
+            const int DP = (D + 2) & ~1;
+            for (int j = 0; j < D; ++j) v += Ar[(l - 1) * D + j] * c[((int64_t)f * B + p) * DP + j];
         }
         F[(int64_t)f * n + k] = v;
     }
@@ -183,9 +191,9 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
             if (q != l) a *= (s - (double)(l0 + q)) / ((double)(l0 + l) - (double)(l0 + q));
         v[l] = a;
     }
-    double u[9];
+    double u[10];
 #pragma unroll
-    for (int j = 0; j < 9; ++j) u[j] = 0.0;
+    for (int j = 0; j < 10; ++j) u[j] = 0.0;
 #pragma unroll
     for (int l = 0; l < M; ++l) {
         const int lev = l0 + l;
@@ -195,7 +203,9 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
                 if (j < D) u[j] += v[l] * sAr[(lev - 1) * D + j];
         }
     }
-    const double v0 = (l0 == 0) ? v[0] : 0.0;
+    // slot D of each normal's record holds its boundary value: weight v_0 when l0 = 0
+    u[D] = (l0 == 0) ? v[0] : 0.0;
+    const int DP = (D + 2) & ~1;
     int pj[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
@@ -204,16 +214,21 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
     }
     const int f0 = blockIdx.y * fpt;
     const int f1 = min(nf, f0 + fpt);
+#pragma unroll 2
     for (int f = f0; f < f1; ++f) {
-        const double* cf = c + (int64_t)f * B * D;
-        const double* bv = fb + (int64_t)f * nbdry;
+        const double* cf = c + (int64_t)f * B * DP;
         double ext = 0.0;
 #pragma unroll
         for (int m = 0; m < M; ++m) {
-            double gsum = v0 * bv[pj[m]];
+            const double2* rec = (const double2*)(cf + (int64_t)pj[m] * DP);
+            double gsum = 0.0;
 #pragma unroll
-            for (int j = 0; j < 9; ++j)
-                if (j < D) gsum += u[j] * cf[(int64_t)pj[m] * D + j];
+            for (int j2 = 0; j2 < 5; ++j2) {
+                if (2 * j2 < DP) {
+                    const double2 cc = rec[j2];
+                    gsum += u[2 * j2] * cc.x + u[2 * j2 + 1] * cc.y;
+                }
+            }
             ext += w[m] * gsum;
         }
         out[(int64_t)f * npts + idx] = ext;
@@ -236,6 +251,15 @@ __global__ void k_mask(const int32_t* __restrict__ run_ptr, const int32_t* __res
     }
 }
 
+// fields per thread in k_strip (0 = automatic); set by the autotuner
+static int g_strip_fpt = 0;
+int strip_fpt_get() { return g_strip_fpt; }
+int strip_fpt_set(int v) {
+    if (v < 0 || v > 128) return FC2D_E_ARG;
+    g_strip_fpt = v;
+    return FC2D_OK;
+}
+
 static int launch_check(const char* what, hipStream_t s) {
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) {
@@ -249,7 +273,7 @@ static int launch_check(const char* what, hipStream_t s) {
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry, double* c_out,
                  double* fD_out, int nf, hipStream_t s) {
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
-    dim3 grid(pl->B, (nf + 63) / 64);
+    dim3 grid(((pl->B + 7) / 8) * 8, (nf + 63) / 64);
     switch (pl->M) {
 #define FC2D_MATCH(MM) \
         case MM: k_match<MM><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); break;
@@ -275,7 +299,9 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
     // fields per thread: enough blocks to fill the chip, weights amortised over the rest
     const int64_t pblocks = (S + 255) / 256;
-    int fpt = (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nf * pblocks / 2048));
+    int fpt = g_strip_fpt > 0 ? g_strip_fpt
+                              : (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nf * pblocks / 2048));
+    fpt = std::max(1, std::min(fpt, nf));
     dim3 grid((unsigned)pblocks, (nf + fpt - 1) / fpt);
     const size_t lds = (size_t)pl->Cr * pl->d * sizeof(double);
     const double lev_scale = pl->n_r / pl->k1;

@@ -243,20 +243,24 @@ __device__ __forceinline__ int out_index(int k, int t) {
 // is assembled on the fly (Sec. 3.5 step 6): cls2[n] holds the classes of the
 // pair (bits 0-1 and 2-3: 0 FAR, 1 IN, 2 STRIP); IN values come from `in`,
 // STRIP values from `strip` (same layout as `in`), FAR values are 0.
+__device__ const double2 g_zero_pair[1] = {{0.0, 0.0}};
+
 template <bool MASKED>
 __device__ __forceinline__ double2 load_pair(const double* row, const double* srow, const uint8_t* crow, int n) {
     if constexpr (!MASKED) {
         return ((const double2*)row)[n];
     } else {
         const int c = crow[n];
+        // common cases with one 16-byte load from a selected source: both IN,
+        // both STRIP, both FAR (a cached zero pair); mixed pairs load per element
+        if (c == 5 || c == 10 || c == 0) {
+            const double2* src = c == 5 ? (const double2*)row + n : (c == 10 ? (const double2*)srow + n : g_zero_pair);
+            return *src;
+        }
         const int c0 = c & 3, c1 = (c >> 2) & 3;
         double2 z;
-        if (c0 == 1 && c1 == 1) {
-            z = ((const double2*)row)[n];
-        } else {
-            z.x = c0 == 1 ? row[2 * n] : (c0 == 2 ? srow[2 * n] : 0.0);
-            z.y = c1 == 1 ? row[2 * n + 1] : (c1 == 2 ? srow[2 * n + 1] : 0.0);
-        }
+        z.x = c0 == 1 ? row[2 * n] : (c0 == 2 ? srow[2 * n] : 0.0);
+        z.y = c1 == 1 ? row[2 * n + 1] : (c1 == 2 ? srow[2 * n + 1] : 0.0);
         return z;
     }
 }
@@ -396,27 +400,55 @@ static void launch_rows(int L, int nx, int nf, const void* in, void* out, const 
 #undef FC2D_ROWS
 }
 
+// Column-tile widths (columns per block, 16 B each) per log2(nx); the
+// autotuner (fc2d_tune_set) may change them among the compiled choices.
+static int g_col_tile[14] = {0, 0, 0, 0, 16, 8, 8, 4, 4, 4, 4, 2, 1, 0};
+
+static bool col_tile_ok(int nx, int T) {
+    switch (nx) {
+        case 16: case 32: case 64: return T == 4 || T == 8 || T == 16;
+        case 128: case 256: case 512: return T == 4 || T == 8;
+        case 1024: return T == 2 || T == 4 || T == 8;
+        case 2048: return T == 1 || T == 2 || T == 4;
+        case 4096: return T == 1 || T == 2;
+    }
+    return false;
+}
+
+int col_tile_get(int nx) {
+    int lg = 0;
+    while ((1 << lg) < nx) ++lg;
+    return (lg >= 4 && lg <= 12) ? g_col_tile[lg] : 0;
+}
+
+int col_tile_set(int nx, int T) {
+    if (!col_tile_ok(nx, T)) return FC2D_E_ARG;
+    int lg = 0;
+    while ((1 << lg) < nx) ++lg;
+    g_col_tile[lg] = T;
+    return FC2D_OK;
+}
+
 template <bool INV>
 static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* tw, hipStream_t s) {
-#define FC2D_COLS(LL, EE, TT)                                                                    \
-    case LL: {                                                                                   \
+    const int T = col_tile_get(nx);
+#define FC2D_COLT(LL, EE, TT)                                                                    \
+    if (nx == LL && T == TT) {                                                                   \
         const int ntiles = (ncol + TT - 1) / TT;                                                 \
         dim3 g(((ntiles + 7) / 8) * 8, nf);                                                      \
         k_cols<LL, EE, TT, INV><<<g, TT * (LL / EE), 0, s>>>(data, ncol, tw);                    \
-        break;                                                                                   \
+        return;                                                                                  \
     }
-    switch (nx) {
-        FC2D_COLS(16, 2, 16)
-        FC2D_COLS(32, 2, 8)
-        FC2D_COLS(64, 2, 8)
-        FC2D_COLS(128, 2, 4)
-        FC2D_COLS(256, 4, 4)
-        FC2D_COLS(512, 8, 4)
-        FC2D_COLS(1024, 16, 4)
-        FC2D_COLS(2048, 16, 2)
-        FC2D_COLS(4096, 16, 1)
-    }
-#undef FC2D_COLS
+    FC2D_COLT(16, 2, 4) FC2D_COLT(16, 2, 8) FC2D_COLT(16, 2, 16)
+    FC2D_COLT(32, 2, 4) FC2D_COLT(32, 2, 8) FC2D_COLT(32, 2, 16)
+    FC2D_COLT(64, 2, 4) FC2D_COLT(64, 2, 8) FC2D_COLT(64, 2, 16)
+    FC2D_COLT(128, 2, 4) FC2D_COLT(128, 2, 8)
+    FC2D_COLT(256, 4, 4) FC2D_COLT(256, 4, 8)
+    FC2D_COLT(512, 8, 4) FC2D_COLT(512, 8, 8)
+    FC2D_COLT(1024, 16, 2) FC2D_COLT(1024, 16, 4) FC2D_COLT(1024, 16, 8)
+    FC2D_COLT(2048, 16, 1) FC2D_COLT(2048, 16, 2) FC2D_COLT(2048, 16, 4)
+    FC2D_COLT(4096, 16, 1) FC2D_COLT(4096, 16, 2)
+#undef FC2D_COLT
 }
 
 int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,

@@ -614,7 +614,8 @@ int ensure_work(const fc2d_plan* cpl, int nf) {
     if (pl->d_c) (void)hipFree(pl->d_c);
     pl->d_c = nullptr;
     pl->nf_cap = 0;
-    if (hipMalloc((void**)&pl->d_c, (size_t)nf * pl->B * pl->d * sizeof(double)) != hipSuccess) {
+    const int DP = (pl->d + 2) & ~1;   // Gram coefficients + boundary value, padded to even
+    if (hipMalloc((void**)&pl->d_c, (size_t)nf * pl->B * DP * sizeof(double)) != hipSuccess) {
         set_error("hipMalloc failed (Gram coefficient work space)");
         return FC2D_E_NOMEM;
     }
@@ -814,6 +815,22 @@ const char* fc2d_strerror(int status) {
 }
 
 const char* fc2d_last_error(void) { return g_last_error.c_str(); }
+
+int fc2d_tune_set(int knob, int n, int value) {
+    int st = FC2D_E_ARG;
+    if (knob == FC2D_TUNE_COL_TILE) st = col_tile_set(n, value);
+    else if (knob == FC2D_TUNE_STRIP_FIELDS) st = strip_fpt_set(value);
+    if (st) set_error("fc2d_tune_set: unsupported knob or value");
+    return st;
+}
+
+int fc2d_tune_get(int knob, int n, int* value) {
+    if (!value) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (knob == FC2D_TUNE_COL_TILE) *value = col_tile_get(n);
+    else if (knob == FC2D_TUNE_STRIP_FIELDS) *value = strip_fpt_get();
+    else { set_error("fc2d_tune_get: unknown knob"); return FC2D_E_ARG; }
+    return FC2D_OK;
+}
 
 int fc2d_trace_begin(hipStream_t stream) {
     {

@@ -21,6 +21,7 @@ FC2D_E_ARG, FC2D_E_TABLE, FC2D_E_GEOMETRY, FC2D_E_NEWTON, FC2D_E_HIP, FC2D_E_NOM
 FC2D_CURVE_POLAR, FC2D_CURVE_CARTESIAN = 1, 2
 FC2D_FORWARD, FC2D_INVERSE = -1, 1
 FC2D_LAPLACE_INV, FC2D_DX, FC2D_DY = 1, 2, 3
+FC2D_TUNE_COL_TILE, FC2D_TUNE_STRIP_FIELDS = 1, 2
 
 FAR, IN, STRIP = 0, 1, 2
 
@@ -76,6 +77,8 @@ def _lib():
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
             "ff_propagate": (C.c_int, [C.POINTER(fc2d_grid), C.c_double, C.c_double, _P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_tune_set": (C.c_int, [C.c_int, C.c_int, C.c_int]),
+            "fc2d_tune_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
             "fc2d_trace_begin": (C.c_int, [_P]),
             "fc2d_trace_end": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.c_int]),
             "fc2d_strerror": (C.c_char_p, [C.c_int]),
@@ -275,6 +278,16 @@ def ff_propagate(grid, c, t, u0h, u1h, uh, uth, stream=None):
     nf = u0h.numel() // (grid.nx * (grid.ny // 2 + 1))
     _check(_lib().ff_propagate(C.byref(grid), float(c), float(t), _dptr(u0h, "u0h"), _dptr(u1h, "u1h"),
                                _dptr(uh, "uh"), _dptr(uth, "uth"), nf, _stream(stream)))
+
+
+def fc2d_tune_set(knob, n, value):
+    _check(_lib().fc2d_tune_set(int(knob), int(n), int(value)))
+
+
+def fc2d_tune_get(knob, n=0):
+    v = C.c_int()
+    _check(_lib().fc2d_tune_get(int(knob), int(n), C.byref(v)))
+    return v.value
 
 
 def fc2d_trace_begin(stream=None):

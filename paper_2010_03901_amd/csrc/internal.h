@@ -57,7 +57,7 @@ struct fc2d_plan {
     double* d_seta = nullptr;       // [S] eta_Q
     int32_t* d_run_ptr = nullptr;   // [nx + 1] row runs
     int32_t* d_run = nullptr;       // [nruns][3] (start, end, class)
-    uint8_t* d_cls2 = nullptr;      // [nx][ny/2] classes of the pair (2n, 2n+1), 2 bits each (ny even)
+    uint8_t* d_cls2 = nullptr;      // [nx][ny/2] pair classes (2 bits per point) in row-pass thread order
     int nruns = 0;
     double* d_c = nullptr;          // [nf_cap][B][DP] Gram coefficients, boundary value, pad (DP = (d+2)&~1)
     int nf_cap = 0;
@@ -109,6 +109,10 @@ int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s)
 int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,
              double* uth, int nf, hipStream_t s);
+
+// masked row pass: elements per thread and the thread-order class layout
+int row_elems(int L);
+void row_class_layout(int L, const uint8_t* pairs, uint8_t* out);
 
 // tuning knobs (autotuner)
 int col_tile_get(int nx);

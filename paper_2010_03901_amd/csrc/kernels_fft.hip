@@ -243,26 +243,35 @@ __device__ __forceinline__ int out_index(int k, int t) {
 // is assembled on the fly (Sec. 3.5 step 6): cls2[n] holds the classes of the
 // pair (bits 0-1 and 2-3: 0 FAR, 1 IN, 2 STRIP); IN values come from `in`,
 // STRIP values from `strip` (same layout as `in`), FAR values are 0.
-__device__ const double2 g_zero_pair[1] = {{0.0, 0.0}};
+// Pair classes for the masked row pass are stored per row in thread order:
+// byte t*E + k is the class of element in_index(k, t), so each thread reads its
+// E class bytes with one vector load.  Bits 0-1 / 2-3: class of 2n / 2n+1.
+template <int E>
+struct ClassWord;
+template <> struct ClassWord<2> { typedef uint16_t type; };
+template <> struct ClassWord<4> { typedef uint32_t type; };
+template <> struct ClassWord<8> { typedef uint64_t type; };
+template <> struct ClassWord<16> { typedef uint4 type; };
 
-template <bool MASKED>
-__device__ __forceinline__ double2 load_pair(const double* row, const double* srow, const uint8_t* crow, int n) {
-    if constexpr (!MASKED) {
-        return ((const double2*)row)[n];
-    } else {
-        const int c = crow[n];
-        // common cases with one 16-byte load from a selected source: both IN,
-        // both STRIP, both FAR (a cached zero pair); mixed pairs load per element
-        if (c == 5 || c == 10 || c == 0) {
-            const double2* src = c == 5 ? (const double2*)row + n : (c == 10 ? (const double2*)srow + n : g_zero_pair);
-            return *src;
-        }
+template <int E>
+__device__ __forceinline__ void load_classes(const uint8_t* p, uint8_t* out) {
+    typedef typename ClassWord<E>::type W;
+    W w = *(const W*)p;
+    __builtin_memcpy(out, &w, E);
+}
+
+__device__ __forceinline__ double2 load_pair_masked(const double* row, const double* srow, int c, int n) {
+    double2 z = make_double2(0.0, 0.0);
+    if (c == 5) {
+        z = ((const double2*)row)[n];           // IN, IN
+    } else if (c == 10) {
+        z = ((const double2*)srow)[n];          // STRIP, STRIP
+    } else if (c != 0) {                        // mixed pair (class boundary)
         const int c0 = c & 3, c1 = (c >> 2) & 3;
-        double2 z;
         z.x = c0 == 1 ? row[2 * n] : (c0 == 2 ? srow[2 * n] : 0.0);
         z.y = c1 == 1 ? row[2 * n + 1] : (c1 == 2 ? srow[2 * n + 1] : 0.0);
-        return z;
     }
+    return z;
 }
 
 template <int L, int E, int RPB, bool MASKED>
@@ -281,10 +290,16 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
     const int64_t roff = ((int64_t)f * nx + (live ? row : 0)) * N;
     const double* src = in + roff;
     const double* ssrc = MASKED ? strip + roff : nullptr;
-    const uint8_t* crow = MASKED ? cls2 + (int64_t)(live ? row : 0) * L : nullptr;
     double2 v[E];
+    if constexpr (MASKED) {
+        uint8_t cb[E];
+        load_classes<E>(cls2 + (int64_t)(live ? row : 0) * L + t * E, cb);
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = load_pair<MASKED>(src, ssrc, crow, in_index<L, E>(k, t));
+        for (int k = 0; k < E; ++k) v[k] = load_pair_masked(src, ssrc, cb[k], in_index<L, E>(k, t));
+    } else {
+#pragma unroll
+        for (int k = 0; k < E; ++k) v[k] = ((const double2*)src)[in_index<L, E>(k, t)];
+    }
     StockhamFrom<L, E, 1, false>::run(v, lds, L, 1, q, t, tw, N);
     __syncthreads();
 #pragma unroll
@@ -398,6 +413,27 @@ static void launch_rows(int L, int nx, int nf, const void* in, void* out, const 
         FC2D_ROWS(4096, 16, 1)
     }
 #undef FC2D_ROWS
+}
+
+// Row-pass elements per thread for half length L (the configuration table of launch_rows).
+int row_elems(int L) {
+    switch (L) {
+        case 8: case 16: case 32: case 64: case 128: return 2;
+        case 256: return 4;
+        case 512: return 8;
+        case 1024: case 2048: case 4096: return 16;
+    }
+    return 0;
+}
+
+// Permute one row's pair classes into the masked row pass's thread order.
+void row_class_layout(int L, const uint8_t* pairs, uint8_t* out) {
+    const int E = row_elems(L);
+    const int P = L / E;
+    int R = 16;
+    while (R > E || L % R != 0) R >>= 1;   // first-stage radix
+    for (int t = 0; t < P; ++t)
+        for (int k = 0; k < E; ++k) out[t * E + k] = pairs[t + (k / R) * P + (k % R) * (L / R)];
 }
 
 // Column-tile widths (columns per block, 16 B each) per log2(nx); the

@@ -596,10 +596,14 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         if ((st = dev_upload(&pl->d_seta, pl->strip_eta.data(), pl->strip_eta.size()))) break;
         if ((st = dev_upload(&pl->d_run_ptr, run_ptr.data(), run_ptr.size()))) break;
         if ((st = dev_upload(&pl->d_run, runs.data(), runs.size()))) break;
-        if (grid->ny % 2 == 0) {
-            std::vector<uint8_t> cls2((size_t)grid->nx * (grid->ny / 2));
-            for (size_t e = 0; e < cls2.size(); ++e)
-                cls2[e] = (uint8_t)(pl->cls[2 * e] | (pl->cls[2 * e + 1] << 2));
+        const int Lh = grid->ny / 2;
+        if (grid->ny % 2 == 0 && row_elems(Lh) > 0) {
+            std::vector<uint8_t> pairs(Lh), cls2((size_t)grid->nx * Lh);
+            for (int i = 0; i < grid->nx; ++i) {
+                const int8_t* c = &pl->cls[(size_t)i * grid->ny];
+                for (int n = 0; n < Lh; ++n) pairs[n] = (uint8_t)(c[2 * n] | (c[2 * n + 1] << 2));
+                row_class_layout(Lh, pairs.data(), &cls2[(size_t)i * Lh]);
+            }
             if ((st = dev_upload(&pl->d_cls2, cls2.data(), cls2.size()))) break;
         }
     } while (0);

@@ -260,17 +260,20 @@ __device__ __forceinline__ void load_classes(const uint8_t* p, uint8_t* out) {
     __builtin_memcpy(out, &w, E);
 }
 
-__device__ __forceinline__ double2 load_pair_masked(const double* row, const double* srow, int c, int n) {
-    double2 z = make_double2(0.0, 0.0);
-    if (c == 5) {
-        z = ((const double2*)row)[n];           // IN, IN
-    } else if (c == 10) {
-        z = ((const double2*)srow)[n];          // STRIP, STRIP
-    } else if (c != 0) {                        // mixed pair (class boundary)
-        const int c0 = c & 3, c1 = (c >> 2) & 3;
-        z.x = c0 == 1 ? row[2 * n] : (c0 == 2 ? srow[2 * n] : 0.0);
-        z.y = c1 == 1 ? row[2 * n + 1] : (c1 == 2 ? srow[2 * n + 1] : 0.0);
-    }
+__device__ const double2 g_zero_pair[1] = {{0.0, 0.0}};
+
+// One unconditional 16-byte load per pair from a selected source: both IN ->
+// the field, both STRIP -> the strip values, anything else -> a cached zero
+// pair (mixed pairs are fixed up afterwards).
+__device__ __forceinline__ const double2* pair_source(const double* row, const double* srow, int c, int n) {
+    return c == 5 ? (const double2*)row + n : (c == 10 ? (const double2*)srow + n : g_zero_pair);
+}
+
+__device__ __forceinline__ double2 mixed_pair(const double* row, const double* srow, int c, int n) {
+    const int c0 = c & 3, c1 = (c >> 2) & 3;
+    double2 z;
+    z.x = c0 == 1 ? row[2 * n] : (c0 == 2 ? srow[2 * n] : 0.0);
+    z.y = c1 == 1 ? row[2 * n + 1] : (c1 == 2 ? srow[2 * n + 1] : 0.0);
     return z;
 }
 
@@ -295,7 +298,12 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
         uint8_t cb[E];
         load_classes<E>(cls2 + (int64_t)(live ? row : 0) * L + t * E, cb);
 #pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = load_pair_masked(src, ssrc, cb[k], in_index<L, E>(k, t));
+        for (int k = 0; k < E; ++k) v[k] = *pair_source(src, ssrc, cb[k], in_index<L, E>(k, t));
+#pragma unroll
+        for (int k = 0; k < E; ++k) {
+            const int c = cb[k];
+            if (c != 0 && c != 5 && c != 10) v[k] = mixed_pair(src, ssrc, c, in_index<L, E>(k, t));
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < E; ++k) v[k] = ((const double2*)src)[in_index<L, E>(k, t)];

@@ -137,6 +137,13 @@ int fc2d_blend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry
 int fc2d_extend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
                 double* out, int nf, hipStream_t stream);
 
+/* Boundary values for a later Fourier-Forwarding step (the paper takes them
+ * from its near-boundary solver; here they are read off the full-box field):
+ * f_bdry [nf][n_bdry] (device) = degree-(M-1) tensor-product Lagrange
+ * interpolation of u [nf][nx][ny] (device) on the centred M x M node block
+ * around each boundary point of fc2d_boundary_points (indices periodic). */
+int fc2d_boundary_values(const fc2d_plan* plan, const double* u, double* f_bdry, int nf, hipStream_t stream);
+
 /* Extension fused with the forward 2D FFT (Sec. 3.5 steps 5-7): spec [nf][nx][ny/2+1]
  * complex128 = the unnormalised forward transform of the grid fc2d_extend would
  * produce, without materialising it: the STRIP values are written into `work`
@@ -186,6 +193,35 @@ int fc2d_tune_get(int knob, int n, int* value);
  * of entries written.  Either output array may be NULL. */
 int fc2d_trace_begin(hipStream_t stream);
 int fc2d_trace_end(int* n, const char** names, float* ms, int cap);
+
+/* Batches (Fourier Forwarding of many fields on several domains and grid
+ * sizes, Sec. 4.2).  A batch holds, for plan k, nf[k] field pairs (u, u_t) on
+ * the plan's full box and advances them together; one step is
+ *   f_bdry <- fc2d_boundary_values(u), (u_t likewise)
+ *   spectra <- fc2d_extend_fft of u and u_t
+ *   spectra <- ff_propagate by dt
+ *   (u, u_t) <- inverse FFT (whole box).
+ * The plan-specific stages run as single persistent launches over all plans;
+ * the FFT passes run once per (nx, ny, h) with those fields contiguous.  The
+ * plans must share d, C, n_r, M and have power-of-two grids, and must outlive
+ * the batch.  flags: FC2D_BATCH_AUTOTUNE times the column-pass tile widths and
+ * the strip kernel's fields per thread on the batch's buffers and keeps the
+ * fastest (process-wide, see fc2d_tune_set).  State starts at zero. */
+typedef struct fc2d_batch fc2d_batch;
+enum { FC2D_BATCH_AUTOTUNE = 1 };
+int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, unsigned flags,
+                      hipStream_t stream, fc2d_batch** out);
+/* Device pointers to plan k's state: u and u_t, each [nf[k]][nx][ny]. */
+int fc2d_batch_state(fc2d_batch* batch, int k, double** u, double** ut);
+/* Grid points extended per step (u and u_t of every field), launches per
+ * step, and the strip kernel's fields per thread. */
+int fc2d_batch_info(const fc2d_batch* batch, int64_t* points_per_step, int* launches_per_step,
+                    int* strip_fields);
+/* Advance by `steps` steps of dt (wave speed c) on `stream`.  use_graph: the
+ * step is captured once in a HIP graph (re-captured when c or dt change) and
+ * replayed. */
+int fc2d_batch_ff_run(fc2d_batch* batch, double c, double dt, int steps, int use_graph, hipStream_t stream);
+int fc2d_batch_destroy(fc2d_batch* batch);
 
 const char* fc2d_strerror(int status);
 const char* fc2d_last_error(void);

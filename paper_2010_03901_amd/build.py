@@ -17,7 +17,7 @@ OUT = os.path.join(PKG, "libfc2d.so")
 BUILD = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRC = ["plan.cpp", "fcgram_quad.cpp"]
+HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp"]
 HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip"]
 
 HIPCC_FLAGS = [

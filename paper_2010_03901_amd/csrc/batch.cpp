@@ -1,0 +1,349 @@
+// Batches: many fields on several domains and grid sizes advanced together by
+// Fourier Forwarding (Sec. 4.2), one step being
+//   boundary values <- tensor interpolation of the full-box fields (u, u_t)
+//   Gram records     <- matching values + blend            (Sec. 3.2)
+//   STRIP values     <- interpolation onto H n V+         (Sec. 3.4)
+//   spectra          <- extension fused into the forward 2D FFT (Sec. 3.5)
+//   spectra          <- modal propagation by dt            (eq. wave_2d_ff)
+//   (u, u_t)         <- inverse 2D FFT on the whole box
+// The plan-specific stages run as single persistent launches over every
+// (plan, field set) of the batch; the FFT passes run once per grid size with
+// the fields of all domains of that size contiguous.  A step can be captured
+// in a HIP graph and replayed.  An optional autotuner times the column-pass
+// tile widths and the strip kernel's fields per thread on the batch's own
+// buffers and keeps the fastest.
+#include <string.h>
+
+#include <algorithm>
+#include <functional>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace fc2d;
+
+namespace fc2d {
+struct Group {
+    fc2d_grid grid;
+    int nf_total = 0;
+    std::vector<int> members;     // plan indices
+    double* state = nullptr;      // [2][nf_total][nx][ny]: u then u_t
+    double* spec = nullptr;       // [2][nf_total][nx][ny/2+1] complex128
+};
+}  // namespace fc2d
+
+struct fc2d_batch {
+    std::vector<const fc2d_plan*> plans;
+    std::vector<int> nf, group_of, field_off;
+    std::vector<Group> groups;
+    std::vector<double*> bufs;    // boundary values and Gram records (freed at destroy)
+    std::vector<PlanDev> pd;
+    PlanDev* d_pd = nullptr;
+    int64_t tot_match = 0, tot_strip = 0, tot_bv = 0;
+    int M = 0, D = 0, Cr = 0, strip_fpt = 4, grid_blocks = 2048;
+    const double* d_Ar = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipStream_t cap = nullptr;        // capture / replay stream (the caller's may be the null stream)
+    hipEvent_t ev_in = nullptr, ev_out = nullptr;
+    double graph_c = 0.0, graph_dt = 0.0;
+    int launches_per_step = 0;
+};
+
+static void batch_free(fc2d_batch* b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->ev_in) (void)hipEventDestroy(b->ev_in);
+    if (b->ev_out) (void)hipEventDestroy(b->ev_out);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    for (Group& g : b->groups) {
+        if (g.state) (void)hipFree(g.state);
+        if (g.spec) (void)hipFree(g.spec);
+    }
+    for (double* p : b->bufs)
+        if (p) (void)hipFree(p);
+    if (b->d_pd) (void)hipFree(b->d_pd);
+    delete b;
+}
+
+// enqueue one Fourier-Forwarding step of the whole batch on s
+static int batch_step(fc2d_batch* b, double c, double dt, hipStream_t s) {
+    int st;
+    const int np = (int)b->pd.size();
+    int n = 0;
+    if ((st = launch_multi(2, b->M, b->d_pd, np, b->tot_bv, 0, b->d_Ar, b->D, b->Cr, b->grid_blocks, s))) return st;
+    if ((st = launch_multi(0, b->M, b->d_pd, np, b->tot_match, 0, b->d_Ar, b->D, b->Cr, b->grid_blocks, s))) return st;
+    if ((st = launch_multi(1, b->M, b->d_pd, np, b->tot_strip, b->strip_fpt, b->d_Ar, b->D, b->Cr, b->grid_blocks, s)))
+        return st;
+    n += 3;
+    for (Group& g : b->groups) {
+        const int64_t npts = (int64_t)g.grid.nx * g.grid.ny;
+        const int64_t nsp = (int64_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;   // doubles per spectrum
+        for (int k : g.members) {
+            const fc2d_plan* pl = b->plans[k];
+            for (int half = 0; half < 2; ++half) {
+                const int64_t f0 = (int64_t)half * g.nf_total + b->field_off[k];
+                double* u = g.state + f0 * npts;
+                if ((st = fft_rows_fwd(&g.grid, u, g.spec + f0 * nsp, b->nf[k], s, u, pl->d_cls2))) return st;
+                ++n;
+            }
+        }
+        double* su = g.spec;
+        double* sut = g.spec + (int64_t)g.nf_total * nsp;
+        if ((st = fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s))) return st;
+        if ((st = ff_apply(&g.grid, c, dt, su, sut, su, sut, g.nf_total, s))) return st;
+        if ((st = fft_cols(&g.grid, g.spec, 2 * g.nf_total, true, s))) return st;
+        if ((st = fft_rows_inv(&g.grid, g.spec, g.state, 2 * g.nf_total, s))) return st;
+        n += 4;
+    }
+    b->launches_per_step = n;
+    return FC2D_OK;
+}
+
+static float time_ms(hipStream_t s, const std::function<int()>& fn, int reps) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.0f; }
+    (void)fn();   // warm-up
+    (void)hipEventRecord(e0, s);
+    for (int r = 0; r < reps; ++r) (void)fn();
+    (void)hipEventRecord(e1, s);
+    (void)hipEventSynchronize(e1);
+    float ms = -1.0f;
+    (void)hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return ms / reps;
+}
+
+static int autotune(fc2d_batch* b, hipStream_t s) {
+    // column-pass tile width per grid size
+    for (Group& g : b->groups) {
+        int best_T = col_tile_get(g.grid.nx);
+        float best = 1e30f;
+        const int cand[] = {1, 2, 4, 8, 16};
+        for (int T : cand) {
+            if (col_tile_set(g.grid.nx, T) != FC2D_OK) continue;
+            const float ms = time_ms(s, [&]() { return fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s); }, 3);
+            if (ms >= 0 && ms < best) { best = ms; best_T = T; }
+        }
+        col_tile_set(g.grid.nx, best_T);
+    }
+    // strip kernel: fields per thread
+    int best_f = b->strip_fpt;
+    float best = 1e30f;
+    const int fcand[] = {1, 2, 4, 8, 16};
+    for (int fpt : fcand) {
+        int64_t tot = 0;
+        for (PlanDev& P : b->pd) {
+            P.off_strip = tot;
+            tot += ((P.S + 255) / 256) * ((P.nf + fpt - 1) / fpt);
+        }
+        if (hipMemcpy(b->d_pd, b->pd.data(), b->pd.size() * sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess)
+            return FC2D_E_HIP;
+        const float ms = time_ms(s, [&]() {
+            return launch_multi(1, b->M, b->d_pd, (int)b->pd.size(), tot, fpt, b->d_Ar, b->D, b->Cr, b->grid_blocks, s);
+        }, 3);
+        if (ms >= 0 && ms < best) { best = ms; best_f = fpt; }
+    }
+    b->strip_fpt = best_f;
+    int64_t tot = 0;
+    for (PlanDev& P : b->pd) {
+        P.off_strip = tot;
+        tot += ((P.S + 255) / 256) * ((P.nf + best_f - 1) / best_f);
+    }
+    b->tot_strip = tot;
+    if (hipMemcpy(b->d_pd, b->pd.data(), b->pd.size() * sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess)
+        return FC2D_E_HIP;
+    return FC2D_OK;
+}
+
+extern "C" {
+
+int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, unsigned flags, hipStream_t s,
+                      fc2d_batch** out) {
+    if (!plans || !nf || nplans <= 0 || !out) { set_error("invalid batch arguments"); return FC2D_E_ARG; }
+    *out = nullptr;
+    fc2d_batch* b = new (std::nothrow) fc2d_batch();
+    if (!b) { set_error("out of host memory"); return FC2D_E_NOMEM; }
+    b->M = plans[0]->M;
+    b->D = plans[0]->d;
+    b->Cr = plans[0]->Cr;
+    b->d_Ar = plans[0]->d_Ar;
+    for (int k = 0; k < nplans; ++k) {
+        const fc2d_plan* pl = plans[k];
+        if (!pl || nf[k] <= 0 || pl->M != b->M || pl->d != b->D || pl->Cr != b->Cr || pl->Ar != plans[0]->Ar ||
+            !pl->d_cls2) {
+            set_error("batch plans must share d, C, n_r, M and tables, have power-of-two grids and nf > 0");
+            batch_free(b);
+            return FC2D_E_ARG;
+        }
+        b->plans.push_back(pl);
+        b->nf.push_back(nf[k]);
+        int gi = -1;
+        for (size_t g = 0; g < b->groups.size(); ++g)
+            if (b->groups[g].grid.nx == pl->grid.nx && b->groups[g].grid.ny == pl->grid.ny &&
+                b->groups[g].grid.h == pl->grid.h)
+                gi = (int)g;   // same transform sizes and wavenumbers
+        if (gi < 0) {
+            Group g;
+            g.grid = pl->grid;
+            b->groups.push_back(g);
+            gi = (int)b->groups.size() - 1;
+        }
+        b->group_of.push_back(gi);
+        b->field_off.push_back(b->groups[gi].nf_total);
+        b->groups[gi].nf_total += nf[k];
+        b->groups[gi].members.push_back(k);
+    }
+    int st = FC2D_OK;
+    for (Group& g : b->groups) {
+        const size_t npts = (size_t)g.grid.nx * g.grid.ny;
+        const size_t nsp = (size_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;
+        if (hipMalloc((void**)&g.state, 2 * g.nf_total * npts * sizeof(double)) != hipSuccess ||
+            hipMalloc((void**)&g.spec, 2 * g.nf_total * nsp * sizeof(double)) != hipSuccess) {
+            set_error("hipMalloc failed (batch state)");
+            batch_free(b);
+            return FC2D_E_NOMEM;
+        }
+        if (hipMemset(g.state, 0, 2 * g.nf_total * npts * sizeof(double)) != hipSuccess ||
+            hipMemset(g.spec, 0, 2 * g.nf_total * nsp * sizeof(double)) != hipSuccess ||
+            fft_prepare(g.grid.nx, g.grid.ny) != FC2D_OK) {
+            set_error("batch initialisation failed");
+            batch_free(b);
+            return FC2D_E_HIP;
+        }
+    }
+    // descriptors: entry 2k = u of plan k, 2k+1 = u_t of plan k
+    int64_t om = 0, ob = 0;
+    for (int k = 0; k < nplans; ++k) {
+        const fc2d_plan* pl = b->plans[k];
+        const Group& g = b->groups[b->group_of[k]];
+        const int64_t npts = (int64_t)g.grid.nx * g.grid.ny;
+        const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
+        const int DP = (pl->d + 2) & ~1;
+        for (int half = 0; half < 2; ++half) {
+            PlanDev P;
+            memset(&P, 0, sizeof P);
+            P.mref = pl->d_mref; P.mwv = pl->d_mwv; P.mwn = pl->d_mwn; P.Q = pl->d_Q;
+            P.sidx = pl->d_sidx; P.sth = pl->d_sth; P.seta = pl->d_seta; P.bxy = pl->d_bxy;
+            P.B = pl->B; P.D = pl->d; P.nf = b->nf[k]; P.nx = g.grid.nx; P.ny = g.grid.ny;
+            P.npts = npts; P.nbdry = nb; P.S = (int64_t)pl->strip_idx.size();
+            P.k2 = pl->k2; P.lev_scale = pl->n_r / pl->k1; P.x0 = g.grid.x0; P.y0 = g.grid.y0; P.h = g.grid.h;
+            P.u = g.state + ((int64_t)half * g.nf_total + b->field_off[k]) * npts;
+            double *fb = nullptr, *cb = nullptr;
+            if (hipMalloc((void**)&fb, (size_t)P.nf * nb * sizeof(double)) != hipSuccess ||
+                hipMalloc((void**)&cb, (size_t)P.nf * pl->B * DP * sizeof(double)) != hipSuccess) {
+                if (fb) (void)hipFree(fb);
+                set_error("hipMalloc failed (batch work)");
+                batch_free(b);
+                return FC2D_E_NOMEM;
+            }
+            b->bufs.push_back(fb);
+            b->bufs.push_back(cb);
+            P.fb = fb;
+            P.c = cb;
+            P.off_match = om;
+            om += (int64_t)((P.B + 7) & ~7) * ((P.nf + 63) / 64);
+            P.off_bv = ob;
+            ob += (int64_t)P.nf * nb;
+            b->pd.push_back(P);
+        }
+    }
+    b->tot_match = om;
+    b->tot_bv = ob;
+    int64_t ot = 0;
+    for (PlanDev& P : b->pd) {
+        P.off_strip = ot;
+        ot += ((P.S + 255) / 256) * ((P.nf + b->strip_fpt - 1) / b->strip_fpt);
+    }
+    b->tot_strip = ot;
+    int dev = 0, cus = 256;
+    (void)hipGetDevice(&dev);
+    (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    b->grid_blocks = std::max(8, (cus * 8 / 8) * 8);
+    if (hipMalloc((void**)&b->d_pd, b->pd.size() * sizeof(PlanDev)) != hipSuccess ||
+        hipMemcpy(b->d_pd, b->pd.data(), b->pd.size() * sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("batch descriptor upload failed");
+        batch_free(b);
+        return FC2D_E_HIP;
+    }
+    if (hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming) != hipSuccess) {
+        set_error("batch stream/event creation failed");
+        batch_free(b);
+        return FC2D_E_HIP;
+    }
+    if (flags & FC2D_BATCH_AUTOTUNE) st = autotune(b, s);
+    if (st) { batch_free(b); return st; }
+    if (hipStreamSynchronize(s) != hipSuccess) { set_error("batch set-up failed"); batch_free(b); return FC2D_E_HIP; }
+    *out = b;
+    return FC2D_OK;
+}
+
+int fc2d_batch_state(fc2d_batch* b, int k, double** u, double** ut) {
+    if (!b || k < 0 || k >= (int)b->plans.size()) { set_error("invalid batch or plan index"); return FC2D_E_ARG; }
+    const Group& g = b->groups[b->group_of[k]];
+    const int64_t npts = (int64_t)g.grid.nx * g.grid.ny;
+    if (u) *u = g.state + (int64_t)b->field_off[k] * npts;
+    if (ut) *ut = g.state + ((int64_t)g.nf_total + b->field_off[k]) * npts;
+    return FC2D_OK;
+}
+
+int fc2d_batch_info(const fc2d_batch* b, int64_t* points_per_step, int* launches_per_step, int* strip_fields) {
+    if (!b) { set_error("NULL batch"); return FC2D_E_ARG; }
+    int64_t pts = 0;
+    for (const Group& g : b->groups) pts += 2 * (int64_t)g.nf_total * g.grid.nx * g.grid.ny;
+    if (points_per_step) *points_per_step = pts;
+    if (launches_per_step) *launches_per_step = b->launches_per_step;
+    if (strip_fields) *strip_fields = b->strip_fpt;
+    return FC2D_OK;
+}
+
+int fc2d_batch_ff_run(fc2d_batch* b, double c, double dt, int steps, int use_graph, hipStream_t s) {
+    if (!b || steps < 0) { set_error("invalid batch arguments"); return FC2D_E_ARG; }
+    int st;
+    if (!use_graph) {
+        for (int i = 0; i < steps; ++i)
+            if ((st = batch_step(b, c, dt, s))) return st;
+        return FC2D_OK;
+    }
+    // capture and replay on the batch's own stream, ordered after and before `s`
+    hipStream_t cs = b->cap;
+    hipError_t e = hipEventRecord(b->ev_in, s);
+    if (e == hipSuccess) e = hipStreamWaitEvent(cs, b->ev_in, 0);
+    if (e != hipSuccess) { set_error(std::string("batch stream ordering: ") + hipGetErrorString(e)); return FC2D_E_HIP; }
+    if (!b->exec || b->graph_c != c || b->graph_dt != dt) {
+        if (b->exec) { (void)hipGraphExecDestroy(b->exec); b->exec = nullptr; }
+        if (b->graph) { (void)hipGraphDestroy(b->graph); b->graph = nullptr; }
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) { set_error(std::string("hipStreamBeginCapture: ") + hipGetErrorString(e)); return FC2D_E_HIP; }
+        st = batch_step(b, c, dt, cs);
+        e = hipStreamEndCapture(cs, &b->graph);
+        if (st) return st;
+        if (e != hipSuccess) { set_error(std::string("hipStreamEndCapture: ") + hipGetErrorString(e)); return FC2D_E_HIP; }
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { set_error(std::string("hipGraphInstantiate: ") + hipGetErrorString(e)); return FC2D_E_HIP; }
+        b->graph_c = c;
+        b->graph_dt = dt;
+    }
+    for (int i = 0; i < steps; ++i) {
+        e = hipGraphLaunch(b->exec, cs);
+        if (e != hipSuccess) { set_error(std::string("hipGraphLaunch: ") + hipGetErrorString(e)); return FC2D_E_HIP; }
+    }
+    e = hipEventRecord(b->ev_out, cs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s, b->ev_out, 0);
+    if (e != hipSuccess) { set_error(std::string("batch stream ordering: ") + hipGetErrorString(e)); return FC2D_E_HIP; }
+    return FC2D_OK;
+}
+
+int fc2d_batch_destroy(fc2d_batch* b) {
+    batch_free(b);
+    return FC2D_OK;
+}
+
+}  // extern "C"

@@ -57,6 +57,7 @@ struct fc2d_plan {
     double* d_seta = nullptr;       // [S] eta_Q
     int32_t* d_run_ptr = nullptr;   // [nx + 1] row runs
     int32_t* d_run = nullptr;       // [nruns][3] (start, end, class)
+    double* d_bxy = nullptr;        // [n_bdry][2] boundary points (feet, then squares)
     uint8_t* d_cls2 = nullptr;      // [nx][ny/2] pair classes (2 bits per point) in row-pass thread order
     int nruns = 0;
     double* d_c = nullptr;          // [nf_cap][B][DP] Gram coefficients, boundary value, pad (DP = (d+2)&~1)
@@ -91,6 +92,29 @@ struct StripRec {
 int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64_t cap,
                     uint64_t* d_near, int* d_counters, hipStream_t s);
 
+// ---- batches: one descriptor per (plan, field set) for the persistent kernels ----
+struct PlanDev {
+    const int32_t* mref;
+    const double* mwv;
+    const double* mwn;
+    const double* Q;
+    const int32_t* sidx;
+    const double* sth;
+    const double* seta;
+    const double* bxy;
+    int B, D, nf, nx, ny, pad;
+    int64_t npts, nbdry, S;
+    double k2, lev_scale, x0, y0, h;
+    double* u;    // [nf][nx][ny] fields: IN values read, STRIP values written
+    double* fb;   // [nf][nbdry] boundary values
+    double* c;    // [nf][B][DP] Gram records
+    int64_t off_match, off_strip, off_bv;   // first work item of this entry
+};
+// which: 0 match, 1 strip, 2 boundary values
+int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, int fpt, const double* Ar, int D,
+                 int Cr, int grid_blocks, hipStream_t s);
+int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipStream_t s);
+
 // ---- extension kernels (kernels_extend.hip) ----
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry,
                  double* c_out, double* fD_out, int nf, hipStream_t s);
@@ -106,6 +130,12 @@ int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, 
 int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s,
              const double* strip = nullptr, const uint8_t* cls2 = nullptr);
 int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s);
+// single passes (batches) and twiddle set-up outside stream capture
+int fft_prepare(int nx, int ny);
+int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
+                 const uint8_t* cls2);
+int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s);
+int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s);
 int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,
              double* uth, int nf, hipStream_t s);

@@ -58,22 +58,12 @@ struct Acc2 {
     }
 };
 
-// One thread per (normal p, field f): the weights of normal p are uniform
-// across the wave (scalar loads), each lane gathers its own field's values.
+// Matching values and Gram coefficients of normal p for field f (one thread).
 template <int M>
-__global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
-                                              const double* __restrict__ mwn, const double* __restrict__ Q, int D,
-                                              int B, const double* __restrict__ fg, int64_t npts,
-                                              const double* __restrict__ fb, int64_t nbdry, int nf,
-                                              double* __restrict__ c_out, double* __restrict__ fD_out) {
-    // consecutive normals share grid lines: give each XCD (blocks are dealt
-    // round-robin to the 8 XCDs) a contiguous range of normals so they share an L2
-    const int per_xcd = (B + 7) / 8;
-    const int p = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    const int f = blockIdx.y * 64 + threadIdx.x;
-    if (p >= B || f >= nf) return;
-    const double* g = fg + (int64_t)f * npts;
-    const double* bv = fb + (int64_t)f * nbdry;
+__device__ __forceinline__ void match_one(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
+                                          const double* __restrict__ mwn, const double* __restrict__ Q, int D, int B,
+                                          const double* __restrict__ g, const double* __restrict__ bv, int p,
+                                          double* __restrict__ co, double* __restrict__ fo) {
     const int32_t* ref = mref + (int64_t)p * M * M;
     const double* wv = mwv + (int64_t)p * M * M * 2;
     const double* wn = mwn + (int64_t)p * (D - 1) * M * 2;
@@ -110,7 +100,6 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
     }
     // c_p = Q^T f_{D_p}, stored with the boundary value appended: [c_0..c_{d-1}, f_{D_p}[d-1], 0 pad]
     const int DP = (D + 2) & ~1;
-    double* co = c_out + ((int64_t)f * B + p) * DP;
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
         if (j < D) {
@@ -123,11 +112,54 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
     }
     co[D] = fbp;
     if (DP > D + 1) co[D + 1] = 0.0;
-    if (fD_out) {
-        double* fo = fD_out + ((int64_t)f * B + p) * D;
+    if (fo) {
 #pragma unroll
         for (int q = 0; q < 9; ++q)
             if (q < D) fo[q] = fD[q].hi;
+    }
+}
+
+// Consecutive normals share grid lines: each XCD (blocks are dealt
+// round-robin to the 8 XCDs) gets a contiguous range of normals so they share
+// an L2.  Local work index l -> normal.
+__device__ __forceinline__ int xcd_normal(int l, int B) {
+    const int per_xcd = (B + 7) / 8;
+    return (l % 8) * per_xcd + l / 8;
+}
+
+// One thread per (normal p, field f): the weights of normal p are uniform
+// across the wave (scalar loads), each lane gathers its own field's values.
+template <int M>
+__global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
+                                              const double* __restrict__ mwn, const double* __restrict__ Q, int D,
+                                              int B, const double* __restrict__ fg, int64_t npts,
+                                              const double* __restrict__ fb, int64_t nbdry, int nf,
+                                              double* __restrict__ c_out, double* __restrict__ fD_out) {
+    const int p = xcd_normal(blockIdx.x, B);
+    const int f = blockIdx.y * 64 + threadIdx.x;
+    if (p >= B || f >= nf) return;
+    const int DP = (D + 2) & ~1;
+    match_one<M>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p,
+                 c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
+}
+
+// Persistent form over several plans (a batch): work item w covers 64 fields
+// of one normal of one plan; items of plan k start at a multiple of 8 so the
+// XCD assignment above is kept.  Every block loops until the items run out.
+template <int M>
+__global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ pd, int np, int64_t total) {
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int k = 0;
+        while (k + 1 < np && pd[k + 1].off_match <= w) ++k;
+        const PlanDev& P = pd[k];
+        const int64_t l = w - P.off_match;
+        const int padB = (P.B + 7) & ~7;
+        const int p = xcd_normal((int)(l % padB), P.B);
+        const int f = (int)(l / padB) * 64 + threadIdx.x;
+        if (p >= P.B || f >= P.nf) continue;
+        const int DP = (P.D + 2) & ~1;
+        match_one<M>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts, P.fb + (int64_t)f * P.nbdry, p,
+                     P.c + ((int64_t)f * P.B + p) * DP, nullptr);
     }
 }
 
@@ -150,17 +182,12 @@ __global__ void k_blend(const double* __restrict__ c, const double* __restrict__
     }
 }
 
+// Interpolated value at STRIP point k for fields [f0, f1) (one thread).
 template <int M>
-__global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
-                                               const double* __restrict__ seta, int64_t S, const double* __restrict__ Ar,
-                                               int D, int Cr, int B, double k2, double lev_scale,
-                                               const double* __restrict__ c, const double* __restrict__ fb,
-                                               int64_t nbdry, double* __restrict__ out, int64_t npts, int nf, int fpt) {
-    extern __shared__ double sAr[];
-    for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
-    __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= S) return;
+__device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
+                                          const double* __restrict__ seta, int64_t k, const double* sAr, int D,
+                                          int Cr, int B, double k2, double lev_scale, const double* __restrict__ c,
+                                          double* __restrict__ out, int64_t npts, int f0, int f1) {
     const double th = sth[k];
     const double eta = seta[k];
     const int32_t idx = sidx[k];
@@ -212,8 +239,6 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
         int q = (p0 - kl + m) % B;
         pj[m] = q < 0 ? q + B : q;
     }
-    const int f0 = blockIdx.y * fpt;
-    const int f1 = min(nf, f0 + fpt);
 #pragma unroll 2
     for (int f = f0; f < f1; ++f) {
         const double* cf = c + (int64_t)f * B * DP;
@@ -232,6 +257,110 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
             ext += w[m] * gsum;
         }
         out[(int64_t)f * npts + idx] = ext;
+    }
+}
+
+template <int M>
+__global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
+                                               const double* __restrict__ seta, int64_t S, const double* __restrict__ Ar,
+                                               int D, int Cr, int B, double k2, double lev_scale,
+                                               const double* __restrict__ c, const double* __restrict__ fb,
+                                               int64_t nbdry, double* __restrict__ out, int64_t npts, int nf, int fpt) {
+    extern __shared__ double sAr[];
+    for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
+    __syncthreads();
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= S) return;
+    const int f0 = blockIdx.y * fpt;
+    strip_one<M>(sidx, sth, seta, k, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0, min(nf, f0 + fpt));
+}
+
+// Persistent form over several plans: work item w = (plan, block of 256 STRIP
+// points, chunk of fpt fields).  All plans of a batch share the FC-Gram tables.
+template <int M>
+__global__ __launch_bounds__(256) void k_strip_multi(const PlanDev* __restrict__ pd, int np, int64_t total, int fpt,
+                                                     const double* __restrict__ Ar, int D, int Cr) {
+    extern __shared__ double sAr[];
+    for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
+    __syncthreads();
+    for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+        int kk = 0;
+        while (kk + 1 < np && pd[kk + 1].off_strip <= w) ++kk;
+        const PlanDev& P = pd[kk];
+        const int64_t l = w - P.off_strip;
+        const int64_t pblocks = (P.S + 255) / 256;
+        const int64_t k = (l % pblocks) * 256 + threadIdx.x;
+        const int f0 = (int)(l / pblocks) * fpt;
+        if (k >= P.S) continue;
+        strip_one<M>(P.sidx, P.sth, P.seta, k, sAr, D, Cr, P.B, P.k2, P.lev_scale, P.c, P.u, P.npts, f0,
+                     min(P.nf, f0 + fpt));
+    }
+}
+
+// Boundary values for the next Fourier-Forwarding step: degree-(M-1)
+// tensor-product Lagrange interpolation of the full-box field on the centred
+// M x M block of nodes around each boundary point (grid indices periodic).
+template <int M>
+__device__ __forceinline__ double bval_one(const double* __restrict__ u, int nx, int ny, double x0, double y0,
+                                           double h, double X, double Y) {
+    const int i0 = (int)floor((X - x0) / h) - M / 2 + 1;
+    const int j0 = (int)floor((Y - y0) / h) - M / 2 + 1;
+    double wx[M], wy[M];
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        double va = 1.0, vb = 1.0;
+        const double xa = x0 + (double)(i0 + a) * h, ya = y0 + (double)(j0 + a) * h;
+#pragma unroll
+        for (int b = 0; b < M; ++b) {
+            if (b == a) continue;
+            const double xb = x0 + (double)(i0 + b) * h, yb = y0 + (double)(j0 + b) * h;
+            va *= (X - xb) / (xa - xb);
+            vb *= (Y - yb) / (ya - yb);
+        }
+        wx[a] = va;
+        wy[a] = vb;
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) {
+        int ii = (i0 + a) % nx;
+        ii = ii < 0 ? ii + nx : ii;
+        const double* rowp = u + (int64_t)ii * ny;
+        double r = 0.0;
+#pragma unroll
+        for (int b = 0; b < M; ++b) {
+            int jj = (j0 + b) % ny;
+            jj = jj < 0 ? jj + ny : jj;
+            r += wy[b] * rowp[jj];
+        }
+        acc += wx[a] * r;
+    }
+    return acc;
+}
+
+template <int M>
+__global__ void k_bvals(const double* __restrict__ bxy, int64_t nb, const double* __restrict__ u, int nx, int ny,
+                        double x0, double y0, double h, int nf, double* __restrict__ fb) {
+    const int64_t total = nb * nf;
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        const int f = (int)(e / nb);
+        const int64_t k = e - (int64_t)f * nb;
+        fb[e] = bval_one<M>(u + (int64_t)f * nx * ny, nx, ny, x0, y0, h, bxy[2 * k], bxy[2 * k + 1]);
+    }
+}
+
+template <int M>
+__global__ void k_bvals_multi(const PlanDev* __restrict__ pd, int np, int64_t total) {
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+        int kk = 0;
+        while (kk + 1 < np && pd[kk + 1].off_bv <= e) ++kk;
+        const PlanDev& P = pd[kk];
+        const int64_t l = e - P.off_bv;
+        const int f = (int)(l / P.nbdry);
+        const int64_t k = l - (int64_t)f * P.nbdry;
+        if (f >= P.nf) continue;
+        P.fb[(int64_t)f * P.nbdry + k] =
+            bval_one<M>(P.u + (int64_t)f * P.npts, P.nx, P.ny, P.x0, P.y0, P.h, P.bxy[2 * k], P.bxy[2 * k + 1]);
     }
 }
 
@@ -320,6 +449,43 @@ int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, 
     dim3 grid(pl->grid.nx, nf);
     k_mask<<<grid, 256, 0, s>>>(pl->d_run_ptr, pl->d_run, pl->grid.ny, f_grid, out, npts, f_grid != out);
     return launch_check("k_mask", s);
+}
+
+}  // namespace fc2d
+
+namespace fc2d {
+
+int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipStream_t s) {
+    const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
+    const int64_t total = nb * nf;
+    const unsigned blocks = (unsigned)std::min<int64_t>((total + 255) / 256, 65535);
+    const fc2d_grid& g = pl->grid;
+    switch (pl->M) {
+#define FC2D_BV(MM) \
+        case MM: k_bvals<MM><<<blocks, 256, 0, s>>>(pl->d_bxy, nb, u, g.nx, g.ny, g.x0, g.y0, g.h, nf, fb); break;
+        FC2D_BV(4) FC2D_BV(5) FC2D_BV(6) FC2D_BV(7) FC2D_BV(8)
+#undef FC2D_BV
+        default: set_error("unsupported M"); return FC2D_E_ARG;
+    }
+    return launch_check("k_bvals", s);
+}
+
+int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, int fpt, const double* Ar, int D,
+                 int Cr, int grid_blocks, hipStream_t s) {
+    const unsigned g = (unsigned)std::max<int64_t>(8, std::min<int64_t>(total, grid_blocks));
+    const size_t lds = (size_t)Cr * D * sizeof(double);
+    switch (M) {
+#define FC2D_MULTI(MM)                                                                                 \
+        case MM:                                                                                       \
+            if (which == 0) k_match_multi<MM><<<g, 64, 0, s>>>(d_pd, np, total);                       \
+            else if (which == 1) k_strip_multi<MM><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr); \
+            else k_bvals_multi<MM><<<g, 256, 0, s>>>(d_pd, np, total);                                 \
+            break;
+        FC2D_MULTI(4) FC2D_MULTI(5) FC2D_MULTI(6) FC2D_MULTI(7) FC2D_MULTI(8)
+#undef FC2D_MULTI
+        default: set_error("unsupported M"); return FC2D_E_ARG;
+    }
+    return launch_check(which == 0 ? "k_match_multi" : (which == 1 ? "k_strip_multi" : "k_bvals_multi"), s);
 }
 
 }  // namespace fc2d

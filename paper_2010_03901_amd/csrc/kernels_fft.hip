@@ -495,29 +495,44 @@ static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* 
 #undef FC2D_COLT
 }
 
+int fft_prepare(int nx, int ny) {
+    return (twiddles(nx) && twiddles(ny)) ? FC2D_OK : FC2D_E_NOMEM;
+}
+
+int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
+                 const uint8_t* cls2) {
+    const double2* twy = twiddles(g->ny);
+    if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
+    launch_rows<true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s);
+    return check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
+}
+
+int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s) {
+    const double2* twx = twiddles(g->nx);
+    if (!twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
+    if (inv) launch_cols<true>(g->nx, g->ny / 2 + 1, nf, (double2*)data, twx, s);
+    else launch_cols<false>(g->nx, g->ny / 2 + 1, nf, (double2*)data, twx, s);
+    return check(inv ? "k_cols_inv" : "k_cols", s);
+}
+
+int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
+    const double2* twy = twiddles(g->ny);
+    if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
+    launch_rows<false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr, nullptr, s);
+    return check("k_rows_c2r", s);
+}
+
 int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
              const uint8_t* cls2) {
-    const int nx = g->nx, ny = g->ny, L = ny / 2;
-    const double2* twy = twiddles(ny);
-    const double2* twx = twiddles(nx);
-    if (!twy || !twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_rows<true>(L, nx, nf, in, out, twy, 1.0, strip, cls2, s);
-    int st = check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
+    int st = fft_rows_fwd(g, in, out, nf, s, strip, cls2);
     if (st) return st;
-    launch_cols<false>(nx, L + 1, nf, (double2*)out, twx, s);
-    return check("k_cols", s);
+    return fft_cols(g, out, nf, false, s);
 }
 
 int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s) {
-    const int nx = g->nx, ny = g->ny, L = ny / 2;
-    const double2* twy = twiddles(ny);
-    const double2* twx = twiddles(nx);
-    if (!twy || !twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_cols<true>(nx, L + 1, nf, (double2*)in, twx, s);
-    int st = check("k_cols_inv", s);
+    int st = fft_cols(g, in, nf, true, s);
     if (st) return st;
-    launch_rows<false>(L, nx, nf, in, out, twy, 1.0 / ((double)nx * (double)ny), nullptr, nullptr, s);
-    return check("k_rows_c2r", s);
+    return fft_rows_inv(g, in, out, nf, s);
 }
 
 // ---------------------------------------------------------------------------

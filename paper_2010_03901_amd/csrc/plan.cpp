@@ -359,7 +359,7 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
 static void free_plan(fc2d_plan* pl) {
     if (!pl) return;
     void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_sidx,
-                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c, pl->d_cls2};
+                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c, pl->d_cls2, pl->d_bxy};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;
@@ -596,6 +596,12 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         if ((st = dev_upload(&pl->d_seta, pl->strip_eta.data(), pl->strip_eta.size()))) break;
         if ((st = dev_upload(&pl->d_run_ptr, run_ptr.data(), run_ptr.size()))) break;
         if ((st = dev_upload(&pl->d_run, runs.data(), runs.size()))) break;
+        {
+            std::vector<double> bxy(2 * (size_t)B + pl->squares.size());
+            for (int p = 0; p < B; ++p) { bxy[2 * p] = pl->bx[p]; bxy[2 * p + 1] = pl->by[p]; }
+            std::copy(pl->squares.begin(), pl->squares.end(), bxy.begin() + 2 * B);
+            if ((st = dev_upload(&pl->d_bxy, bxy.data(), bxy.size()))) break;
+        }
         const int Lh = grid->ny / 2;
         if (grid->ny % 2 == 0 && row_elems(Lh) > 0) {
             std::vector<uint8_t> pairs(Lh), cls2((size_t)grid->nx * Lh);
@@ -766,6 +772,14 @@ int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_b
     if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
     if ((st = launch_strip(pl, pl->d_c, f_bdry, nb, work, nf, s))) return st;
     return fft2_r2c(g, f_grid, (double*)spec, nf, s, work, pl->d_cls2);
+}
+
+int fc2d_boundary_values(const fc2d_plan* pl, const double* u, double* f_bdry, int nf, hipStream_t s) {
+    int st = check_fields(pl, nf);
+    if (st) return st;
+    if (nf == 0) return FC2D_OK;
+    if (!u || !f_bdry) { set_error("NULL argument"); return FC2D_E_ARG; }
+    return launch_bvals(pl, u, f_bdry, nf, s);
 }
 
 static bool pow2_ok(int n, int nmax) { return n >= 16 && n <= nmax && (n & (n - 1)) == 0; }

@@ -22,6 +22,7 @@ FC2D_CURVE_POLAR, FC2D_CURVE_CARTESIAN = 1, 2
 FC2D_FORWARD, FC2D_INVERSE = -1, 1
 FC2D_LAPLACE_INV, FC2D_DX, FC2D_DY = 1, 2, 3
 FC2D_TUNE_COL_TILE, FC2D_TUNE_STRIP_FIELDS = 1, 2
+FC2D_BATCH_AUTOTUNE = 1
 
 FAR, IN, STRIP = 0, 1, 2
 
@@ -77,6 +78,12 @@ def _lib():
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
             "ff_propagate": (C.c_int, [C.POINTER(fc2d_grid), C.c_double, C.c_double, _P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_boundary_values": (C.c_int, [_P, _P, _P, C.c_int, _P]),
+            "fc2d_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int), C.c_int, C.c_uint, _P, C.POINTER(_P)]),
+            "fc2d_batch_state": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P)]),
+            "fc2d_batch_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+            "fc2d_batch_ff_run": (C.c_int, [_P, C.c_double, C.c_double, C.c_int, C.c_int, _P]),
+            "fc2d_batch_destroy": (C.c_int, [_P]),
             "fc2d_tune_set": (C.c_int, [C.c_int, C.c_int, C.c_int]),
             "fc2d_tune_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
             "fc2d_trace_begin": (C.c_int, [_P]),
@@ -278,6 +285,71 @@ def ff_propagate(grid, c, t, u0h, u1h, uh, uth, stream=None):
     nf = u0h.numel() // (grid.nx * (grid.ny // 2 + 1))
     _check(_lib().ff_propagate(C.byref(grid), float(c), float(t), _dptr(u0h, "u0h"), _dptr(u1h, "u1h"),
                                _dptr(uh, "uh"), _dptr(uth, "uth"), nf, _stream(stream)))
+
+
+def fc2d_boundary_values(plan, u, f_bdry, stream=None):
+    import torch
+    nf = _nf(u, plan.grid)
+    if f_bdry.numel() != nf * plan.info.n_bdry:
+        raise ValueError("f_bdry size does not match the plan")
+    _check(_lib().fc2d_boundary_values(plan.handle, _dptr(u, "u", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+                                       nf, _stream(stream)))
+
+
+class Batch:
+    """Owning wrapper of fc2d_batch* (keeps its plans alive)."""
+
+    def __init__(self, plans, nf, autotune=False, stream=None):
+        self.plans = list(plans)
+        arr = (C.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
+        nfa = (C.c_int * len(self.plans))(*[int(n) for n in nf])
+        self.nf = [int(n) for n in nf]
+        h = C.c_void_p()
+        _check(_lib().fc2d_batch_create(arr, nfa, len(self.plans), FC2D_BATCH_AUTOTUNE if autotune else 0,
+                                        _stream(stream), C.byref(h)))
+        self._h = h
+
+    def state(self, k):
+        """(u, u_t) of plan k as torch tensors viewing the batch's device memory."""
+        import torch
+        u = C.c_void_p()
+        ut = C.c_void_p()
+        _check(_lib().fc2d_batch_state(self._h, int(k), C.byref(u), C.byref(ut)))
+        g = self.plans[k].grid
+        n = self.nf[k] * g.nx * g.ny
+        return _view_device(u.value, n, (self.nf[k], g.nx, g.ny)), _view_device(ut.value, n, (self.nf[k], g.nx, g.ny))
+
+    def info(self):
+        pts = C.c_int64()
+        nl = C.c_int()
+        sf = C.c_int()
+        _check(_lib().fc2d_batch_info(self._h, C.byref(pts), C.byref(nl), C.byref(sf)))
+        return pts.value, nl.value, sf.value
+
+    def ff_run(self, c, dt, steps, use_graph=True, stream=None):
+        _check(_lib().fc2d_batch_ff_run(self._h, float(c), float(dt), int(steps), 1 if use_graph else 0,
+                                        _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib().fc2d_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _view_device(ptr, n, shape):
+    """A float64 torch tensor over library-owned device memory (no copy)."""
+    import torch
+
+    class _Arr:
+        __cuda_array_interface__ = {"shape": (n,), "typestr": "<f8", "data": (ptr, False), "version": 2}
+
+    return torch.as_tensor(_Arr(), device="cuda:0").view(*shape)
 
 
 def fc2d_tune_set(knob, n, value):

@@ -149,6 +149,18 @@ def cfg_star(n=1024):
     return box_case("star%d" % n, star5(), -1.6, 1.6, n, 2 * n, k1=min(h, STAR_K1))
 
 
+FF_DOMAINS = {"disc": disc, "star5": star5, "kite": lambda: kite(0.65, 1.5), "ellipse": ellipse}
+
+
+def cfg_ff(domain, n):
+    """Batched Fourier-Forwarding workload: one common box [-2, 2]^2 for every
+    domain (so fields of one grid size share transform sizes and wavenumbers),
+    B = 2n, k1 = h except the star (k1 = min(h, 0.0024))."""
+    h = 4.0 / n
+    k1 = min(h, STAR_K1) if domain == "star5" else h
+    return box_case("%s%d" % (domain, n), FF_DOMAINS[domain](), -2.0, 2.0, n, 2 * n, k1=k1)
+
+
 def cfg_kite(n=2048):
     return fitted_case("kite%d" % n, kite(0.65, 1.5), n)
 

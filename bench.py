@@ -64,6 +64,9 @@ def parse():
     ap.add_argument("--nf", type=int, default=128, help="fields per step")
     ap.add_argument("--n", type=int, default=1024)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched Fourier-Forwarding measurement")
+    ap.add_argument("--ff-fields", type=int, default=128, help="fields per (grid size) in the batched run")
+    ap.add_argument("--ff-steps", type=int, default=100)
     ap.add_argument("--cpu-sample-fields", type=int, default=96)
     ap.add_argument("--col-tile", type=int, default=0, help="columns per block of the column FFT pass (0 = default)")
     ap.add_argument("--strip-fields", type=int, default=-1, help="fields per thread of the strip kernel (-1 = default)")
@@ -114,6 +117,58 @@ def cpu_baseline(case, nf_sample):
     return {"value": nf_sample * case.n * case.n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
             "sample": "%d fields of the %dx%d star workload (plan excluded), extend + rfft2, one thread"
                       % (nf_sample, case.n, case.n)}
+
+
+def run_batched(args):
+    """Batched Fourier Forwarding: 4 domains x 4 grid sizes, ff_fields fields per
+    size (domains round-robin), Gaussian pulses, 100 steps of dt = 0.01, c = 1,
+    one HIP-graph replay per step, autotuned launch shapes."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2010_03901_amd import fc2d
+    sizes = [256, 512, 1024, 2048]
+    doms = list(W.FF_DOMAINS)
+    plans, nf, cases = [], [], []
+    t0 = time.perf_counter()
+    for n in sizes:
+        for k, dom in enumerate(doms):
+            m = args.ff_fields // len(doms) + (1 if k < args.ff_fields % len(doms) else 0)
+            case = W.cfg_ff(dom, n)
+            grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+            plans.append(fc2d.Plan(fc2d.make_curve(*case.curve), grid, d=case.d, C_=case.C, B=case.B, k1=case.k1,
+                                   M=case.M))
+            nf.append(m)
+            cases.append(case)
+    plan_s = time.perf_counter() - t0
+    batch = fc2d.Batch(plans, nf, autotune=True)
+    # initial data: seeded Gaussian pulses inside each domain, u_t = 0 (built on the device)
+    for k, (case, m) in enumerate(zip(cases, nf)):
+        u, ut = batch.state(k)
+        x = case.x0 + torch.arange(case.n, device="cuda:0", dtype=torch.float64) * case.h
+        for f in range(m):
+            _, (xc, yc, sig) = W.gaussian_pulse(case.curve, 1000 * k + f)
+            u[f].copy_(torch.exp(-((x[:, None] - xc) ** 2 + (x[None, :] - yc) ** 2) / sig ** 2))
+        ut.zero_()
+    torch.cuda.synchronize()
+    pts, _, sf = batch.info()
+    batch.ff_run(1.0, 0.01, 1, use_graph=True)          # capture + warm-up
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    batch.ff_run(1.0, 0.01, args.ff_steps, use_graph=True)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.ff_steps
+    _, nl, _ = batch.info()
+    tiles = {n: fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_TILE, n) for n in sizes}
+    batch.close()
+    return {"points_per_s": pts / (ms * 1e-3), "ms_per_step": ms, "points_per_step": pts,
+            "fields": int(sum(nf)), "steps": args.ff_steps, "dt": 0.01, "launches_per_step": nl, "graph": True,
+            "autotuned": {"col_tile": tiles, "strip_fields_per_thread": sf}, "plan_s": plan_s,
+            "workload": "disc, star5, kite(0.65,1.5), ellipse(1,0.5) on [-2,2]^2 at 256^2..2048^2, "
+                        "Gaussian pulses, u and u_t extended each step"}
 
 
 def main():
@@ -211,6 +266,15 @@ def main():
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_ms": dk["avg_ms"]}
     print("[bench] kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
 
+    batched = None
+    if not args.no_batched:
+        print("[bench] batched Fourier Forwarding ...", file=sys.stderr, flush=True)
+        del fg, fb, ext, spec
+        torch.cuda.empty_cache()
+        batched = run_batched(args)
+        print("[bench] batched: %.3f ms/step, %.3e points/s" % (batched["ms_per_step"], batched["points_per_s"]),
+              file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -228,6 +292,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,
+        "batched_ff": batched,
         "plan_s": plan_s,
     }
     print(json.dumps(out))

@@ -47,6 +47,31 @@ enum { FC2D_FORWARD = -1, FC2D_INVERSE = 1 };
 enum { FC2D_LAPLACE_INV = 1, FC2D_DX = 2, FC2D_DY = 3 };
 enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2 };
 
+/* How the foot-of-normal solve of each grid point near Gamma is started
+ * (fc2d_opts.seed):
+ *  PROXIMITY  every boundary sample marks the grid points within C k1 of it
+ *             (the proximity map of Sec. 3.3, reduced to the nearest sample),
+ *             the seed is T(tau) over the normals of S_{theta_p} (Sec. 3.4);
+ *             any curve; points away from Gamma are classified by the
+ *             crossing parity of their grid column.
+ *  POLAR      polar curves only: points with rho - r(phi) in a band around
+ *             Gamma (phi = atan2(y, x)) are solved from the seed phi; the
+ *             others are IN (rho < r(phi)) or FAR.
+ *  MLP        as POLAR, but the seed comes from the learned network
+ *             (fc2d_opts.mlp_weights) followed by two plain Newton steps;
+ *             the root is kept when the residual |g / g'| after them is at
+ *             most mlp_tol, g' > 0 and it lies within the exterior reach,
+ *             otherwise the point falls back to the bracketed solve of POLAR.
+ * All three give the same classes and STRIP list, and feet equal to rounding. */
+enum { FC2D_SEED_PROXIMITY = 0, FC2D_SEED_POLAR = 1, FC2D_SEED_MLP = 2 };
+
+/* The learned seed network: 8 inputs, three hidden layers of 64 tanh units, 2
+ * linear outputs, float32 weights stored flat layer by layer, each layer as W
+ * (row-major [fan_in][fan_out]) followed by its bias. */
+#define FC2D_MLP_NIN 8
+#define FC2D_MLP_HIDDEN 64
+#define FC2D_MLP_NW 9026
+
 /* Boundary Gamma as a smooth 2 pi-periodic counter-clockwise curve q(theta)
  * (eq. param).  Series s(t) = s0 + sum_{m=1..nmodes} (s_{2m-1} cos mt + s_{2m} sin mt),
  * arrays of 1 + 2 nmodes doubles:
@@ -78,6 +103,9 @@ typedef struct {
     int n_os;          /* oversampling factor (eq. q_over) */
     int mf;            /* band limit of the trigonometric fit (eq. auxi_trig_poly) */
     int newton_maxit;  /* cap on foot-of-normal iterations (failure testing); 0 -> 60 */
+    int seed;          /* FC2D_SEED_*; 0 -> PROXIMITY */
+    double mlp_tol;    /* MLP seed: residual threshold; 0 -> 1e-13; < 0 -> every point falls back */
+    const float* mlp_weights;   /* MLP seed: FC2D_MLP_NW floats, host memory (copied) */
 } fc2d_opts;
 
 typedef struct fc2d_plan fc2d_plan;
@@ -88,7 +116,11 @@ typedef struct {
     int64_t n_bdry;     /* B feet + squares: length of f_bdry */
     int64_t n_strip;    /* grid points with 0 < eta <= C k1 */
     int64_t n_in, n_far;
-    int newton_max_iters;
+    int newton_max_iters;   /* most Newton steps taken by a STRIP point */
+    int seed;               /* FC2D_SEED_* the plan was built with */
+    int64_t n_solved;       /* grid points whose foot was solved (candidates near Gamma) */
+    int64_t n_fallback;     /* MLP seed: points that took the bracketed fallback */
+    int64_t newton_iters;   /* Newton steps summed over the solved points */
 } fc2d_plan_info;
 
 void fc2d_opts_default(const fc2d_grid* grid, fc2d_opts* opts);
@@ -222,6 +254,50 @@ int fc2d_batch_info(const fc2d_batch* batch, int64_t* points_per_step, int* laun
  * replayed. */
 int fc2d_batch_ff_run(fc2d_batch* batch, double c, double dt, int steps, int use_graph, hipStream_t stream);
 int fc2d_batch_destroy(fc2d_batch* batch);
+
+/* ---- Learned foot-of-normal seed: training data, training, inference ----
+ * Not part of the paper's method; see FC2D_SEED_MLP.  For a point Q =
+ * rho (cos phi, sin phi) near the polar curve r(t) and strip width w = C k1 the
+ * network's inputs are (R_k = r^(k)(phi)):
+ *   f0 = (rho - R_0)/w, f1 = R_0 - 1, f2 = R_1/R_0, f3..f6 = R_k/(R_0 S_k) for
+ *   k = 2..5 with S = (2, 10, 60, 400), f7 = f0 f2 / (1 + f2^2);
+ * its outputs are 100 (delta/w - f7/R_0, eta/w - f0/sqrt(1 + f2^2)), delta =
+ * theta^Q - phi, i.e. what one Newton step from phi leaves out, and the seed is
+ * theta^(0) = phi + w (f7/R_0 + out_0/100). */
+
+/* Training pairs from the method's own foot solves.  curves: device
+ * [ncurves][1 + 2 nmodes] polar coefficients (nmodes <= 16, r > 0); sample k
+ * is the point q(theta[k]) + eta[k] n(theta[k]) of curve cidx[k] (device
+ * arrays of n), whose foot is solved from the seed phi by the bracketed Newton.
+ * Outputs (device): X [n][8] float, Y [n][2] float (features and targets for
+ * width w), foot [n][2] float64 (theta^Q in [0, 2 pi), eta_Q; may be NULL),
+ * iters [n] (Newton steps; -1 where the solve failed or cidx[k] is not in
+ * [0, ncurves), whose other outputs are then left untouched; may be NULL). */
+int fc2d_mlp_make_data(const double* curves, int ncurves, int nmodes, const int32_t* cidx,
+                       const double* theta, const double* eta, int64_t n, double width,
+                       float* X, float* Y, double* foot, int32_t* iters, hipStream_t stream);
+
+/* Network outputs out [n][2] for inputs X [n][8] (device float). */
+int fc2d_mlp_forward(const float* weights, const float* X, int64_t n, float* out, hipStream_t stream);
+
+/* Loss 0.5 mean |net(X) - Y|^2 over the n samples and its gradient with
+ * respect to the weights (device float: grad [FC2D_MLP_NW], loss [1]; either
+ * may be NULL).  Partial sums per 64 samples are added in a fixed order, so
+ * results are reproducible.  Synchronises the stream (releases work space). */
+int fc2d_mlp_loss_grad(const float* weights, const float* X, const float* Y, int64_t n,
+                       float* grad, float* loss, hipStream_t stream);
+
+/* `steps` Adam steps (beta 0.9 / 0.999, eps 1e-8) on minibatches of `batch`
+ * samples of (X, Y) (n samples, device).  Step s uses Adam step number
+ * t = t0 + s + 1 and learning rate lr_min + (lr0 - lr_min)(1 + cos(pi t / t_total))/2
+ * (t capped at t_total); its samples are positions t-1 batch ... of an endless
+ * sequence that visits every sample once per pass, in an order that changes
+ * from pass to pass.  weights, adam_m, adam_v: device float [FC2D_MLP_NW],
+ * updated in place (moments start at zero).  loss_hist (device float [steps],
+ * may be NULL) receives each step's minibatch loss.  Synchronises the stream. */
+int fc2d_mlp_train(float* weights, float* adam_m, float* adam_v, const float* X, const float* Y, int64_t n,
+                   int batch, int steps, int64_t t0, float lr0, float lr_min, int64_t t_total,
+                   float* loss_hist, hipStream_t stream);
 
 const char* fc2d_strerror(int status);
 const char* fc2d_last_error(void);

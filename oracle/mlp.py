@@ -1,45 +1,90 @@
 """Reference multilayer perceptron for the learned foot-of-normal seed (oracle side).
 
-Not part of the paper: a small network maps (x, y, curve descriptors) of a
-point near Gamma to a guess of its foot of the normal, which then seeds the
-Newton solve of Sec. 3.4.  Architecture: 16 inputs, three hidden layers of 64
-tanh units, 2 linear outputs; weights stored flat, layer by layer, each layer
-as W (row-major [fan_in][fan_out]) followed by b [fan_out].
+TEST INFRASTRUCTURE ONLY: this module is the float64 reference that the
+library's FP32 training and inference kernels are checked against.  It is not
+part of the paper: a small network maps a point near a polar curve to a guess
+of its foot of the normal, which then seeds the Newton solve of Sec. 3.4.
 
-Features of a point (x, y) near a curve r(t) = 1 + sum_{m=2..8} (a_m cos mt + b_m sin mt):
-    (x, y, a_2 s_2, b_2 s_2, ..., a_8 s_8, b_8 s_8),  s_m = m / 0.15
-Targets: (delta / DELTA_SCALE, eta / width) with delta = theta^Q - atan2(y, x)
-wrapped to (-pi, pi] and eta the signed distance; width = C k1 of the strip.
-Loss: mean over the batch of 0.5 |out - target|^2.
+Architecture: 8 inputs, three hidden layers of 64 tanh units, 2 linear
+outputs.  Weights are stored flat, layer by layer, each layer as W (row-major
+[fan_in][fan_out]) followed by b [fan_out].
 
-This module computes in float64 and is the reference for the library's FP32
-forward / backward kernels.
+Features.  For a polar curve r(t) = c_0 + sum_m (a_m cos mt + b_m sin mt) and a
+point Q = rho (cos phi, sin phi) (phi = atan2(y, x)), the foot depends on Q
+and the curve only through rho and the derivatives R_k = r^(k)(phi): rotating
+the picture by -phi changes neither.  With w the strip width C k1:
+    f0 = (rho - R_0) / w                 radial offset in strip widths
+    f1 = R_0 - 1
+    f2 = R_1 / R_0
+    f3..f6 = R_k / (R_0 S_k), k = 2..5   (S_k = 2, 10, 60, 400)
+    f7 = f0 f2 / (1 + f2^2)              the first-order Newton step from phi, / w
+Targets.  With delta = theta^Q - phi wrapped to (-pi, pi] and eta the signed
+distance, one Newton step on g(t) = (q(t) - Q) . q'(t) from t = phi gives the
+first-order estimates  delta / w ~ f7 / R_0  and  eta / w ~ f0 / sqrt(1 + f2^2);
+the network learns what these miss, scaled by TARGET_SCALE:
+    target = TARGET_SCALE (delta / w - f7 / R_0,  eta / w - f0 / sqrt(1 + f2^2)).
+Loss: mean over the batch of 0.5 |out - target|^2.  The Newton seed is
+    theta^(0) = phi + w (f7 / R_0 + out_0 / TARGET_SCALE).
 """
 import math
 
 import numpy as np
 
-LAYERS = [(16, 64), (64, 64), (64, 64), (64, 2)]
+NIN = 8
+LAYERS = [(NIN, 64), (64, 64), (64, 64), (64, 2)]
 NW = sum(i * o + o for i, o in LAYERS)
-DELTA_SCALE = 0.05
-DESC_SCALE = 1.0 / 0.15
+DERIV_SCALE = (1.0, 1.0, 2.0, 10.0, 60.0, 400.0)
+TARGET_SCALE = 100.0
 
 
-def features(x, y, desc):
-    """desc [14] = (a_2, b_2, ..., a_8, b_8); returns [n, 16]."""
-    x = np.asarray(x, dtype=np.float64)
-    y = np.asarray(y, dtype=np.float64)
-    d = np.asarray(desc, dtype=np.float64).reshape(7, 2) * (np.arange(2, 9)[:, None] * DESC_SCALE)
-    out = np.empty((x.size, 16))
-    out[:, 0] = x.ravel()
-    out[:, 1] = y.ravel()
-    out[:, 2:] = d.ravel()[None, :]
+def polar_derivatives(coef, t, kmax=5):
+    """r^(k)(t) for k = 0..kmax of r = c0 + sum_m (a_m cos mt + b_m sin mt),
+    coef = [c0, a1, b1, a2, b2, ...].  Uses d^k/dt^k cos(mt) = m^k cos(mt + k pi/2)
+    and likewise for sin."""
+    t = np.asarray(t, dtype=np.float64)
+    out = np.zeros((kmax + 1,) + t.shape)
+    out[0] += coef[0]
+    nm = (len(coef) - 1) // 2
+    for m in range(1, nm + 1):
+        a, b = coef[2 * m - 1], coef[2 * m]
+        for k in range(kmax + 1):
+            ph = m * t + k * math.pi / 2
+            out[k] += float(m) ** k * (a * np.cos(ph) + b * np.sin(ph))
     return out
 
 
-def targets(x, y, theta, eta, width):
+def features(x, y, coef, width):
+    """Points (x, y) near the polar curve coef -> [n, 8] features."""
+    x = np.asarray(x, dtype=np.float64).ravel()
+    y = np.asarray(y, dtype=np.float64).ravel()
+    phi = np.arctan2(y, x)
+    rho = np.hypot(x, y)
+    R = polar_derivatives(coef, phi)
+    f = np.empty((x.size, NIN))
+    f[:, 0] = (rho - R[0]) / width
+    f[:, 1] = R[0] - 1.0
+    f[:, 2] = R[1] / R[0]
+    for k in range(2, 6):
+        f[:, k + 1] = R[k] / (R[0] * DERIV_SCALE[k])
+    f[:, 7] = f[:, 0] * f[:, 2] / (1.0 + f[:, 2] ** 2)
+    return f
+
+
+def first_order(F):
+    """First-order estimates (delta / w, eta / w) from the features [n, 8]."""
+    return np.stack([F[:, 7] / (1.0 + F[:, 1]), F[:, 0] / np.sqrt(1.0 + F[:, 2] ** 2)], axis=1)
+
+
+def targets(x, y, theta, eta, width, F):
+    """Training targets for points (x, y) with foot theta and distance eta; F their features."""
     delta = np.mod(theta - np.arctan2(y, x) + math.pi, 2 * math.pi) - math.pi
-    return np.stack([delta / DELTA_SCALE, eta / width], axis=1)
+    exact = np.stack([delta / width, eta / width], axis=1)
+    return TARGET_SCALE * (exact - first_order(F))
+
+
+def seed_theta(out, x, y, width, F):
+    """Network output -> Newton seed theta^(0)."""
+    return np.arctan2(y, x) + width * (first_order(F)[:, 0] + out[:, 0] / TARGET_SCALE)
 
 
 def unpack(w):

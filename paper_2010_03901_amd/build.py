@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp"]
-HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip"]
+HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip", "kernels_mlp.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

@@ -46,6 +46,8 @@ struct fc2d_plan {
     std::vector<double> strip_theta, strip_eta;
     int newton_max_iters = 0;
     int64_t n_in = 0, n_far = 0;
+    int seed = 0;
+    int64_t n_solved = 0, n_fallback = 0, newton_iters = 0;
     // device
     double* d_Q = nullptr;          // [d][d]
     double* d_Ar = nullptr;         // [Cr][d]
@@ -91,6 +93,27 @@ struct StripRec {
 // foot failures, counters[2] = max iterations.
 int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64_t cap,
                     uint64_t* d_near, int* d_counters, hipStream_t s);
+
+// Seeds from the polar angle (FC2D_SEED_POLAR, FC2D_SEED_MLP).
+struct SeedArgs {
+    CurveC curve;                 // polar
+    double x0, y0, h;
+    int nx, ny;
+    int B, maxit;
+    double k2;
+    double band_lo, band_hi;      // candidates: band_lo <= rho - r(phi) <= band_hi
+    double width;                 // C k1
+    double dist2_max;             // MLP roots farther than this (squared) from Q are rejected
+    double mlp_tol;               // residual threshold after the two MLP-seeded steps
+};
+// counters: [0] STRIP records, [1] failed solves, [2] most Newton steps of a
+// STRIP point, [3] candidates, [4] fallbacks, [5] Newton steps summed.
+int launch_radial_band(const SeedArgs& a, int8_t* d_cls, int32_t* d_cand, int64_t cap, int* d_counters,
+                       hipStream_t s);
+int launch_seed_polar(const SeedArgs& a, const int32_t* d_cand, int64_t ncand, int8_t* d_cls, StripRec* d_rec,
+                      int64_t cap, int* d_counters, hipStream_t s);
+int launch_seed_mlp(const SeedArgs& a, const float* d_w, const int32_t* d_cand, int64_t ncand, int8_t* d_cls,
+                    StripRec* d_rec, int64_t cap, int* d_counters, hipStream_t s);
 
 // ---- batches: one descriptor per (plan, field set) for the persistent kernels ----
 struct PlanDev {

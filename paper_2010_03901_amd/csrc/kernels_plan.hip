@@ -10,9 +10,13 @@
 //    within r_out, inside within r_in of their nearest sample) solve for the
 //    foot (theta^Q, eta_Q) from the seed p and are reclassified by eta:
 //    IN (eta <= 0), STRIP (0 < eta <= C k1), FAR.  STRIP points append a record.
+//  k_radial_band / k_seed_polar (polar curves): rho - r(phi) decides IN / FAR
+//    away from Gamma and selects the candidates near it, which are compacted
+//    into a list and solved from the seed phi = atan2(y, x), one thread each.
 #include <hip/hip_runtime.h>
 
 #include "internal.h"
+#include "seed_dev.h"
 
 namespace fc2d {
 
@@ -73,30 +77,66 @@ __global__ __launch_bounds__(256) void k_classify(ClassifyArgs a, const uint64_t
             double th = 0.0, eta = 0.0;
             int it = 0;
             const int stt = foot_solve<M>(a.curve, bd, X, Y, p, a.maxit, &th, &eta, &it);
-            if (stt != FOOT_OK) {
-                atomicAdd(&counters[1], 1);
-            } else {
-                // within rounding distance of Gamma counts as on Gamma: IN
-                const double on_tol = 1e-13 * (1.0 + fabs(X) + fabs(Y));
-                c = eta <= on_tol ? 1 : (eta <= a.width ? 2 : 0);
-                if (c == 2) {
-                    const int slot = atomicAdd(&counters[0], 1);
-                    if (slot < cap) {
-                        StripRec r;
-                        r.idx = (int32_t)idx;
-                        r.seed = p;
-                        r.iters = it;
-                        r.pad = 0;
-                        r.theta = th;
-                        r.eta = eta;
-                        rec[slot] = r;
-                    }
-                    atomicMax(&counters[2], it);
-                }
-            }
+            atomicAdd(&counters[3], 1);
+            store_solved(idx, X, Y, stt, th, eta, it, p, a.width, cls, rec, cap, counters);
+            return;
         }
     }
     cls[idx] = c;
+}
+
+// r(phi) of a polar curve at the point (X, Y) = rho (cos phi, sin phi), with
+// cos m phi, sin m phi by the angle-addition recurrence from X / rho, Y / rho
+__device__ inline double polar_radius_at(const CurveC& cv, double X, double Y, double rho) {
+    const double c1 = X / rho, s1 = Y / rho;
+    double cm = 1.0, sm = 0.0, r = cv.a[0];
+    for (int m = 1; m <= cv.nmodes; ++m) {
+        const double cn = cm * c1 - sm * s1;
+        sm = sm * c1 + cm * s1;
+        cm = cn;
+        r += cv.a[2 * m - 1] * cm + cv.a[2 * m] * sm;
+    }
+    return r;
+}
+
+__global__ __launch_bounds__(256) void k_radial_band(SeedArgs a, int8_t* cls, int32_t* cand, int64_t cap,
+                                                     int* counters) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= (int64_t)a.nx * a.ny) return;
+    const int i = (int)(idx / a.ny);
+    const int j = (int)(idx - (int64_t)i * a.ny);
+    const double X = a.x0 + i * a.h;
+    const double Y = a.y0 + j * a.h;
+    const double rho = sqrt(X * X + Y * Y);
+    int8_t c;
+    if (rho == 0.0) {
+        c = 1;   // the origin is inside a polar domain
+    } else {
+        const double dr = rho - polar_radius_at(a.curve, X, Y, rho);
+        if (dr >= a.band_lo && dr <= a.band_hi) {
+            const int slot = atomicAdd(&counters[3], 1);
+            if (slot < cap) cand[slot] = (int32_t)idx;
+            c = 3;   // pending: written by the seed kernel
+        } else {
+            c = dr < 0 ? 1 : 0;
+        }
+    }
+    cls[idx] = c;
+}
+
+__global__ __launch_bounds__(256) void k_seed_polar(SeedArgs a, const int32_t* __restrict__ cand, int64_t ncand,
+                                                    int8_t* cls, StripRec* rec, int64_t cap, int* counters) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= ncand) return;
+    const int64_t idx = cand[k];
+    const int i = (int)(idx / a.ny);
+    const int j = (int)(idx - (int64_t)i * a.ny);
+    const double X = a.x0 + i * a.h;
+    const double Y = a.y0 + j * a.h;
+    double th = 0.0, eta = 0.0;
+    int it = 0;
+    const int st = foot_from_seed(a.curve, X, Y, atan2(Y, X), 2.0 * a.k2, a.maxit, &th, &eta, &it);
+    store_solved(idx, X, Y, st, th, eta, it, nearest_sample(th, a.k2, a.B), a.width, cls, rec, cap, counters);
 }
 
 __global__ void k_zero_int(int* p, int n) {
@@ -106,7 +146,7 @@ __global__ void k_zero_int(int* p, int n) {
 int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64_t cap, uint64_t* d_near,
                     int* d_counters, hipStream_t s) {
     const int64_t npts = (int64_t)a.nx * a.ny;
-    k_zero_int<<<1, 64, 0, s>>>(d_counters, 4);
+    k_zero_int<<<1, 64, 0, s>>>(d_counters, 8);
     k_fill_u64<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(d_near, npts, ~0ull);
     k_near_scatter<<<a.B, 256, 0, s>>>(a, d_near);
     const unsigned nb = (unsigned)((npts + 255) / 256);
@@ -124,6 +164,34 @@ int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64
         return FC2D_E_HIP;
     }
     trace_point("k_classify", s);
+    return FC2D_OK;
+}
+
+static int launch_status(const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) {
+        set_error(std::string(what) + ": " + hipGetErrorString(e));
+        return FC2D_E_HIP;
+    }
+    return FC2D_OK;
+}
+
+int launch_radial_band(const SeedArgs& a, int8_t* d_cls, int32_t* d_cand, int64_t cap, int* d_counters,
+                       hipStream_t s) {
+    const int64_t npts = (int64_t)a.nx * a.ny;
+    k_zero_int<<<1, 64, 0, s>>>(d_counters, 8);
+    k_radial_band<<<(unsigned)((npts + 255) / 256), 256, 0, s>>>(a, d_cls, d_cand, cap, d_counters);
+    if (int st = launch_status("radial band launch")) return st;
+    trace_point("k_radial_band", s);
+    return FC2D_OK;
+}
+
+int launch_seed_polar(const SeedArgs& a, const int32_t* d_cand, int64_t ncand, int8_t* d_cls, StripRec* d_rec,
+                      int64_t cap, int* d_counters, hipStream_t s) {
+    if (ncand <= 0) return FC2D_OK;
+    k_seed_polar<<<(unsigned)((ncand + 255) / 256), 256, 0, s>>>(a, d_cand, ncand, d_cls, d_rec, cap, d_counters);
+    if (int st = launch_status("polar seed launch")) return st;
+    trace_point("k_seed_polar", s);
     return FC2D_OK;
 }
 

@@ -380,6 +380,15 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         if (opts_in->n_os > 0) o.n_os = opts_in->n_os;
         if (opts_in->mf > 0) o.mf = opts_in->mf;
         if (opts_in->newton_maxit > 0) o.newton_maxit = opts_in->newton_maxit;
+        o.seed = opts_in->seed;
+        if (opts_in->mlp_tol != 0.0) o.mlp_tol = opts_in->mlp_tol < 0.0 ? -1.0 : opts_in->mlp_tol;
+        o.mlp_weights = opts_in->mlp_weights;
+    }
+    if (o.seed < FC2D_SEED_PROXIMITY || o.seed > FC2D_SEED_MLP ||
+        (o.seed != FC2D_SEED_PROXIMITY && curve->kind != FC2D_CURVE_POLAR) ||
+        (o.seed == FC2D_SEED_MLP && !o.mlp_weights)) {
+        set_error("invalid seed option (POLAR and MLP need a polar curve, MLP needs weights)");
+        return FC2D_E_ARG;
     }
     if (o.M <= 0) o.M = d + 3;
     if (d < 2 || d > 12 || C < 2 || o.M < 4 || o.M > 8 || o.M < d - 1 || grid->h <= 0 || grid->nx < 8 ||
@@ -396,6 +405,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     pl->d = d; pl->C = C; pl->M = o.M; pl->n_r = o.n_r; pl->Cr = C * o.n_r; pl->B = o.B;
     pl->k1 = o.k1;
     pl->k2 = 2.0 * M_PI / o.B;
+    pl->seed = o.seed;
     memset(&pl->curve, 0, sizeof pl->curve);
     pl->curve.kind = curve->kind;
     pl->curve.nmodes = curve->nmodes;
@@ -419,6 +429,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         spmax = std::max(spmax, sp);
     }
     // admissibility: exterior reach and the box
+    double reach_ext = INFINITY;
     {
         const int ns = 16 * B;
         double kmin = 0.0;   // most negative curvature
@@ -429,7 +440,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             const double kap = (v[2] * v[5] - v[3] * v[4]) / (s2 * sqrt(s2));
             kmin = std::min(kmin, kap);
         }
-        const double reach_ext = kmin < 0 ? 1.0 / -kmin : INFINITY;
+        reach_ext = kmin < 0 ? 1.0 / -kmin : INFINITY;
         if (C * pl->k1 > 0.9 * reach_ext) {
             char buf[160];
             snprintf(buf, sizeof buf, "C k1 = %.4g exceeds 0.9 x exterior reach %.4g", C * pl->k1, reach_ext);
@@ -451,10 +462,10 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                 }
         }
     }
-    // column crossings of the 16 B-vertex polygon (parity test)
+    // column crossings of the 16 B-vertex polygon (parity test of the proximity seed)
     std::vector<int32_t> col_ptr(grid->nx + 1, 0);
     std::vector<double> col_y;
-    {
+    if (o.seed == FC2D_SEED_PROXIMITY) {
         const int nv = 16 * B;
         std::vector<double> px(nv), py(nv);
         for (int k = 0; k < nv; ++k) {
@@ -498,46 +509,105 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     int8_t* d_cls = nullptr;
     StripRec* d_rec = nullptr;
     uint64_t* d_near = nullptr;
+    int32_t* d_cand = nullptr;
+    float* d_w = nullptr;
     int* d_cnt = nullptr;
     // capacity for STRIP records: twice the area of a band of width r_out
     // along the boundary, plus a margin of a few grid rows
-    double perim = 0.0;
+    double perim = 0.0, rmin = INFINITY, rmax = 0.0, slope = 0.0;
     for (int p = 0; p < B; ++p) {
         double v[6];
         curve_eval(pl->curve, p * pl->k2, v);
         perim += sqrt(v[2] * v[2] + v[3] * v[3]) * pl->k2;
+        if (pl->curve.kind == FC2D_CURVE_POLAR) {
+            double r, r1, r2;
+            series3(pl->curve.a, pl->curve.nmodes, p * pl->k2, &r, &r1, &r2);
+            rmin = std::min(rmin, r);
+            rmax = std::max(rmax, r);
+            slope = std::max(slope, fabs(r1) / r);
+        }
     }
     const double hh = grid->h;
     int64_t cap = std::min<int64_t>(
         npts, (int64_t)(2.0 * perim * ca.r_out / (hh * hh) + 4.0 * perim / hh) + 4096);
+    // polar seeds: candidates have rho - r(phi) in [band_lo, band_hi].  To first
+    // order rho - r(phi) = eta sqrt(1 + (r'/r)^2); the band takes 1.25 times
+    // that for the outer search radius plus two grid steps, and inside only
+    // points within rounding distance of Gamma (the rest are IN).
+    SeedArgs sa;
+    memset(&sa, 0, sizeof sa);
+    int64_t cap_cand = 0;
+    if (o.seed != FC2D_SEED_PROXIMITY) {
+        if (!(rmin > 0.0)) {
+            set_error("polar seeds need r(t) > 0");
+            free_plan(pl);
+            return FC2D_E_ARG;
+        }
+        sa.curve = pl->curve;
+        sa.x0 = grid->x0; sa.y0 = grid->y0; sa.h = grid->h; sa.nx = grid->nx; sa.ny = grid->ny;
+        sa.B = B; sa.maxit = o.newton_maxit; sa.k2 = pl->k2;
+        sa.band_hi = 1.25 * ca.r_out * sqrt(1.0 + slope * slope) + 2.0 * hh;
+        sa.band_lo = -1e-12 * (1.0 + rmax);
+        sa.width = ca.width;
+        const double dmax = std::min(sa.band_hi, 0.99 * reach_ext);
+        sa.dist2_max = dmax * dmax;
+        sa.mlp_tol = o.mlp_tol;
+        cap_cand = std::min<int64_t>(
+            npts, (int64_t)(2.0 * perim * (sa.band_hi - sa.band_lo) / (hh * hh) + 4.0 * perim / hh) + 4096);
+    }
     std::vector<StripRec> rec;
-    int cnt[3] = {0, 0, 0};
+    int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto cleanup = [&]() {
-        void* ps[] = {d_bx, d_by, d_bnx, d_bny, d_coly, d_colptr, d_cls, d_rec, d_near, d_cnt};
+        void* ps[] = {d_bx, d_by, d_bnx, d_bny, d_coly, d_colptr, d_cls, d_rec, d_near, d_cand, d_w, d_cnt};
         for (void* q : ps)
             if (q) (void)hipFree(q);
     };
     st = FC2D_OK;
     do {
-        if ((st = dev_upload(&d_bx, pl->bx.data(), B))) break;
-        if ((st = dev_upload(&d_by, pl->by.data(), B))) break;
-        if ((st = dev_upload(&d_bnx, pl->bnx.data(), B))) break;
-        if ((st = dev_upload(&d_bny, pl->bny.data(), B))) break;
-        if ((st = dev_upload(&d_colptr, col_ptr.data(), col_ptr.size()))) break;
-        if (!col_y.empty() && (st = dev_upload(&d_coly, col_y.data(), col_y.size()))) break;
         if (hipMalloc((void**)&d_cls, npts) != hipSuccess || hipMalloc((void**)&d_rec, cap * sizeof(StripRec)) != hipSuccess ||
-            hipMalloc((void**)&d_near, npts * sizeof(uint64_t)) != hipSuccess ||
-            hipMalloc((void**)&d_cnt, 4 * sizeof(int)) != hipSuccess) {
+            hipMalloc((void**)&d_cnt, 8 * sizeof(int)) != hipSuccess) {
             set_error("hipMalloc failed (classification work space)");
             st = FC2D_E_NOMEM;
             break;
         }
-        ca.bx = d_bx; ca.by = d_by; ca.bnx = d_bnx; ca.bny = d_bny;
-        ca.col_ptr = d_colptr; ca.col_y = d_coly;
-        if ((st = launch_classify(ca, d_cls, d_rec, cap, d_near, d_cnt, stream))) break;
-        hipError_t e = hipStreamSynchronize(stream);
+        hipError_t e;
+        if (o.seed == FC2D_SEED_PROXIMITY) {
+            if ((st = dev_upload(&d_bx, pl->bx.data(), B))) break;
+            if ((st = dev_upload(&d_by, pl->by.data(), B))) break;
+            if ((st = dev_upload(&d_bnx, pl->bnx.data(), B))) break;
+            if ((st = dev_upload(&d_bny, pl->bny.data(), B))) break;
+            if ((st = dev_upload(&d_colptr, col_ptr.data(), col_ptr.size()))) break;
+            if (!col_y.empty() && (st = dev_upload(&d_coly, col_y.data(), col_y.size()))) break;
+            if (hipMalloc((void**)&d_near, npts * sizeof(uint64_t)) != hipSuccess) {
+                set_error("hipMalloc failed (proximity map)");
+                st = FC2D_E_NOMEM;
+                break;
+            }
+            ca.bx = d_bx; ca.by = d_by; ca.bnx = d_bnx; ca.bny = d_bny;
+            ca.col_ptr = d_colptr; ca.col_y = d_coly;
+            if ((st = launch_classify(ca, d_cls, d_rec, cap, d_near, d_cnt, stream))) break;
+        } else {
+            if (hipMalloc((void**)&d_cand, cap_cand * sizeof(int32_t)) != hipSuccess) {
+                set_error("hipMalloc failed (candidate list)");
+                st = FC2D_E_NOMEM;
+                break;
+            }
+            if (o.seed == FC2D_SEED_MLP && (st = dev_upload(&d_w, o.mlp_weights, FC2D_MLP_NW))) break;
+            if ((st = launch_radial_band(sa, d_cls, d_cand, cap_cand, d_cnt, stream))) break;
+            if ((e = hipMemcpyAsync(cnt, d_cnt, 8 * sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+                (e = hipStreamSynchronize(stream)) != hipSuccess) {
+                st = hip_fail(e, "radial band");
+                break;
+            }
+            if (cnt[3] > cap_cand) { set_error("candidate capacity exceeded"); st = FC2D_E_GEOMETRY; break; }
+            st = o.seed == FC2D_SEED_MLP
+                     ? launch_seed_mlp(sa, d_w, d_cand, cnt[3], d_cls, d_rec, cap, d_cnt, stream)
+                     : launch_seed_polar(sa, d_cand, cnt[3], d_cls, d_rec, cap, d_cnt, stream);
+            if (st) break;
+        }
+        e = hipStreamSynchronize(stream);
         if (e != hipSuccess) { st = hip_fail(e, "classification kernels"); break; }
-        if ((e = hipMemcpy(cnt, d_cnt, 3 * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
+        if ((e = hipMemcpy(cnt, d_cnt, 8 * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
         if (cnt[1] > 0) {
             char buf[128];
             snprintf(buf, sizeof buf, "foot of the normal failed at %d grid points", cnt[1]);
@@ -555,6 +625,9 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     if (st) { free_plan(pl); return st; }
     std::sort(rec.begin(), rec.end(), [](const StripRec& a, const StripRec& b) { return a.idx < b.idx; });
     pl->newton_max_iters = cnt[2];
+    pl->n_solved = cnt[3];
+    pl->n_fallback = cnt[4];
+    pl->newton_iters = cnt[5];
     pl->strip_idx.resize(rec.size()); pl->strip_seed.resize(rec.size());
     pl->strip_theta.resize(rec.size()); pl->strip_eta.resize(rec.size());
     for (size_t k = 0; k < rec.size(); ++k) {
@@ -645,6 +718,7 @@ void fc2d_opts_default(const fc2d_grid* grid, fc2d_opts* o) {
     if (!o) return;
     memset(o, 0, sizeof *o);
     o->n_r = 6; o->Z = 12; o->n_os = 20; o->mf = 20; o->newton_maxit = 60;
+    o->seed = FC2D_SEED_PROXIMITY; o->mlp_tol = 1e-13; o->mlp_weights = nullptr;
     o->M = 0;
     o->k1 = grid ? grid->h : 0.0;
     int B = 256;
@@ -678,6 +752,10 @@ int fc2d_plan_get_info(const fc2d_plan* pl, fc2d_plan_info* info) {
     info->n_strip = (int64_t)pl->strip_idx.size();
     info->n_in = pl->n_in; info->n_far = pl->n_far;
     info->newton_max_iters = pl->newton_max_iters;
+    info->seed = pl->seed;
+    info->n_solved = pl->n_solved;
+    info->n_fallback = pl->n_fallback;
+    info->newton_iters = pl->newton_iters;
     return FC2D_OK;
 }
 

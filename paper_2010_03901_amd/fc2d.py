@@ -23,6 +23,8 @@ FC2D_FORWARD, FC2D_INVERSE = -1, 1
 FC2D_LAPLACE_INV, FC2D_DX, FC2D_DY = 1, 2, 3
 FC2D_TUNE_COL_TILE, FC2D_TUNE_STRIP_FIELDS = 1, 2
 FC2D_BATCH_AUTOTUNE = 1
+FC2D_SEED_PROXIMITY, FC2D_SEED_POLAR, FC2D_SEED_MLP = 0, 1, 2
+FC2D_MLP_NIN, FC2D_MLP_HIDDEN, FC2D_MLP_NW = 8, 64, 9026
 
 FAR, IN, STRIP = 0, 1, 2
 
@@ -43,13 +45,15 @@ class fc2d_grid(C.Structure):
 
 class fc2d_opts(C.Structure):
     _fields_ = [("B", C.c_int), ("k1", C.c_double), ("M", C.c_int), ("n_r", C.c_int), ("Z", C.c_int),
-                ("n_os", C.c_int), ("mf", C.c_int), ("newton_maxit", C.c_int)]
+                ("n_os", C.c_int), ("mf", C.c_int), ("newton_maxit", C.c_int), ("seed", C.c_int),
+                ("mlp_tol", C.c_double), ("mlp_weights", C.POINTER(C.c_float))]
 
 
 class fc2d_plan_info(C.Structure):
     _fields_ = [("d", C.c_int), ("C", C.c_int), ("M", C.c_int), ("n_r", C.c_int), ("Cr", C.c_int), ("B", C.c_int),
                 ("k1", C.c_double), ("k2", C.c_double), ("n_bdry", C.c_int64), ("n_strip", C.c_int64),
-                ("n_in", C.c_int64), ("n_far", C.c_int64), ("newton_max_iters", C.c_int)]
+                ("n_in", C.c_int64), ("n_far", C.c_int64), ("newton_max_iters", C.c_int), ("seed", C.c_int),
+                ("n_solved", C.c_int64), ("n_fallback", C.c_int64), ("newton_iters", C.c_int64)]
 
 
 _LIB = None
@@ -88,6 +92,12 @@ def _lib():
             "fc2d_tune_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
             "fc2d_trace_begin": (C.c_int, [_P]),
             "fc2d_trace_end": (C.c_int, [C.POINTER(C.c_int), C.POINTER(C.c_char_p), C.POINTER(C.c_float), C.c_int]),
+            "fc2d_mlp_make_data": (C.c_int, [_P, C.c_int, C.c_int, _P, _P, _P, C.c_int64, C.c_double, _P, _P, _P,
+                                             _P, _P]),
+            "fc2d_mlp_forward": (C.c_int, [_P, _P, C.c_int64, _P, _P]),
+            "fc2d_mlp_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
+            "fc2d_mlp_train": (C.c_int, [_P, _P, _P, _P, _P, C.c_int64, C.c_int, C.c_int, C.c_int64, C.c_float,
+                                         C.c_float, C.c_int64, _P, _P]),
             "fc2d_strerror": (C.c_char_p, [C.c_int]),
             "fc2d_last_error": (C.c_char_p, []),
             "fc2d_version": (C.c_int, []),
@@ -156,15 +166,20 @@ class Plan:
     """Owning wrapper of fc2d_plan*."""
 
     def __init__(self, curve, grid, d=5, C_=27, B=None, k1=None, M=None, n_r=None, Z=None, n_os=None, mf=None,
-                 newton_maxit=None, stream=None):
+                 newton_maxit=None, seed=None, mlp_weights=None, mlp_tol=None, stream=None):
         lib = _lib()
         self.grid = grid
         opts = fc2d_opts()
         lib.fc2d_opts_default(C.byref(grid), C.byref(opts))
         for name, v in (("B", B), ("k1", k1), ("M", M), ("n_r", n_r), ("Z", Z), ("n_os", n_os), ("mf", mf),
-                        ("newton_maxit", newton_maxit)):
+                        ("newton_maxit", newton_maxit), ("seed", seed), ("mlp_tol", mlp_tol)):
             if v is not None:
                 setattr(opts, name, v)
+        if mlp_weights is not None:
+            wts = np.ascontiguousarray(mlp_weights, dtype=np.float32)
+            if wts.size != FC2D_MLP_NW:
+                raise ValueError("mlp_weights must hold %d floats" % FC2D_MLP_NW)
+            opts.mlp_weights = wts.ctypes.data_as(C.POINTER(C.c_float))
         h = C.c_void_p()
         _check(lib.fc2d_plan_create(C.byref(curve), C.byref(grid), int(d), int(C_), C.byref(opts),
                                     _stream(stream), C.byref(h)))
@@ -373,6 +388,60 @@ def fc2d_trace_end(cap=4096):
     ms = (C.c_float * cap)()
     _check(_lib().fc2d_trace_end(C.byref(n), names, ms, cap))
     return [(names[i].decode(), float(ms[i])) for i in range(n.value)]
+
+
+def fc2d_mlp_make_data(curves, cidx, theta, eta, width, X, Y, foot=None, iters=None, stream=None):
+    """Training pairs: curves [ncurves][1 + 2 nmodes] float64, cidx [n] int32,
+    theta / eta [n] float64 (device) -> X [n][8], Y [n][2] float32, foot [n][2]
+    float64, iters [n] int32 (device, optional)."""
+    import torch
+    ncurves, ncoef = curves.shape
+    n = cidx.numel()
+    if X.numel() != n * FC2D_MLP_NIN or Y.numel() != 2 * n or theta.numel() != n or eta.numel() != n:
+        raise ValueError("training-data array sizes disagree")
+    _check(_lib().fc2d_mlp_make_data(_dptr(curves, "curves", torch.float64), int(ncurves), (int(ncoef) - 1) // 2,
+                                     _dptr(cidx, "cidx", torch.int32), _dptr(theta, "theta", torch.float64),
+                                     _dptr(eta, "eta", torch.float64), int(n), float(width),
+                                     _dptr(X, "X", torch.float32), _dptr(Y, "Y", torch.float32),
+                                     _dptr(foot, "foot", torch.float64) if foot is not None else None,
+                                     _dptr(iters, "iters", torch.int32) if iters is not None else None,
+                                     _stream(stream)))
+
+
+def fc2d_mlp_forward(weights, X, out, stream=None):
+    import torch
+    n = X.numel() // FC2D_MLP_NIN
+    if out.numel() != 2 * n or weights.numel() != FC2D_MLP_NW:
+        raise ValueError("forward array sizes disagree")
+    _check(_lib().fc2d_mlp_forward(_dptr(weights, "weights", torch.float32), _dptr(X, "X", torch.float32), int(n),
+                                   _dptr(out, "out", torch.float32), _stream(stream)))
+
+
+def fc2d_mlp_loss_grad(weights, X, Y, grad=None, loss=None, stream=None):
+    import torch
+    n = X.numel() // FC2D_MLP_NIN
+    if Y.numel() != 2 * n or weights.numel() != FC2D_MLP_NW:
+        raise ValueError("loss/gradient array sizes disagree")
+    _check(_lib().fc2d_mlp_loss_grad(_dptr(weights, "weights", torch.float32), _dptr(X, "X", torch.float32),
+                                     _dptr(Y, "Y", torch.float32), int(n),
+                                     _dptr(grad, "grad", torch.float32) if grad is not None else None,
+                                     _dptr(loss, "loss", torch.float32) if loss is not None else None,
+                                     _stream(stream)))
+
+
+def fc2d_mlp_train(weights, adam_m, adam_v, X, Y, batch, steps, t0, lr0, lr_min, t_total, loss_hist=None,
+                   stream=None):
+    import torch
+    n = X.numel() // FC2D_MLP_NIN
+    if Y.numel() != 2 * n or weights.numel() != FC2D_MLP_NW or adam_m.numel() != FC2D_MLP_NW or \
+            adam_v.numel() != FC2D_MLP_NW or (loss_hist is not None and loss_hist.numel() < steps):
+        raise ValueError("training array sizes disagree")
+    _check(_lib().fc2d_mlp_train(_dptr(weights, "weights", torch.float32), _dptr(adam_m, "adam_m", torch.float32),
+                                 _dptr(adam_v, "adam_v", torch.float32), _dptr(X, "X", torch.float32),
+                                 _dptr(Y, "Y", torch.float32), int(n), int(batch), int(steps), int(t0),
+                                 float(lr0), float(lr_min), int(t_total),
+                                 _dptr(loss_hist, "loss_hist", torch.float32) if loss_hist is not None else None,
+                                 _stream(stream)))
 
 
 def fc2d_version():

@@ -68,3 +68,34 @@ def test_opts_default_follows_the_paper():
     lib.fc2d_opts_default(C.byref(g), C.byref(o))
     assert (o.n_r, o.Z, o.n_os, o.mf) == (6, 12, 20, 20)
     assert o.k1 == g.h and o.B == 256
+    assert o.seed == fc2d.FC2D_SEED_PROXIMITY and o.mlp_tol == 1e-13 and not o.mlp_weights
+
+
+def test_seed_options_rejected_without_gpu():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    g = fc2d.make_grid(-1.5, -1.5, 3.0 / 128, 128, 128)
+    h = C.c_void_p()
+    o = fc2d.fc2d_opts()
+    lib.fc2d_opts_default(C.byref(g), C.byref(o))
+    polar = fc2d.make_curve("polar", [1.0])
+    kite = fc2d.make_curve("cartesian", ([-0.65, 1.0, 0.0, 0.65], [0.0, 0.0, 1.5]))
+    o.seed = fc2d.FC2D_SEED_MLP                       # no weights
+    assert lib.fc2d_plan_create(C.byref(polar), C.byref(g), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_ARG
+    o.seed = fc2d.FC2D_SEED_POLAR                     # not a polar curve
+    assert lib.fc2d_plan_create(C.byref(kite), C.byref(g), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_ARG
+    o.seed = 7
+    assert lib.fc2d_plan_create(C.byref(polar), C.byref(g), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_ARG
+    assert b"seed" in lib.fc2d_last_error()
+
+
+def test_mlp_argument_errors_without_gpu():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    p = C.c_void_p(256)
+    assert lib.fc2d_mlp_forward(p, p, -1, p, None) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_mlp_forward(None, None, 0, None, None) == fc2d.FC2D_OK          # nothing to do
+    assert lib.fc2d_mlp_loss_grad(p, p, p, 0, p, p, None) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_mlp_train(p, p, p, p, p, 10, 0, 1, 0, 1e-3, 1e-5, 1, None, None) == fc2d.FC2D_E_ARG   # batch 0
+    assert lib.fc2d_mlp_train(p, p, p, p, p, 10, 4, 0, 0, 1e-3, 1e-5, 1, None, None) == fc2d.FC2D_OK     # no steps
+    assert lib.fc2d_mlp_make_data(p, 1, 8, p, p, p, 5, 0.0, p, p, None, None, None) == fc2d.FC2D_E_ARG   # width 0

@@ -165,6 +165,47 @@ def cfg_kite(n=2048):
     return fitted_case("kite%d" % n, kite(0.65, 1.5), n)
 
 
+def mlp_k1():
+    """Normal step of the learned-seed workload: h of the fitted 4096^2 box
+    around the held-out random curve (seed 1)."""
+    return fitted_case("rnd4096", random_polar(1)[0], 4096).h
+
+
+def cfg_mlp(n=4096):
+    """Held-out random curve (seed 1) in its fitted box on n^2 points, with the
+    normal step of the 4096^2 box at every n (so the strip width C k1 the
+    network was trained for is the same) and B = 8192 at n = 4096, B = 2n below."""
+    curve = random_polar(1)[0]
+    return fitted_case("rnd%d" % n, curve, n, B=8192 if n >= 4096 else 2 * n, k1=mlp_k1())
+
+
+def random_polar_batch(seed, ncurves, mmin=2, mmax=8, amp=0.15):
+    """ncurves curves of the random_polar family from one generator -> [ncurves, 1 + 2 mmax]."""
+    rng = np.random.default_rng(seed)
+    out = np.zeros((ncurves, 1 + 2 * mmax))
+    out[:, 0] = 1.0
+    for c in range(ncurves):
+        a = np.array([rng.uniform(-amp / m, amp / m) for m in range(mmin, mmax + 1)])
+        ph = rng.uniform(0.0, 2 * math.pi, mmax - mmin + 1)
+        for k, m in enumerate(range(mmin, mmax + 1)):
+            out[c, 2 * m - 1] = a[k] * math.cos(ph[k])
+            out[c, 2 * m] = -a[k] * math.sin(ph[k])
+    return out
+
+
+def mlp_training_draws(seed=0, ncurves=1000, npts=1000, width=1.0):
+    """Training set of the learned foot seed: ncurves random curves and, per
+    curve, npts parameters theta ~ U[0, 2 pi) and distances eta ~ U(0, width]
+    (the point is placed at q(theta) + eta n(theta) by the consumer).
+    Returns (curves [ncurves, 17], curve index [n] int32, theta [n], eta [n])."""
+    curves = random_polar_batch(seed, ncurves)
+    rng = np.random.default_rng(seed + 1000)
+    cidx = np.repeat(np.arange(ncurves, dtype=np.int32), npts)
+    theta = rng.uniform(0.0, 2 * math.pi, cidx.size)
+    eta = width * (1.0 - rng.uniform(0.0, 1.0, cidx.size))
+    return curves, cidx, theta, eta
+
+
 # --------------------------------------------------------------------------
 # test functions (closed forms) and seeded parameters
 # --------------------------------------------------------------------------

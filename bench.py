@@ -70,6 +70,11 @@ def parse():
     ap.add_argument("--cpu-sample-fields", type=int, default=96)
     ap.add_argument("--col-tile", type=int, default=0, help="columns per block of the column FFT pass (0 = default)")
     ap.add_argument("--strip-fields", type=int, default=-1, help="fields per thread of the strip kernel (-1 = default)")
+    ap.add_argument("--no-mlp", action="store_true", help="skip the learned-seed measurement")
+    ap.add_argument("--mlp-curves", type=int, default=1000)
+    ap.add_argument("--mlp-steps", type=int, default=20000)
+    ap.add_argument("--mlp-batch", type=int, default=4096)
+    ap.add_argument("--mlp-fields", type=int, default=8)
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (known-size kernel for counter calibration)")
     return ap.parse_args()
@@ -169,6 +174,127 @@ def run_batched(args):
             "autotuned": {"col_tile": tiles, "strip_fields_per_thread": sf}, "plan_s": plan_s,
             "workload": "disc, star5, kite(0.65,1.5), ellipse(1,0.5) on [-2,2]^2 at 256^2..2048^2, "
                         "Gaussian pulses, u and u_t extended each step"}
+
+
+def run_mlp(args):
+    """Learned foot seed: training pairs (the method's own foot solves on
+    mlp_curves random curves x 1000 points in the exterior strip) and training on
+    the GPU, then the plan of the held-out random curve (seed 1) on 4096^2 with
+    B = 8192 built with the proximity, polar-angle and learned seeds.  Reports
+    plan wall time, classification-kernel time (HIP events), Newton steps per
+    solved point and the fallback rate, and the extend + FFT throughput of the
+    learned-seed plan."""
+    import math
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2010_03901_amd import fc2d
+    width = 27 * W.mlp_k1()
+    curves, cidx, th, eta = W.mlp_training_draws(0, args.mlp_curves, 1000, width)
+    n = cidx.size
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    X = torch.empty((n, 8), dtype=torch.float32, device="cuda:0")
+    Y = torch.empty((n, 2), dtype=torch.float32, device="cuda:0")
+    its = torch.empty(n, dtype=torch.int32, device="cuda:0")
+    dc, di, dth, deta = dev(curves), dev(cidx), dev(th), dev(eta)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    fc2d.fc2d_mlp_make_data(dc, di, dth, deta, width, X, Y, None, its)
+    torch.cuda.synchronize()
+    data_s = time.perf_counter() - t0
+    if int(its.min().item()) < 1:
+        raise RuntimeError("training pairs: foot solve failed")
+    label_steps = float(its.double().mean().item())
+    # Glorot-uniform initial weights, zero biases
+    rng = np.random.default_rng(0)
+    parts = []
+    for fi, fo in [(8, 64), (64, 64), (64, 64), (64, 2)]:
+        lim = math.sqrt(6.0 / (fi + fo))
+        parts += [rng.uniform(-lim, lim, fi * fo), np.zeros(fo)]
+    w = dev(np.concatenate(parts).astype(np.float32))
+    m = torch.zeros_like(w)
+    v = torch.zeros_like(w)
+    steps = args.mlp_steps
+    hist = torch.zeros(steps, dtype=torch.float32, device="cuda:0")
+    t0 = time.perf_counter()
+    fc2d.fc2d_mlp_train(w, m, v, X, Y, args.mlp_batch, steps, 0, 3e-3, 1e-5, steps, hist)
+    train_s = time.perf_counter() - t0
+    h = hist.cpu().numpy()
+    weights = w.cpu().numpy()
+    print("[bench] mlp: data %.2fs, %d steps in %.2fs, loss %.3e -> %.3e" % (data_s, steps, train_s, h[:20].mean(),
+                                                                        h[-100:].mean()), file=sys.stderr, flush=True)
+    del X, Y, its
+    torch.cuda.empty_cache()
+
+    case = W.cfg_mlp(4096)
+    grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+    curve = fc2d.make_curve(*case.curve)
+
+    def build(**kw):
+        return fc2d.Plan(curve, grid, d=case.d, C_=case.C, B=case.B, k1=case.k1, M=case.M, **kw)
+
+    build().close()                                       # tables and code objects warm
+    modes = {"proximity": {}, "polar": {"seed": fc2d.FC2D_SEED_POLAR},
+             "mlp": {"seed": fc2d.FC2D_SEED_MLP, "mlp_weights": weights}}
+    res, plans = {}, {}
+    for name, kw in modes.items():
+        best = None
+        for _ in range(3):
+            torch.cuda.synchronize()
+            fc2d.fc2d_trace_begin()
+            t0 = time.perf_counter()
+            pl = build(**kw)
+            wall = time.perf_counter() - t0
+            tr = fc2d.fc2d_trace_end()
+            kms = sum(t for k, t in tr if k.startswith("k_"))
+            if best is None or kms < best["classify_kernel_ms"]:
+                inf = pl.info
+                best = {"plan_s": wall, "classify_kernel_ms": kms,
+                        "kernels_ms": {k: t for k, t in tr if k.startswith("k_")},
+                        "solved": inf.n_solved, "strip": inf.n_strip,
+                        "newton_steps_per_point": inf.newton_iters / max(inf.n_solved, 1),
+                        "fallback_rate": inf.n_fallback / max(inf.n_solved, 1)}
+                plans[name] = pl
+        res[name] = best
+        print("[bench] mlp plan %-9s %s" % (name, json.dumps(best)), file=sys.stderr, flush=True)
+    same = all(np.array_equal(fc2d.fc2d_plan_classes(plans["proximity"]), fc2d.fc2d_plan_classes(plans[k]))
+               for k in ("polar", "mlp"))
+    # extend + FFT on the learned-seed plan: nf fields built on the device
+    nf = args.mlp_fields
+    pl = plans["mlp"]
+    bp = torch.from_numpy(fc2d.fc2d_boundary_points(pl)).to("cuda:0")
+    x = case.x0 + torch.arange(case.n, device="cuda:0", dtype=torch.float64) * case.h
+    fg = torch.empty((nf, case.n, case.n), dtype=torch.float64, device="cuda:0")
+    fb = torch.empty((nf, bp.shape[0]), dtype=torch.float64, device="cuda:0")
+    for s in range(nf):
+        k1, k2 = W.star_wavenumbers(s)
+        fg[s] = torch.sin(k1 * x)[:, None] * torch.cos(k2 * x)[None, :] + (x ** 3)[:, None] * x[None, :]
+        fb[s] = torch.sin(k1 * bp[:, 0]) * torch.cos(k2 * bp[:, 1]) + bp[:, 0] ** 3 * bp[:, 1]
+    spec = torch.empty((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    for _ in range(2):
+        fc2d.fc2d_extend_fft(pl, fg, fb, fg, spec)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    reps = 10
+    ev0.record()
+    for _ in range(reps):
+        fc2d.fc2d_extend_fft(pl, fg, fb, fg, spec)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / reps
+    for p in plans.values():
+        p.close()
+    sp = lambda a, b: res[a]["classify_kernel_ms"] / res[b]["classify_kernel_ms"]
+    return {"workload": "held-out random curve (seed 1), fitted box 4096^2, B=8192, k1=%.4g" % case.k1,
+            "training": {"pairs": int(n), "curves": int(args.mlp_curves), "data_s": data_s,
+                         "label_newton_steps": label_steps, "steps": steps, "batch": args.mlp_batch,
+                         "train_s": train_s, "loss_first": float(h[:20].mean()), "loss_last": float(h[-100:].mean())},
+            "plans": res, "identical_classes": bool(same),
+            "classify_speedup_mlp_vs_proximity": sp("proximity", "mlp"),
+            "classify_speedup_mlp_vs_polar": sp("polar", "mlp"),
+            "plan_speedup_mlp_vs_proximity": res["proximity"]["plan_s"] / res["mlp"]["plan_s"],
+            "extend_fft": {"fields": nf, "ms": ms, "points_per_s": nf * case.n * case.n / (ms * 1e-3)}}
 
 
 def main():
@@ -275,6 +401,15 @@ def main():
         print("[bench] batched: %.3f ms/step, %.3e points/s" % (batched["ms_per_step"], batched["points_per_s"]),
               file=sys.stderr, flush=True)
 
+    learned = None
+    if not args.no_mlp:
+        print("[bench] learned foot seed ...", file=sys.stderr, flush=True)
+        if batched is None:
+            del fg, fb, ext, spec
+            torch.cuda.empty_cache()
+        learned = run_mlp(args)
+        print("[bench] learned seed: " + json.dumps(learned), file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -293,6 +428,7 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "batched_ff": batched,
+        "learned_seed": learned,
         "plan_s": plan_s,
     }
     print(json.dumps(out))

@@ -585,6 +585,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             }
             ca.bx = d_bx; ca.by = d_by; ca.bnx = d_bnx; ca.bny = d_bny;
             ca.col_ptr = d_colptr; ca.col_y = d_coly;
+            trace_point("plan_host", stream);   // kernel times below exclude the host set-up
             if ((st = launch_classify(ca, d_cls, d_rec, cap, d_near, d_cnt, stream))) break;
         } else {
             if (hipMalloc((void**)&d_cand, cap_cand * sizeof(int32_t)) != hipSuccess) {
@@ -593,6 +594,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                 break;
             }
             if (o.seed == FC2D_SEED_MLP && (st = dev_upload(&d_w, o.mlp_weights, FC2D_MLP_NW))) break;
+            trace_point("plan_host", stream);
             if ((st = launch_radial_band(sa, d_cls, d_cand, cap_cand, d_cnt, stream))) break;
             if ((e = hipMemcpyAsync(cnt, d_cnt, 8 * sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
                 (e = hipStreamSynchronize(stream)) != hipSuccess) {
@@ -600,6 +602,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                 break;
             }
             if (cnt[3] > cap_cand) { set_error("candidate capacity exceeded"); st = FC2D_E_GEOMETRY; break; }
+            trace_point("plan_host", stream);
             st = o.seed == FC2D_SEED_MLP
                      ? launch_seed_mlp(sa, d_w, d_cand, cnt[3], d_cls, d_rec, cap, d_cnt, stream)
                      : launch_seed_polar(sa, d_cand, cnt[3], d_cls, d_rec, cap, d_cnt, stream);

@@ -23,12 +23,15 @@ HBM_PEAK_GBS = 8000.0
 COUNTERS = os.path.join(ROOT, "profiles", "star1024_extend_fft_counters.json")
 
 
+# sources of the extension and FFT kernels whose HBM counters are committed
+KERNEL_SOURCES = ["kernels_extend.hip", "kernels_fft.hip", "dd.h", "geom.h", "internal.h"]
+
+
 def source_hash():
-    import glob
     import hashlib
     h = hashlib.sha256()
-    for f in sorted(glob.glob(os.path.join(ROOT, "paper_2010_03901_amd", "csrc", "*"))):
-        with open(f, "rb") as fh:
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2010_03901_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 

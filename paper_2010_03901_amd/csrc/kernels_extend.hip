@@ -59,11 +59,13 @@ struct Acc2 {
 };
 
 // Matching values and Gram coefficients of normal p for field f (one thread).
-template <int M>
+// DT > 0 fixes d = DT at compile time (straight-line code); DT = 0 takes d = Drt.
+template <int M, int DT>
 __device__ __forceinline__ void match_one(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
-                                          const double* __restrict__ mwn, const double* __restrict__ Q, int D, int B,
+                                          const double* __restrict__ mwn, const double* __restrict__ Q, int Drt, int B,
                                           const double* __restrict__ g, const double* __restrict__ bv, int p,
                                           double* __restrict__ co, double* __restrict__ fo) {
+    const int D = DT > 0 ? DT : Drt;
     const int32_t* ref = mref + (int64_t)p * M * M;
     const double* wv = mwv + (int64_t)p * M * M * 2;
     const double* wn = mwn + (int64_t)p * (D - 1) * M * 2;
@@ -76,7 +78,7 @@ __device__ __forceinline__ void match_one(const int32_t* __restrict__ mref, cons
         for (int k = 0; k < M; ++k) {
             const int o = s * M + k;
             const int32_t r = ref[o];
-            const double val = r >= 0 ? g[r] : bv[B + (-r - 1)];
+            const double val = *(r >= 0 ? g + r : bv + B + (-r - 1));   // grid node or square: one load
             a.add(dd{wv[2 * o], wv[2 * o + 1]}, val);
         }
         star[s] = a.result();
@@ -129,7 +131,7 @@ __device__ __forceinline__ int xcd_normal(int l, int B) {
 
 // One thread per (normal p, field f): the weights of normal p are uniform
 // across the wave (scalar loads), each lane gathers its own field's values.
-template <int M>
+template <int M, int DT>
 __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
                                               const double* __restrict__ mwn, const double* __restrict__ Q, int D,
                                               int B, const double* __restrict__ fg, int64_t npts,
@@ -139,14 +141,14 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
     const int f = blockIdx.y * 64 + threadIdx.x;
     if (p >= B || f >= nf) return;
     const int DP = (D + 2) & ~1;
-    match_one<M>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p,
+    match_one<M, DT>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p,
                  c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
 }
 
 // Persistent form over several plans (a batch): work item w covers 64 fields
 // of one normal of one plan; items of plan k start at a multiple of 8 so the
 // XCD assignment above is kept.  Every block loops until the items run out.
-template <int M>
+template <int M, int DT>
 __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ pd, int np, int64_t total) {
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         int k = 0;
@@ -158,7 +160,7 @@ __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ 
         const int f = (int)(l / padB) * 64 + threadIdx.x;
         if (p >= P.B || f >= P.nf) continue;
         const int DP = (P.D + 2) & ~1;
-        match_one<M>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts, P.fb + (int64_t)f * P.nbdry, p,
+        match_one<M, DT>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts, P.fb + (int64_t)f * P.nbdry, p,
                      P.c + ((int64_t)f * P.B + p) * DP, nullptr);
     }
 }
@@ -182,53 +184,65 @@ __global__ void k_blend(const double* __restrict__ c, const double* __restrict__
     }
 }
 
-// Interpolated value at STRIP point k for fields [f0, f1) (one thread).
+// 1 / prod_{q != m} (m - q) = 1 / ((-1)^(M-1-m) m! (M-1-m)!): the denominators of the
+// Lagrange weights on the nodes 0, 1, ..., M-1
 template <int M>
+__host__ __device__ constexpr double equi_inv_den(int m) {
+    double d = 1.0;
+    for (int q = 0; q < M; ++q)
+        if (q != m) d *= (double)(m - q);
+    return 1.0 / d;
+}
+
+// Lagrange weights of degree M-1 on the equispaced nodes 0..M-1 at x:
+// w_m = prod_{q < m}(x - q) prod_{q > m}(x - q) / prod_{q != m}(m - q), the
+// numerators from prefix and suffix products (no division at run time).
+template <int M>
+__device__ __forceinline__ void equi_weights(double x, double* w) {
+    double pre[M], suf[M];
+    pre[0] = 1.0;
+#pragma unroll
+    for (int m = 1; m < M; ++m) pre[m] = pre[m - 1] * (x - (double)(m - 1));
+    suf[M - 1] = 1.0;
+#pragma unroll
+    for (int m = M - 2; m >= 0; --m) suf[m] = suf[m + 1] * (x - (double)(m + 1));
+#pragma unroll
+    for (int m = 0; m < M; ++m) w[m] = pre[m] * suf[m] * equi_inv_den<M>(m);
+}
+
+// Interpolated value at STRIP point k for fields [f0, f1) (one thread).
+// DT > 0 fixes d = DT at compile time (straight-line code); DT = 0 takes d = Drt.
+template <int M, int DT>
 __device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
-                                          const double* __restrict__ seta, int64_t k, const double* sAr, int D,
+                                          const double* __restrict__ seta, int64_t k, const double* sAr, int Drt,
                                           int Cr, int B, double k2, double lev_scale, const double* __restrict__ c,
                                           double* __restrict__ out, int64_t npts, int f0, int f1) {
+    const int D = DT > 0 ? DT : Drt;
     const double th = sth[k];
     const double eta = seta[k];
     const int32_t idx = sidx[k];
     constexpr int kl = (M - 1) / 2;
     const int p0 = (M % 2 == 0) ? (int)floor(th / k2) : (int)rint(th / k2);
-    // theta weights over S_{theta^Q}
-    double tn[M], w[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) tn[m] = (double)(p0 - kl + m) * k2;
-#pragma unroll
-    for (int m = 0; m < M; ++m) {
-        double v = 1.0;
-#pragma unroll
-        for (int q = 0; q < M; ++q)
-            if (q != m) v *= (th - tn[q]) / (tn[m] - tn[q]);
-        w[m] = v;
-    }
-    // level weights at s = eta n_r / k1 and u = A_r^T v (factored blend)
+    // theta weights over S_{theta^Q}: nodes theta_{p0-kl+m}, m = 0..M-1, in units of k2
+    double w[M];
+    equi_weights<M>((th - (double)(p0 - kl) * k2) / k2, w);
+    // level weights at s = eta n_r / k1 (nodes l0..l0+M-1) and u = A_r^T v (factored blend)
     const double s = eta * lev_scale;
     int l0 = (int)floor(s) - M / 2 + 1;
     l0 = l0 < 0 ? 0 : (l0 > Cr - M + 1 ? Cr - M + 1 : l0);
     double v[M];
-#pragma unroll
-    for (int l = 0; l < M; ++l) {
-        double a = 1.0;
-#pragma unroll
-        for (int q = 0; q < M; ++q)
-            if (q != l) a *= (s - (double)(l0 + q)) / ((double)(l0 + l) - (double)(l0 + q));
-        v[l] = a;
-    }
+    equi_weights<M>(s - (double)l0, v);
     double u[10];
 #pragma unroll
     for (int j = 0; j < 10; ++j) u[j] = 0.0;
 #pragma unroll
     for (int l = 0; l < M; ++l) {
-        const int lev = l0 + l;
-        if (lev >= 1) {
+        const int lev = l0 + l;            // level 0 is the boundary value, not a row of A_r
+        const double vl = lev >= 1 ? v[l] : 0.0;
+        const double* row = sAr + (lev >= 1 ? lev - 1 : 0) * D;
 #pragma unroll
-            for (int j = 0; j < 9; ++j)
-                if (j < D) u[j] += v[l] * sAr[(lev - 1) * D + j];
-        }
+        for (int j = 0; j < 9; ++j)
+            if (j < D) u[j] += vl * row[j];
     }
     // slot D of each normal's record holds its boundary value: weight v_0 when l0 = 0
     u[D] = (l0 == 0) ? v[0] : 0.0;
@@ -260,7 +274,7 @@ __device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, cons
     }
 }
 
-template <int M>
+template <int M, int DT>
 __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
                                                const double* __restrict__ seta, int64_t S, const double* __restrict__ Ar,
                                                int D, int Cr, int B, double k2, double lev_scale,
@@ -272,12 +286,12 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= S) return;
     const int f0 = blockIdx.y * fpt;
-    strip_one<M>(sidx, sth, seta, k, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0, min(nf, f0 + fpt));
+    strip_one<M, DT>(sidx, sth, seta, k, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0, min(nf, f0 + fpt));
 }
 
 // Persistent form over several plans: work item w = (plan, block of 256 STRIP
 // points, chunk of fpt fields).  All plans of a batch share the FC-Gram tables.
-template <int M>
+template <int M, int DT>
 __global__ __launch_bounds__(256) void k_strip_multi(const PlanDev* __restrict__ pd, int np, int64_t total, int fpt,
                                                      const double* __restrict__ Ar, int D, int Cr) {
     extern __shared__ double sAr[];
@@ -292,7 +306,7 @@ __global__ __launch_bounds__(256) void k_strip_multi(const PlanDev* __restrict__
         const int64_t k = (l % pblocks) * 256 + threadIdx.x;
         const int f0 = (int)(l / pblocks) * fpt;
         if (k >= P.S) continue;
-        strip_one<M>(P.sidx, P.sth, P.seta, k, sAr, D, Cr, P.B, P.k2, P.lev_scale, P.c, P.u, P.npts, f0,
+        strip_one<M, DT>(P.sidx, P.sth, P.seta, k, sAr, D, Cr, P.B, P.k2, P.lev_scale, P.c, P.u, P.npts, f0,
                      min(P.nf, f0 + fpt));
     }
 }
@@ -306,20 +320,8 @@ __device__ __forceinline__ double bval_one(const double* __restrict__ u, int nx,
     const int i0 = (int)floor((X - x0) / h) - M / 2 + 1;
     const int j0 = (int)floor((Y - y0) / h) - M / 2 + 1;
     double wx[M], wy[M];
-#pragma unroll
-    for (int a = 0; a < M; ++a) {
-        double va = 1.0, vb = 1.0;
-        const double xa = x0 + (double)(i0 + a) * h, ya = y0 + (double)(j0 + a) * h;
-#pragma unroll
-        for (int b = 0; b < M; ++b) {
-            if (b == a) continue;
-            const double xb = x0 + (double)(i0 + b) * h, yb = y0 + (double)(j0 + b) * h;
-            va *= (X - xb) / (xa - xb);
-            vb *= (Y - yb) / (ya - yb);
-        }
-        wx[a] = va;
-        wy[a] = vb;
-    }
+    equi_weights<M>((X - (x0 + (double)i0 * h)) / h, wx);
+    equi_weights<M>((Y - (y0 + (double)j0 * h)) / h, wy);
     double acc = 0.0;
 #pragma unroll
     for (int a = 0; a < M; ++a) {
@@ -405,7 +407,10 @@ int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry
     dim3 grid(((pl->B + 7) / 8) * 8, (nf + 63) / 64);
     switch (pl->M) {
 #define FC2D_MATCH(MM) \
-        case MM: k_match<MM><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); break;
+        case MM: \
+            if (pl->d == 5) k_match<MM, 5><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else k_match<MM, 0><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            break;
         FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8)
 #undef FC2D_MATCH
         default: set_error("unsupported M"); return FC2D_E_ARG;
@@ -436,7 +441,10 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     const double lev_scale = pl->n_r / pl->k1;
     switch (pl->M) {
 #define FC2D_STRIP(MM) \
-        case MM: k_strip<MM><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts, nf, fpt); break;
+        case MM: \
+            if (pl->d == 5) k_strip<MM, 5><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts, nf, fpt); \
+            else k_strip<MM, 0><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts, nf, fpt); \
+            break;
         FC2D_STRIP(4) FC2D_STRIP(5) FC2D_STRIP(6) FC2D_STRIP(7) FC2D_STRIP(8)
 #undef FC2D_STRIP
         default: set_error("unsupported M"); return FC2D_E_ARG;
@@ -477,8 +485,10 @@ int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, i
     switch (M) {
 #define FC2D_MULTI(MM)                                                                                 \
         case MM:                                                                                       \
-            if (which == 0) k_match_multi<MM><<<g, 64, 0, s>>>(d_pd, np, total);                       \
-            else if (which == 1) k_strip_multi<MM><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr); \
+            if (which == 0 && D == 5) k_match_multi<MM, 5><<<g, 64, 0, s>>>(d_pd, np, total);          \
+            else if (which == 0) k_match_multi<MM, 0><<<g, 64, 0, s>>>(d_pd, np, total);               \
+            else if (which == 1 && D == 5) k_strip_multi<MM, 5><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr); \
+            else if (which == 1) k_strip_multi<MM, 0><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr); \
             else k_bvals_multi<MM><<<g, 256, 0, s>>>(d_pd, np, total);                                 \
             break;
         FC2D_MULTI(4) FC2D_MULTI(5) FC2D_MULTI(6) FC2D_MULTI(7) FC2D_MULTI(8)

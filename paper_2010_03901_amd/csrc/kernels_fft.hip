@@ -151,6 +151,39 @@ constexpr int pick_radix(int rem, int E) {
     return r;
 }
 
+// LDS slot of element x: the low 3 bits XORed with the next 3, so a wave
+// writing with a stride of 4, 8 or 16 elements (16-byte complex values)
+// spreads over the banks; a bijection on every aligned block of 64 elements.
+__device__ __forceinline__ int swz(int x) { return x ^ ((x >> 3) & 7); }
+
+// exp(-2 pi i a / n) for 0 <= a < n, n a power of two (2a/n is exact)
+__device__ __forceinline__ double2 unit_root(int a, int n) {
+    double sn, cs;
+    sincospi(2.0 * (double)a / (double)n, &sn, &cs);
+    return make_double2(cs, -sn);
+}
+
+// w[r] = w1^r for r = 1..R-1 (R a power of two <= 16) by a product tree of
+// depth log2 R, so each power carries a few rounding errors at most
+template <int R>
+__device__ __forceinline__ void root_powers(double2 w1, double2* w) {
+    w[1] = w1;
+    if constexpr (R > 2) {
+        w[2] = cmul(w1, w1);
+        w[3] = cmul(w[2], w1);
+    }
+    if constexpr (R > 4) {
+        w[4] = cmul(w[2], w[2]);
+#pragma unroll
+        for (int r = 5; r < 8; ++r) w[r] = cmul(w[4], w[r - 4]);
+    }
+    if constexpr (R > 8) {
+        w[8] = cmul(w[4], w[4]);
+#pragma unroll
+        for (int r = 9; r < 16; ++r) w[r] = cmul(w[8], w[r - 8]);
+    }
+}
+
 // Register-resident Stockham FFT of length L, E elements per thread
 // (P = L / E threads per sequence).  Thread t owns butterflies b_i = t + i P;
 // v[i R + r] holds element b_i + r L/R of the current stage.  On entry v holds
@@ -172,20 +205,17 @@ struct StockhamFrom {
             for (int i = 0; i < NB; ++i) {
                 const int b = t + i * P;
 #pragma unroll
-                for (int r = 0; r < R; ++r) v[i * R + r] = lds[(b + r * (L / R)) * NS + q * QS];
+                for (int r = 0; r < R; ++r) v[i * R + r] = lds[swz((b + r * (L / R)) * NS + q * QS)];
             }
-            // twiddles
-            constexpr int tstep_div = Ns * R;
+            // twiddles W_{Ns R}^{j r}, computed (no table reads on the critical path)
 #pragma unroll
             for (int i = 0; i < NB; ++i) {
                 const int b = t + i * P;
                 const int j = b % Ns;
+                double2 w[R];
+                root_powers<R>(unit_root(j, Ns * R), w);
 #pragma unroll
-                for (int r = 1; r < R; ++r) {
-                    double2 w = tw[(j * r) * (NT / tstep_div)];
-                    if (INV) w = cconj(w);
-                    v[i * R + r] = cmul(v[i * R + r], w);
-                }
+                for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], INV ? cconj(w[r]) : w[r]);
             }
         }
 #pragma unroll
@@ -198,7 +228,7 @@ struct StockhamFrom {
                 const int j = b % Ns;
                 const int base = (b / Ns) * Ns * R + j;
 #pragma unroll
-                for (int r = 0; r < R; ++r) lds[(base + r * Ns) * NS + q * QS] = v[i * R + r];
+                for (int r = 0; r < R; ++r) lds[swz((base + r * Ns) * NS + q * QS)] = v[i * R + r];
             }
             __syncthreads();
             StockhamFrom<L, E, Ns * R, INV>::run(v, lds, QS, NS, q, t, tw, NT);
@@ -311,17 +341,21 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
     StockhamFrom<L, E, 1, false>::run(v, lds, L, 1, q, t, tw, N);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) lds[q * L + out_index<L, E>(k, t)] = v[k];
+    for (int k = 0; k < E; ++k) lds[swz(q * L + out_index<L, E>(k, t))] = v[k];
     __syncthreads();
     if (!live) return;
     double2* dst = out + ((int64_t)f * nx + row) * (L + 1);
+    // split weights W_N^k for k = t + m P: W_N^t times powers of W_N^P
+    const double2 wstep = unit_root(P, N);
+    double2 wk = unit_root(t, N);
     for (int k = t; k <= L; k += P) {
-        const double2 zk = lds[q * L + (k == L ? 0 : k)];
-        const double2 zc = cconj(lds[q * L + (k == 0 ? 0 : L - k)]);
+        const double2 zk = lds[swz(q * L + (k == L ? 0 : k))];
+        const double2 zc = cconj(lds[swz(q * L + (k == 0 ? 0 : L - k))]);
         const double2 Eh = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
         const double2 D = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y - zc.y));
         const double2 O = make_double2(D.y, -D.x);   // D / i
-        dst[k] = cadd(Eh, cmul(tw[k], O));
+        dst[k] = cadd(Eh, cmul(wk, O));
+        wk = cmul(wk, wstep);
     }
 }
 

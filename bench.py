@@ -72,6 +72,7 @@ def parse():
     ap.add_argument("--ff-steps", type=int, default=100)
     ap.add_argument("--cpu-sample-fields", type=int, default=96)
     ap.add_argument("--col-tile", type=int, default=0, help="columns per block of the column FFT pass (0 = default)")
+    ap.add_argument("--col-elems", type=int, default=0, help="elements per thread of the column FFT pass (0 = default)")
     ap.add_argument("--strip-fields", type=int, default=-1, help="fields per thread of the strip kernel (-1 = default)")
     ap.add_argument("--no-mlp", action="store_true", help="skip the learned-seed measurement")
     ap.add_argument("--mlp-curves", type=int, default=1000)
@@ -170,11 +171,12 @@ def run_batched(args):
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.ff_steps
     _, nl, _ = batch.info()
-    tiles = {n: fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_TILE, n) for n in sizes}
+    tiles = {n: (fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_ELEMS, n), fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_TILE, n))
+             for n in sizes}
     batch.close()
     return {"points_per_s": pts / (ms * 1e-3), "ms_per_step": ms, "points_per_step": pts,
             "fields": int(sum(nf)), "steps": args.ff_steps, "dt": 0.01, "launches_per_step": nl, "graph": True,
-            "autotuned": {"col_tile": tiles, "strip_fields_per_thread": sf}, "plan_s": plan_s,
+            "autotuned": {"col_elems_tile": tiles, "strip_fields_per_thread": sf}, "plan_s": plan_s,
             "workload": "disc, star5, kite(0.65,1.5), ellipse(1,0.5) on [-2,2]^2 at 256^2..2048^2, "
                         "Gaussian pulses, u and u_t extended each step"}
 
@@ -316,6 +318,8 @@ def main():
     print("[bench] workload star%d nf=%d steps=%d warmup=%d" % (case.n, nf, args.steps, args.warmup),
           file=sys.stderr, flush=True)
     grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+    if args.col_elems:
+        fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_COL_ELEMS, case.n, args.col_elems)
     if args.col_tile:
         fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_COL_TILE, case.n, args.col_tile)
     if args.strip_fields >= 0:

@@ -45,7 +45,7 @@ enum {
 enum { FC2D_CURVE_POLAR = 1, FC2D_CURVE_CARTESIAN = 2 };
 enum { FC2D_FORWARD = -1, FC2D_INVERSE = 1 };
 enum { FC2D_LAPLACE_INV = 1, FC2D_DX = 2, FC2D_DY = 3 };
-enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2 };
+enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2, FC2D_TUNE_COL_ELEMS = 3 };
 
 /* How the foot-of-normal solve of each grid point near Gamma is started
  * (fc2d_opts.seed):
@@ -207,11 +207,14 @@ int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, con
                  void* uh, void* uth, int nf, hipStream_t stream);
 
 /* Launch-shape knobs, process-wide (set by the autotuner; results do not
- * depend on them).  FC2D_TUNE_COL_TILE: columns per block of the column FFT
- * pass for length n = nx (compiled choices: 4/8/16 for n <= 64, 4/8 up to 512,
- * 2/4/8 for 1024, 1/2/4 for 2048, 1/2 for 4096).  FC2D_TUNE_STRIP_FIELDS:
- * fields per thread of the strip interpolation (0 = automatic, n ignored).
- * Not thread-safe against concurrent launches. */
+ * depend on them beyond rounding).  For the column FFT pass of length n = nx:
+ * FC2D_TUNE_COL_TILE = columns per block T, FC2D_TUNE_COL_ELEMS = elements per
+ * thread E; compiled (E, T): n <= 64 (2; 4/8/16), 128 (2; 4/8), 256 (4; 4/8),
+ * 512 (4 or 8; 4/8), 1024 (8 or 16; 2/4/8), 2048 (16; 1/2/4 and 8; 1/2),
+ * 4096 (16; 1/2 and 8; 1).  A setting that would form an uncompiled pair is
+ * refused with FC2D_E_ARG.  FC2D_TUNE_STRIP_FIELDS: fields per thread of the
+ * strip interpolation (0 = automatic, n ignored).  Not thread-safe against
+ * concurrent launches. */
 int fc2d_tune_set(int knob, int n, int value);
 int fc2d_tune_get(int knob, int n, int* value);
 

@@ -120,17 +120,20 @@ static float time_ms(hipStream_t s, const std::function<int()>& fn, int reps) {
 }
 
 static int autotune(fc2d_batch* b, hipStream_t s) {
-    // column-pass tile width per grid size
+    // column-pass shape (elements per thread, columns per block) per grid size
     for (Group& g : b->groups) {
-        int best_T = col_tile_get(g.grid.nx);
+        int best_E = col_elems_get(g.grid.nx), best_T = col_tile_get(g.grid.nx);
         float best = 1e30f;
-        const int cand[] = {1, 2, 4, 8, 16};
-        for (int T : cand) {
-            if (col_tile_set(g.grid.nx, T) != FC2D_OK) continue;
-            const float ms = time_ms(s, [&]() { return fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s); }, 3);
-            if (ms >= 0 && ms < best) { best = ms; best_T = T; }
-        }
-        col_tile_set(g.grid.nx, best_T);
+        const int ecand[] = {2, 4, 8, 16};
+        const int tcand[] = {1, 2, 4, 8, 16};
+        for (int E : ecand)
+            for (int T : tcand) {
+                if (col_cfg_set(g.grid.nx, E, T) != FC2D_OK) continue;
+                const float ms =
+                    time_ms(s, [&]() { return fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s); }, 3);
+                if (ms >= 0 && ms < best) { best = ms; best_E = E; best_T = T; }
+            }
+        col_cfg_set(g.grid.nx, best_E, best_T);
     }
     // strip kernel: fields per thread
     int best_f = b->strip_fpt;

@@ -170,6 +170,9 @@ void row_class_layout(int L, const uint8_t* pairs, uint8_t* out);
 // tuning knobs (autotuner)
 int col_tile_get(int nx);
 int col_tile_set(int nx, int T);
+int col_elems_get(int nx);
+int col_elems_set(int nx, int E);
+int col_cfg_set(int nx, int E, int T);
 int strip_fpt_get();
 int strip_fpt_set(int v);
 

@@ -283,9 +283,23 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
     extern __shared__ double sAr[];
     for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
     __syncthreads();
-    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // blocks are dealt round-robin to the 8 XCDs: when the field chunks divide
+    // evenly, each XCD gets a contiguous range of them, so its L2 holds only
+    // those fields' Gram records
+    const int pblocks = (int)((S + 255) / 256);
+    const int nchunks = (nf + fpt - 1) / fpt;
+    int chunk, pb;
+    if (nchunks % 8 == 0) {
+        const int local = blockIdx.x / 8;
+        chunk = (blockIdx.x % 8) * (nchunks / 8) + local / pblocks;
+        pb = local % pblocks;
+    } else {
+        chunk = blockIdx.x / pblocks;
+        pb = blockIdx.x % pblocks;
+    }
+    const int64_t k = (int64_t)pb * 256 + threadIdx.x;
     if (k >= S) return;
-    const int f0 = blockIdx.y * fpt;
+    const int f0 = chunk * fpt;
     strip_one<M, DT>(sidx, sth, seta, k, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0, min(nf, f0 + fpt));
 }
 
@@ -431,12 +445,14 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     const int64_t S = (int64_t)pl->strip_idx.size();
     if (S == 0) return FC2D_OK;
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
-    // fields per thread: enough blocks to fill the chip, weights amortised over the rest
+    // fields per thread: at most 8, the chunks a multiple of 8 (an equal range
+    // per XCD) when there are at least 8 fields
     const int64_t pblocks = (S + 255) / 256;
-    int fpt = g_strip_fpt > 0 ? g_strip_fpt
-                              : (int)std::max<int64_t>(1, std::min<int64_t>(16, (int64_t)nf * pblocks / 2048));
+    int fpt = g_strip_fpt;
+    if (fpt <= 0) fpt = nf >= 8 ? (nf + 8 * ((nf + 63) / 64) - 1) / (8 * ((nf + 63) / 64)) : 1;
     fpt = std::max(1, std::min(fpt, nf));
-    dim3 grid((unsigned)pblocks, (nf + fpt - 1) / fpt);
+    const int64_t nchunks = (nf + fpt - 1) / fpt;
+    const dim3 grid((unsigned)(nchunks * pblocks));
     const size_t lds = (size_t)pl->Cr * pl->d * sizeof(double);
     const double lev_scale = pl->n_r / pl->k1;
     switch (pl->M) {

@@ -17,6 +17,7 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <algorithm>
 #include <map>
 #include <mutex>
 #include <vector>
@@ -480,38 +481,57 @@ void row_class_layout(int L, const uint8_t* pairs, uint8_t* out) {
 
 // Column-tile widths (columns per block, 16 B each) per log2(nx); the
 // autotuner (fc2d_tune_set) may change them among the compiled choices.
+// column-pass launch shape per length nx = 2^lg: elements per thread E and
+// columns per block T (compiled pairs below; the autotuner may switch)
 static int g_col_tile[14] = {0, 0, 0, 0, 16, 8, 8, 4, 4, 4, 4, 2, 1, 0};
+static int g_col_elems[14] = {0, 0, 0, 0, 2, 2, 2, 2, 4, 8, 16, 16, 16, 0};
 
-static bool col_tile_ok(int nx, int T) {
+static bool col_cfg_ok(int nx, int E, int T) {
     switch (nx) {
-        case 16: case 32: case 64: return T == 4 || T == 8 || T == 16;
-        case 128: case 256: case 512: return T == 4 || T == 8;
-        case 1024: return T == 2 || T == 4 || T == 8;
-        case 2048: return T == 1 || T == 2 || T == 4;
-        case 4096: return T == 1 || T == 2;
+        case 16: case 32: case 64: return E == 2 && (T == 4 || T == 8 || T == 16);
+        case 128: return E == 2 && (T == 4 || T == 8);
+        case 256: return E == 4 && (T == 4 || T == 8);
+        case 512: return (E == 4 || E == 8) && (T == 4 || T == 8);
+        case 1024: return (E == 8 || E == 16) && (T == 2 || T == 4 || T == 8);
+        case 2048: return (E == 16 && (T == 1 || T == 2 || T == 4)) || (E == 8 && (T == 1 || T == 2));
+        case 4096: return (E == 16 && (T == 1 || T == 2)) || (E == 8 && T == 1);
     }
     return false;
 }
 
-int col_tile_get(int nx) {
+static int log2_len(int nx) {
     int lg = 0;
     while ((1 << lg) < nx) ++lg;
+    return lg;
+}
+
+int col_tile_get(int nx) {
+    const int lg = log2_len(nx);
     return (lg >= 4 && lg <= 12) ? g_col_tile[lg] : 0;
 }
 
-int col_tile_set(int nx, int T) {
-    if (!col_tile_ok(nx, T)) return FC2D_E_ARG;
-    int lg = 0;
-    while ((1 << lg) < nx) ++lg;
+int col_elems_get(int nx) {
+    const int lg = log2_len(nx);
+    return (lg >= 4 && lg <= 12) ? g_col_elems[lg] : 0;
+}
+
+int col_cfg_set(int nx, int E, int T) {
+    if (!col_cfg_ok(nx, E, T)) return FC2D_E_ARG;
+    const int lg = log2_len(nx);
+    g_col_elems[lg] = E;
     g_col_tile[lg] = T;
     return FC2D_OK;
 }
 
+int col_tile_set(int nx, int T) { return col_cfg_set(nx, col_elems_get(nx), T); }
+int col_elems_set(int nx, int E) { return col_cfg_set(nx, E, col_tile_get(nx)); }
+
 template <bool INV>
 static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* tw, hipStream_t s) {
     const int T = col_tile_get(nx);
+    const int E = col_elems_get(nx);
 #define FC2D_COLT(LL, EE, TT)                                                                    \
-    if (nx == LL && T == TT) {                                                                   \
+    if (nx == LL && E == EE && T == TT) {                                                        \
         const int ntiles = (ncol + TT - 1) / TT;                                                 \
         dim3 g(((ntiles + 7) / 8) * 8, nf);                                                      \
         k_cols<LL, EE, TT, INV><<<g, TT * (LL / EE), 0, s>>>(data, ncol, tw);                    \
@@ -522,9 +542,12 @@ static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* 
     FC2D_COLT(64, 2, 4) FC2D_COLT(64, 2, 8) FC2D_COLT(64, 2, 16)
     FC2D_COLT(128, 2, 4) FC2D_COLT(128, 2, 8)
     FC2D_COLT(256, 4, 4) FC2D_COLT(256, 4, 8)
-    FC2D_COLT(512, 8, 4) FC2D_COLT(512, 8, 8)
+    FC2D_COLT(512, 4, 4) FC2D_COLT(512, 4, 8) FC2D_COLT(512, 8, 4) FC2D_COLT(512, 8, 8)
+    FC2D_COLT(1024, 8, 2) FC2D_COLT(1024, 8, 4) FC2D_COLT(1024, 8, 8)
     FC2D_COLT(1024, 16, 2) FC2D_COLT(1024, 16, 4) FC2D_COLT(1024, 16, 8)
+    FC2D_COLT(2048, 8, 1) FC2D_COLT(2048, 8, 2)
     FC2D_COLT(2048, 16, 1) FC2D_COLT(2048, 16, 2) FC2D_COLT(2048, 16, 4)
+    FC2D_COLT(4096, 8, 1)
     FC2D_COLT(4096, 16, 1) FC2D_COLT(4096, 16, 2)
 #undef FC2D_COLT
 }

@@ -918,6 +918,7 @@ const char* fc2d_last_error(void) { return g_last_error.c_str(); }
 int fc2d_tune_set(int knob, int n, int value) {
     int st = FC2D_E_ARG;
     if (knob == FC2D_TUNE_COL_TILE) st = col_tile_set(n, value);
+    else if (knob == FC2D_TUNE_COL_ELEMS) st = col_elems_set(n, value);
     else if (knob == FC2D_TUNE_STRIP_FIELDS) st = strip_fpt_set(value);
     if (st) set_error("fc2d_tune_set: unsupported knob or value");
     return st;
@@ -926,6 +927,7 @@ int fc2d_tune_set(int knob, int n, int value) {
 int fc2d_tune_get(int knob, int n, int* value) {
     if (!value) { set_error("NULL argument"); return FC2D_E_ARG; }
     if (knob == FC2D_TUNE_COL_TILE) *value = col_tile_get(n);
+    else if (knob == FC2D_TUNE_COL_ELEMS) *value = col_elems_get(n);
     else if (knob == FC2D_TUNE_STRIP_FIELDS) *value = strip_fpt_get();
     else { set_error("fc2d_tune_get: unknown knob"); return FC2D_E_ARG; }
     return FC2D_OK;

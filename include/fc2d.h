@@ -239,11 +239,14 @@ int fc2d_trace_end(int* n, const char** names, float* ms, int cap);
  * The plan-specific stages run as single persistent launches over all plans;
  * the FFT passes run once per (nx, ny, h) with those fields contiguous.  The
  * plans must share d, C, n_r, M and have power-of-two grids, and must outlive
- * the batch.  flags: FC2D_BATCH_AUTOTUNE times the column-pass tile widths and
- * the strip kernel's fields per thread on the batch's buffers and keeps the
- * fastest (process-wide, see fc2d_tune_set).  State starts at zero. */
+ * the batch.  flags: FC2D_BATCH_FUSED_FF runs the forward column pass, the
+ * propagation and the inverse column pass of each grid size as one kernel
+ * (instead of three); FC2D_BATCH_AUTOTUNE times the column-pass shapes, the
+ * fused against the separate spectral step per grid size and the strip
+ * kernel's fields per thread on the batch's buffers and keeps the fastest
+ * (launch shapes are process-wide, see fc2d_tune_set).  State starts at zero. */
 typedef struct fc2d_batch fc2d_batch;
-enum { FC2D_BATCH_AUTOTUNE = 1 };
+enum { FC2D_BATCH_AUTOTUNE = 1, FC2D_BATCH_FUSED_FF = 2 };
 int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, unsigned flags,
                       hipStream_t stream, fc2d_batch** out);
 /* Device pointers to plan k's state: u and u_t, each [nf[k]][nx][ny]. */

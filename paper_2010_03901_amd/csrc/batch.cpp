@@ -31,6 +31,7 @@ struct Group {
     std::vector<int> members;     // plan indices
     double* state = nullptr;      // [2][nf_total][nx][ny]: u then u_t
     double* spec = nullptr;       // [2][nf_total][nx][ny/2+1] complex128
+    bool fused_ff = false;        // column passes and propagation in one launch (k_cols_ff)
 };
 }  // namespace fc2d
 
@@ -69,6 +70,18 @@ static void batch_free(fc2d_batch* b) {
     delete b;
 }
 
+// column transforms and propagation of one grid-size group (rows already transformed)
+static int spectral_step(Group& g, double c, double dt, hipStream_t s) {
+    const int64_t nsp = (int64_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;
+    double* su = g.spec;
+    double* sut = g.spec + (int64_t)g.nf_total * nsp;
+    if (g.fused_ff) return cols_ff(&g.grid, c, dt, su, sut, g.nf_total, s);
+    int st;
+    if ((st = fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s))) return st;
+    if ((st = ff_apply(&g.grid, c, dt, su, sut, su, sut, g.nf_total, s))) return st;
+    return fft_cols(&g.grid, g.spec, 2 * g.nf_total, true, s);
+}
+
 // enqueue one Fourier-Forwarding step of the whole batch on s
 static int batch_step(fc2d_batch* b, double c, double dt, hipStream_t s) {
     int st;
@@ -91,13 +104,9 @@ static int batch_step(fc2d_batch* b, double c, double dt, hipStream_t s) {
                 ++n;
             }
         }
-        double* su = g.spec;
-        double* sut = g.spec + (int64_t)g.nf_total * nsp;
-        if ((st = fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s))) return st;
-        if ((st = ff_apply(&g.grid, c, dt, su, sut, su, sut, g.nf_total, s))) return st;
-        if ((st = fft_cols(&g.grid, g.spec, 2 * g.nf_total, true, s))) return st;
+        if ((st = spectral_step(g, c, dt, s))) return st;
         if ((st = fft_rows_inv(&g.grid, g.spec, g.state, 2 * g.nf_total, s))) return st;
-        n += 4;
+        n += g.fused_ff ? 2 : 4;
     }
     b->launches_per_step = n;
     return FC2D_OK;
@@ -134,6 +143,19 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
                 if (ms >= 0 && ms < best) { best = ms; best_E = E; best_T = T; }
             }
         col_cfg_set(g.grid.nx, best_E, best_T);
+        // separate column passes + propagation, or the fused kernel
+        float t_sep = -1.0f, t_fused = -1.0f;
+        g.fused_ff = false;
+        t_sep = time_ms(s, [&]() { return spectral_step(g, 1.0, 0.0, s); }, 3);
+        g.fused_ff = true;
+        int best_v = colff_get(g.grid.nx);
+        for (int v = 0; v < colff_variants(g.grid.nx); ++v) {
+            colff_set(g.grid.nx, v);
+            const float ms = time_ms(s, [&]() { return spectral_step(g, 1.0, 0.0, s); }, 3);
+            if (ms >= 0 && (t_fused < 0 || ms < t_fused)) { t_fused = ms; best_v = v; }
+        }
+        colff_set(g.grid.nx, best_v);
+        g.fused_ff = t_fused >= 0 && (t_sep < 0 || t_fused < t_sep);
     }
     // strip kernel: fields per thread
     int best_f = b->strip_fpt;
@@ -281,6 +303,8 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
         batch_free(b);
         return FC2D_E_HIP;
     }
+    if (flags & FC2D_BATCH_FUSED_FF)
+        for (Group& g : b->groups) g.fused_ff = true;
     if (flags & FC2D_BATCH_AUTOTUNE) st = autotune(b, s);
     if (st) { batch_free(b); return st; }
     if (hipStreamSynchronize(s) != hipSuccess) { set_error("batch set-up failed"); batch_free(b); return FC2D_E_HIP; }

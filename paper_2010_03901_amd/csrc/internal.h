@@ -162,6 +162,12 @@ int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipS
 int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,
              double* uth, int nf, hipStream_t s);
+// column pass + propagation by t + inverse column pass in one launch, in place
+// on row-transformed spectra su, sut ([nf][nx][ny/2+1] each)
+int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s);
+int colff_variants(int nx);   // compiled launch shapes of cols_ff for length nx
+int colff_get(int nx);
+int colff_set(int nx, int v);
 
 // masked row pass: elements per thread and the thread-order class layout
 int row_elems(int L);

@@ -157,6 +157,14 @@ constexpr int pick_radix(int rem, int E) {
 // spreads over the banks; a bijection on every aligned block of 64 elements.
 __device__ __forceinline__ int swz(int x) { return x ^ ((x >> 3) & 7); }
 
+// x, hidden from the optimiser (an empty asm that claims to change it): keeps
+// the twiddles of a later transform from being merged with an earlier one's
+// and held in registers in between
+__device__ __forceinline__ int opaque(int x) {
+    asm volatile("" : "+v"(x));
+    return x;
+}
+
 // exp(-2 pi i a / n) for 0 <= a < n, n a power of two (2a/n is exact)
 __device__ __forceinline__ double2 unit_root(int a, int n) {
     double sn, cs;
@@ -214,7 +222,7 @@ struct StockhamFrom {
                 const int b = t + i * P;
                 const int j = b % Ns;
                 double2 w[R];
-                root_powers<R>(unit_root(j, Ns * R), w);
+                root_powers<R>(unit_root(opaque(j), Ns * R), w);
 #pragma unroll
                 for (int r = 1; r < R; ++r) v[i * R + r] = cmul(v[i * R + r], INV ? cconj(w[r]) : w[r]);
             }
@@ -633,6 +641,26 @@ int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, in
     return check("k_spectral", s);
 }
 
+// Propagation of mode (i, j) by t (eq. wave_2d_ff): (f0, f1) = (u0h, u1h) -> (uh, uth)
+__device__ __forceinline__ void ff_mode(int i, int j, int nx, double Lx, double Ly, double c, double t, double2 f0,
+                                        double2 f1, double2* ra, double2* rt) {
+    const double l = (i <= nx / 2) ? (double)i : (double)(i - nx);
+    const double m = (double)j;
+    const double a = l / Lx, b = m / Ly;
+    const double w = 2.0 * M_PI * c * sqrt(a * a + b * b);
+    if (i == 0 && j == 0) {
+        *ra = make_double2(f0.x + t * f1.x, f0.y + t * f1.y);
+        *rt = f1;
+    } else {
+        double sw, cw;
+        sincos(w * t, &sw, &cw);
+        const double sinc = w > 0 ? sw / w : t;
+        *ra = make_double2(cw * f0.x + sinc * f1.x, cw * f0.y + sinc * f1.y);
+        const double mw = -w * sw;
+        *rt = make_double2(mw * f0.x + cw * f1.x, mw * f0.y + cw * f1.y);
+    }
+}
+
 __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2* uth, int64_t n, int nx, int ny,
                      double h, double c, double t) {
     const int ncol = ny / 2 + 1;
@@ -640,26 +668,107 @@ __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2*
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         int i, j;
         mode_of(e, nx, ncol, &i, &j);
-        const double l = (i <= nx / 2) ? (double)i : (double)(i - nx);
-        const double m = (double)j;
-        const double a = l / Lx, b = m / Ly;
-        const double w = 2.0 * M_PI * c * sqrt(a * a + b * b);
-        const double2 f0 = u0[e], f1 = u1[e];
         double2 ra, rt;
-        if (i == 0 && j == 0) {
-            ra = make_double2(f0.x + t * f1.x, f0.y + t * f1.y);
-            rt = f1;
-        } else {
-            double sw, cw;
-            sincos(w * t, &sw, &cw);
-            const double sinc = w > 0 ? sw / w : t;
-            ra = make_double2(cw * f0.x + sinc * f1.x, cw * f0.y + sinc * f1.y);
-            const double mw = -w * sw;
-            rt = make_double2(mw * f0.x + cw * f1.x, mw * f0.y + cw * f1.y);
-        }
+        ff_mode(i, j, nx, Lx, Ly, c, t, u0[e], u1[e], &ra, &rt);
         uh[e] = ra;
         uth[e] = rt;
     }
+}
+
+// Column pass fused with the propagation, for spectra whose rows are already
+// transformed (the middle of a Fourier-Forwarding step): a block takes the
+// same T/2 adjacent columns of u_hat and of u_t_hat of one field, transforms
+// them along x, propagates every mode by t (the partner value comes through
+// LDS), transforms back along x and writes both in place.  Replaces forward
+// column pass + propagation + inverse column pass (three reads and writes of
+// both spectra) by one.
+template <int L, int E, int T>
+__global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict__ su, double2* __restrict__ sut,
+                                                         int ncol, int nx, double Lx, double Ly, double c, double t) {
+    constexpr int H = T / 2;
+    __shared__ double2 lds[L * T];
+    const int q = threadIdx.x % T;
+    const int tt = threadIdx.x / T;
+    const int comp = q / H;            // 0: u_hat, 1: u_t_hat
+    const int ntiles = (ncol + H - 1) / H;
+    const int per_xcd = (ntiles + 7) / 8;
+    const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    if (tile >= ntiles) return;   // uniform per block
+    const int col = tile * H + q % H;
+    const bool live = col < ncol;
+    double2* base = (comp ? sut : su) + (int64_t)blockIdx.y * L * ncol + (live ? col : 0);
+    double2 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, tt) * ncol];
+    StockhamFrom<L, E, 1, false>::run(v, lds, 1, T, q, tt, nullptr, L);
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[swz(out_index<L, E>(k, tt) * T + q)] = v[k];
+    __syncthreads();
+    // propagate every (row i, column pair) in LDS; one mode at a time keeps the
+    // transcendental work out of the unrolled register code
+    const int tile_col0 = tile * H;
+#pragma unroll 1
+    for (int e = threadIdx.x; e < L * H; e += T * (L / E)) {
+        const int i = e / H, cq = e % H;
+        const int a = swz(i * T + cq), b = swz(i * T + cq + H);
+        double2 ra, rt;
+        ff_mode(i, tile_col0 + cq, nx, Lx, Ly, c, t, lds[a], lds[b], &ra, &rt);
+        lds[a] = ra;
+        lds[b] = rt;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) v[k] = lds[swz(in_index<L, E>(k, tt) * T + q)];
+    __syncthreads();   // the inverse transform reuses lds
+    StockhamFrom<L, E, 1, true>::run(v, lds, 1, T, q, tt, nullptr, L);
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, tt) * ncol] = v[k];
+}
+
+// shapes (elements per thread, columns per block) of the fused kernel per
+// length 2^lg: g_colff_var[lg] indexes the compiled list of that length
+static int g_colff_var[14] = {0};
+
+int colff_variants(int nx) {
+    switch (nx) {
+        case 256: case 512: case 1024: return 3;
+        case 2048: return 4;
+        case 16: case 32: case 64: case 128: case 4096: return 1;
+    }
+    return 0;
+}
+int colff_get(int nx) { int lg = 0; while ((1 << lg) < nx) ++lg; return lg <= 13 ? g_colff_var[lg] : 0; }
+int colff_set(int nx, int v) {
+    if (v < 0 || v >= colff_variants(nx)) return FC2D_E_ARG;
+    int lg = 0;
+    while ((1 << lg) < nx) ++lg;
+    g_colff_var[lg] = v;
+    return FC2D_OK;
+}
+
+int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s) {
+    const int ncol = g->ny / 2 + 1;
+    const double Lx = g->nx * g->h, Ly = g->ny * g->h;
+    const int var = colff_get(g->nx);
+#define FC2D_COLFF(LL, VV, EE, TT)                                                                           \
+    if (g->nx == LL && var == VV) {                                                                         \
+        const int ntiles = (ncol + TT / 2 - 1) / (TT / 2);                                                  \
+        dim3 grid(((ntiles + 7) / 8) * 8, nf);                                                              \
+        k_cols_ff<LL, EE, TT><<<grid, TT * (LL / EE), 0, s>>>((double2*)su, (double2*)sut, ncol, g->nx, Lx, \
+                                                               Ly, c, t);                                   \
+        return check("k_cols_ff", s);                                                                       \
+    }
+    FC2D_COLFF(16, 0, 2, 8) FC2D_COLFF(32, 0, 2, 8) FC2D_COLFF(64, 0, 2, 8) FC2D_COLFF(128, 0, 2, 8)
+    FC2D_COLFF(256, 0, 4, 8) FC2D_COLFF(256, 1, 4, 4) FC2D_COLFF(256, 2, 2, 8)
+    FC2D_COLFF(512, 0, 8, 8) FC2D_COLFF(512, 1, 8, 4) FC2D_COLFF(512, 2, 4, 8)
+    FC2D_COLFF(1024, 0, 8, 4) FC2D_COLFF(1024, 1, 8, 8) FC2D_COLFF(1024, 2, 16, 4)
+    FC2D_COLFF(2048, 0, 8, 2) FC2D_COLFF(2048, 1, 8, 4) FC2D_COLFF(2048, 2, 16, 2) FC2D_COLFF(2048, 3, 16, 4)
+    FC2D_COLFF(4096, 0, 16, 2)
+#undef FC2D_COLFF
+    set_error("cols_ff: unsupported length");
+    return FC2D_E_ARG;
 }
 
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh, double* uth,

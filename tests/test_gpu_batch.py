@@ -111,3 +111,26 @@ def test_batch_graph_replays_match_eager(batch_setup, torch_mod):
             du, dut = batch.state(k)
             assert np.array_equal(du.cpu().numpy(), eager[step][k][0]), (step, k)
             assert np.array_equal(dut.cpu().numpy(), eager[step][k][1]), (step, k)
+
+
+def test_fused_spectral_step_matches_separate(batch_setup, torch_mod):
+    """The fused column-pass + propagation kernel against the separate passes
+    and against the oracle's step, on the same plans and initial data."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    _, cases, oplans, gplans, nf, u0 = batch_setup
+    dt = 0.02
+    res = []
+    for fused in (False, True):
+        b = fc2d.Batch(gplans, nf, fused_ff=fused)
+        _load_state(b, u0)
+        b.ff_run(1.0, dt, 1, use_graph=False)
+        torch.cuda.synchronize()
+        res.append([tuple(t.cpu().numpy().copy() for t in b.state(k)) for k in range(len(nf))])
+        b.close()
+    for k, (opl, m) in enumerate(zip(oplans, nf)):
+        for f in range(m):
+            ou, out_ = OF.ff_step(opl, u0[k][f], np.zeros_like(u0[k][f]), dt)
+            for j, ref in ((0, ou), (1, out_)):
+                assert rel_err(res[1][k][j][f], res[0][k][j][f]) < 1e-13
+                assert rel_err(res[1][k][j][f], ref) < 1e-11

@@ -58,66 +58,97 @@ struct Acc2 {
     }
 };
 
-// Matching values and Gram coefficients of normal p for field f (one thread).
-// DT > 0 fixes d = DT at compile time (straight-line code); DT = 0 takes d = Drt.
+// Matching values and Gram coefficients of normal p for field f, computed by
+// the 4 consecutive lanes sq = 0..3 of a group (lane sq handles stars sq and
+// sq + 4, matching values q = sq, sq + 4, ... and coefficients j = sq, sq + 4,
+// ...; the rest travel by cross-lane shuffles).  Every sum is the same Dot2 in
+// the same order as a one-lane evaluation, so results do not depend on the
+// split.  DT > 0 fixes d = DT at compile time; DT = 0 takes d = Drt.  `live`
+// lanes store; the others only take part in the shuffles.
 template <int M, int DT>
-__device__ __forceinline__ void match_one(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
-                                          const double* __restrict__ mwn, const double* __restrict__ Q, int Drt, int B,
-                                          const double* __restrict__ g, const double* __restrict__ bv, int p,
-                                          double* __restrict__ co, double* __restrict__ fo) {
+__device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
+                                            const double* __restrict__ mwn, const double* __restrict__ Q, int Drt,
+                                            int B, const double* __restrict__ g, const double* __restrict__ bv, int p,
+                                            int sq, bool live, double* __restrict__ co, double* __restrict__ fo) {
     const int D = DT > 0 ? DT : Drt;
+    const int lane = threadIdx.x & 63;
+    const int gbase = lane & ~3;
     const int32_t* ref = mref + (int64_t)p * M * M;
     const double* wv = mwv + (int64_t)p * M * M * 2;
     const double* wn = mwn + (int64_t)p * (D - 1) * M * 2;
-    // red-star values along the grid lines (Sec. 3.2, first interpolation)
+    // red-star values along the grid lines (Sec. 3.2, first interpolation): stars sq, sq + 4
+    dd mine[2];
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+        const int s = sq + 4 * r;
+        Acc2 a;
+        if (s < M) {
+#pragma unroll
+            for (int k = 0; k < M; ++k) {
+                const int o = s * M + k;
+                const int32_t rr = ref[o];
+                const double val = *(rr >= 0 ? g + rr : bv + B + (-rr - 1));   // grid node or square: one load
+                a.add(dd{wv[2 * o], wv[2 * o + 1]}, val);
+            }
+        }
+        mine[r] = a.result();
+    }
     dd star[M];
 #pragma unroll
     for (int s = 0; s < M; ++s) {
-        Acc2 a;
-#pragma unroll
-        for (int k = 0; k < M; ++k) {
-            const int o = s * M + k;
-            const int32_t r = ref[o];
-            const double val = *(r >= 0 ? g + r : bv + B + (-r - 1));   // grid node or square: one load
-            a.add(dd{wv[2 * o], wv[2 * o + 1]}, val);
-        }
-        star[s] = a.result();
+        const int src = gbase + (s & 3);
+        const dd v = (s < 4) ? mine[0] : mine[1];
+        star[s] = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
     }
-    // matching values along the normal (second interpolation), then Q^T f_D
+    // matching values along the normal (second interpolation)
     const double fbp = bv[p];
-    dd fD[9];
+    dd fq[3];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int r = 0; r < 3; ++r) {
+        const int q = sq + 4 * r;
+        Acc2 a;
         if (q < D - 1) {
-            Acc2 a;
 #pragma unroll
             for (int s = 0; s < M; ++s) {
                 const int o = q * M + s;
                 a.add(dd{wn[2 * o], wn[2 * o + 1]}, star[s]);
             }
-            fD[q] = a.result();
-        } else {
-            fD[q] = dd{fbp, 0.0};
+        }
+        fq[r] = q < D - 1 ? a.result() : dd{fbp, 0.0};
+    }
+    dd fD[12];
+#pragma unroll
+    for (int q = 0; q < 12; ++q) {
+        if (q < D) {
+            const int src = gbase + (q & 3);
+            const dd v = (q < 4) ? fq[0] : ((q < 8) ? fq[1] : fq[2]);
+            const dd x = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
+            fD[q] = q < D - 1 ? x : dd{fbp, 0.0};
         }
     }
     // c_p = Q^T f_{D_p}, stored with the boundary value appended: [c_0..c_{d-1}, f_{D_p}[d-1], 0 pad]
     const int DP = (D + 2) & ~1;
 #pragma unroll
-    for (int j = 0; j < 9; ++j) {
+    for (int r = 0; r < 3; ++r) {
+        const int j = sq + 4 * r;
         if (j < D) {
             Acc2 a;
 #pragma unroll
-            for (int q = 0; q < 9; ++q)
+            for (int q = 0; q < 12; ++q)
                 if (q < D) a.add(fD[q], Q[q * D + j]);
-            co[j] = a.result().hi;
+            if (live) co[j] = a.result().hi;
         }
     }
-    co[D] = fbp;
-    if (DP > D + 1) co[D + 1] = 0.0;
-    if (fo) {
+    if (live && sq == 0) {
+        co[D] = fbp;
+        if (DP > D + 1) co[D + 1] = 0.0;
+    }
+    if (live && fo) {
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
-            if (q < D) fo[q] = fD[q].hi;
+        for (int r = 0; r < 3; ++r) {
+            const int q = sq + 4 * r;
+            if (q < D) fo[q] = fq[r].hi;   // this lane's own value (the boundary value for q = d-1)
+        }
     }
 }
 
@@ -129,8 +160,9 @@ __device__ __forceinline__ int xcd_normal(int l, int B) {
     return (l % 8) * per_xcd + l / 8;
 }
 
-// One thread per (normal p, field f): the weights of normal p are uniform
-// across the wave (scalar loads), each lane gathers its own field's values.
+// A wave takes one normal p and 16 fields, 4 lanes per field (stars and sums
+// split as in match_group); the normal's references and weights are shared by
+// the wave, each lane gathers its own field's values.
 template <int M, int DT>
 __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
                                               const double* __restrict__ mwn, const double* __restrict__ Q, int D,
@@ -138,14 +170,16 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
                                               const double* __restrict__ fb, int64_t nbdry, int nf,
                                               double* __restrict__ c_out, double* __restrict__ fD_out) {
     const int p = xcd_normal(blockIdx.x, B);
-    const int f = blockIdx.y * 64 + threadIdx.x;
-    if (p >= B || f >= nf) return;
+    if (p >= B) return;   // uniform per block
+    const int fl = blockIdx.y * 16 + threadIdx.x / 4;
+    const bool live = fl < nf;
+    const int f = live ? fl : 0;
     const int DP = (D + 2) & ~1;
-    match_one<M, DT>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p,
-                 c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
+    match_group<M, DT>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p, threadIdx.x & 3,
+                       live, c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
 }
 
-// Persistent form over several plans (a batch): work item w covers 64 fields
+// Persistent form over several plans (a batch): work item w covers 16 fields
 // of one normal of one plan; items of plan k start at a multiple of 8 so the
 // XCD assignment above is kept.  Every block loops until the items run out.
 template <int M, int DT>
@@ -157,11 +191,14 @@ __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ 
         const int64_t l = w - P.off_match;
         const int padB = (P.B + 7) & ~7;
         const int p = xcd_normal((int)(l % padB), P.B);
-        const int f = (int)(l / padB) * 64 + threadIdx.x;
-        if (p >= P.B || f >= P.nf) continue;
+        if (p >= P.B) continue;   // uniform per block
+        const int fl = (int)(l / padB) * 16 + threadIdx.x / 4;
+        const bool live = fl < P.nf;
+        const int f = live ? fl : 0;
         const int DP = (P.D + 2) & ~1;
-        match_one<M, DT>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts, P.fb + (int64_t)f * P.nbdry, p,
-                     P.c + ((int64_t)f * P.B + p) * DP, nullptr);
+        match_group<M, DT>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts,
+                           P.fb + (int64_t)f * P.nbdry, p, threadIdx.x & 3, live, P.c + ((int64_t)f * P.B + p) * DP,
+                           nullptr);
     }
 }
 
@@ -418,7 +455,7 @@ static int launch_check(const char* what, hipStream_t s) {
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry, double* c_out,
                  double* fD_out, int nf, hipStream_t s) {
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
-    dim3 grid(((pl->B + 7) / 8) * 8, (nf + 63) / 64);
+    dim3 grid(((pl->B + 7) / 8) * 8, (nf + 15) / 16);
     switch (pl->M) {
 #define FC2D_MATCH(MM) \
         case MM: \

@@ -101,12 +101,15 @@ def test_ff_propagate_against_oracle(torch_mod):
         assert rel_err(at[k].cpu().numpy(), rat) < 1e-13
 
 
-def test_poisson_chain_kite(torch_mod):
+@pytest.mark.parametrize("n", [256, 2048])
+def test_poisson_chain_kite(torch_mod, n):
     """Extension -> R2C -> division by -|k|^2 -> C2R on the kite (the Poisson
-    particular-solution consumer), compared with the oracle chain."""
+    particular-solution consumer), compared with the oracle chain; n = 2048 is
+    the full Poisson workload (fitted box, B = 4096, about 169k STRIP points)."""
     from paper_2010_03901_amd import fc2d
     torch = torch_mod
-    case, opl = oracle_plan("kite256", W.cfg_kite, 256)
+    print("\n[poisson] kite%d" % n, flush=True)
+    case, opl = oracle_plan("kite%d" % n, W.cfg_kite, n)
     gpl = gpu_plan(case)
     f = W.poisson_rhs(0)
     fg, fbo = fields(case, [f], OP.boundary_points(opl))
@@ -125,7 +128,7 @@ def test_poisson_chain_kite(torch_mod):
     err_all = rel_err(up[0].cpu().numpy(), ref)
     inm = opl.cls == OP.IN
     err_in = rel_err(up[0].cpu().numpy()[inm], ref[inm])
-    print("[poisson] kite256 rel err all %.3e interior %.3e" % (err_all, err_in))
+    print("[poisson] kite%d rel err all %.3e interior %.3e" % (n, err_all, err_in))
     assert err_all < 1e-11 and err_in < 1e-11
 
 

@@ -260,3 +260,32 @@ def test_forced_fallback_keeps_results(rnd1024, trained, how):
         pl = _plan(case, seed=fc2d.FC2D_SEED_MLP, mlp_weights=w, mlp_tol=-1.0)
     assert pl.info.n_fallback == pl.info.n_solved
     _same_plan(prox, pl)
+
+
+def test_mlp_plan_full_size_parity(trained, torch_mod):
+    """The learned-seed workload at full size (held-out curve, 4096^2, B = 8192),
+    in the launch configuration the benchmark times: classes and STRIP list
+    against the oracle plan, and the fused extension + FFT of one field
+    against numpy's FFT of the oracle's extension."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    w, _ = trained
+    print("\n[mlp] rnd4096 oracle plan", flush=True)
+    case, opl = oracle_plan("rnd4096", W.cfg_mlp, 4096)
+    mlp = _plan(case, seed=fc2d.FC2D_SEED_MLP, mlp_weights=w)
+    assert np.array_equal(fc2d.fc2d_plan_classes(mlp), opl.cls)
+    idx, th, eta, _ = fc2d.fc2d_plan_strip(mlp)
+    assert np.array_equal(idx, opl.strip_idx)
+    assert np.abs(np.mod(th - opl.strip_theta + math.pi, 2 * math.pi) - math.pi).max() < 1e-13
+    assert np.abs(eta - opl.strip_eta).max() < 1e-14
+    f = W.f_star(2)
+    fg, fbo = fields(case, [f], OP.boundary_points(opl))
+    _, fbg = fields(case, [f], fc2d.fc2d_boundary_points(mlp))
+    dfg = _dev(torch, fg)
+    spec = torch.zeros((1, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    fc2d.fc2d_extend_fft(mlp, dfg, _dev(torch, fbg), dfg, spec)
+    torch.cuda.synchronize()
+    ref = np.fft.rfft2(OE.extend(opl, fg[0], fbo[0]))
+    e = rel_err(spec[0].cpu().numpy(), ref)
+    print("[mlp] rnd4096 fallback %.4f, extend_fft rel err %.2e" % (mlp.info.n_fallback / mlp.info.n_solved, e))
+    assert e < 1e-11

@@ -92,6 +92,62 @@ __device__ inline void output_layer(const float* __restrict__ w, const float* in
     out[1] = o1;
 }
 
+// ---- inference on the matrix cores: FP32 MFMA 32x32x2 -------------------
+// One wave evaluates 64 points: each layer is [64 points x K] x [K x 64] as
+// 2 x 2 output tiles of 32 x 32, K/2 MFMA steps each.  Operand lanes (checked
+// on the device): A lane l holds row l % 32, k = l / 32; B lane l holds k =
+// l / 32, column l % 32; D lane l, element r holds row 8 (r / 4) + 4 (l / 32)
+// + r % 4, column l % 32.  Activations pass between layers through per-wave
+// LDS rows of stride kHS (odd, so both access patterns are conflict-free).
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kHS = 65;
+
+template <int K>
+__device__ inline void mfma_layer(const float* __restrict__ W, const float* __restrict__ b, float* Hs, int lane) {
+    const int r32 = lane & 31, hi = lane >> 5;
+    float a[2][K / 2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int ks = 0; ks < K / 2; ++ks) a[mt][ks] = Hs[(r32 + 32 * mt) * kHS + 2 * ks + hi];
+    f32x16 acc[2][2];
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[mt][nt][r] = 0.0f;
+#pragma unroll
+    for (int ks = 0; ks < K / 2; ++ks) {
+        const float b0 = W[(2 * ks + hi) * kH + r32];
+        const float b1 = W[(2 * ks + hi) * kH + 32 + r32];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt) {
+            acc[mt][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mt][ks], b0, acc[mt][0], 0, 0, 0);
+            acc[mt][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a[mt][ks], b1, acc[mt][1], 0, 0, 0);
+        }
+    }
+    // every input of this wave has been read (above, into registers): overwrite in place
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        const float bias = b[r32 + 32 * nt];
+#pragma unroll
+        for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+            for (int r = 0; r < 16; ++r)
+                Hs[(8 * (r / 4) + 4 * hi + (r & 3) + 32 * mt) * kHS + r32 + 32 * nt] = tanhf(acc[mt][nt][r] + bias);
+    }
+}
+
+// Network outputs for the wave's 64 points; row `lane` of Hs holds this lane's
+// 8 inputs on entry (all 64 lanes take part).
+__device__ inline void forward_wave(const float* __restrict__ w, float* Hs, int lane, float* out) {
+    mfma_layer<kNin>(w + kOffW0, w + kOffB0, Hs, lane);
+    mfma_layer<kH>(w + kOffW1, w + kOffB1, Hs, lane);
+    mfma_layer<kH>(w + kOffW2, w + kOffB2, Hs, lane);
+    output_layer<1>(w, Hs + lane * kHS, out);
+}
+
 // forward pass of one lane; x0 = its inputs (stride STRIDE), a1..a3 its
 // activation columns (stride STRIDE, may alias each other for inference)
 template <int STRIDE>
@@ -111,11 +167,11 @@ __device__ inline void forward_lane(const float* __restrict__ w, const float* x0
 __global__ __launch_bounds__(64) void k_seed_mlp(SeedArgs a, const float* __restrict__ w,
                                                  const int32_t* __restrict__ cand, int64_t ncand, int8_t* cls,
                                                  StripRec* rec, int64_t cap, int* counters) {
-    __shared__ float col[(kH + kNin) * 64];   // per-lane columns [feature][64]
+    __shared__ float Hs[64 * kHS];   // the wave's activation rows
     const int lane = threadIdx.x;
     const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-    if (k >= ncand) return;
-    const int64_t idx = cand[k];
+    const bool live = k < ncand;     // every lane takes part in the matrix products
+    const int64_t idx = cand[live ? k : ncand - 1];
     const int i = (int)(idx / a.ny);
     const int j = (int)(idx - (int64_t)i * a.ny);
     const double X = a.x0 + i * a.h;
@@ -123,12 +179,11 @@ __global__ __launch_bounds__(64) void k_seed_mlp(SeedArgs a, const float* __rest
     float f[kNin];
     double phi, b0, b1;
     mlp_features(a.curve.a, a.curve.nmodes, X, Y, a.width, f, &phi, &b0, &b1);
-    float* xin = col + kH * 64 + lane;
 #pragma unroll
-    for (int q = 0; q < kNin; ++q) xin[q * 64] = f[q];
+    for (int q = 0; q < kNin; ++q) Hs[lane * kHS + q] = f[q];
     float out[2];
-    float* c = col + lane;
-    forward_lane<64>(w, xin, c, c, c, out);
+    forward_wave(w, Hs, lane, out);
+    if (!live) return;
     double th = phi + a.width * (b0 + (double)out[0] / kTargetScale);
     // two plain Newton steps, then the residual |g / g'|
     double o[6], dx = 0.0, dy = 0.0, g = 0.0, gp = 0.0;
@@ -210,16 +265,15 @@ __global__ __launch_bounds__(256) void k_mlp_data(const double* __restrict__ cur
 
 __global__ __launch_bounds__(64) void k_mlp_forward(const float* __restrict__ w, const float* __restrict__ X,
                                                     int64_t n, float* out) {
-    __shared__ float col[(kH + kNin) * 64];
+    __shared__ float Hs[64 * kHS];
     const int lane = threadIdx.x;
     const int64_t k = (int64_t)blockIdx.x * 64 + lane;
-    if (k >= n) return;
-    float* xin = col + kH * 64 + lane;
+    const int64_t kk = k < n ? k : n - 1;   // every lane takes part in the matrix products
 #pragma unroll
-    for (int q = 0; q < kNin; ++q) xin[q * 64] = X[k * kNin + q];
+    for (int q = 0; q < kNin; ++q) Hs[lane * kHS + q] = X[kk * kNin + q];
     float r[2];
-    float* c = col + lane;
-    forward_lane<64>(w, xin, c, c, c, r);
+    forward_wave(w, Hs, lane, r);
+    if (k >= n) return;
     out[2 * k] = r[0];
     out[2 * k + 1] = r[1];
 }

@@ -402,8 +402,9 @@ def main():
         if name == "begin":
             continue
         per.setdefault(name, []).append(t)
+    # the fused path may split the fields into chunks: bytes per launch = bytes per step / launches per step
     kernels = {k: {"avg_ms": float(np.mean(v)), "launches": len(v),
-                   "alg_bytes": algorithmic_bytes(k, case.n, nf, info)} for k, v in per.items()}
+                   "alg_bytes": algorithmic_bytes(k, case.n, nf, info) * args.steps / len(v)} for k, v in per.items()}
     for k, v in kernels.items():
         v["GBs"] = v["alg_bytes"] / (v["avg_ms"] * 1e-3) / 1e9 if v["avg_ms"] > 0 else None
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])

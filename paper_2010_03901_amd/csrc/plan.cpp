@@ -39,10 +39,17 @@ namespace fc2d {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-// kernel tracer
+// kernel tracer: an event after every launch; a kernel's time is measured from
+// the previous event on the same stream (a marker, name == nullptr, is recorded
+// after each cross-stream wait so waiting is not counted)
+struct TraceRec {
+    const char* name;
+    hipEvent_t ev;
+    hipStream_t stream;
+};
 static std::mutex g_trace_mu;
 static bool g_trace_on = false;
-static std::vector<std::pair<const char*, hipEvent_t>> g_trace;
+static std::vector<TraceRec> g_trace;
 
 void trace_point(const char* name, hipStream_t s) {
     std::lock_guard<std::mutex> lk(g_trace_mu);
@@ -53,7 +60,7 @@ void trace_point(const char* name, hipStream_t s) {
         (void)hipEventDestroy(e);
         return;
     }
-    g_trace.push_back({name, e});
+    g_trace.push_back({name, e, s});
 }
 
 static int hip_fail(hipError_t e, const char* what) {
@@ -711,6 +718,7 @@ int ensure_work(const fc2d_plan* cpl, int nf) {
 
 static std::mutex g_work_mu;
 
+
 }  // namespace fc2d
 
 using namespace fc2d;
@@ -936,7 +944,7 @@ int fc2d_tune_get(int knob, int n, int* value) {
 int fc2d_trace_begin(hipStream_t stream) {
     {
         std::lock_guard<std::mutex> lk(g_trace_mu);
-        for (auto& t : g_trace) (void)hipEventDestroy(t.second);
+        for (auto& t : g_trace) (void)hipEventDestroy(t.ev);
         g_trace.clear();
         g_trace_on = true;
     }
@@ -949,20 +957,24 @@ int fc2d_trace_end(int* n, const char** names, float* ms, int cap) {
     g_trace_on = false;
     int k = 0;
     int st = FC2D_OK;
-    if (!g_trace.empty()) {
-        hipError_t e = hipEventSynchronize(g_trace.back().second);
-        if (e != hipSuccess) st = hip_fail(e, "fc2d_trace_end");
-        for (size_t i = 1; i < g_trace.size() && st == FC2D_OK; ++i) {
-            if (k < cap) {
-                float t = 0.0f;
-                if (hipEventElapsedTime(&t, g_trace[i - 1].second, g_trace[i].second) != hipSuccess) t = -1.0f;
-                if (names) names[k] = g_trace[i].first;
-                if (ms) ms[k] = t;
-            }
-            ++k;
-        }
+    for (const TraceRec& r : g_trace) {
+        hipError_t e = hipEventSynchronize(r.ev);
+        if (e != hipSuccess) { st = hip_fail(e, "fc2d_trace_end"); break; }
     }
-    for (auto& t : g_trace) (void)hipEventDestroy(t.second);
+    for (size_t i = 1; i < g_trace.size() && st == FC2D_OK; ++i) {
+        if (!g_trace[i].name) continue;   // marker
+        size_t j = i;
+        while (j > 0 && g_trace[j - 1].stream != g_trace[i].stream) --j;
+        const size_t prev = j > 0 ? j - 1 : 0;
+        if (k < cap) {
+            float t = 0.0f;
+            if (hipEventElapsedTime(&t, g_trace[prev].ev, g_trace[i].ev) != hipSuccess) t = -1.0f;
+            if (names) names[k] = g_trace[i].name;
+            if (ms) ms[k] = t;
+        }
+        ++k;
+    }
+    for (auto& t : g_trace) (void)hipEventDestroy(t.ev);
     g_trace.clear();
     if (n) *n = std::min(k, cap);
     return st;

@@ -5,7 +5,8 @@
 //            c_p = Q^T f_{D_p}, each a compensated dot product with
 //            double-double weights (rounded once); the normal's weights are
 //            uniform over the wave.
-//  k_strip   one thread per STRIP point looping over a chunk of fields:
+//  k_strip   one thread per two STRIP points (consecutive in foot-parameter
+//            order, sharing most of their normals) looping over a chunk of fields:
 //            interpolation onto H n V+
 //            (Sec. 3.4).  Because every normal carries the same level weights
 //            v(eta_Q), the continuation values never need to be formed:
@@ -247,31 +248,37 @@ __device__ __forceinline__ void equi_weights(double x, double* w) {
     for (int m = 0; m < M; ++m) w[m] = pre[m] * suf[m] * equi_inv_den<M>(m);
 }
 
-// Interpolated value at STRIP point k for fields [f0, f1) (one thread).
+// Per-point part of the interpolation at STRIP point k: theta weights w over
+// S_{theta^Q} (nodes p0 - kl .. p0 - kl + M - 1), the factored level vector u
+// (u[j] = sum_l v_l A_r[l-1, j], u[d] = v_0 at level 0) and the grid index.
 // DT > 0 fixes d = DT at compile time (straight-line code); DT = 0 takes d = Drt.
+template <int M>
+struct StripPt {
+    double w[M];
+    double u[10];
+    int p0;
+    int32_t idx;
+};
+
 template <int M, int DT>
-__device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
-                                          const double* __restrict__ seta, int64_t k, const double* sAr, int Drt,
-                                          int Cr, int B, double k2, double lev_scale, const double* __restrict__ c,
-                                          double* __restrict__ out, int64_t npts, int f0, int f1) {
+__device__ __forceinline__ void strip_setup(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
+                                            const double* __restrict__ seta, int64_t k, const double* sAr, int Drt,
+                                            int Cr, double k2, double lev_scale, StripPt<M>& P) {
     const int D = DT > 0 ? DT : Drt;
     const double th = sth[k];
     const double eta = seta[k];
-    const int32_t idx = sidx[k];
+    P.idx = sidx[k];
     constexpr int kl = (M - 1) / 2;
-    const int p0 = (M % 2 == 0) ? (int)floor(th / k2) : (int)rint(th / k2);
-    // theta weights over S_{theta^Q}: nodes theta_{p0-kl+m}, m = 0..M-1, in units of k2
-    double w[M];
-    equi_weights<M>((th - (double)(p0 - kl) * k2) / k2, w);
+    P.p0 = (M % 2 == 0) ? (int)floor(th / k2) : (int)rint(th / k2);
+    equi_weights<M>((th - (double)(P.p0 - kl) * k2) / k2, P.w);
     // level weights at s = eta n_r / k1 (nodes l0..l0+M-1) and u = A_r^T v (factored blend)
     const double s = eta * lev_scale;
     int l0 = (int)floor(s) - M / 2 + 1;
     l0 = l0 < 0 ? 0 : (l0 > Cr - M + 1 ? Cr - M + 1 : l0);
     double v[M];
     equi_weights<M>(s - (double)l0, v);
-    double u[10];
 #pragma unroll
-    for (int j = 0; j < 10; ++j) u[j] = 0.0;
+    for (int j = 0; j < 10; ++j) P.u[j] = 0.0;
 #pragma unroll
     for (int l = 0; l < M; ++l) {
         const int lev = l0 + l;            // level 0 is the boundary value, not a row of A_r
@@ -279,35 +286,123 @@ __device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, cons
         const double* row = sAr + (lev >= 1 ? lev - 1 : 0) * D;
 #pragma unroll
         for (int j = 0; j < 9; ++j)
-            if (j < D) u[j] += vl * row[j];
+            if (j < D) P.u[j] += vl * row[j];
     }
     // slot D of each normal's record holds its boundary value: weight v_0 when l0 = 0
-    u[D] = (l0 == 0) ? v[0] : 0.0;
+    P.u[D] = (l0 == 0) ? v[0] : 0.0;
+}
+
+// u . c_q for the Gram record of normal q (slots 0..d-1 = c, slot d = boundary value)
+__device__ __forceinline__ double record_dot(const double* __restrict__ cf, int q, int DP, const double* u) {
+    const double2* rec = (const double2*)(cf + (int64_t)q * DP);
+    double g = 0.0;
+#pragma unroll
+    for (int j2 = 0; j2 < 5; ++j2) {
+        if (2 * j2 < DP) {
+            const double2 cc = rec[j2];
+            g += u[2 * j2] * cc.x + u[2 * j2 + 1] * cc.y;
+        }
+    }
+    return g;
+}
+
+__device__ __forceinline__ int wrap_index(int q, int B) {
+    q %= B;
+    return q < 0 ? q + B : q;
+}
+
+// Interpolated value at STRIP point k for fields [f0, f1) (one thread).
+template <int M, int DT>
+__device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
+                                          const double* __restrict__ seta, int64_t k, const double* sAr, int Drt,
+                                          int Cr, int B, double k2, double lev_scale, const double* __restrict__ c,
+                                          double* __restrict__ out, int64_t npts, int f0, int f1) {
+    const int D = DT > 0 ? DT : Drt;
+    StripPt<M> P;
+    strip_setup<M, DT>(sidx, sth, seta, k, sAr, Drt, Cr, k2, lev_scale, P);
+    constexpr int kl = (M - 1) / 2;
     const int DP = (D + 2) & ~1;
     int pj[M];
 #pragma unroll
-    for (int m = 0; m < M; ++m) {
-        int q = (p0 - kl + m) % B;
-        pj[m] = q < 0 ? q + B : q;
-    }
+    for (int m = 0; m < M; ++m) pj[m] = wrap_index(P.p0 - kl + m, B);
 #pragma unroll 2
     for (int f = f0; f < f1; ++f) {
         const double* cf = c + (int64_t)f * B * DP;
         double ext = 0.0;
 #pragma unroll
-        for (int m = 0; m < M; ++m) {
-            const double2* rec = (const double2*)(cf + (int64_t)pj[m] * DP);
-            double gsum = 0.0;
+        for (int m = 0; m < M; ++m) ext += P.w[m] * record_dot(cf, pj[m], DP, P.u);
+        out[(int64_t)f * npts + P.idx] = ext;
+    }
+}
+
+// Two STRIP points ka, kb (kb = -1: none) for fields [f0, f1) (one thread).
+// The points are consecutive in foot-parameter order, so their stencils
+// usually start at the same or the next normal: then the M + 1 Gram records
+// of the shared window are read once for both points.
+template <int M, int DT>
+__device__ __forceinline__ void strip_pair(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
+                                           const double* __restrict__ seta, int64_t ka, int64_t kb,
+                                           const double* sAr, int Drt, int Cr, int B, double k2, double lev_scale,
+                                           const double* __restrict__ c, double* __restrict__ out, int64_t npts,
+                                           int f0, int f1) {
+    const int D = DT > 0 ? DT : Drt;
+    StripPt<M> A, Bp;
+    strip_setup<M, DT>(sidx, sth, seta, ka, sAr, Drt, Cr, k2, lev_scale, A);
+    strip_setup<M, DT>(sidx, sth, seta, kb >= 0 ? kb : ka, sAr, Drt, Cr, k2, lev_scale, Bp);
+    constexpr int kl = (M - 1) / 2;
+    const int DP = (D + 2) & ~1;
+    const int dlt = Bp.p0 - A.p0;
+    if (kb >= 0 && (dlt == 0 || dlt == 1)) {
+        double wa[M + 1], wb[M + 1];
+        int pj[M + 1];
 #pragma unroll
-            for (int j2 = 0; j2 < 5; ++j2) {
-                if (2 * j2 < DP) {
-                    const double2 cc = rec[j2];
-                    gsum += u[2 * j2] * cc.x + u[2 * j2 + 1] * cc.y;
-                }
-            }
-            ext += w[m] * gsum;
+        for (int m = 0; m <= M; ++m) {
+            wa[m] = m < M ? A.w[m] : 0.0;
+            wb[m] = dlt == 0 ? (m < M ? Bp.w[m] : 0.0) : (m >= 1 ? Bp.w[m - 1] : 0.0);
+            pj[m] = wrap_index(A.p0 - kl + m, B);
         }
-        out[(int64_t)f * npts + idx] = ext;
+#pragma unroll 2
+        for (int f = f0; f < f1; ++f) {
+            const double* cf = c + (int64_t)f * B * DP;
+            double ea = 0.0, eb = 0.0;
+#pragma unroll
+            for (int m = 0; m <= M; ++m) {
+                const double2* rec = (const double2*)(cf + (int64_t)pj[m] * DP);
+                double ga = 0.0, gb = 0.0;
+#pragma unroll
+                for (int j2 = 0; j2 < 5; ++j2) {
+                    if (2 * j2 < DP) {
+                        const double2 cc = rec[j2];
+                        ga += A.u[2 * j2] * cc.x + A.u[2 * j2 + 1] * cc.y;
+                        gb += Bp.u[2 * j2] * cc.x + Bp.u[2 * j2 + 1] * cc.y;
+                    }
+                }
+                ea += wa[m] * ga;
+                eb += wb[m] * gb;
+            }
+            out[(int64_t)f * npts + A.idx] = ea;
+            out[(int64_t)f * npts + Bp.idx] = eb;
+        }
+        return;
+    }
+    // stencils apart (or a single point): one window each
+    int pa[M], pb[M];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+        pa[m] = wrap_index(A.p0 - kl + m, B);
+        pb[m] = wrap_index(Bp.p0 - kl + m, B);
+    }
+    for (int f = f0; f < f1; ++f) {
+        const double* cf = c + (int64_t)f * B * DP;
+        double ea = 0.0, eb = 0.0;
+#pragma unroll
+        for (int m = 0; m < M; ++m) ea += A.w[m] * record_dot(cf, pa[m], DP, A.u);
+        out[(int64_t)f * npts + A.idx] = ea;
+        if (kb >= 0) {
+#pragma unroll
+            for (int m = 0; m < M; ++m) eb += Bp.w[m] * record_dot(cf, pb[m], DP, Bp.u);
+            out[(int64_t)f * npts + Bp.idx] = eb;
+        }
     }
 }
 
@@ -323,7 +418,7 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
     // blocks are dealt round-robin to the 8 XCDs: when the field chunks divide
     // evenly, each XCD gets a contiguous range of them, so its L2 holds only
     // those fields' Gram records
-    const int pblocks = (int)((S + 255) / 256);
+    const int pblocks = (int)((S + 511) / 512);   // 256 threads x 2 points
     const int nchunks = (nf + fpt - 1) / fpt;
     int chunk, pb;
     if (nchunks % 8 == 0) {
@@ -334,10 +429,11 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
         chunk = blockIdx.x / pblocks;
         pb = blockIdx.x % pblocks;
     }
-    const int64_t k = (int64_t)pb * 256 + threadIdx.x;
-    if (k >= S) return;
+    const int64_t ka = ((int64_t)pb * 256 + threadIdx.x) * 2;   // two consecutive points per thread
+    if (ka >= S) return;
     const int f0 = chunk * fpt;
-    strip_one<M, DT>(sidx, sth, seta, k, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0, min(nf, f0 + fpt));
+    strip_pair<M, DT>(sidx, sth, seta, ka, ka + 1 < S ? ka + 1 : -1, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0,
+                      min(nf, f0 + fpt));
 }
 
 // Persistent form over several plans: work item w = (plan, block of 256 STRIP
@@ -483,8 +579,8 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     if (S == 0) return FC2D_OK;
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
     // fields per thread: at most 8, the chunks a multiple of 8 (an equal range
-    // per XCD) when there are at least 8 fields
-    const int64_t pblocks = (S + 255) / 256;
+    // per XCD) when there are at least 8 fields; two points per thread
+    const int64_t pblocks = (S + 511) / 512;
     int fpt = g_strip_fpt;
     if (fpt <= 0) fpt = nf >= 8 ? (nf + 8 * ((nf + 63) / 64) - 1) / (8 * ((nf + 63) / 64)) : 1;
     fpt = std::max(1, std::min(fpt, nf));

@@ -674,9 +674,27 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         if ((st = dev_upload(&pl->d_mref, mref.data(), mref.size()))) break;
         if ((st = dev_upload(&pl->d_mwv, mwv.data(), mwv.size()))) break;
         if ((st = dev_upload(&pl->d_mwn, mwn.data(), mwn.size()))) break;
-        if ((st = dev_upload(&pl->d_sidx, pl->strip_idx.data(), pl->strip_idx.size()))) break;
-        if ((st = dev_upload(&pl->d_sth, pl->strip_theta.data(), pl->strip_theta.size()))) break;
-        if ((st = dev_upload(&pl->d_seta, pl->strip_eta.data(), pl->strip_eta.size()))) break;
+        {
+            // the strip kernel takes the points in order of their foot parameter,
+            // so the lanes of a wave share the Gram records of nearly the same
+            // normals (the host copies stay in row-major order)
+            const size_t S = pl->strip_idx.size();
+            std::vector<size_t> ord(S);
+            for (size_t k = 0; k < S; ++k) ord[k] = k;
+            std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
+                return pl->strip_theta[a] < pl->strip_theta[b];
+            });
+            std::vector<int32_t> oi(S);
+            std::vector<double> ot(S), oe(S);
+            for (size_t k = 0; k < S; ++k) {
+                oi[k] = pl->strip_idx[ord[k]];
+                ot[k] = pl->strip_theta[ord[k]];
+                oe[k] = pl->strip_eta[ord[k]];
+            }
+            if ((st = dev_upload(&pl->d_sidx, oi.data(), S))) break;
+            if ((st = dev_upload(&pl->d_sth, ot.data(), S))) break;
+            if ((st = dev_upload(&pl->d_seta, oe.data(), S))) break;
+        }
         if ((st = dev_upload(&pl->d_run_ptr, run_ptr.data(), run_ptr.size()))) break;
         if ((st = dev_upload(&pl->d_run, runs.data(), runs.size()))) break;
         {

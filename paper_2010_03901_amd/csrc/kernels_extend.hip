@@ -161,20 +161,26 @@ __device__ __forceinline__ int xcd_normal(int l, int B) {
     return (l % 8) * per_xcd + l / 8;
 }
 
-// A wave takes one normal p and 16 fields, 4 lanes per field (stars and sums
-// split as in match_group); the normal's references and weights are shared by
-// the wave, each lane gathers its own field's values.
-template <int M, int DT>
+// A wave takes NPW consecutive normals and 16 / NPW fields, 4 lanes per
+// (normal, field) (stars and sums split as in match_group).  With NPW = 1 the
+// normal's references and weights are shared by the wave; with NPW > 1 the
+// lanes of one field gather from overlapping stencils, so fewer distinct lines.
+template <int M, int DT, int NPW>
 __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
                                               const double* __restrict__ mwn, const double* __restrict__ Q, int D,
                                               int B, const double* __restrict__ fg, int64_t npts,
                                               const double* __restrict__ fb, int64_t nbdry, int nf,
                                               double* __restrict__ c_out, double* __restrict__ fD_out) {
-    const int p = xcd_normal(blockIdx.x, B);
-    if (p >= B) return;   // uniform per block
-    const int fl = blockIdx.y * 16 + threadIdx.x / 4;
-    const bool live = fl < nf;
-    const int f = live ? fl : 0;
+    constexpr int FPW = 16 / NPW;
+    const int nq = (B + NPW - 1) / NPW;
+    const int qd = xcd_normal(blockIdx.x, nq);
+    if (qd >= nq) return;   // uniform per block
+    const int gi = threadIdx.x / 4;
+    const int pn = qd * NPW + gi / FPW;
+    const int fl = blockIdx.y * FPW + gi % FPW;
+    const bool live = fl < nf && pn < B;
+    const int f = fl < nf ? fl : 0;
+    const int p = pn < B ? pn : B - 1;
     const int DP = (D + 2) & ~1;
     match_group<M, DT>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p, threadIdx.x & 3,
                        live, c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
@@ -551,12 +557,17 @@ static int launch_check(const char* what, hipStream_t s) {
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry, double* c_out,
                  double* fD_out, int nf, hipStream_t s) {
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
-    dim3 grid(((pl->B + 7) / 8) * 8, (nf + 15) / 16);
+    // four normals x four fields per wave when there are enough fields to share
+    const int npw = nf >= 4 ? 4 : 1;
+    const int nq = (pl->B + npw - 1) / npw;
+    dim3 grid(((nq + 7) / 8) * 8, (nf + 16 / npw - 1) / (16 / npw));
     switch (pl->M) {
 #define FC2D_MATCH(MM) \
         case MM: \
-            if (pl->d == 5) k_match<MM, 5><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else k_match<MM, 0><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            if (pl->d == 5 && npw == 4) k_match<MM, 5, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else if (pl->d == 5) k_match<MM, 5, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else if (npw == 4) k_match<MM, 0, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else k_match<MM, 0, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
             break;
         FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8)
 #undef FC2D_MATCH

@@ -272,7 +272,7 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
             P.fb = fb;
             P.c = cb;
             P.off_match = om;
-            om += (int64_t)((P.B + 7) & ~7) * ((P.nf + 15) / 16);   // k_match_multi: 16 fields per item
+            om += (int64_t)((((P.B + 3) / 4) + 7) & ~7) * ((P.nf + 3) / 4);   // k_match_multi: 4 normals x 4 fields
             P.off_bv = ob;
             ob += (int64_t)P.nf * nb;
             b->pd.push_back(P);

@@ -186,9 +186,10 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
                        live, c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
 }
 
-// Persistent form over several plans (a batch): work item w covers 16 fields
-// of one normal of one plan; items of plan k start at a multiple of 8 so the
-// XCD assignment above is kept.  Every block loops until the items run out.
+// Persistent form over several plans (a batch): work item w covers four
+// consecutive normals x four fields of one plan (as k_match with NPW = 4);
+// items of plan k start at a multiple of 8 so the XCD assignment is kept.
+// Every block loops until the items run out.
 template <int M, int DT>
 __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ pd, int np, int64_t total) {
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
@@ -196,12 +197,16 @@ __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ 
         while (k + 1 < np && pd[k + 1].off_match <= w) ++k;
         const PlanDev& P = pd[k];
         const int64_t l = w - P.off_match;
-        const int padB = (P.B + 7) & ~7;
-        const int p = xcd_normal((int)(l % padB), P.B);
-        if (p >= P.B) continue;   // uniform per block
-        const int fl = (int)(l / padB) * 16 + threadIdx.x / 4;
-        const bool live = fl < P.nf;
-        const int f = live ? fl : 0;
+        const int nq = (P.B + 3) / 4;
+        const int padQ = (nq + 7) & ~7;
+        const int qd = xcd_normal((int)(l % padQ), nq);
+        if (qd >= nq) continue;   // uniform per block
+        const int gi = threadIdx.x / 4;
+        const int pn = qd * 4 + gi / 4;
+        const int fl = (int)(l / padQ) * 4 + gi % 4;
+        const bool live = fl < P.nf && pn < P.B;
+        const int f = fl < P.nf ? fl : 0;
+        const int p = pn < P.B ? pn : P.B - 1;
         const int DP = (P.D + 2) & ~1;
         match_group<M, DT>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts,
                            P.fb + (int64_t)f * P.nbdry, p, threadIdx.x & 3, live, P.c + ((int64_t)f * P.B + p) * DP,

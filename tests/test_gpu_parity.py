@@ -179,3 +179,39 @@ def test_extend_fft_fused(both, torch_mod):
         e = rel_err(s1[k], ref)
         print("[parity] extend_fft", name, "field", k, "rel err %.3e" % e)
         assert e < 1e-11
+
+
+@pytest.mark.parametrize("nf", [16, 128])
+def test_extend_fft_benchmark_configuration(torch_mod, nf):
+    """The star workload at 1024^2 with as many fields as the benchmark times
+    (nf = 128: the launch shapes used there -- four normals x four fields per
+    matching wave, strip field chunks split over the XCDs); sampled fields
+    against numpy's FFT of the oracle's extension, and the plain path against
+    the fused one."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    case, opl = oracle_plan("star1024", W.cfg_star, 1024)
+    gpl = gpu_plan(case)
+    print("\n[parity] star1024 nf=%d" % nf, flush=True)
+    bpg = fc2d.fc2d_boundary_points(gpl)
+    fg = torch.empty((nf, case.n, case.n), dtype=torch.float64, device="cuda:0")
+    fb = torch.empty((nf, bpg.shape[0]), dtype=torch.float64, device="cuda:0")
+    for s in range(nf):                     # the same host values feed both sides
+        f = W.f_star(s)
+        fg[s].copy_(torch.from_numpy(W.grid_values(case, f)))
+        fb[s].copy_(torch.from_numpy(f(bpg[:, 0], bpg[:, 1])))
+    spec = torch.empty((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    work = torch.empty_like(fg)
+    fc2d.fc2d_extend_fft(gpl, fg, fb, work, spec)
+    ext = torch.empty_like(fg)
+    fc2d.fc2d_extend(gpl, fg, fb, ext)
+    torch.cuda.synchronize()
+    bpo = OP.boundary_points(opl)
+    for s in sorted({0, 1, nf // 2 - 1, nf - 1}):
+        f = W.f_star(s)
+        fgo = W.grid_values(case, f)
+        ref = OE.extend(opl, fgo, f(bpo[:, 0], bpo[:, 1]))
+        e_ext = rel_err(ext[s].cpu().numpy(), ref)
+        e_spec = rel_err(spec[s].cpu().numpy(), np.fft.rfft2(ref))
+        print("[parity] nf=%d field %d: extend %.2e, extend_fft %.2e" % (nf, s, e_ext, e_spec))
+        assert e_ext < 1e-11 and e_spec < 1e-11

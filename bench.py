@@ -161,12 +161,12 @@ def run_batched(args):
         ut.zero_()
     torch.cuda.synchronize()
     pts, _, sf = batch.info()
-    batch.ff_run(1.0, 0.01, 1, use_graph=True)          # capture + warm-up
+    batch.run_ff(1.0, 0.01, 1, use_graph=True)          # capture + warm-up
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     ev0.record()
-    batch.ff_run(1.0, 0.01, args.ff_steps, use_graph=True)
+    batch.run_ff(1.0, 0.01, args.ff_steps, use_graph=True)
     ev1.record()
     torch.cuda.synchronize()
     ms = ev0.elapsed_time(ev1) / args.ff_steps

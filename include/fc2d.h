@@ -258,7 +258,7 @@ int fc2d_batch_info(const fc2d_batch* batch, int64_t* points_per_step, int* laun
 /* Advance by `steps` steps of dt (wave speed c) on `stream`.  use_graph: the
  * step is captured once in a HIP graph (re-captured when c or dt change) and
  * replayed. */
-int fc2d_batch_ff_run(fc2d_batch* batch, double c, double dt, int steps, int use_graph, hipStream_t stream);
+int fc2d_batch_run_ff(fc2d_batch* batch, double c, double dt, int steps, int use_graph, hipStream_t stream);
 int fc2d_batch_destroy(fc2d_batch* batch);
 
 /* ---- Learned foot-of-normal seed: training data, training, inference ----

@@ -331,7 +331,7 @@ int fc2d_batch_info(const fc2d_batch* b, int64_t* points_per_step, int* launches
     return FC2D_OK;
 }
 
-int fc2d_batch_ff_run(fc2d_batch* b, double c, double dt, int steps, int use_graph, hipStream_t s) {
+int fc2d_batch_run_ff(fc2d_batch* b, double c, double dt, int steps, int use_graph, hipStream_t s) {
     if (!b || steps < 0) { set_error("invalid batch arguments"); return FC2D_E_ARG; }
     int st;
     if (!use_graph) {

@@ -86,7 +86,7 @@ def _lib():
             "fc2d_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int), C.c_int, C.c_uint, _P, C.POINTER(_P)]),
             "fc2d_batch_state": (C.c_int, [_P, C.c_int, C.POINTER(_P), C.POINTER(_P)]),
             "fc2d_batch_info": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int), C.POINTER(C.c_int)]),
-            "fc2d_batch_ff_run": (C.c_int, [_P, C.c_double, C.c_double, C.c_int, C.c_int, _P]),
+            "fc2d_batch_run_ff": (C.c_int, [_P, C.c_double, C.c_double, C.c_int, C.c_int, _P]),
             "fc2d_batch_destroy": (C.c_int, [_P]),
             "fc2d_tune_set": (C.c_int, [C.c_int, C.c_int, C.c_int]),
             "fc2d_tune_get": (C.c_int, [C.c_int, C.c_int, C.POINTER(C.c_int)]),
@@ -342,8 +342,8 @@ class Batch:
         _check(_lib().fc2d_batch_info(self._h, C.byref(pts), C.byref(nl), C.byref(sf)))
         return pts.value, nl.value, sf.value
 
-    def ff_run(self, c, dt, steps, use_graph=True, stream=None):
-        _check(_lib().fc2d_batch_ff_run(self._h, float(c), float(dt), int(steps), 1 if use_graph else 0,
+    def run_ff(self, c, dt, steps, use_graph=True, stream=None):
+        _check(_lib().fc2d_batch_run_ff(self._h, float(c), float(dt), int(steps), 1 if use_graph else 0,
                                         _stream(stream)))
 
     def close(self):

@@ -99,3 +99,24 @@ def test_mlp_argument_errors_without_gpu():
     assert lib.fc2d_mlp_train(p, p, p, p, p, 10, 0, 1, 0, 1e-3, 1e-5, 1, None, None) == fc2d.FC2D_E_ARG   # batch 0
     assert lib.fc2d_mlp_train(p, p, p, p, p, 10, 4, 0, 0, 1e-3, 1e-5, 1, None, None) == fc2d.FC2D_OK     # no steps
     assert lib.fc2d_mlp_make_data(p, 1, 8, p, p, p, 5, 0.0, p, p, None, None, None) == fc2d.FC2D_E_ARG   # width 0
+
+
+def test_geometry_rejected_before_any_device_work():
+    """Admissibility (Sec. 3.1): C k1 above 0.9 x the exterior reach, or a box
+    that does not hold Omega u V+, fail with FC2D_E_GEOMETRY on the host."""
+    from paper_2010_03901_amd import fc2d
+    import workloads as W
+    lib = fc2d._lib()
+    star = fc2d.make_curve(*W.star5())
+    g = fc2d.make_grid(-1.6, -1.6, 3.2 / 256, 256, 256)
+    h = C.c_void_p()
+    o = fc2d.fc2d_opts()
+    lib.fc2d_opts_default(C.byref(g), C.byref(o))
+    o.k1 = 0.01                                       # C k1 = 0.27 > 0.9 x reach 0.072
+    assert lib.fc2d_plan_create(C.byref(star), C.byref(g), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_GEOMETRY
+    assert b"reach" in lib.fc2d_last_error()
+    small = fc2d.make_grid(-1.2, -1.2, 2.4 / 256, 256, 256)   # the star reaches 1.3
+    lib.fc2d_opts_default(C.byref(small), C.byref(o))
+    o.k1 = 0.002
+    assert lib.fc2d_plan_create(C.byref(star), C.byref(small), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_GEOMETRY
+    assert b"box" in lib.fc2d_last_error()

@@ -80,7 +80,7 @@ def test_batch_one_step_matches_oracle(batch_setup, torch_mod):
     print("[batch] points/step", pts, "launches/step", nl, "strip fields/thread", sf)
     _load_state(batch, u0)
     dt = 0.02
-    batch.ff_run(1.0, dt, 1, use_graph=False)
+    batch.run_ff(1.0, dt, 1, use_graph=False)
     torch.cuda.synchronize()
     for k, (opl, m) in enumerate(zip(oplans, nf)):
         du, dut = batch.state(k)
@@ -99,12 +99,12 @@ def test_batch_graph_replays_match_eager(batch_setup, torch_mod):
     _load_state(batch, u0)
     eager = []
     for _ in range(3):
-        batch.ff_run(1.0, dt, 1, use_graph=False)
+        batch.run_ff(1.0, dt, 1, use_graph=False)
         torch.cuda.synchronize()
         eager.append([tuple(t.cpu().numpy().copy() for t in batch.state(k)) for k in range(len(nf))])
     _load_state(batch, u0)
     for step in range(3):
-        batch.ff_run(1.0, dt, 1, use_graph=True)
+        batch.run_ff(1.0, dt, 1, use_graph=True)
         torch.cuda.synchronize()
         _ = torch.ones(1, device="cuda:0").sum().item()       # unrelated eager work between replays
         for k in range(len(nf)):
@@ -124,7 +124,7 @@ def test_fused_spectral_step_matches_separate(batch_setup, torch_mod):
     for fused in (False, True):
         b = fc2d.Batch(gplans, nf, fused_ff=fused)
         _load_state(b, u0)
-        b.ff_run(1.0, dt, 1, use_graph=False)
+        b.run_ff(1.0, dt, 1, use_graph=False)
         torch.cuda.synchronize()
         res.append([tuple(t.cpu().numpy().copy() for t in b.state(k)) for k in range(len(nf))])
         b.close()
@@ -150,7 +150,7 @@ def test_batch_three_steps_match_oracle(batch_setup, torch_mod):
     batch, cases, oplans, gplans, nf, u0 = batch_setup
     dt = 0.02
     _load_state(batch, u0)
-    batch.ff_run(1.0, dt, 3, use_graph=True)
+    batch.run_ff(1.0, dt, 3, use_graph=True)
     torch.cuda.synchronize()
     rng = np.random.default_rng(42)
 

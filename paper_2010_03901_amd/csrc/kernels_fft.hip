@@ -404,20 +404,37 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __res
 // are dispatched round-robin over the 8 XCDs), letting the two halves of a
 // 128-byte line be served by one L2.
 // ---------------------------------------------------------------------------
+// Block -> (field, column tile).  Blocks are dealt round-robin to the 8 XCDs.
+// by_field (field count a multiple of 8): XCD x takes whole fields x, x + 8, ...,
+// so no cache line is fetched by two XCDs (the 16-byte shift of the half-spectrum
+// rows puts the column-range boundaries inside lines); otherwise each XCD takes
+// a contiguous range of tiles of every field (grid y = field).
+__device__ __forceinline__ bool col_block(int ntiles, bool by_field, int* tile, int* field) {
+    if (by_field) {
+        const int local = blockIdx.x / 8;
+        *tile = local % ntiles;
+        *field = (local / ntiles) * 8 + (int)(blockIdx.x % 8);
+        return true;
+    }
+    const int per_xcd = (ntiles + 7) / 8;
+    *tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
+    *field = blockIdx.y;
+    return *tile < ntiles;
+}
+
 template <int L, int E, int T, bool INV>
 __global__ __launch_bounds__(T * (L / E)) void k_cols(double2* __restrict__ data, int ncol,
-                                                      const double2* __restrict__ tw) {
+                                                      const double2* __restrict__ tw, int by_field) {
     constexpr int P = L / E;
     __shared__ double2 lds[L * T];
     const int q = threadIdx.x % T;
     const int t = threadIdx.x / T;
     const int ntiles = (ncol + T - 1) / T;
-    const int per_xcd = (ntiles + 7) / 8;
-    const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (tile >= ntiles) return;   // uniform per block
+    int tile, field;
+    if (!col_block(ntiles, by_field != 0, &tile, &field)) return;   // uniform per block
     const int col = tile * T + q;
     const bool live = col < ncol;
-    double2* base = data + (int64_t)blockIdx.y * L * ncol + (live ? col : 0);
+    double2* base = data + (int64_t)field * L * ncol + (live ? col : 0);
     double2 v[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, t) * ncol];
@@ -541,8 +558,9 @@ static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* 
 #define FC2D_COLT(LL, EE, TT)                                                                    \
     if (nx == LL && E == EE && T == TT) {                                                        \
         const int ntiles = (ncol + TT - 1) / TT;                                                 \
-        dim3 g(((ntiles + 7) / 8) * 8, nf);                                                      \
-        k_cols<LL, EE, TT, INV><<<g, TT * (LL / EE), 0, s>>>(data, ncol, tw);                    \
+        const bool byf = nf % 8 == 0;                                                            \
+        const dim3 g = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);   \
+        k_cols<LL, EE, TT, INV><<<g, TT * (LL / EE), 0, s>>>(data, ncol, tw, byf ? 1 : 0);       \
         return;                                                                                  \
     }
     FC2D_COLT(16, 2, 4) FC2D_COLT(16, 2, 8) FC2D_COLT(16, 2, 16)
@@ -684,19 +702,19 @@ __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2*
 // both spectra) by one.
 template <int L, int E, int T>
 __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict__ su, double2* __restrict__ sut,
-                                                         int ncol, int nx, double Lx, double Ly, double c, double t) {
+                                                         int ncol, int nx, double Lx, double Ly, double c, double t,
+                                                         int by_field) {
     constexpr int H = T / 2;
     __shared__ double2 lds[L * T];
     const int q = threadIdx.x % T;
     const int tt = threadIdx.x / T;
     const int comp = q / H;            // 0: u_hat, 1: u_t_hat
     const int ntiles = (ncol + H - 1) / H;
-    const int per_xcd = (ntiles + 7) / 8;
-    const int tile = (blockIdx.x % 8) * per_xcd + blockIdx.x / 8;
-    if (tile >= ntiles) return;   // uniform per block
+    int tile, field;
+    if (!col_block(ntiles, by_field != 0, &tile, &field)) return;   // uniform per block
     const int col = tile * H + q % H;
     const bool live = col < ncol;
-    double2* base = (comp ? sut : su) + (int64_t)blockIdx.y * L * ncol + (live ? col : 0);
+    double2* base = (comp ? sut : su) + (int64_t)field * L * ncol + (live ? col : 0);
     double2 v[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, tt) * ncol];
@@ -755,9 +773,10 @@ int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int
 #define FC2D_COLFF(LL, VV, EE, TT)                                                                           \
     if (g->nx == LL && var == VV) {                                                                         \
         const int ntiles = (ncol + TT / 2 - 1) / (TT / 2);                                                  \
-        dim3 grid(((ntiles + 7) / 8) * 8, nf);                                                              \
+        const bool byf = nf % 8 == 0;                                                                       \
+        const dim3 grid = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);           \
         k_cols_ff<LL, EE, TT><<<grid, TT * (LL / EE), 0, s>>>((double2*)su, (double2*)sut, ncol, g->nx, Lx, \
-                                                               Ly, c, t);                                   \
+                                                               Ly, c, t, byf ? 1 : 0);                      \
         return check("k_cols_ff", s);                                                                       \
     }
     FC2D_COLFF(16, 0, 2, 8) FC2D_COLFF(32, 0, 2, 8) FC2D_COLFF(64, 0, 2, 8) FC2D_COLFF(128, 0, 2, 8)

@@ -170,3 +170,26 @@ def test_batch_three_steps_match_oracle(batch_setup, torch_mod):
         et = rel_err(dut[0].cpu().numpy(), out_)
         print("[batch] three steps plan %d: u %.2e (bar %.2e) u_t %.2e (bar %.2e)" % (k, eu, bar_u, et, bar_t))
         assert eu < bar_u and et < bar_t
+
+
+def test_fused_spectral_step_eight_fields(torch_mod):
+    """Eight fields on one plan (the whole-fields-per-XCD mapping of the column
+    kernels): fused against separate spectral steps, and a field against the
+    oracle's step."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    case, opl = oracle_plan("disc256ff", W.cfg_ff, "disc", 256)
+    gpl = gpu_plan(case)
+    u0 = _pulses(case, range(50, 58))
+    dt = 0.02
+    res = []
+    for fused in (False, True):
+        b = fc2d.Batch([gpl], [8], fused_ff=fused)
+        _load_state(b, [u0])
+        b.run_ff(1.0, dt, 1, use_graph=False)
+        torch.cuda.synchronize()
+        res.append(tuple(t.cpu().numpy().copy() for t in b.state(0)))
+        b.close()
+    assert rel_err(res[1][0], res[0][0]) < 1e-13 and rel_err(res[1][1], res[0][1]) < 1e-13
+    ou, out_ = OF.ff_step(opl, u0[5], np.zeros_like(u0[5]), dt)
+    assert rel_err(res[1][0][5], ou) < 1e-11 and rel_err(res[1][1][5], out_) < 1e-11

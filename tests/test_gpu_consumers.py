@@ -25,14 +25,15 @@ def _dev(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
 
 
-@pytest.mark.parametrize("nx,ny", [(16, 16), (32, 64), (64, 16), (128, 128), (256, 512), (512, 512), (1024, 1024),
-                                   (2048, 256), (256, 2048), (4096, 64), (64, 8192), (16, 4096)])
-def test_fft_sizes(torch_mod, nx, ny):
+@pytest.mark.parametrize("nx,ny,nf", [(16, 16, 3), (32, 64, 3), (64, 16, 3), (128, 128, 3), (256, 512, 3),
+                                      (512, 512, 3), (1024, 1024, 3), (2048, 256, 3), (256, 2048, 3), (4096, 64, 3),
+                                      (64, 8192, 3), (16, 4096, 3), (512, 256, 8), (1024, 128, 16)])
+def test_fft_sizes(torch_mod, nx, ny, nf):
+    """nf a multiple of 8 takes the whole-fields-per-XCD column mapping."""
     from paper_2010_03901_amd import fc2d
     torch = torch_mod
-    print("\n[fft] %dx%d" % (nx, ny), flush=True)
+    print("\n[fft] %dx%d nf=%d" % (nx, ny, nf), flush=True)
     rng = np.random.default_rng(nx * 7 + ny)
-    nf = 3
     u = rng.standard_normal((nf, nx, ny))
     grid = fc2d.make_grid(0.0, 0.0, 0.01, nx, ny)
     du = _dev(torch, u)

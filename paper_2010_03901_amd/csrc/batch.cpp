@@ -253,7 +253,7 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
         for (int half = 0; half < 2; ++half) {
             PlanDev P;
             memset(&P, 0, sizeof P);
-            P.mref = pl->d_mref; P.mwv = pl->d_mwv; P.mwn = pl->d_mwn; P.Q = pl->d_Q;
+            P.mref = pl->d_mref; P.mlab = pl->d_mlab; P.mwv = pl->d_mwv; P.mwn = pl->d_mwn; P.Q = pl->d_Q;
             P.sidx = pl->d_sidx; P.sth = pl->d_sth; P.seta = pl->d_seta; P.bxy = pl->d_bxy;
             P.B = pl->B; P.D = pl->d; P.nf = b->nf[k]; P.nx = g.grid.nx; P.ny = g.grid.ny;
             P.npts = npts; P.nbdry = nb; P.S = (int64_t)pl->strip_idx.size();

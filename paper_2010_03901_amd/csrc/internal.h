@@ -45,15 +45,21 @@ struct fc2d_plan {
     std::vector<int32_t> strip_idx, strip_seed;  // row-major STRIP list
     std::vector<double> strip_theta, strip_eta;
     int newton_max_iters = 0;
+    int strip_wmax = 0;   // widest stencil window (normals) of a block of 512 theta-sorted STRIP points
     int64_t n_in = 0, n_far = 0;
     int seed = 0;
     int64_t n_solved = 0, n_fallback = 0, newton_iters = 0;
     // device
     double* d_Q = nullptr;          // [d][d]
     double* d_Ar = nullptr;         // [Cr][d]
-    int32_t* d_mref = nullptr;      // [B][M][M] grid flat index (>= 0) or -(1 + square)
-    double* d_mwv = nullptr;        // [B][M][M][2] double-double weights along the grid line
-    double* d_mwn = nullptr;        // [B][d-1][M][2] double-double weights along the normal
+    // matching stencils, per normal (NU = ceil(M*M / 4), RQ = ceil((d-1) / 4)):
+    int32_t* d_mref = nullptr;      // [B][4][NU] stencil entries in address order (entry 4u + sq at [sq][u]):
+                                    //   grid flat index (>= 0) or -(1 + square)
+    uint8_t* d_mlab = nullptr;      // [B][4][NU] star s, node k of each entry as s M + k (255: padding)
+    double* d_mwv = nullptr;        // [B][2][M][4][2] weights along the grid line of star 4r + sq, node k at
+                                    //   [r][k][sq] (double-double; zero for stars >= M)
+    double* d_mwn = nullptr;        // [B][RQ][M][4][2] weights along the normal of matching value 4r + sq,
+                                    //   star s at [r][s][sq] (double-double; zero for values >= d-1)
     int32_t* d_sidx = nullptr;      // [S] STRIP flat index
     double* d_sth = nullptr;        // [S] theta^Q
     double* d_seta = nullptr;       // [S] eta_Q
@@ -118,6 +124,7 @@ int launch_seed_mlp(const SeedArgs& a, const float* d_w, const int32_t* d_cand, 
 // ---- batches: one descriptor per (plan, field set) for the persistent kernels ----
 struct PlanDev {
     const int32_t* mref;
+    const uint8_t* mlab;
     const double* mwv;
     const double* mwn;
     const double* Q;

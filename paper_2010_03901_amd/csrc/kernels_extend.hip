@@ -60,24 +60,49 @@ struct Acc2 {
 };
 
 // Matching values and Gram coefficients of normal p for field f, computed by
-// the 4 consecutive lanes sq = 0..3 of a group (lane sq handles stars sq and
-// sq + 4, matching values q = sq, sq + 4, ... and coefficients j = sq, sq + 4,
-// ...; the rest travel by cross-lane shuffles).  Every sum is the same Dot2 in
-// the same order as a one-lane evaluation, so results do not depend on the
-// split.  DT > 0 fixes d = DT at compile time; DT = 0 takes d = Drt.  `live`
-// lanes store; the others only take part in the shuffles.
+// the 4 consecutive lanes sq = 0..3 of a group.
+//  1. Gather: the normal's M*M stencil values (star s, node k) are listed in
+//     order of their address (plan: mref, mlab); lane sq loads list entries
+//     4u + sq, u = 0, 1, ..., so the four lanes of a load read neighbouring
+//     addresses, and stores each value in the group's LDS block xg at s M + k.
+//  2. Red stars (first interpolation, along the grid lines): lane sq forms
+//     stars sq and sq + 4 from xg; the others travel by cross-lane shuffles.
+//  3. Matching values along the normal (second interpolation) q = sq, sq + 4, ...
+//  4. Gram coefficients c_j, j = sq, sq + 4, ...
+// Every sum is a Dot2 over the stencil in node / star order, as in a one-lane
+// evaluation.  DT > 0 fixes d = DT at compile time; DT = 0 takes d = Drt.
+// `live` lanes store; the others only take part in the shuffles.  The caller
+// is one 64-lane block (16 groups); the LDS exchange is fenced by barriers.
 template <int M, int DT>
-__device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
-                                            const double* __restrict__ mwn, const double* __restrict__ Q, int Drt,
-                                            int B, const double* __restrict__ g, const double* __restrict__ bv, int p,
-                                            int sq, bool live, double* __restrict__ co, double* __restrict__ fo) {
+__device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, const uint8_t* __restrict__ mlab,
+                                            const double* __restrict__ mwv, const double* __restrict__ mwn,
+                                            const double* __restrict__ Q, int Drt, int B,
+                                            const double* __restrict__ g, const double* __restrict__ bv, int p,
+                                            int sq, bool live, double* __restrict__ co, double* __restrict__ fo,
+                                            double* xg) {
     const int D = DT > 0 ? DT : Drt;
+    constexpr int NU = ((M * M + 3) & ~3) / 4;   // list entries per lane
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~3;
-    const int32_t* ref = mref + (int64_t)p * M * M;
-    const double* wv = mwv + (int64_t)p * M * M * 2;
-    const double* wn = mwn + (int64_t)p * (D - 1) * M * 2;
-    // red-star values along the grid lines (Sec. 3.2, first interpolation): stars sq, sq + 4
+    // 1. gather in address order
+    {
+        const int32_t* ref = mref + ((int64_t)p * 4 + sq) * NU;
+        const uint8_t* lab = mlab + ((int64_t)p * 4 + sq) * NU;
+        double val[NU];
+        int slot[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u) {
+            const int32_t rr = ref[u];
+            slot[u] = lab[u];
+            val[u] = slot[u] < M * M ? *(rr >= 0 ? g + rr : bv + B + (-rr - 1)) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            if (slot[u] < M * M) xg[slot[u]] = val[u];
+    }
+    __syncthreads();
+    // 2. red-star values along the grid lines (Sec. 3.2, first interpolation): stars sq, sq + 4
+    const double* wv = mwv + (int64_t)p * 2 * M * 4 * 2;   // [r][k][sq] double-double
     dd mine[2];
 #pragma unroll
     for (int r = 0; r < 2; ++r) {
@@ -86,14 +111,13 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
         if (s < M) {
 #pragma unroll
             for (int k = 0; k < M; ++k) {
-                const int o = s * M + k;
-                const int32_t rr = ref[o];
-                const double val = *(rr >= 0 ? g + rr : bv + B + (-rr - 1));   // grid node or square: one load
-                a.add(dd{wv[2 * o], wv[2 * o + 1]}, val);
+                const int o = (r * M + k) * 4 + sq;
+                a.add(dd{wv[2 * o], wv[2 * o + 1]}, xg[s * M + k]);
             }
         }
         mine[r] = a.result();
     }
+    __syncthreads();   // xg may be overwritten by the caller's next item
     dd star[M];
 #pragma unroll
     for (int s = 0; s < M; ++s) {
@@ -101,7 +125,9 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
         const dd v = (s < 4) ? mine[0] : mine[1];
         star[s] = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
     }
-    // matching values along the normal (second interpolation)
+    // 3. matching values along the normal (second interpolation)
+    const int RQ = (D - 1 + 3) / 4;
+    const double* wn = mwn + (int64_t)p * RQ * M * 4 * 2;   // [r][s][sq] double-double
     const double fbp = bv[p];
     dd fq[3];
 #pragma unroll
@@ -111,7 +137,7 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
         if (q < D - 1) {
 #pragma unroll
             for (int s = 0; s < M; ++s) {
-                const int o = q * M + s;
+                const int o = (r * M + s) * 4 + sq;
                 a.add(dd{wn[2 * o], wn[2 * o + 1]}, star[s]);
             }
         }
@@ -127,7 +153,7 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
             fD[q] = q < D - 1 ? x : dd{fbp, 0.0};
         }
     }
-    // c_p = Q^T f_{D_p}, stored with the boundary value appended: [c_0..c_{d-1}, f_{D_p}[d-1], 0 pad]
+    // 4. c_p = Q^T f_{D_p}, stored with the boundary value appended: [c_0..c_{d-1}, f_{D_p}[d-1], 0 pad]
     const int DP = (D + 2) & ~1;
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
@@ -161,16 +187,18 @@ __device__ __forceinline__ int xcd_normal(int l, int B) {
     return (l % 8) * per_xcd + l / 8;
 }
 
-// A wave takes NPW consecutive normals and 16 / NPW fields, 4 lanes per
-// (normal, field) (stars and sums split as in match_group).  With NPW = 1 the
-// normal's references and weights are shared by the wave; with NPW > 1 the
-// lanes of one field gather from overlapping stencils, so fewer distinct lines.
+// A wave (one block) takes NPW consecutive normals and 16 / NPW fields, 4
+// lanes per (normal, field) (as in match_group).  With NPW = 1 the normal's
+// references and weights are shared by the wave; with NPW > 1 the lanes of one
+// field gather from overlapping stencils, so fewer distinct lines.
 template <int M, int DT, int NPW>
-__global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const double* __restrict__ mwv,
-                                              const double* __restrict__ mwn, const double* __restrict__ Q, int D,
-                                              int B, const double* __restrict__ fg, int64_t npts,
+__global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const uint8_t* __restrict__ mlab,
+                                              const double* __restrict__ mwv, const double* __restrict__ mwn,
+                                              const double* __restrict__ Q, int D, int B,
+                                              const double* __restrict__ fg, int64_t npts,
                                               const double* __restrict__ fb, int64_t nbdry, int nf,
                                               double* __restrict__ c_out, double* __restrict__ fD_out) {
+    __shared__ double xg[16 * M * M];
     constexpr int FPW = 16 / NPW;
     const int nq = (B + NPW - 1) / NPW;
     const int qd = xcd_normal(blockIdx.x, nq);
@@ -182,8 +210,9 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
     const int f = fl < nf ? fl : 0;
     const int p = pn < B ? pn : B - 1;
     const int DP = (D + 2) & ~1;
-    match_group<M, DT>(mref, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p, threadIdx.x & 3,
-                       live, c_out + ((int64_t)f * B + p) * DP, fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr);
+    match_group<M, DT>(mref, mlab, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p,
+                       threadIdx.x & 3, live, c_out + ((int64_t)f * B + p) * DP,
+                       fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr, xg + gi * M * M);
 }
 
 // Persistent form over several plans (a batch): work item w covers four
@@ -192,6 +221,7 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
 // Every block loops until the items run out.
 template <int M, int DT>
 __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ pd, int np, int64_t total) {
+    __shared__ double xg[16 * M * M];
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         int k = 0;
         while (k + 1 < np && pd[k + 1].off_match <= w) ++k;
@@ -208,9 +238,9 @@ __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ 
         const int f = fl < P.nf ? fl : 0;
         const int p = pn < P.B ? pn : P.B - 1;
         const int DP = (P.D + 2) & ~1;
-        match_group<M, DT>(P.mref, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts,
+        match_group<M, DT>(P.mref, P.mlab, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts,
                            P.fb + (int64_t)f * P.nbdry, p, threadIdx.x & 3, live, P.c + ((int64_t)f * P.B + p) * DP,
-                           nullptr);
+                           nullptr, xg + gi * M * M);
     }
 }
 
@@ -271,6 +301,13 @@ struct StripPt {
     int32_t idx;
 };
 
+// First normal index of the stencil window of foot parameter th (before the
+// shift by kl): the interval [p0 k2, (p0 + 1) k2) for even M, the nearest node for odd M
+template <int M>
+__device__ __forceinline__ int strip_p0(double th, double k2) {
+    return (M % 2 == 0) ? (int)floor(th / k2) : (int)rint(th / k2);
+}
+
 template <int M, int DT>
 __device__ __forceinline__ void strip_setup(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
                                             const double* __restrict__ seta, int64_t k, const double* sAr, int Drt,
@@ -280,7 +317,7 @@ __device__ __forceinline__ void strip_setup(const int32_t* __restrict__ sidx, co
     const double eta = seta[k];
     P.idx = sidx[k];
     constexpr int kl = (M - 1) / 2;
-    P.p0 = (M % 2 == 0) ? (int)floor(th / k2) : (int)rint(th / k2);
+    P.p0 = strip_p0<M>(th, k2);
     equi_weights<M>((th - (double)(P.p0 - kl) * k2) / k2, P.w);
     // level weights at s = eta n_r / k1 (nodes l0..l0+M-1) and u = A_r^T v (factored blend)
     const double s = eta * lev_scale;
@@ -346,39 +383,38 @@ __device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, cons
     }
 }
 
-// Two STRIP points ka, kb (kb = -1: none) for fields [f0, f1) (one thread).
-// The points are consecutive in foot-parameter order, so their stencils
-// usually start at the same or the next normal: then the M + 1 Gram records
-// of the shared window are read once for both points.
-template <int M, int DT>
-__device__ __forceinline__ void strip_pair(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
-                                           const double* __restrict__ seta, int64_t ka, int64_t kb,
-                                           const double* sAr, int Drt, int Cr, int B, double k2, double lev_scale,
-                                           const double* __restrict__ c, double* __restrict__ out, int64_t npts,
-                                           int f0, int f1) {
+// Two STRIP points A, Bp (hasb = false: A only) for fields [f0, f1) (one
+// thread).  The Gram record of normal q (unwrapped index) for field f is read
+// at base + (f - f0) fstride + r DP, r = q - qoff when the records are staged
+// (STAGED: a window of consecutive normals in LDS), else r = q mod B (the
+// plan's record array).  The points are consecutive in foot-parameter order,
+// so their stencils usually start at the same or the next normal: then the
+// M + 1 records of the shared window are read once for both points.
+template <int M, int DT, bool STAGED>
+__device__ __forceinline__ void strip_pair_fields(const StripPt<M>& A, const StripPt<M>& Bp, bool hasb, int Drt,
+                                                  int B, const double* base, int64_t fstride, int qoff,
+                                                  double* __restrict__ out, int64_t npts, int f0, int f1) {
     const int D = DT > 0 ? DT : Drt;
-    StripPt<M> A, Bp;
-    strip_setup<M, DT>(sidx, sth, seta, ka, sAr, Drt, Cr, k2, lev_scale, A);
-    strip_setup<M, DT>(sidx, sth, seta, kb >= 0 ? kb : ka, sAr, Drt, Cr, k2, lev_scale, Bp);
     constexpr int kl = (M - 1) / 2;
     const int DP = (D + 2) & ~1;
     const int dlt = Bp.p0 - A.p0;
-    if (kb >= 0 && (dlt == 0 || dlt == 1)) {
+    auto rec_index = [&](int q) { return STAGED ? q - qoff : wrap_index(q, B); };
+    if (hasb && (dlt == 0 || dlt == 1)) {
         double wa[M + 1], wb[M + 1];
         int pj[M + 1];
 #pragma unroll
         for (int m = 0; m <= M; ++m) {
             wa[m] = m < M ? A.w[m] : 0.0;
             wb[m] = dlt == 0 ? (m < M ? Bp.w[m] : 0.0) : (m >= 1 ? Bp.w[m - 1] : 0.0);
-            pj[m] = wrap_index(A.p0 - kl + m, B);
+            pj[m] = rec_index(A.p0 - kl + m) * DP;
         }
-#pragma unroll 2
+#pragma unroll 1
         for (int f = f0; f < f1; ++f) {
-            const double* cf = c + (int64_t)f * B * DP;
+            const double* cf = base + (int64_t)(f - f0) * fstride;
             double ea = 0.0, eb = 0.0;
 #pragma unroll
             for (int m = 0; m <= M; ++m) {
-                const double2* rec = (const double2*)(cf + (int64_t)pj[m] * DP);
+                const double2* rec = (const double2*)(cf + pj[m]);
                 double ga = 0.0, gb = 0.0;
 #pragma unroll
                 for (int j2 = 0; j2 < 5; ++j2) {
@@ -400,16 +436,17 @@ __device__ __forceinline__ void strip_pair(const int32_t* __restrict__ sidx, con
     int pa[M], pb[M];
 #pragma unroll
     for (int m = 0; m < M; ++m) {
-        pa[m] = wrap_index(A.p0 - kl + m, B);
-        pb[m] = wrap_index(Bp.p0 - kl + m, B);
+        pa[m] = rec_index(A.p0 - kl + m);
+        pb[m] = rec_index(Bp.p0 - kl + m);
     }
+#pragma unroll 1
     for (int f = f0; f < f1; ++f) {
-        const double* cf = c + (int64_t)f * B * DP;
+        const double* cf = base + (int64_t)(f - f0) * fstride;
         double ea = 0.0, eb = 0.0;
 #pragma unroll
         for (int m = 0; m < M; ++m) ea += A.w[m] * record_dot(cf, pa[m], DP, A.u);
         out[(int64_t)f * npts + A.idx] = ea;
-        if (kb >= 0) {
+        if (hasb) {
 #pragma unroll
             for (int m = 0; m < M; ++m) eb += Bp.w[m] * record_dot(cf, pb[m], DP, Bp.u);
             out[(int64_t)f * npts + Bp.idx] = eb;
@@ -417,13 +454,36 @@ __device__ __forceinline__ void strip_pair(const int32_t* __restrict__ sidx, con
     }
 }
 
+// Gram records of the normals q0 .. q0 + L - 1 (wrapped mod B) for fields
+// [f0, f0 + nfs) copied to LDS: record r of local field f at st + (f lcap + r) DP.
+__device__ __forceinline__ void stage_records(const double* __restrict__ c, int B, int DP, int q0, int L, int lcap,
+                                              int f0, int nfs, double* st) {
+    const int per = L * DP / 2;   // 16-byte parts per field (DP is even)
+    for (int e = threadIdx.x; e < nfs * per; e += blockDim.x) {
+        const int f = e / per;
+        const int h = 2 * (e - f * per);
+        const int r = h / DP;
+        const int j = h - r * DP;
+        const double2 v = *(const double2*)(c + ((int64_t)(f0 + f) * B + wrap_index(q0 + r, B)) * DP + j);
+        *(double2*)(st + ((int64_t)f * lcap + r) * DP + j) = v;
+    }
+}
+
+// One block = 512 consecutive STRIP points (foot-parameter order, two per
+// thread) x one chunk of fields.  The block's stencils cover the normals
+// p0(first) - kl .. p0(last) - kl + M (p0 is monotone in theta); when that
+// window has at most lcap normals, its Gram records are staged in LDS, fstage
+// fields at a time, and every thread reads its records from there; otherwise
+// the threads read the plan's record array directly.
 template <int M, int DT>
 __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
                                                const double* __restrict__ seta, int64_t S, const double* __restrict__ Ar,
                                                int D, int Cr, int B, double k2, double lev_scale,
-                                               const double* __restrict__ c, const double* __restrict__ fb,
-                                               int64_t nbdry, double* __restrict__ out, int64_t npts, int nf, int fpt) {
-    extern __shared__ double sAr[];
+                                               const double* __restrict__ c, double* __restrict__ out, int64_t npts,
+                                               int nf, int fpt, int lcap, int fstage) {
+    extern __shared__ double smem[];
+    double* sAr = smem;
+    double* st = smem + ((Cr * D + 1) & ~1);
     for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
     __syncthreads();
     // blocks are dealt round-robin to the 8 XCDs: when the field chunks divide
@@ -440,11 +500,37 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
         chunk = blockIdx.x / pblocks;
         pb = blockIdx.x % pblocks;
     }
-    const int64_t ka = ((int64_t)pb * 256 + threadIdx.x) * 2;   // two consecutive points per thread
-    if (ka >= S) return;
+    const int64_t kfirst = (int64_t)pb * 512;
+    const int64_t klast = min(S - 1, kfirst + 511);
+    const int64_t ka = kfirst + 2 * threadIdx.x;   // two consecutive points per thread
+    const bool live = ka < S;
     const int f0 = chunk * fpt;
-    strip_pair<M, DT>(sidx, sth, seta, ka, ka + 1 < S ? ka + 1 : -1, sAr, D, Cr, B, k2, lev_scale, c, out, npts, f0,
-                      min(nf, f0 + fpt));
+    const int f1 = min(nf, f0 + fpt);
+    const int Dd = DT > 0 ? DT : D;
+    const int DP = (Dd + 2) & ~1;
+    constexpr int kl = (M - 1) / 2;
+    StripPt<M> A, Bp;
+    const bool hasb = ka + 1 < S;
+    if (live) {
+        strip_setup<M, DT>(sidx, sth, seta, ka, sAr, D, Cr, k2, lev_scale, A);
+        strip_setup<M, DT>(sidx, sth, seta, hasb ? ka + 1 : ka, sAr, D, Cr, k2, lev_scale, Bp);
+    }
+    const int pfirst = strip_p0<M>(sth[kfirst], k2);
+    const int L = strip_p0<M>(sth[klast], k2) - pfirst + M + 1;   // uniform over the block
+    if (L <= lcap) {
+        for (int fs = f0; fs < f1; fs += fstage) {
+            const int nfs = min(fstage, f1 - fs);
+            if (fs > f0) __syncthreads();   // the previous stage has been read
+            stage_records(c, B, DP, pfirst - kl, L, lcap, fs, nfs, st);
+            __syncthreads();
+            if (live)
+                strip_pair_fields<M, DT, true>(A, Bp, hasb, D, B, st, (int64_t)lcap * DP, pfirst - kl, out, npts, fs,
+                                               fs + nfs);
+        }
+    } else if (live) {
+        strip_pair_fields<M, DT, false>(A, Bp, hasb, D, B, c + (int64_t)f0 * B * DP, (int64_t)B * DP, 0, out, npts,
+                                        f0, f1);
+    }
 }
 
 // Persistent form over several plans: work item w = (plan, block of 256 STRIP
@@ -569,10 +655,10 @@ int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry
     switch (pl->M) {
 #define FC2D_MATCH(MM) \
         case MM: \
-            if (pl->d == 5 && npw == 4) k_match<MM, 5, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else if (pl->d == 5) k_match<MM, 5, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else if (npw == 4) k_match<MM, 0, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else k_match<MM, 0, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            if (pl->d == 5 && npw == 4) k_match<MM, 5, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else if (pl->d == 5) k_match<MM, 5, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else if (npw == 4) k_match<MM, 0, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else k_match<MM, 0, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
             break;
         FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8)
 #undef FC2D_MATCH
@@ -602,13 +688,18 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     fpt = std::max(1, std::min(fpt, nf));
     const int64_t nchunks = (nf + fpt - 1) / fpt;
     const dim3 grid((unsigned)(nchunks * pblocks));
-    const size_t lds = (size_t)pl->Cr * pl->d * sizeof(double);
+    // LDS: the blend table, then the staged Gram records (a block's window of
+    // at most lcap normals, at most 16 KB per field and 32 KB per stage)
+    const size_t rec_bytes = (size_t)((pl->d + 2) & ~1) * sizeof(double);
+    const int lcap = (int)std::max<size_t>(1, std::min<size_t>((size_t)pl->strip_wmax, 16384 / rec_bytes));
+    const int fstage = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(fpt, 8), 32768 / (lcap * rec_bytes)));
+    const size_t lds = (size_t)((pl->Cr * pl->d + 1) & ~1) * sizeof(double) + (size_t)fstage * lcap * rec_bytes;
     const double lev_scale = pl->n_r / pl->k1;
     switch (pl->M) {
 #define FC2D_STRIP(MM) \
         case MM: \
-            if (pl->d == 5) k_strip<MM, 5><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts, nf, fpt); \
-            else k_strip<MM, 0><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, f_bdry, nbdry, out, npts, nf, fpt); \
+            if (pl->d == 5) k_strip<MM, 5><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, out, npts, nf, fpt, lcap, fstage); \
+            else k_strip<MM, 0><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, out, npts, nf, fpt, lcap, fstage); \
             break;
         FC2D_STRIP(4) FC2D_STRIP(5) FC2D_STRIP(6) FC2D_STRIP(7) FC2D_STRIP(8)
 #undef FC2D_STRIP

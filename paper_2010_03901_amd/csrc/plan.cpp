@@ -365,7 +365,7 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
 // ----------------------------------------------------------------------------
 static void free_plan(fc2d_plan* pl) {
     if (!pl) return;
-    void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mwv, pl->d_mwn, pl->d_sidx,
+    void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_sidx,
                     pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c, pl->d_cls2, pl->d_bxy};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -671,9 +671,53 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     do {
         if ((st = dev_upload(&pl->d_Q, pl->Q.data(), pl->Q.size()))) break;
         if ((st = dev_upload(&pl->d_Ar, pl->Ar.data(), pl->Ar.size()))) break;
-        if ((st = dev_upload(&pl->d_mref, mref.data(), mref.size()))) break;
-        if ((st = dev_upload(&pl->d_mwv, mwv.data(), mwv.size()))) break;
-        if ((st = dev_upload(&pl->d_mwn, mwn.data(), mwn.size()))) break;
+        {
+            // device layout of the matching stencils: each normal's M*M entries in
+            // address order, dealt to the 4 lanes of a group (entry 4u + sq to lane
+            // sq), and the weights interleaved over the 4 lanes
+            const int M = pl->M, d = pl->d, B = pl->B;
+            const int MM = M * M, NU = ((MM + 3) & ~3) / 4, RQ = (d - 1 + 3) / 4;
+            const int64_t npts = (int64_t)grid->nx * grid->ny;
+            std::vector<int32_t> dref((size_t)B * 4 * NU, 0);
+            std::vector<uint8_t> dlab((size_t)B * 4 * NU, 255);
+            std::vector<double> dwv((size_t)B * 2 * M * 4 * 2, 0.0), dwn((size_t)B * RQ * M * 4 * 2, 0.0);
+            std::vector<int> ord(MM);
+            for (int p = 0; p < B; ++p) {
+                const int32_t* r0 = &mref[(size_t)p * MM];
+                auto key = [&](int e) { return r0[e] >= 0 ? (int64_t)r0[e] : npts + (int64_t)(-r0[e] - 1); };
+                for (int e = 0; e < MM; ++e) ord[e] = e;
+                std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
+                for (int i = 0; i < MM; ++i) {
+                    const size_t o = ((size_t)p * 4 + i % 4) * NU + i / 4;
+                    dref[o] = r0[ord[i]];
+                    dlab[o] = (uint8_t)ord[i];
+                }
+                for (int r = 0; r < 2; ++r)
+                    for (int k = 0; k < M; ++k)
+                        for (int sq = 0; sq < 4; ++sq) {
+                            const int sv = 4 * r + sq;
+                            if (sv >= M) continue;
+                            const size_t on = (((size_t)p * 2 + r) * M + k) * 4 + sq;
+                            const size_t oo = ((size_t)p * M + sv) * M + k;
+                            dwv[2 * on] = mwv[2 * oo];
+                            dwv[2 * on + 1] = mwv[2 * oo + 1];
+                        }
+                for (int r = 0; r < RQ; ++r)
+                    for (int sv = 0; sv < M; ++sv)
+                        for (int sq = 0; sq < 4; ++sq) {
+                            const int q = 4 * r + sq;
+                            if (q >= d - 1) continue;
+                            const size_t on = (((size_t)p * RQ + r) * M + sv) * 4 + sq;
+                            const size_t oo = ((size_t)p * (d - 1) + q) * M + sv;
+                            dwn[2 * on] = mwn[2 * oo];
+                            dwn[2 * on + 1] = mwn[2 * oo + 1];
+                        }
+            }
+            if ((st = dev_upload(&pl->d_mref, dref.data(), dref.size()))) break;
+            if ((st = dev_upload(&pl->d_mlab, dlab.data(), dlab.size()))) break;
+            if ((st = dev_upload(&pl->d_mwv, dwv.data(), dwv.size()))) break;
+            if ((st = dev_upload(&pl->d_mwn, dwn.data(), dwn.size()))) break;
+        }
         {
             // the strip kernel takes the points in order of their foot parameter,
             // so the lanes of a wave share the Gram records of nearly the same
@@ -690,6 +734,16 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                 oi[k] = pl->strip_idx[ord[k]];
                 ot[k] = pl->strip_theta[ord[k]];
                 oe[k] = pl->strip_eta[ord[k]];
+            }
+            // widest window of normals under a strip-kernel block of 512 points
+            // (p0 as the kernel computes it; monotone in theta)
+            auto p0_of = [&](double th) {
+                return (pl->M % 2 == 0) ? (int)floor(th / pl->k2) : (int)rint(th / pl->k2);
+            };
+            pl->strip_wmax = 0;
+            for (size_t k0 = 0; k0 < S; k0 += 512) {
+                const size_t k1 = std::min(S, k0 + 512) - 1;
+                pl->strip_wmax = std::max(pl->strip_wmax, p0_of(ot[k1]) - p0_of(ot[k0]) + pl->M + 1);
             }
             if ((st = dev_upload(&pl->d_sidx, oi.data(), S))) break;
             if ((st = dev_upload(&pl->d_sth, ot.data(), S))) break;

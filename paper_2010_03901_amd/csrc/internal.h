@@ -52,7 +52,7 @@ struct fc2d_plan {
     // device
     double* d_Q = nullptr;          // [d][d]
     double* d_Ar = nullptr;         // [Cr][d]
-    // matching stencils, per normal (NU = ceil(M*M / 4), RQ = ceil((d-1) / 4)):
+    // matching stencils, per normal (NU = 4 ceil(M*M / 16), RQ = ceil((d-1) / 4)):
     int32_t* d_mref = nullptr;      // [B][4][NU] stencil entries in address order (entry 4u + sq at [sq][u]):
                                     //   grid flat index (>= 0) or -(1 + square)
     uint8_t* d_mlab = nullptr;      // [B][4][NU] star s, node k of each entry as s M + k (255: padding)

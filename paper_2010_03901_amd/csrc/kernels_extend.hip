@@ -81,21 +81,27 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
                                             int sq, bool live, double* __restrict__ co, double* __restrict__ fo,
                                             double* xg) {
     const int D = DT > 0 ? DT : Drt;
-    constexpr int NU = ((M * M + 3) & ~3) / 4;   // list entries per lane
+    constexpr int NU = (M * M + 15) / 16 * 4;   // list entries per lane (a multiple of 4)
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~3;
-    // 1. gather in address order
+    // 1. gather in address order (entries and labels read as 16- and 4-byte words)
     {
-        const int32_t* ref = mref + ((int64_t)p * 4 + sq) * NU;
-        const uint8_t* lab = mlab + ((int64_t)p * 4 + sq) * NU;
-        double val[NU];
+        const int4* ref4 = (const int4*)(mref + ((int64_t)p * 4 + sq) * NU);
+        const uint32_t* lab4 = (const uint32_t*)(mlab + ((int64_t)p * 4 + sq) * NU);
+        int32_t rr[NU];
         int slot[NU];
 #pragma unroll
-        for (int u = 0; u < NU; ++u) {
-            const int32_t rr = ref[u];
-            slot[u] = lab[u];
-            val[u] = slot[u] < M * M ? *(rr >= 0 ? g + rr : bv + B + (-rr - 1)) : 0.0;
+        for (int u4 = 0; u4 < NU / 4; ++u4) {
+            const int4 r = ref4[u4];
+            const uint32_t l = lab4[u4];
+            rr[4 * u4] = r.x; rr[4 * u4 + 1] = r.y; rr[4 * u4 + 2] = r.z; rr[4 * u4 + 3] = r.w;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) slot[4 * u4 + b] = (l >> (8 * b)) & 255;
         }
+        double val[NU];
+#pragma unroll
+        for (int u = 0; u < NU; ++u)
+            val[u] = slot[u] < M * M ? *(rr[u] >= 0 ? g + rr[u] : bv + B + (-rr[u] - 1)) : 0.0;
 #pragma unroll
         for (int u = 0; u < NU; ++u)
             if (slot[u] < M * M) xg[slot[u]] = val[u];

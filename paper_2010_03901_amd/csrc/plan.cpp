@@ -676,7 +676,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             // address order, dealt to the 4 lanes of a group (entry 4u + sq to lane
             // sq), and the weights interleaved over the 4 lanes
             const int M = pl->M, d = pl->d, B = pl->B;
-            const int MM = M * M, NU = ((MM + 3) & ~3) / 4, RQ = (d - 1 + 3) / 4;
+            const int MM = M * M, NU = (MM + 15) / 16 * 4, RQ = (d - 1 + 3) / 4;
             const int64_t npts = (int64_t)grid->nx * grid->ny;
             std::vector<int32_t> dref((size_t)B * 4 * NU, 0);
             std::vector<uint8_t> dlab((size_t)B * 4 * NU, 255);

@@ -45,7 +45,7 @@ enum {
 enum { FC2D_CURVE_POLAR = 1, FC2D_CURVE_CARTESIAN = 2 };
 enum { FC2D_FORWARD = -1, FC2D_INVERSE = 1 };
 enum { FC2D_LAPLACE_INV = 1, FC2D_DX = 2, FC2D_DY = 3 };
-enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2, FC2D_TUNE_COL_ELEMS = 3 };
+enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2, FC2D_TUNE_COL_ELEMS = 3, FC2D_TUNE_STRIP_WINDOW = 4 };
 
 /* How the foot-of-normal solve of each grid point near Gamma is started
  * (fc2d_opts.seed):
@@ -213,8 +213,11 @@ int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, con
  * 512 (4 or 8; 4/8), 1024 (8 or 16; 2/4/8), 2048 (16; 1/2/4 and 8; 1/2),
  * 4096 (16; 1/2 and 8; 1).  A setting that would form an uncompiled pair is
  * refused with FC2D_E_ARG.  FC2D_TUNE_STRIP_FIELDS: fields per thread of the
- * strip interpolation (0 = automatic, n ignored).  Not thread-safe against
- * concurrent launches. */
+ * strip interpolation (0 = automatic, n ignored).  FC2D_TUNE_STRIP_WINDOW: at
+ * most this many normals of Gram records are staged in LDS per block of 512
+ * STRIP points (0 = no cap beyond the LDS budget; n ignored); blocks whose
+ * stencils span more normals read the records from device memory instead.
+ * Not thread-safe against concurrent launches. */
 int fc2d_tune_set(int knob, int n, int value);
 int fc2d_tune_get(int knob, int n, int* value);
 

@@ -44,6 +44,7 @@ struct fc2d_batch {
     PlanDev* d_pd = nullptr;
     int64_t tot_match = 0, tot_strip = 0, tot_bv = 0;
     int M = 0, D = 0, Cr = 0, strip_fpt = 4, grid_blocks = 2048;
+    int strip_wmax = 1;   // widest strip-kernel block window over the plans (normals)
     const double* d_Ar = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -87,9 +88,10 @@ static int batch_step(fc2d_batch* b, double c, double dt, hipStream_t s) {
     int st;
     const int np = (int)b->pd.size();
     int n = 0;
-    if ((st = launch_multi(2, b->M, b->d_pd, np, b->tot_bv, 0, b->d_Ar, b->D, b->Cr, b->grid_blocks, s))) return st;
-    if ((st = launch_multi(0, b->M, b->d_pd, np, b->tot_match, 0, b->d_Ar, b->D, b->Cr, b->grid_blocks, s))) return st;
-    if ((st = launch_multi(1, b->M, b->d_pd, np, b->tot_strip, b->strip_fpt, b->d_Ar, b->D, b->Cr, b->grid_blocks, s)))
+    if ((st = launch_multi(2, b->M, b->d_pd, np, b->tot_bv, 0, b->d_Ar, b->D, b->Cr, 1, b->grid_blocks, s))) return st;
+    if ((st = launch_multi(0, b->M, b->d_pd, np, b->tot_match, 0, b->d_Ar, b->D, b->Cr, 1, b->grid_blocks, s))) return st;
+    if ((st = launch_multi(1, b->M, b->d_pd, np, b->tot_strip, b->strip_fpt, b->d_Ar, b->D, b->Cr, b->strip_wmax, b->grid_blocks,
+                           s)))
         return st;
     n += 3;
     for (Group& g : b->groups) {
@@ -165,12 +167,13 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
         int64_t tot = 0;
         for (PlanDev& P : b->pd) {
             P.off_strip = tot;
-            tot += ((P.S + 255) / 256) * ((P.nf + fpt - 1) / fpt);
+            tot += ((P.S + 511) / 512) * ((P.nf + fpt - 1) / fpt);
         }
         if (hipMemcpy(b->d_pd, b->pd.data(), b->pd.size() * sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess)
             return FC2D_E_HIP;
         const float ms = time_ms(s, [&]() {
-            return launch_multi(1, b->M, b->d_pd, (int)b->pd.size(), tot, fpt, b->d_Ar, b->D, b->Cr, b->grid_blocks, s);
+            return launch_multi(1, b->M, b->d_pd, (int)b->pd.size(), tot, fpt, b->d_Ar, b->D, b->Cr, b->strip_wmax,
+                                b->grid_blocks, s);
         }, 3);
         if (ms >= 0 && ms < best) { best = ms; best_f = fpt; }
     }
@@ -178,7 +181,7 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
     int64_t tot = 0;
     for (PlanDev& P : b->pd) {
         P.off_strip = tot;
-        tot += ((P.S + 255) / 256) * ((P.nf + best_f - 1) / best_f);
+        tot += ((P.S + 511) / 512) * ((P.nf + best_f - 1) / best_f);
     }
     b->tot_strip = tot;
     if (hipMemcpy(b->d_pd, b->pd.data(), b->pd.size() * sizeof(PlanDev), hipMemcpyHostToDevice) != hipSuccess)
@@ -280,10 +283,11 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
     }
     b->tot_match = om;
     b->tot_bv = ob;
+    for (int k = 0; k < nplans; ++k) b->strip_wmax = std::max(b->strip_wmax, plans[k]->strip_wmax);
     int64_t ot = 0;
     for (PlanDev& P : b->pd) {
         P.off_strip = ot;
-        ot += ((P.S + 255) / 256) * ((P.nf + b->strip_fpt - 1) / b->strip_fpt);
+        ot += ((P.S + 511) / 512) * ((P.nf + b->strip_fpt - 1) / b->strip_fpt);
     }
     b->tot_strip = ot;
     int dev = 0, cus = 256;

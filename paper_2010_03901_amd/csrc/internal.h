@@ -141,8 +141,11 @@ struct PlanDev {
     int64_t off_match, off_strip, off_bv;   // first work item of this entry
 };
 // which: 0 match, 1 strip, 2 boundary values
+// LDS bytes of the strip kernels for a widest block window wmax (normals), and
+// the stage shape they use: at most lcap normals, fstage fields per stage
+size_t strip_lds(int wmax, int d, int Cr, int fpt, int* lcap, int* fstage);
 int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, int fpt, const double* Ar, int D,
-                 int Cr, int grid_blocks, hipStream_t s);
+                 int Cr, int wmax, int grid_blocks, hipStream_t s);
 int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipStream_t s);
 
 // ---- extension kernels (kernels_extend.hip) ----
@@ -188,5 +191,7 @@ int col_elems_set(int nx, int E);
 int col_cfg_set(int nx, int E, int T);
 int strip_fpt_get();
 int strip_fpt_set(int v);
+int strip_wcap_get();
+int strip_wcap_set(int v);
 
 }  // namespace fc2d

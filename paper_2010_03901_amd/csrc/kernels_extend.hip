@@ -1,14 +1,14 @@
 // Cartesian Evaluation kernels (Sec. 3.5 steps 5-6).
 //
-//  k_match   one thread per (normal p, field): the red-star values along the
+//  k_match   four lanes per (normal p, field): the red-star values along the
 //            grid lines, the matching values along the normal (Sec. 3.2) and
 //            c_p = Q^T f_{D_p}, each a compensated dot product with
-//            double-double weights (rounded once); the normal's weights are
-//            uniform over the wave.
+//            double-double weights (rounded once); the stencil values are
+//            gathered in address order and exchanged through LDS.
 //  k_strip   one thread per two STRIP points (consecutive in foot-parameter
-//            order, sharing most of their normals) looping over a chunk of fields:
-//            interpolation onto H n V+
-//            (Sec. 3.4).  Because every normal carries the same level weights
+//            order, sharing most of their normals) looping over a chunk of
+//            fields, the block's Gram records staged in LDS: interpolation onto
+//            H n V+ (Sec. 3.4).  Because every normal carries the same level weights
 //            v(eta_Q), the continuation values never need to be formed:
 //                ext(Q) = sum_j w_j(theta^Q) [ v_0 f_{D_j}[d-1] + u . c_j ],
 //                u = sum_{l >= 1} v_l A_r[l-1, :]
@@ -59,6 +59,21 @@ struct Acc2 {
     }
 };
 
+// LDS slot of stencil value (star s, node k) in the block of group gi (M * M
+// doubles per group): the node pairs (k even, k + 1) of a star are permuted by
+// an XOR with bits of the star and the group, so the 16-byte reads of the 8
+// lanes of two neighbouring groups (stars s = sq, sq + 4 at the same k) fall
+// in different banks
+template <int M>
+__device__ __forceinline__ int xg_index(int s, int k, int gi) {
+    if constexpr (M == 8) {
+        const int sw = ((s & 3) >> 1) | ((gi & 1) << 1);
+        return s * 8 + ((((k >> 1) ^ sw) << 1) | (k & 1));
+    } else {
+        return s * M + k;
+    }
+}
+
 // Matching values and Gram coefficients of normal p for field f, computed by
 // the 4 consecutive lanes sq = 0..3 of a group.
 //  1. Gather: the normal's M*M stencil values (star s, node k) are listed in
@@ -84,6 +99,7 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
     constexpr int NU = (M * M + 15) / 16 * 4;   // list entries per lane (a multiple of 4)
     const int lane = threadIdx.x & 63;
     const int gbase = lane & ~3;
+    const int gi = lane >> 2;
     // 1. gather in address order (entries and labels read as 16- and 4-byte words)
     {
         const int4* ref4 = (const int4*)(mref + ((int64_t)p * 4 + sq) * NU);
@@ -104,7 +120,7 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
             val[u] = slot[u] < M * M ? *(rr[u] >= 0 ? g + rr[u] : bv + B + (-rr[u] - 1)) : 0.0;
 #pragma unroll
         for (int u = 0; u < NU; ++u)
-            if (slot[u] < M * M) xg[slot[u]] = val[u];
+            if (slot[u] < M * M) xg[xg_index<M>(slot[u] / M, slot[u] % M, gi)] = val[u];
     }
     __syncthreads();
     // 2. red-star values along the grid lines (Sec. 3.2, first interpolation): stars sq, sq + 4
@@ -118,7 +134,7 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
 #pragma unroll
             for (int k = 0; k < M; ++k) {
                 const int o = (r * M + k) * 4 + sq;
-                a.add(dd{wv[2 * o], wv[2 * o + 1]}, xg[s * M + k]);
+                a.add(dd{wv[2 * o], wv[2 * o + 1]}, xg[xg_index<M>(s, k, gi)]);
             }
         }
         mine[r] = a.result();
@@ -204,7 +220,7 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
                                               const double* __restrict__ fg, int64_t npts,
                                               const double* __restrict__ fb, int64_t nbdry, int nf,
                                               double* __restrict__ c_out, double* __restrict__ fD_out) {
-    __shared__ double xg[16 * M * M];
+    __shared__ __attribute__((aligned(16))) double xg[16 * M * M];
     constexpr int FPW = 16 / NPW;
     const int nq = (B + NPW - 1) / NPW;
     const int qd = xcd_normal(blockIdx.x, nq);
@@ -227,7 +243,7 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
 // Every block loops until the items run out.
 template <int M, int DT>
 __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ pd, int np, int64_t total) {
-    __shared__ double xg[16 * M * M];
+    __shared__ __attribute__((aligned(16))) double xg[16 * M * M];
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
         int k = 0;
         while (k + 1 < np && pd[k + 1].off_match <= w) ++k;
@@ -365,30 +381,6 @@ __device__ __forceinline__ int wrap_index(int q, int B) {
     return q < 0 ? q + B : q;
 }
 
-// Interpolated value at STRIP point k for fields [f0, f1) (one thread).
-template <int M, int DT>
-__device__ __forceinline__ void strip_one(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
-                                          const double* __restrict__ seta, int64_t k, const double* sAr, int Drt,
-                                          int Cr, int B, double k2, double lev_scale, const double* __restrict__ c,
-                                          double* __restrict__ out, int64_t npts, int f0, int f1) {
-    const int D = DT > 0 ? DT : Drt;
-    StripPt<M> P;
-    strip_setup<M, DT>(sidx, sth, seta, k, sAr, Drt, Cr, k2, lev_scale, P);
-    constexpr int kl = (M - 1) / 2;
-    const int DP = (D + 2) & ~1;
-    int pj[M];
-#pragma unroll
-    for (int m = 0; m < M; ++m) pj[m] = wrap_index(P.p0 - kl + m, B);
-#pragma unroll 2
-    for (int f = f0; f < f1; ++f) {
-        const double* cf = c + (int64_t)f * B * DP;
-        double ext = 0.0;
-#pragma unroll
-        for (int m = 0; m < M; ++m) ext += P.w[m] * record_dot(cf, pj[m], DP, P.u);
-        out[(int64_t)f * npts + P.idx] = ext;
-    }
-}
-
 // Two STRIP points A, Bp (hasb = false: A only) for fields [f0, f1) (one
 // thread).  The Gram record of normal q (unwrapped index) for field f is read
 // at base + (f - f0) fstride + r DP, r = q - qoff when the records are staged
@@ -476,11 +468,52 @@ __device__ __forceinline__ void stage_records(const double* __restrict__ c, int 
 }
 
 // One block = 512 consecutive STRIP points (foot-parameter order, two per
-// thread) x one chunk of fields.  The block's stencils cover the normals
+// thread; block pb) x fields [f0, f1).  The block's stencils cover the normals
 // p0(first) - kl .. p0(last) - kl + M (p0 is monotone in theta); when that
-// window has at most lcap normals, its Gram records are staged in LDS, fstage
-// fields at a time, and every thread reads its records from there; otherwise
-// the threads read the plan's record array directly.
+// window has at most lcap normals, its Gram records are staged in LDS (st),
+// fstage fields at a time, and every thread reads its records from there;
+// otherwise the threads read the plan's record array c ([nf][B][DP]) directly.
+// Every thread of the block calls this with the same arguments.
+template <int M, int DT>
+__device__ __forceinline__ void strip_block(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
+                                            const double* __restrict__ seta, int64_t S, const double* sAr, int D,
+                                            int Cr, int B, double k2, double lev_scale, const double* __restrict__ c,
+                                            double* __restrict__ out, int64_t npts, int pb, int f0, int f1, int lcap,
+                                            int fstage, double* st) {
+    const int64_t kfirst = (int64_t)pb * 512;
+    const int64_t klast = min(S - 1, kfirst + 511);
+    const int64_t ka = kfirst + 2 * threadIdx.x;   // two consecutive points per thread
+    const bool live = ka < S;
+    const int Dd = DT > 0 ? DT : D;
+    const int DP = (Dd + 2) & ~1;
+    constexpr int kl = (M - 1) / 2;
+    StripPt<M> A, Bp;
+    const bool hasb = ka + 1 < S;
+    if (live) {
+        strip_setup<M, DT>(sidx, sth, seta, ka, sAr, D, Cr, k2, lev_scale, A);
+        strip_setup<M, DT>(sidx, sth, seta, hasb ? ka + 1 : ka, sAr, D, Cr, k2, lev_scale, Bp);
+    }
+    const int pfirst = strip_p0<M>(sth[kfirst], k2);
+    const int L = strip_p0<M>(sth[klast], k2) - pfirst + M + 1;   // uniform over the block
+    if (L <= lcap) {
+        for (int fs = f0; fs < f1; fs += fstage) {
+            const int nfs = min(fstage, f1 - fs);
+            __syncthreads();   // the stage's previous contents have been read
+            stage_records(c, B, DP, pfirst - kl, L, lcap, fs, nfs, st);
+            __syncthreads();
+            if (live)
+                strip_pair_fields<M, DT, true>(A, Bp, hasb, D, B, st, (int64_t)lcap * DP, pfirst - kl, out, npts, fs,
+                                               fs + nfs);
+        }
+    } else if (live) {
+        strip_pair_fields<M, DT, false>(A, Bp, hasb, D, B, c + (int64_t)f0 * B * DP, (int64_t)B * DP, 0, out, npts,
+                                        f0, f1);
+    }
+}
+
+// LDS of the strip kernels: the blend table A_r, then the record stage
+__device__ __forceinline__ double* strip_stage(double* smem, int Cr, int D) { return smem + ((Cr * D + 1) & ~1); }
+
 template <int M, int DT>
 __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx, const double* __restrict__ sth,
                                                const double* __restrict__ seta, int64_t S, const double* __restrict__ Ar,
@@ -489,7 +522,6 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
                                                int nf, int fpt, int lcap, int fstage) {
     extern __shared__ double smem[];
     double* sAr = smem;
-    double* st = smem + ((Cr * D + 1) & ~1);
     for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
     __syncthreads();
     // blocks are dealt round-robin to the 8 XCDs: when the field chunks divide
@@ -506,45 +538,19 @@ __global__ __launch_bounds__(256) void k_strip(const int32_t* __restrict__ sidx,
         chunk = blockIdx.x / pblocks;
         pb = blockIdx.x % pblocks;
     }
-    const int64_t kfirst = (int64_t)pb * 512;
-    const int64_t klast = min(S - 1, kfirst + 511);
-    const int64_t ka = kfirst + 2 * threadIdx.x;   // two consecutive points per thread
-    const bool live = ka < S;
     const int f0 = chunk * fpt;
-    const int f1 = min(nf, f0 + fpt);
-    const int Dd = DT > 0 ? DT : D;
-    const int DP = (Dd + 2) & ~1;
-    constexpr int kl = (M - 1) / 2;
-    StripPt<M> A, Bp;
-    const bool hasb = ka + 1 < S;
-    if (live) {
-        strip_setup<M, DT>(sidx, sth, seta, ka, sAr, D, Cr, k2, lev_scale, A);
-        strip_setup<M, DT>(sidx, sth, seta, hasb ? ka + 1 : ka, sAr, D, Cr, k2, lev_scale, Bp);
-    }
-    const int pfirst = strip_p0<M>(sth[kfirst], k2);
-    const int L = strip_p0<M>(sth[klast], k2) - pfirst + M + 1;   // uniform over the block
-    if (L <= lcap) {
-        for (int fs = f0; fs < f1; fs += fstage) {
-            const int nfs = min(fstage, f1 - fs);
-            if (fs > f0) __syncthreads();   // the previous stage has been read
-            stage_records(c, B, DP, pfirst - kl, L, lcap, fs, nfs, st);
-            __syncthreads();
-            if (live)
-                strip_pair_fields<M, DT, true>(A, Bp, hasb, D, B, st, (int64_t)lcap * DP, pfirst - kl, out, npts, fs,
-                                               fs + nfs);
-        }
-    } else if (live) {
-        strip_pair_fields<M, DT, false>(A, Bp, hasb, D, B, c + (int64_t)f0 * B * DP, (int64_t)B * DP, 0, out, npts,
-                                        f0, f1);
-    }
+    strip_block<M, DT>(sidx, sth, seta, S, sAr, D, Cr, B, k2, lev_scale, c, out, npts, pb, f0, min(nf, f0 + fpt), lcap,
+                       fstage, strip_stage(smem, Cr, D));
 }
 
-// Persistent form over several plans: work item w = (plan, block of 256 STRIP
+// Persistent form over several plans: work item w = (plan, block of 512 STRIP
 // points, chunk of fpt fields).  All plans of a batch share the FC-Gram tables.
 template <int M, int DT>
 __global__ __launch_bounds__(256) void k_strip_multi(const PlanDev* __restrict__ pd, int np, int64_t total, int fpt,
-                                                     const double* __restrict__ Ar, int D, int Cr) {
-    extern __shared__ double sAr[];
+                                                     const double* __restrict__ Ar, int D, int Cr, int lcap,
+                                                     int fstage) {
+    extern __shared__ double smem[];
+    double* sAr = smem;
     for (int k = threadIdx.x; k < Cr * D; k += blockDim.x) sAr[k] = Ar[k];
     __syncthreads();
     for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
@@ -552,12 +558,11 @@ __global__ __launch_bounds__(256) void k_strip_multi(const PlanDev* __restrict__
         while (kk + 1 < np && pd[kk + 1].off_strip <= w) ++kk;
         const PlanDev& P = pd[kk];
         const int64_t l = w - P.off_strip;
-        const int64_t pblocks = (P.S + 255) / 256;
-        const int64_t k = (l % pblocks) * 256 + threadIdx.x;
+        const int64_t pblocks = (P.S + 511) / 512;
+        const int pb = (int)(l % pblocks);
         const int f0 = (int)(l / pblocks) * fpt;
-        if (k >= P.S) continue;
-        strip_one<M, DT>(P.sidx, P.sth, P.seta, k, sAr, D, Cr, P.B, P.k2, P.lev_scale, P.c, P.u, P.npts, f0,
-                     min(P.nf, f0 + fpt));
+        strip_block<M, DT>(P.sidx, P.sth, P.seta, P.S, sAr, D, Cr, P.B, P.k2, P.lev_scale, P.c, P.u, P.npts, pb, f0,
+                           min(P.nf, f0 + fpt), lcap, fstage, strip_stage(smem, Cr, D));
     }
 }
 
@@ -681,6 +686,25 @@ int launch_blend(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     return launch_check("k_blend", s);
 }
 
+// LDS of the strip kernels: the blend table, then the staged Gram records (a
+// block's window of at most lcap normals, at most 16 KB per field and 32 KB
+// per stage of fstage fields)
+static int g_strip_wcap = 0;   // cap on the staged window (normals), 0 = none; set through the tuning interface
+int strip_wcap_get() { return g_strip_wcap; }
+int strip_wcap_set(int v) {
+    if (v < 0) return FC2D_E_ARG;
+    g_strip_wcap = v;
+    return FC2D_OK;
+}
+
+size_t strip_lds(int wmax, int d, int Cr, int fpt, int* lcap, int* fstage) {
+    const size_t rec_bytes = (size_t)((d + 2) & ~1) * sizeof(double);
+    if (g_strip_wcap > 0) wmax = std::min(wmax, g_strip_wcap);
+    *lcap = (int)std::max<size_t>(1, std::min<size_t>((size_t)wmax, 16384 / rec_bytes));
+    *fstage = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(fpt, 8), 32768 / (*lcap * rec_bytes)));
+    return (size_t)((Cr * d + 1) & ~1) * sizeof(double) + (size_t)*fstage * *lcap * rec_bytes;
+}
+
 int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry, double* out, int nf,
                  hipStream_t s) {
     const int64_t S = (int64_t)pl->strip_idx.size();
@@ -694,12 +718,8 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
     fpt = std::max(1, std::min(fpt, nf));
     const int64_t nchunks = (nf + fpt - 1) / fpt;
     const dim3 grid((unsigned)(nchunks * pblocks));
-    // LDS: the blend table, then the staged Gram records (a block's window of
-    // at most lcap normals, at most 16 KB per field and 32 KB per stage)
-    const size_t rec_bytes = (size_t)((pl->d + 2) & ~1) * sizeof(double);
-    const int lcap = (int)std::max<size_t>(1, std::min<size_t>((size_t)pl->strip_wmax, 16384 / rec_bytes));
-    const int fstage = (int)std::max<size_t>(1, std::min<size_t>((size_t)std::min(fpt, 8), 32768 / (lcap * rec_bytes)));
-    const size_t lds = (size_t)((pl->Cr * pl->d + 1) & ~1) * sizeof(double) + (size_t)fstage * lcap * rec_bytes;
+    int lcap, fstage;
+    const size_t lds = strip_lds(pl->strip_wmax, pl->d, pl->Cr, fpt, &lcap, &fstage);
     const double lev_scale = pl->n_r / pl->k1;
     switch (pl->M) {
 #define FC2D_STRIP(MM) \
@@ -741,16 +761,17 @@ int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipSt
 }
 
 int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, int fpt, const double* Ar, int D,
-                 int Cr, int grid_blocks, hipStream_t s) {
+                 int Cr, int wmax, int grid_blocks, hipStream_t s) {
     const unsigned g = (unsigned)std::max<int64_t>(8, std::min<int64_t>(total, grid_blocks));
-    const size_t lds = (size_t)Cr * D * sizeof(double);
+    int lcap = 1, fstage = 1;
+    const size_t lds = which == 1 ? strip_lds(wmax, D, Cr, fpt, &lcap, &fstage) : 0;
     switch (M) {
 #define FC2D_MULTI(MM)                                                                                 \
         case MM:                                                                                       \
             if (which == 0 && D == 5) k_match_multi<MM, 5><<<g, 64, 0, s>>>(d_pd, np, total);          \
             else if (which == 0) k_match_multi<MM, 0><<<g, 64, 0, s>>>(d_pd, np, total);               \
-            else if (which == 1 && D == 5) k_strip_multi<MM, 5><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr); \
-            else if (which == 1) k_strip_multi<MM, 0><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr); \
+            else if (which == 1 && D == 5) k_strip_multi<MM, 5><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr, lcap, fstage); \
+            else if (which == 1) k_strip_multi<MM, 0><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr, lcap, fstage); \
             else k_bvals_multi<MM><<<g, 256, 0, s>>>(d_pd, np, total);                                 \
             break;
         FC2D_MULTI(4) FC2D_MULTI(5) FC2D_MULTI(6) FC2D_MULTI(7) FC2D_MULTI(8)

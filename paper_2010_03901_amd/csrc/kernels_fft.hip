@@ -665,13 +665,16 @@ __device__ __forceinline__ void ff_mode(int i, int j, int nx, double Lx, double 
     const double l = (i <= nx / 2) ? (double)i : (double)(i - nx);
     const double m = (double)j;
     const double a = l / Lx, b = m / Ly;
-    const double w = 2.0 * M_PI * c * sqrt(a * a + b * b);
+    const double wpi = 2.0 * c * sqrt(a * a + b * b);   // w / pi
+    const double w = M_PI * wpi;
     if (i == 0 && j == 0) {
         *ra = make_double2(f0.x + t * f1.x, f0.y + t * f1.y);
         *rt = f1;
     } else {
+        // sin(w t), cos(w t) as sincospi(t w / pi): an exact argument reduction
+        // without the large-argument path of sincos
         double sw, cw;
-        sincos(w * t, &sw, &cw);
+        sincospi(wpi * t, &sw, &cw);
         const double sinc = w > 0 ? sw / w : t;
         *ra = make_double2(cw * f0.x + sinc * f1.x, cw * f0.y + sinc * f1.y);
         const double mw = -w * sw;

@@ -120,3 +120,21 @@ def test_geometry_rejected_before_any_device_work():
     o.k1 = 0.002
     assert lib.fc2d_plan_create(C.byref(star), C.byref(small), 5, 27, C.byref(o), None, C.byref(h)) == fc2d.FC2D_E_GEOMETRY
     assert b"box" in lib.fc2d_last_error()
+
+
+def test_tuning_knobs_host_side():
+    """The launch-shape knobs are host state: set, read back and restored
+    without a GPU; invalid settings are refused."""
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    v = C.c_int()
+    for knob, good, bad in ((fc2d.FC2D_TUNE_STRIP_FIELDS, 4, -1), (fc2d.FC2D_TUNE_STRIP_WINDOW, 16, -3)):
+        assert lib.fc2d_tune_get(knob, 0, C.byref(v)) == fc2d.FC2D_OK
+        old = v.value
+        assert lib.fc2d_tune_set(knob, 0, good) == fc2d.FC2D_OK
+        assert lib.fc2d_tune_get(knob, 0, C.byref(v)) == fc2d.FC2D_OK and v.value == good
+        assert lib.fc2d_tune_set(knob, 0, bad) == fc2d.FC2D_E_ARG
+        assert lib.fc2d_tune_set(knob, 0, old) == fc2d.FC2D_OK
+    # column shapes: only compiled (E, T) pairs
+    assert lib.fc2d_tune_set(fc2d.FC2D_TUNE_COL_TILE, 1024, 3) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_tune_set(99, 0, 1) == fc2d.FC2D_E_ARG

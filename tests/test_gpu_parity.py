@@ -4,6 +4,7 @@ Bars (floating point): matching values, blend and extension within 1e-11 of
 the oracle relative to the field's largest magnitude, IN points bitwise equal
 to f, FAR points exactly 0; spectra within 1e-12 relative; integer work
 (classification, STRIP index list) bit-exact."""
+import dataclasses
 import math
 
 import numpy as np
@@ -215,3 +216,75 @@ def test_extend_fft_benchmark_configuration(torch_mod, nf):
         e_spec = rel_err(spec[s].cpu().numpy(), np.fft.rfft2(ref))
         print("[parity] nf=%d field %d: extend %.2e, extend_fft %.2e" % (nf, s, e_ext, e_spec))
         assert e_ext < 1e-11 and e_spec < 1e-11
+
+
+def _kite256_d4m6():
+    return dataclasses.replace(W.cfg_kite(256), name="kite256_d4M6", d=4, M=6)
+
+
+def _disc128_m7():
+    return dataclasses.replace(W.cfg_disc128(), name="disc128_M7", M=7)
+
+
+@pytest.mark.parametrize("builder", [_kite256_d4m6, _disc128_m7], ids=["kite256_d4M6", "disc128_M7"])
+def test_generic_d_and_M(torch_mod, builder):
+    """The kernels' generic paths: d = 4 (d known only at run time) with an
+    even M = 6, and d = 5 with an odd M = 7 (nearest-node stencils, padded
+    stencil lists): classes and STRIP list bit-exact, matching values, the
+    extension and its spectrum against the oracle."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    case, opl = oracle_plan(builder.__name__, builder)
+    print("\n[parity] generic case", case.name, "d", case.d, "M", case.M, flush=True)
+    gpl = gpu_plan(case)
+    assert np.array_equal(fc2d.fc2d_plan_classes(gpl), opl.cls)
+    idx, _, _, _ = fc2d.fc2d_plan_strip(gpl)
+    assert np.array_equal(idx, opl.strip_idx)
+    funcs = [W.f_cfg1, W.f_paper_disc, W.poisson_rhs(0)]
+    fg, fbo = fields(case, funcs, OP.boundary_points(opl))
+    _, fbg = fields(case, funcs, fc2d.fc2d_boundary_points(gpl))
+    nf = len(funcs)
+    dfg, dfb = _device(torch, fg), _device(torch, fbg)
+    fD = torch.zeros((nf, case.B, case.d), dtype=torch.float64, device="cuda:0")
+    fc2d.fc2d_matching(gpl, dfg, dfb, fD)
+    out = torch.empty_like(dfg)
+    fc2d.fc2d_extend(gpl, dfg, dfb, out)
+    spec = torch.zeros((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    fc2d.fc2d_extend_fft(gpl, dfg, dfb, torch.empty_like(dfg), spec)
+    torch.cuda.synchronize()
+    out = out.cpu().numpy()
+    for k in range(nf):
+        assert rel_err(fD[k].cpu().numpy(), OE.matching_values(opl, fg[k], fbo[k])) < 1e-13
+        ref = OE.extend(opl, fg[k], fbo[k])
+        e = rel_err(out[k], ref)
+        print("[parity] generic", case.name, "field", k, "rel err %.3e" % e)
+        assert e < 1e-11
+        assert rel_err(spec[k].cpu().numpy(), np.fft.rfft2(ref)) < 1e-11
+
+
+def test_strip_window_fallback(torch_mod):
+    """With the staged window capped at one normal, every block of the strip
+    kernel reads its Gram records from device memory: same values, bit for
+    bit, as the staged path (the sums run in the same order), and within the
+    bar of the oracle."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    case, opl = oracle_plan("kite256", W.cfg_kite, 256)
+    gpl = gpu_plan(case)
+    funcs = [W.poisson_rhs(0), W.f_cfg1]
+    fg, fbo = fields(case, funcs, OP.boundary_points(opl))
+    _, fbg = fields(case, funcs, fc2d.fc2d_boundary_points(gpl))
+    dfg, dfb = _device(torch, fg), _device(torch, fbg)
+    staged = torch.empty_like(dfg)
+    fc2d.fc2d_extend(gpl, dfg, dfb, staged)
+    direct = torch.empty_like(dfg)
+    assert fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_STRIP_WINDOW, 0) == 0
+    fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_STRIP_WINDOW, 0, 1)
+    try:
+        fc2d.fc2d_extend(gpl, dfg, dfb, direct)
+        torch.cuda.synchronize()
+    finally:
+        fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_STRIP_WINDOW, 0, 0)
+    assert torch.equal(staged, direct)
+    for k in range(len(funcs)):
+        assert rel_err(direct[k].cpu().numpy(), OE.extend(opl, fg[k], fbo[k])) < 1e-11

@@ -45,7 +45,13 @@ enum {
 enum { FC2D_CURVE_POLAR = 1, FC2D_CURVE_CARTESIAN = 2 };
 enum { FC2D_FORWARD = -1, FC2D_INVERSE = 1 };
 enum { FC2D_LAPLACE_INV = 1, FC2D_DX = 2, FC2D_DY = 3 };
-enum { FC2D_TUNE_COL_TILE = 1, FC2D_TUNE_STRIP_FIELDS = 2, FC2D_TUNE_COL_ELEMS = 3, FC2D_TUNE_STRIP_WINDOW = 4 };
+enum {
+    FC2D_TUNE_COL_TILE = 1,
+    FC2D_TUNE_STRIP_FIELDS = 2,
+    FC2D_TUNE_COL_ELEMS = 3,
+    FC2D_TUNE_STRIP_WINDOW = 4,
+    FC2D_TUNE_FF_SHAPE = 5
+};
 
 /* How the foot-of-normal solve of each grid point near Gamma is started
  * (fc2d_opts.seed):
@@ -217,7 +223,10 @@ int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, con
  * most this many normals of Gram records are staged in LDS per block of 512
  * STRIP points (0 = no cap beyond the LDS budget; n ignored); blocks whose
  * stencils span more normals read the records from device memory instead.
- * Not thread-safe against concurrent launches. */
+ * FC2D_TUNE_FF_SHAPE: index of the compiled (E, T) shape of the fused
+ * column-pass + propagation kernel for length n (batches; n = 256, 512, 1024:
+ * 0..2, n = 2048: 0..3, other lengths: 0).  Not thread-safe against
+ * concurrent launches. */
 int fc2d_tune_set(int knob, int n, int value);
 int fc2d_tune_get(int knob, int n, int* value);
 

@@ -659,38 +659,55 @@ int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, in
     return check("k_spectral", s);
 }
 
-// Propagation of mode (i, j) by t (eq. wave_2d_ff): (f0, f1) = (u0h, u1h) -> (uh, uth)
-__device__ __forceinline__ void ff_mode(int i, int j, int nx, double Lx, double Ly, double c, double t, double2 f0,
-                                        double2 f1, double2* ra, double2* rt) {
-    const double l = (i <= nx / 2) ? (double)i : (double)(i - nx);
-    const double m = (double)j;
-    const double a = l / Lx, b = m / Ly;
+// Propagation of a mode by t (eq. wave_2d_ff): with w = 2 pi c |k| the
+// spectra (f0, f1) = (u_hat, u_t_hat) map to
+//     (cos(w t) f0 + sin(w t)/w f1,  -w sin(w t) f0 + cos(w t) f1),
+// and to (f0 + t f1, f1) for the zero mode.  The factors depend only on
+// (|l|, m) (row i and row nx - i share them): FFCoef holds them for one pair.
+struct FFCoef {
+    double cw, sinc, mw;
+};
+
+// factors of the modes with |row frequency| la and column frequency m
+// (iLx = 1 / Lx, iLy = 1 / Ly)
+__device__ __forceinline__ FFCoef ff_coef(int la, int m, double iLx, double iLy, double c, double t) {
+    FFCoef k;
+    if (la == 0 && m == 0) {
+        k.cw = 1.0;
+        k.sinc = t;
+        k.mw = 0.0;
+        return k;
+    }
+    const double a = (double)la * iLx, b = (double)m * iLy;
     const double wpi = 2.0 * c * sqrt(a * a + b * b);   // w / pi
     const double w = M_PI * wpi;
-    if (i == 0 && j == 0) {
-        *ra = make_double2(f0.x + t * f1.x, f0.y + t * f1.y);
-        *rt = f1;
-    } else {
-        // sin(w t), cos(w t) as sincospi(t w / pi): an exact argument reduction
-        // without the large-argument path of sincos
-        double sw, cw;
-        sincospi(wpi * t, &sw, &cw);
-        const double sinc = w > 0 ? sw / w : t;
-        *ra = make_double2(cw * f0.x + sinc * f1.x, cw * f0.y + sinc * f1.y);
-        const double mw = -w * sw;
-        *rt = make_double2(mw * f0.x + cw * f1.x, mw * f0.y + cw * f1.y);
-    }
+    // sin(w t), cos(w t) as sincospi(t w / pi): an exact argument reduction
+    // without the large-argument path of sincos
+    double sw, cw;
+    sincospi(wpi * t, &sw, &cw);
+    k.cw = cw;
+    k.sinc = sw / w;
+    k.mw = -w * sw;
+    return k;
 }
+
+__device__ __forceinline__ void ff_apply(const FFCoef& k, double2 f0, double2 f1, double2* ra, double2* rt) {
+    *ra = make_double2(k.cw * f0.x + k.sinc * f1.x, k.cw * f0.y + k.sinc * f1.y);
+    *rt = make_double2(k.mw * f0.x + k.cw * f1.x, k.mw * f0.y + k.cw * f1.y);
+}
+
+// |row frequency| of row i of an nx-point transform
+__device__ __forceinline__ int row_freq(int i, int nx) { return i <= nx / 2 ? i : nx - i; }
 
 __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2* uth, int64_t n, int nx, int ny,
                      double h, double c, double t) {
     const int ncol = ny / 2 + 1;
-    const double Lx = nx * h, Ly = ny * h;
+    const double iLx = 1.0 / (nx * h), iLy = 1.0 / (ny * h);
     for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
         int i, j;
         mode_of(e, nx, ncol, &i, &j);
         double2 ra, rt;
-        ff_mode(i, j, nx, Lx, Ly, c, t, u0[e], u1[e], &ra, &rt);
+        ff_apply(ff_coef(row_freq(i, nx), j, iLx, iLy, c, t), u0[e], u1[e], &ra, &rt);
         uh[e] = ra;
         uth[e] = rt;
     }
@@ -729,12 +746,13 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
     // propagate every (row i, column pair) in LDS; one mode at a time keeps the
     // transcendental work out of the unrolled register code
     const int tile_col0 = tile * H;
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly;
 #pragma unroll 1
     for (int e = threadIdx.x; e < L * H; e += T * (L / E)) {
         const int i = e / H, cq = e % H;
         const int a = swz(i * T + cq), b = swz(i * T + cq + H);
         double2 ra, rt;
-        ff_mode(i, tile_col0 + cq, nx, Lx, Ly, c, t, lds[a], lds[b], &ra, &rt);
+        ff_apply(ff_coef(row_freq(i, L), tile_col0 + cq, iLx, iLy, c, t), lds[a], lds[b], &ra, &rt);
         lds[a] = ra;
         lds[b] = rt;
     }

@@ -1001,6 +1001,7 @@ int fc2d_tune_set(int knob, int n, int value) {
     else if (knob == FC2D_TUNE_COL_ELEMS) st = col_elems_set(n, value);
     else if (knob == FC2D_TUNE_STRIP_FIELDS) st = strip_fpt_set(value);
     else if (knob == FC2D_TUNE_STRIP_WINDOW) st = strip_wcap_set(value);
+    else if (knob == FC2D_TUNE_FF_SHAPE) st = colff_set(n, value);
     if (st) set_error("fc2d_tune_set: unsupported knob or value");
     return st;
 }
@@ -1011,6 +1012,7 @@ int fc2d_tune_get(int knob, int n, int* value) {
     else if (knob == FC2D_TUNE_COL_ELEMS) *value = col_elems_get(n);
     else if (knob == FC2D_TUNE_STRIP_FIELDS) *value = strip_fpt_get();
     else if (knob == FC2D_TUNE_STRIP_WINDOW) *value = strip_wcap_get();
+    else if (knob == FC2D_TUNE_FF_SHAPE) *value = colff_get(n);
     else { set_error("fc2d_tune_get: unknown knob"); return FC2D_E_ARG; }
     return FC2D_OK;
 }

@@ -21,7 +21,7 @@ FC2D_E_ARG, FC2D_E_TABLE, FC2D_E_GEOMETRY, FC2D_E_NEWTON, FC2D_E_HIP, FC2D_E_NOM
 FC2D_CURVE_POLAR, FC2D_CURVE_CARTESIAN = 1, 2
 FC2D_FORWARD, FC2D_INVERSE = -1, 1
 FC2D_LAPLACE_INV, FC2D_DX, FC2D_DY = 1, 2, 3
-FC2D_TUNE_COL_TILE, FC2D_TUNE_STRIP_FIELDS, FC2D_TUNE_COL_ELEMS, FC2D_TUNE_STRIP_WINDOW = 1, 2, 3, 4
+FC2D_TUNE_COL_TILE, FC2D_TUNE_STRIP_FIELDS, FC2D_TUNE_COL_ELEMS, FC2D_TUNE_STRIP_WINDOW, FC2D_TUNE_FF_SHAPE = 1, 2, 3, 4, 5
 FC2D_BATCH_AUTOTUNE, FC2D_BATCH_FUSED_FF = 1, 2
 FC2D_SEED_PROXIMITY, FC2D_SEED_POLAR, FC2D_SEED_MLP = 0, 1, 2
 FC2D_MLP_NIN, FC2D_MLP_HIDDEN, FC2D_MLP_NW = 8, 64, 9026

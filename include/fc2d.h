@@ -254,11 +254,17 @@ int fc2d_trace_end(int* n, const char** names, float* ms, int cap);
  * the batch.  flags: FC2D_BATCH_FUSED_FF runs the forward column pass, the
  * propagation and the inverse column pass of each grid size as one kernel
  * (instead of three); FC2D_BATCH_AUTOTUNE times the column-pass shapes, the
- * fused against the separate spectral step per grid size and the strip
- * kernel's fields per thread on the batch's buffers and keeps the fastest
- * (launch shapes are process-wide, see fc2d_tune_set).  State starts at zero. */
+ * fused against the separate spectral step per grid size, row-major against
+ * transposed spectra, and the strip kernel's fields per thread on the batch's
+ * buffers and keeps the fastest (launch shapes are process-wide, see
+ * fc2d_tune_set); FC2D_BATCH_TRANSPOSED keeps each grid size's spectra
+ * transposed ([field][column][row], so the column passes read contiguous
+ * columns; the row passes write and read them 4 rows at a time; grids with
+ * ny <= 4096) and implies the fused spectral step for those sizes.  The
+ * spectra are internal: results do not depend on the layout beyond rounding.
+ * State starts at zero. */
 typedef struct fc2d_batch fc2d_batch;
-enum { FC2D_BATCH_AUTOTUNE = 1, FC2D_BATCH_FUSED_FF = 2 };
+enum { FC2D_BATCH_AUTOTUNE = 1, FC2D_BATCH_FUSED_FF = 2, FC2D_BATCH_TRANSPOSED = 4 };
 int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, unsigned flags,
                       hipStream_t stream, fc2d_batch** out);
 /* Device pointers to plan k's state: u and u_t, each [nf[k]][nx][ny]. */

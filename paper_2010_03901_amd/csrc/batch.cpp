@@ -32,6 +32,7 @@ struct Group {
     double* state = nullptr;      // [2][nf_total][nx][ny]: u then u_t
     double* spec = nullptr;       // [2][nf_total][nx][ny/2+1] complex128
     bool fused_ff = false;        // column passes and propagation in one launch (k_cols_ff)
+    bool trans = false;           // spectra stored transposed, [field][column][row] (implies fused_ff)
 };
 }  // namespace fc2d
 
@@ -45,6 +46,7 @@ struct fc2d_batch {
     int64_t tot_match = 0, tot_strip = 0, tot_bv = 0;
     int M = 0, D = 0, Cr = 0, strip_fpt = 4, grid_blocks = 2048;
     int strip_wmax = 1;   // widest strip-kernel block window over the plans (normals)
+    bool trans_fixed = false;   // layout of the spectra fixed by the caller (FC2D_BATCH_TRANSPOSED)
     const double* d_Ar = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -76,11 +78,39 @@ static int spectral_step(Group& g, double c, double dt, hipStream_t s) {
     const int64_t nsp = (int64_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;
     double* su = g.spec;
     double* sut = g.spec + (int64_t)g.nf_total * nsp;
-    if (g.fused_ff) return cols_ff(&g.grid, c, dt, su, sut, g.nf_total, s);
+    if (g.trans || g.fused_ff) return cols_ff(&g.grid, c, dt, su, sut, g.nf_total, s, g.trans);
     int st;
     if ((st = fft_cols(&g.grid, g.spec, 2 * g.nf_total, false, s))) return st;
     if ((st = ff_apply(&g.grid, c, dt, su, sut, su, sut, g.nf_total, s))) return st;
     return fft_cols(&g.grid, g.spec, 2 * g.nf_total, true, s);
+}
+
+// the spectral part of a step for one grid-size group: forward row passes
+// with the extension (per member plan), column passes + propagation, inverse
+// row passes; *launches counts the kernels
+static int group_fft_step(fc2d_batch* b, Group& g, double c, double dt, hipStream_t s, int* launches) {
+    int st;
+    const int64_t npts = (int64_t)g.grid.nx * g.grid.ny;
+    const int64_t nsp = (int64_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;   // doubles per spectrum
+    int n = 0;
+    for (int k : g.members) {
+        const fc2d_plan* pl = b->plans[k];
+        for (int half = 0; half < 2; ++half) {
+            const int64_t f0 = (int64_t)half * g.nf_total + b->field_off[k];
+            double* u = g.state + f0 * npts;
+            st = g.trans ? fft_rows_fwd_t(&g.grid, u, g.spec + f0 * nsp, b->nf[k], s, u, pl->d_cls2)
+                         : fft_rows_fwd(&g.grid, u, g.spec + f0 * nsp, b->nf[k], s, u, pl->d_cls2);
+            if (st) return st;
+            ++n;
+        }
+    }
+    if ((st = spectral_step(g, c, dt, s))) return st;
+    st = g.trans ? fft_rows_inv_t(&g.grid, g.spec, g.state, 2 * g.nf_total, s)
+                 : fft_rows_inv(&g.grid, g.spec, g.state, 2 * g.nf_total, s);
+    if (st) return st;
+    n += (g.trans || g.fused_ff) ? 2 : 4;
+    *launches = n;
+    return FC2D_OK;
 }
 
 // enqueue one Fourier-Forwarding step of the whole batch on s
@@ -95,20 +125,9 @@ static int batch_step(fc2d_batch* b, double c, double dt, hipStream_t s) {
         return st;
     n += 3;
     for (Group& g : b->groups) {
-        const int64_t npts = (int64_t)g.grid.nx * g.grid.ny;
-        const int64_t nsp = (int64_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;   // doubles per spectrum
-        for (int k : g.members) {
-            const fc2d_plan* pl = b->plans[k];
-            for (int half = 0; half < 2; ++half) {
-                const int64_t f0 = (int64_t)half * g.nf_total + b->field_off[k];
-                double* u = g.state + f0 * npts;
-                if ((st = fft_rows_fwd(&g.grid, u, g.spec + f0 * nsp, b->nf[k], s, u, pl->d_cls2))) return st;
-                ++n;
-            }
-        }
-        if ((st = spectral_step(g, c, dt, s))) return st;
-        if ((st = fft_rows_inv(&g.grid, g.spec, g.state, 2 * g.nf_total, s))) return st;
-        n += g.fused_ff ? 2 : 4;
+        int ng = 0;
+        if ((st = group_fft_step(b, g, c, dt, s, &ng))) return st;
+        n += ng;
     }
     b->launches_per_step = n;
     return FC2D_OK;
@@ -158,6 +177,33 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
         }
         colff_set(g.grid.nx, best_v);
         g.fused_ff = t_fused >= 0 && (t_sep < 0 || t_fused < t_sep);
+        // row-major spectra (as chosen above) against transposed spectra, over
+        // the group's whole spectral step, unless the layout was fixed
+        if (!b->trans_fixed && g.grid.ny <= 4096) {
+            int nl = 0;
+            g.trans = false;
+            const float t_rm = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 2);
+            g.trans = true;
+            float t_tr = -1.0f;
+            int best_tv = colff_get(g.grid.nx);
+            for (int v = 0; v < colff_variants(g.grid.nx); ++v) {
+                colff_set(g.grid.nx, v);
+                const float ms = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 2);
+                if (ms >= 0 && (t_tr < 0 || ms < t_tr)) { t_tr = ms; best_tv = v; }
+            }
+            g.trans = t_tr >= 0 && (t_rm < 0 || t_tr < t_rm);
+            colff_set(g.grid.nx, g.trans ? best_tv : best_v);
+        } else if (g.trans) {
+            int best_tv = colff_get(g.grid.nx), nl = 0;
+            float t_tr = -1.0f;
+            for (int v = 0; v < colff_variants(g.grid.nx); ++v) {
+                colff_set(g.grid.nx, v);
+                const float ms = time_ms(s, [&]() { return spectral_step(g, 1.0, 0.0, s); }, 3);
+                if (ms >= 0 && (t_tr < 0 || ms < t_tr)) { t_tr = ms; best_tv = v; }
+            }
+            (void)nl;
+            colff_set(g.grid.nx, best_tv);
+        }
     }
     // strip kernel: fields per thread
     int best_f = b->strip_fpt;
@@ -309,8 +355,23 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
     }
     if (flags & FC2D_BATCH_FUSED_FF)
         for (Group& g : b->groups) g.fused_ff = true;
+    if (flags & FC2D_BATCH_TRANSPOSED) {
+        b->trans_fixed = true;
+        for (Group& g : b->groups) g.trans = g.grid.ny <= 4096;
+    }
     if (flags & FC2D_BATCH_AUTOTUNE) st = autotune(b, s);
     if (st) { batch_free(b); return st; }
+    // the timed trial steps ran on the batch's own buffers: back to zero
+    for (Group& g : b->groups) {
+        const int64_t npts = (int64_t)g.grid.nx * g.grid.ny;
+        const int64_t nsp = (int64_t)g.grid.nx * (g.grid.ny / 2 + 1) * 2;
+        if (hipMemsetAsync(g.state, 0, 2 * g.nf_total * npts * sizeof(double), s) != hipSuccess ||
+            hipMemsetAsync(g.spec, 0, 2 * g.nf_total * nsp * sizeof(double), s) != hipSuccess) {
+            set_error("batch state reset failed");
+            batch_free(b);
+            return FC2D_E_HIP;
+        }
+    }
     if (hipStreamSynchronize(s) != hipSuccess) { set_error("batch set-up failed"); batch_free(b); return FC2D_E_HIP; }
     *out = b;
     return FC2D_OK;

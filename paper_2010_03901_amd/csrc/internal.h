@@ -169,12 +169,18 @@ int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipS
                  const uint8_t* cls2);
 int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s);
 int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s);
+// the same row passes with the half spectrum transposed, [field][bin][row] (ny <= 4096)
+int fft_rows_fwd_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
+                   const uint8_t* cls2);
+int fft_rows_inv_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s);
 int spectral_apply(const fc2d_grid* g, int op, const double* in, double* out, int nf, hipStream_t s);
 int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* uh,
              double* uth, int nf, hipStream_t s);
 // column pass + propagation by t + inverse column pass in one launch, in place
 // on row-transformed spectra su, sut ([nf][nx][ny/2+1] each)
-int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s);
+// trans: spectra stored transposed ([field][column][row]), as fft_rows_fwd_t writes them
+int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s,
+            bool trans = false);
 int colff_variants(int nx);   // compiled launch shapes of cols_ff for length nx
 int colff_get(int nx);
 int colff_set(int nx, int v);

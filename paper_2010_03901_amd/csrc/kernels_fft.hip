@@ -299,6 +299,17 @@ __device__ __forceinline__ void load_classes(const uint8_t* p, uint8_t* out) {
     __builtin_memcpy(out, &w, E);
 }
 
+// Row block of this block for the transposed-spectrum row passes (nrb row
+// blocks; gridDim.x = nrb rounded up to a multiple of 8): blocks are dealt
+// round-robin to the 8 XCDs, so XCD x takes the contiguous range starting at
+// x * ceil(nrb / 8); neighbouring row blocks share the 128-byte lines of each
+// spectrum column and so share one L2.  -1 for a padding block.
+__device__ __forceinline__ int xcd_row_block(int nrb) {
+    const int per_xcd = (nrb + 7) / 8;
+    const int rb = (int)(blockIdx.x % 8) * per_xcd + (int)(blockIdx.x / 8);
+    return rb < nrb ? rb : -1;
+}
+
 __device__ const double2 g_zero_pair[1] = {{0.0, 0.0}};
 
 // One unconditional 16-byte load per pair from a selected source: both IN ->
@@ -316,17 +327,24 @@ __device__ __forceinline__ double2 mixed_pair(const double* row, const double* s
     return z;
 }
 
-template <int L, int E, int RPB, bool MASKED>
+// TRANS: the half spectrum is written transposed, [field][bin k][row]
+// (each column contiguous), the RPB rows of a block as RPB x 16 contiguous
+// bytes per bin; the LDS rows are padded to L + 2 so the RPB rows of one bin
+// sit in different banks.
+template <int L, int E, int RPB, bool MASKED, bool TRANS>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __restrict__ in, double2* __restrict__ out,
                                                             int nx, const double2* __restrict__ tw,
                                                             const double* __restrict__ strip,
                                                             const uint8_t* __restrict__ cls2) {
     constexpr int P = L / E;
     constexpr int N = 2 * L;
-    __shared__ double2 lds[RPB * L];
+    constexpr int QS = TRANS ? L + 2 : L;
+    __shared__ double2 lds[RPB * QS];
     const int q = threadIdx.x / P;
     const int t = threadIdx.x % P;
-    const int row = blockIdx.x * RPB + q;
+    const int rblk = TRANS ? xcd_row_block((nx + RPB - 1) / RPB) : (int)blockIdx.x;
+    if (rblk < 0) return;   // padding block (uniform)
+    const int row = rblk * RPB + q;
     const int f = blockIdx.y;
     const bool live = row < nx;
     const int64_t roff = ((int64_t)f * nx + (live ? row : 0)) * N;
@@ -347,40 +365,62 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
 #pragma unroll
         for (int k = 0; k < E; ++k) v[k] = ((const double2*)src)[in_index<L, E>(k, t)];
     }
-    StockhamFrom<L, E, 1, false>::run(v, lds, L, 1, q, t, tw, N);
+    StockhamFrom<L, E, 1, false>::run(v, lds, QS, 1, q, t, tw, N);
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < E; ++k) lds[swz(q * L + out_index<L, E>(k, t))] = v[k];
+    for (int k = 0; k < E; ++k) lds[swz(q * QS + out_index<L, E>(k, t))] = v[k];
     __syncthreads();
-    if (!live) return;
-    double2* dst = out + ((int64_t)f * nx + row) * (L + 1);
-    // split weights W_N^k for k = t + m P: W_N^t times powers of W_N^P
+    // split into the L + 1 bins of the real transform: thread (qq, k0) takes
+    // row qq, bins k = k0 + m P, with W_N^k = W_N^k0 times powers of W_N^P
+    // (row-major output: qq = q, k0 = t; transposed: the RPB rows of a bin
+    // on consecutive lanes)
+    const int qq = TRANS ? (int)(threadIdx.x % RPB) : q;
+    const int k0 = TRANS ? (int)(threadIdx.x / RPB) : t;
+    const int orow = rblk * RPB + qq;
+    if (orow >= nx) return;
     const double2 wstep = unit_root(P, N);
-    double2 wk = unit_root(t, N);
-    for (int k = t; k <= L; k += P) {
-        const double2 zk = lds[swz(q * L + (k == L ? 0 : k))];
-        const double2 zc = cconj(lds[swz(q * L + (k == 0 ? 0 : L - k))]);
+    double2 wk = unit_root(k0, N);
+    for (int k = k0; k <= L; k += P) {
+        const double2 zk = lds[swz(qq * QS + (k == L ? 0 : k))];
+        const double2 zc = cconj(lds[swz(qq * QS + (k == 0 ? 0 : L - k))]);
         const double2 Eh = make_double2(0.5 * (zk.x + zc.x), 0.5 * (zk.y + zc.y));
         const double2 D = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y - zc.y));
         const double2 O = make_double2(D.y, -D.x);   // D / i
-        dst[k] = cadd(Eh, cmul(wk, O));
+        const double2 X = cadd(Eh, cmul(wk, O));
+        if (TRANS) out[((int64_t)f * (L + 1) + k) * nx + orow] = X;
+        else out[((int64_t)f * nx + orow) * (L + 1) + k] = X;
         wk = cmul(wk, wstep);
     }
 }
 
 // pass R': half-spectrum rows -> real rows, scaled
-template <int L, int E, int RPB>
+// TRANS: the half spectrum is read transposed ([field][bin][row]); the block
+// first stages its RPB rows in LDS (RPB x 16 contiguous bytes per bin).
+template <int L, int E, int RPB, bool TRANS>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __restrict__ in, double* __restrict__ out,
                                                             int nx, const double2* __restrict__ tw, double scale) {
     constexpr int P = L / E;
     constexpr int N = 2 * L;
-    __shared__ double2 lds[RPB * L];
+    constexpr int QS = TRANS ? L + 2 : L;
+    __shared__ double2 lds[RPB * QS];
     const int q = threadIdx.x / P;
     const int t = threadIdx.x % P;
-    const int row = blockIdx.x * RPB + q;
+    const int rblk = TRANS ? xcd_row_block((nx + RPB - 1) / RPB) : (int)blockIdx.x;
+    if (rblk < 0) return;   // padding block (uniform)
+    const int row = rblk * RPB + q;
     const int f = blockIdx.y;
     const bool live = row < nx;
     const double2* src = in + ((int64_t)f * nx + (live ? row : 0)) * (L + 1);
+    if constexpr (TRANS) {
+        // bins 0..L of the block's rows
+        for (int e = threadIdx.x; e < RPB * (L + 1); e += RPB * P) {
+            const int qq = e % RPB, n = e / RPB;
+            const int r = rblk * RPB + qq;
+            lds[qq * QS + n] = r < nx ? in[((int64_t)f * (L + 1) + n) * nx + r] : make_double2(0.0, 0.0);
+        }
+        __syncthreads();
+        src = lds + q * QS;
+    }
     double2 v[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
@@ -391,7 +431,7 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __res
         const double2 Dw = cmul(csub(xk, xc), cconj(tw[n]));   // exp(+2 pi i n / N)
         v[k] = make_double2(S.x - Dw.y, S.y + Dw.x);           // S + i Dw
     }
-    StockhamFrom<L, E, 1, true>::run(v, lds, L, 1, q, t, tw, N);
+    StockhamFrom<L, E, 1, true>::run(v, lds, QS, 1, q, t, tw, N);
     if (!live) return;
     double2* dst = (double2*)(out + ((int64_t)f * nx + row) * N);
 #pragma unroll
@@ -454,18 +494,23 @@ static int check(const char* what, hipStream_t s) {
     return FC2D_OK;
 }
 
-// row-pass configurations: (L, E, rows per block)
-template <bool FWD>
+// row-pass configurations: (L, E, rows per block); the transposed-spectrum
+// forms take 4 rows per block (64 contiguous bytes per bin)
+template <bool FWD, bool TRANS>
 static void launch_rows(int L, int nx, int nf, const void* in, void* out, const double2* tw, double scale,
                         const double* strip, const uint8_t* cls2, hipStream_t s) {
-#define FC2D_ROWS(LL, EE, RR)                                                                              \
+#define FC2D_ROWS(LL, EE, RR0)                                                                             \
     case LL: {                                                                                             \
-        dim3 g((nx + RR - 1) / RR, nf);                                                                    \
-        if (FWD && cls2)                                                                                   \
-            k_rows_r2c<LL, EE, RR, true><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, strip, cls2); \
-        else if (FWD)                                                                                      \
-            k_rows_r2c<LL, EE, RR, false><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, nullptr, nullptr); \
-        else k_rows_c2r<LL, EE, RR><<<g, RR * (LL / EE), 0, s>>>((const double2*)in, (double*)out, nx, tw, scale); \
+        constexpr int RR = TRANS ? 4 : RR0;                                                                \
+        if constexpr (!TRANS || LL <= 2048) {                                                              \
+            const int nrb = (nx + RR - 1) / RR;                                                            \
+            dim3 g(TRANS ? (nrb + 7) / 8 * 8 : nrb, nf);                                                   \
+            if (FWD && cls2)                                                                               \
+                k_rows_r2c<LL, EE, RR, true, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, strip, cls2); \
+            else if (FWD)                                                                                  \
+                k_rows_r2c<LL, EE, RR, false, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, nullptr, nullptr); \
+            else k_rows_c2r<LL, EE, RR, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double2*)in, (double*)out, nx, tw, scale); \
+        }                                                                                                  \
         break;                                                                                             \
     }
     switch (L) {
@@ -586,7 +631,16 @@ int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipS
                  const uint8_t* cls2) {
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_rows<true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s);
+    launch_rows<true, false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s);
+    return check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
+}
+
+int fft_rows_fwd_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
+                   const uint8_t* cls2) {
+    if (g->ny > 4096) { set_error("transposed spectra: rows of at most 4096 points"); return FC2D_E_ARG; }
+    const double2* twy = twiddles(g->ny);
+    if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
+    launch_rows<true, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s);
     return check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
 }
 
@@ -601,7 +655,17 @@ int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s) 
 int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_rows<false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr, nullptr, s);
+    launch_rows<false, false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr,
+                              nullptr, s);
+    return check("k_rows_c2r", s);
+}
+
+int fft_rows_inv_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
+    if (g->ny > 4096) { set_error("transposed spectra: rows of at most 4096 points"); return FC2D_E_ARG; }
+    const double2* twy = twiddles(g->ny);
+    if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
+    launch_rows<false, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr,
+                             nullptr, s);
     return check("k_rows_c2r", s);
 }
 
@@ -720,7 +784,9 @@ __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2*
 // LDS), transforms back along x and writes both in place.  Replaces forward
 // column pass + propagation + inverse column pass (three reads and writes of
 // both spectra) by one.
-template <int L, int E, int T>
+// TRANS: spectra stored transposed ([field][column][row], each column
+// contiguous), as the transposed row passes write and read them.
+template <int L, int E, int T, bool TRANS>
 __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict__ su, double2* __restrict__ sut,
                                                          int ncol, int nx, double Lx, double Ly, double c, double t,
                                                          int by_field) {
@@ -734,10 +800,12 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
     if (!col_block(ntiles, by_field != 0, &tile, &field)) return;   // uniform per block
     const int col = tile * H + q % H;
     const bool live = col < ncol;
-    double2* base = (comp ? sut : su) + (int64_t)field * L * ncol + (live ? col : 0);
+    const int64_t rs = TRANS ? 1 : ncol;   // row stride of a column
+    double2* base = (comp ? sut : su) + (TRANS ? ((int64_t)field * ncol + (live ? col : 0)) * L
+                                               : (int64_t)field * L * ncol + (live ? col : 0));
     double2 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, tt) * ncol];
+    for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, tt) * rs];
     StockhamFrom<L, E, 1, false>::run(v, lds, 1, T, q, tt, nullptr, L);
     __syncthreads();
 #pragma unroll
@@ -763,7 +831,7 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
     StockhamFrom<L, E, 1, true>::run(v, lds, 1, T, q, tt, nullptr, L);
     if (!live) return;
 #pragma unroll
-    for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, tt) * ncol] = v[k];
+    for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, tt) * rs] = v[k];
 }
 
 // shapes (elements per thread, columns per block) of the fused kernel per
@@ -787,18 +855,22 @@ int colff_set(int nx, int v) {
     return FC2D_OK;
 }
 
-int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s) {
+int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s, bool trans) {
     const int ncol = g->ny / 2 + 1;
     const double Lx = g->nx * g->h, Ly = g->ny * g->h;
     const int var = colff_get(g->nx);
-#define FC2D_COLFF(LL, VV, EE, TT)                                                                           \
-    if (g->nx == LL && var == VV) {                                                                         \
-        const int ntiles = (ncol + TT / 2 - 1) / (TT / 2);                                                  \
-        const bool byf = nf % 8 == 0;                                                                       \
-        const dim3 grid = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);           \
-        k_cols_ff<LL, EE, TT><<<grid, TT * (LL / EE), 0, s>>>((double2*)su, (double2*)sut, ncol, g->nx, Lx, \
-                                                               Ly, c, t, byf ? 1 : 0);                      \
-        return check("k_cols_ff", s);                                                                       \
+#define FC2D_COLFF(LL, VV, EE, TT)                                                                            \
+    if (g->nx == LL && var == VV) {                                                                          \
+        const int ntiles = (ncol + TT / 2 - 1) / (TT / 2);                                                   \
+        const bool byf = nf % 8 == 0;                                                                        \
+        const dim3 grid = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);            \
+        if (trans)                                                                                           \
+            k_cols_ff<LL, EE, TT, true><<<grid, TT * (LL / EE), 0, s>>>((double2*)su, (double2*)sut, ncol,   \
+                                                                       g->nx, Lx, Ly, c, t, byf ? 1 : 0);   \
+        else                                                                                                 \
+            k_cols_ff<LL, EE, TT, false><<<grid, TT * (LL / EE), 0, s>>>((double2*)su, (double2*)sut, ncol,  \
+                                                                        g->nx, Lx, Ly, c, t, byf ? 1 : 0);  \
+        return check("k_cols_ff", s);                                                                        \
     }
     FC2D_COLFF(16, 0, 2, 8) FC2D_COLFF(32, 0, 2, 8) FC2D_COLFF(64, 0, 2, 8) FC2D_COLFF(128, 0, 2, 8)
     FC2D_COLFF(256, 0, 4, 8) FC2D_COLFF(256, 1, 4, 4) FC2D_COLFF(256, 2, 2, 8)

@@ -22,7 +22,7 @@ FC2D_CURVE_POLAR, FC2D_CURVE_CARTESIAN = 1, 2
 FC2D_FORWARD, FC2D_INVERSE = -1, 1
 FC2D_LAPLACE_INV, FC2D_DX, FC2D_DY = 1, 2, 3
 FC2D_TUNE_COL_TILE, FC2D_TUNE_STRIP_FIELDS, FC2D_TUNE_COL_ELEMS, FC2D_TUNE_STRIP_WINDOW, FC2D_TUNE_FF_SHAPE = 1, 2, 3, 4, 5
-FC2D_BATCH_AUTOTUNE, FC2D_BATCH_FUSED_FF = 1, 2
+FC2D_BATCH_AUTOTUNE, FC2D_BATCH_FUSED_FF, FC2D_BATCH_TRANSPOSED = 1, 2, 4
 FC2D_SEED_PROXIMITY, FC2D_SEED_POLAR, FC2D_SEED_MLP = 0, 1, 2
 FC2D_MLP_NIN, FC2D_MLP_HIDDEN, FC2D_MLP_NW = 8, 64, 9026
 
@@ -314,13 +314,14 @@ def fc2d_boundary_values(plan, u, f_bdry, stream=None):
 class Batch:
     """Owning wrapper of fc2d_batch* (keeps its plans alive)."""
 
-    def __init__(self, plans, nf, autotune=False, fused_ff=False, stream=None):
+    def __init__(self, plans, nf, autotune=False, fused_ff=False, transposed=False, stream=None):
         self.plans = list(plans)
         arr = (C.c_void_p * len(self.plans))(*[p.handle.value for p in self.plans])
         nfa = (C.c_int * len(self.plans))(*[int(n) for n in nf])
         self.nf = [int(n) for n in nf]
         h = C.c_void_p()
-        flags = (FC2D_BATCH_AUTOTUNE if autotune else 0) | (FC2D_BATCH_FUSED_FF if fused_ff else 0)
+        flags = ((FC2D_BATCH_AUTOTUNE if autotune else 0) | (FC2D_BATCH_FUSED_FF if fused_ff else 0)
+                 | (FC2D_BATCH_TRANSPOSED if transposed else 0))
         _check(_lib().fc2d_batch_create(arr, nfa, len(self.plans), flags,
                                         _stream(stream), C.byref(h)))
         self._h = h

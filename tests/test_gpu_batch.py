@@ -193,3 +193,40 @@ def test_fused_spectral_step_eight_fields(torch_mod):
     assert rel_err(res[1][0], res[0][0]) < 1e-13 and rel_err(res[1][1], res[0][1]) < 1e-13
     ou, out_ = OF.ff_step(opl, u0[5], np.zeros_like(u0[5]), dt)
     assert rel_err(res[1][0][5], ou) < 1e-11 and rel_err(res[1][1][5], out_) < 1e-11
+
+
+@pytest.mark.parametrize("nf8", [False, True], ids=["mixed", "eight_fields"])
+def test_transposed_spectra_bitwise(batch_setup, torch_mod, nf8):
+    """Transposed spectra ([field][column][row]) change only where the
+    spectrum sits in memory: the step equals the row-major fused step bit for
+    bit, on the mixed batch and on eight fields of one plan (the
+    whole-fields-per-XCD mapping), and matches the oracle's step."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    _, cases, oplans, gplans, nf, u0 = batch_setup
+    if nf8:
+        case, opl = oracle_plan("disc256ff", W.cfg_ff, "disc", 256)
+        gplans, oplans, nf = [gpu_plan(case)], [opl], [8]
+        u0 = [_pulses(case, range(50, 58))]
+    dt = 0.02
+    res = []
+    for trans in (False, True):
+        b = fc2d.Batch(gplans, nf, fused_ff=True, transposed=trans)
+        _load_state(b, u0)
+        b.run_ff(1.0, dt, 2, use_graph=False)
+        torch.cuda.synchronize()
+        res.append([tuple(t.cpu().numpy().copy() for t in b.state(k)) for k in range(len(nf))])
+        b.close()
+    for k in range(len(nf)):
+        assert np.array_equal(res[0][k][0], res[1][k][0]) and np.array_equal(res[0][k][1], res[1][k][1]), k
+    # one step against the oracle
+    b = fc2d.Batch(gplans, nf, transposed=True)
+    _load_state(b, u0)
+    b.run_ff(1.0, dt, 1, use_graph=True)
+    torch.cuda.synchronize()
+    for k, (opl, m) in enumerate(zip(oplans, nf)):
+        du, dut = b.state(k)
+        f = m - 1
+        ou, out_ = OF.ff_step(opl, u0[k][f], np.zeros_like(u0[k][f]), dt)
+        assert rel_err(du[f].cpu().numpy(), ou) < 1e-11 and rel_err(dut[f].cpu().numpy(), out_) < 1e-11
+    b.close()

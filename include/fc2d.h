@@ -103,7 +103,8 @@ typedef struct {
 typedef struct {
     int B;             /* boundary points, k2 = 2 pi / B (eq. bdry_grid) */
     double k1;         /* normal step (eq. vnbj_m, eq. vnbj_p); 0 -> h */
-    int M;             /* interpolation nodes (degree M - 1); 0 -> d + 3 */
+    int M;             /* interpolation nodes (degree M - 1); 0 -> d + 3; compiled sizes
+                          4..8, 13 and 15 (d = 10, 12 with M = d + 3, Remark 3.5); M >= d - 1 */
     int n_r;           /* refinement factor, C_r = n_r C (Remark 2.2) */
     int Z;             /* zero-matching points (eq. min_prob) */
     int n_os;          /* oversampling factor (eq. q_over) */

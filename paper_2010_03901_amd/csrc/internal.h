@@ -56,7 +56,7 @@ struct fc2d_plan {
     int32_t* d_mref = nullptr;      // [B][4][NU] stencil entries in address order (entry 4u + sq at [sq][u]):
                                     //   grid flat index (>= 0) or -(1 + square)
     uint8_t* d_mlab = nullptr;      // [B][4][NU] star s, node k of each entry as s M + k (255: padding)
-    double* d_mwv = nullptr;        // [B][2][M][4][2] weights along the grid line of star 4r + sq, node k at
+    double* d_mwv = nullptr;        // [B][RS][M][4][2] (RS = ceil(M / 4)) weights along the grid line of star 4r + sq, node k at
                                     //   [r][k][sq] (double-double; zero for stars >= M)
     double* d_mwn = nullptr;        // [B][RQ][M][4][2] weights along the normal of matching value 4r + sq,
                                     //   star s at [r][s][sq] (double-double; zero for values >= d-1)

@@ -81,7 +81,7 @@ __device__ __forceinline__ int xg_index(int s, int k, int gi) {
 //     4u + sq, u = 0, 1, ..., so the four lanes of a load read neighbouring
 //     addresses, and stores each value in the group's LDS block xg at s M + k.
 //  2. Red stars (first interpolation, along the grid lines): lane sq forms
-//     stars sq and sq + 4 from xg; the others travel by cross-lane shuffles.
+//     stars sq, sq + 4, ... from xg; the others travel by cross-lane shuffles.
 //  3. Matching values along the normal (second interpolation) q = sq, sq + 4, ...
 //  4. Gram coefficients c_j, j = sq, sq + 4, ...
 // Every sum is a Dot2 over the stencil in node / star order, as in a one-lane
@@ -123,11 +123,12 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
             if (slot[u] < M * M) xg[xg_index<M>(slot[u] / M, slot[u] % M, gi)] = val[u];
     }
     __syncthreads();
-    // 2. red-star values along the grid lines (Sec. 3.2, first interpolation): stars sq, sq + 4
-    const double* wv = mwv + (int64_t)p * 2 * M * 4 * 2;   // [r][k][sq] double-double
-    dd mine[2];
+    // 2. red-star values along the grid lines (Sec. 3.2, first interpolation): stars sq, sq + 4, ...
+    constexpr int RS = (M + 3) / 4;   // stars per lane
+    const double* wv = mwv + (int64_t)p * RS * M * 4 * 2;   // [r][k][sq] double-double
+    dd mine[RS];
 #pragma unroll
-    for (int r = 0; r < 2; ++r) {
+    for (int r = 0; r < RS; ++r) {
         const int s = sq + 4 * r;
         Acc2 a;
         if (s < M) {
@@ -144,7 +145,7 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
 #pragma unroll
     for (int s = 0; s < M; ++s) {
         const int src = gbase + (s & 3);
-        const dd v = (s < 4) ? mine[0] : mine[1];
+        const dd v = mine[s >> 2];
         star[s] = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
     }
     // 3. matching values along the normal (second interpolation)
@@ -318,7 +319,7 @@ __device__ __forceinline__ void equi_weights(double x, double* w) {
 template <int M>
 struct StripPt {
     double w[M];
-    double u[10];
+    double u[13];   // d + 1 <= 13 entries
     int p0;
     int32_t idx;
 };
@@ -348,14 +349,14 @@ __device__ __forceinline__ void strip_setup(const int32_t* __restrict__ sidx, co
     double v[M];
     equi_weights<M>(s - (double)l0, v);
 #pragma unroll
-    for (int j = 0; j < 10; ++j) P.u[j] = 0.0;
+    for (int j = 0; j < 13; ++j) P.u[j] = 0.0;
 #pragma unroll
     for (int l = 0; l < M; ++l) {
         const int lev = l0 + l;            // level 0 is the boundary value, not a row of A_r
         const double vl = lev >= 1 ? v[l] : 0.0;
         const double* row = sAr + (lev >= 1 ? lev - 1 : 0) * D;
 #pragma unroll
-        for (int j = 0; j < 9; ++j)
+        for (int j = 0; j < 12; ++j)
             if (j < D) P.u[j] += vl * row[j];
     }
     // slot D of each normal's record holds its boundary value: weight v_0 when l0 = 0
@@ -367,7 +368,7 @@ __device__ __forceinline__ double record_dot(const double* __restrict__ cf, int 
     const double2* rec = (const double2*)(cf + (int64_t)q * DP);
     double g = 0.0;
 #pragma unroll
-    for (int j2 = 0; j2 < 5; ++j2) {
+    for (int j2 = 0; j2 < 7; ++j2) {   // DP <= 14
         if (2 * j2 < DP) {
             const double2 cc = rec[j2];
             g += u[2 * j2] * cc.x + u[2 * j2 + 1] * cc.y;
@@ -415,7 +416,7 @@ __device__ __forceinline__ void strip_pair_fields(const StripPt<M>& A, const Str
                 const double2* rec = (const double2*)(cf + pj[m]);
                 double ga = 0.0, gb = 0.0;
 #pragma unroll
-                for (int j2 = 0; j2 < 5; ++j2) {
+                for (int j2 = 0; j2 < 7; ++j2) {   // DP <= 14
                     if (2 * j2 < DP) {
                         const double2 cc = rec[j2];
                         ga += A.u[2 * j2] * cc.x + A.u[2 * j2 + 1] * cc.y;
@@ -671,7 +672,7 @@ int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry
             else if (npw == 4) k_match<MM, 0, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
             else k_match<MM, 0, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
             break;
-        FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8)
+        FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8) FC2D_MATCH(13) FC2D_MATCH(15)
 #undef FC2D_MATCH
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
@@ -727,7 +728,7 @@ int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int
             if (pl->d == 5) k_strip<MM, 5><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, out, npts, nf, fpt, lcap, fstage); \
             else k_strip<MM, 0><<<grid, 256, lds, s>>>(pl->d_sidx, pl->d_sth, pl->d_seta, S, pl->d_Ar, pl->d, pl->Cr, pl->B, pl->k2, lev_scale, c, out, npts, nf, fpt, lcap, fstage); \
             break;
-        FC2D_STRIP(4) FC2D_STRIP(5) FC2D_STRIP(6) FC2D_STRIP(7) FC2D_STRIP(8)
+        FC2D_STRIP(4) FC2D_STRIP(5) FC2D_STRIP(6) FC2D_STRIP(7) FC2D_STRIP(8) FC2D_STRIP(13) FC2D_STRIP(15)
 #undef FC2D_STRIP
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
@@ -753,7 +754,7 @@ int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipSt
     switch (pl->M) {
 #define FC2D_BV(MM) \
         case MM: k_bvals<MM><<<blocks, 256, 0, s>>>(pl->d_bxy, nb, u, g.nx, g.ny, g.x0, g.y0, g.h, nf, fb); break;
-        FC2D_BV(4) FC2D_BV(5) FC2D_BV(6) FC2D_BV(7) FC2D_BV(8)
+        FC2D_BV(4) FC2D_BV(5) FC2D_BV(6) FC2D_BV(7) FC2D_BV(8) FC2D_BV(13) FC2D_BV(15)
 #undef FC2D_BV
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
@@ -774,7 +775,7 @@ int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, i
             else if (which == 1) k_strip_multi<MM, 0><<<g, 256, lds, s>>>(d_pd, np, total, fpt, Ar, D, Cr, lcap, fstage); \
             else k_bvals_multi<MM><<<g, 256, 0, s>>>(d_pd, np, total);                                 \
             break;
-        FC2D_MULTI(4) FC2D_MULTI(5) FC2D_MULTI(6) FC2D_MULTI(7) FC2D_MULTI(8)
+        FC2D_MULTI(4) FC2D_MULTI(5) FC2D_MULTI(6) FC2D_MULTI(7) FC2D_MULTI(8) FC2D_MULTI(13) FC2D_MULTI(15)
 #undef FC2D_MULTI
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }

@@ -156,6 +156,8 @@ int launch_classify(const ClassifyArgs& a, int8_t* d_cls, StripRec* d_rec, int64
         case 6: k_classify<6><<<nb, 256, 0, s>>>(a, d_near, d_cls, d_rec, cap, d_counters); break;
         case 7: k_classify<7><<<nb, 256, 0, s>>>(a, d_near, d_cls, d_rec, cap, d_counters); break;
         case 8: k_classify<8><<<nb, 256, 0, s>>>(a, d_near, d_cls, d_rec, cap, d_counters); break;
+        case 13: k_classify<13><<<nb, 256, 0, s>>>(a, d_near, d_cls, d_rec, cap, d_counters); break;
+        case 15: k_classify<15><<<nb, 256, 0, s>>>(a, d_near, d_cls, d_rec, cap, d_counters); break;
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
     hipError_t e = hipGetLastError();

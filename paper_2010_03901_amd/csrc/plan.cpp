@@ -141,6 +141,8 @@ static int foot_host(int M, const CurveC& cv, const BndView& bd, double X, doubl
         case 10: return foot_solve<10>(cv, bd, X, Y, p, maxit, th, eta, it);
         case 11: return foot_solve<11>(cv, bd, X, Y, p, maxit, th, eta, it);
         case 12: return foot_solve<12>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 13: return foot_solve<13>(cv, bd, X, Y, p, maxit, th, eta, it);
+        case 15: return foot_solve<15>(cv, bd, X, Y, p, maxit, th, eta, it);
     }
     return FOOT_NO_BRACKET;
 }
@@ -398,12 +400,13 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         return FC2D_E_ARG;
     }
     if (o.M <= 0) o.M = d + 3;
-    if (d < 2 || d > 12 || C < 2 || o.M < 4 || o.M > 8 || o.M < d - 1 || grid->h <= 0 || grid->nx < 8 ||
+    const bool m_ok = (o.M >= 4 && o.M <= 8) || o.M == 13 || o.M == 15;   // compiled stencil sizes
+    if (d < 2 || d > 12 || C < 2 || !m_ok || o.M < d - 1 || grid->h <= 0 || grid->nx < 8 ||
         grid->ny < 8 || (int64_t)grid->nx * grid->ny >= (int64_t)1 << 31 || o.B < 16 ||
         curve->nmodes < 0 || curve->nmodes > kMaxModes || !curve->a ||
         (curve->kind == FC2D_CURVE_CARTESIAN && !curve->b) ||
         (curve->kind != FC2D_CURVE_POLAR && curve->kind != FC2D_CURVE_CARTESIAN)) {
-        set_error("invalid plan arguments (supported: 2 <= d <= 12, 4 <= M <= 8, M >= d - 1, B >= 16)");
+        set_error("invalid plan arguments (supported: 2 <= d <= 12, M in 4..8, 13, 15, M >= d - 1, B >= 16)");
         return FC2D_E_ARG;
     }
     fc2d_plan* pl = new (std::nothrow) fc2d_plan();
@@ -680,7 +683,8 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             const int64_t npts = (int64_t)grid->nx * grid->ny;
             std::vector<int32_t> dref((size_t)B * 4 * NU, 0);
             std::vector<uint8_t> dlab((size_t)B * 4 * NU, 255);
-            std::vector<double> dwv((size_t)B * 2 * M * 4 * 2, 0.0), dwn((size_t)B * RQ * M * 4 * 2, 0.0);
+            const int RS = (M + 3) / 4;   // stars per lane
+            std::vector<double> dwv((size_t)B * RS * M * 4 * 2, 0.0), dwn((size_t)B * RQ * M * 4 * 2, 0.0);
             std::vector<int> ord(MM);
             for (int p = 0; p < B; ++p) {
                 const int32_t* r0 = &mref[(size_t)p * MM];
@@ -692,12 +696,12 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                     dref[o] = r0[ord[i]];
                     dlab[o] = (uint8_t)ord[i];
                 }
-                for (int r = 0; r < 2; ++r)
+                for (int r = 0; r < RS; ++r)
                     for (int k = 0; k < M; ++k)
                         for (int sq = 0; sq < 4; ++sq) {
                             const int sv = 4 * r + sq;
                             if (sv >= M) continue;
-                            const size_t on = (((size_t)p * 2 + r) * M + k) * 4 + sq;
+                            const size_t on = (((size_t)p * RS + r) * M + k) * 4 + sq;
                             const size_t oo = ((size_t)p * M + sv) * M + k;
                             dwv[2 * on] = mwv[2 * oo];
                             dwv[2 * on + 1] = mwv[2 * oo + 1];

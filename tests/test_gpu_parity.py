@@ -226,12 +226,27 @@ def _disc128_m7():
     return dataclasses.replace(W.cfg_disc128(), name="disc128_M7", M=7)
 
 
-@pytest.mark.parametrize("builder", [_kite256_d4m6, _disc128_m7], ids=["kite256_d4M6", "disc128_M7"])
+def _disc128_d10():
+    return dataclasses.replace(W.cfg_disc128(), name="disc128_d10", d=10, M=13)
+
+
+def _star320_d10():
+    return dataclasses.replace(W.cfg_star(320), name="star320_d10", d=10, M=13)
+
+
+def _kite256_d12():
+    return dataclasses.replace(W.cfg_kite(256), name="kite256_d12", d=12, M=15)
+
+
+@pytest.mark.parametrize("builder", [_kite256_d4m6, _disc128_m7, _disc128_d10, _star320_d10, _kite256_d12],
+                         ids=["kite256_d4M6", "disc128_M7", "disc128_d10M13", "star320_d10M13", "kite256_d12M15"])
 def test_generic_d_and_M(torch_mod, builder):
     """The kernels' generic paths: d = 4 (d known only at run time) with an
-    even M = 6, and d = 5 with an odd M = 7 (nearest-node stencils, padded
-    stencil lists): classes and STRIP list bit-exact, matching values, the
-    extension and its spectrum against the oracle."""
+    even M = 6, d = 5 with an odd M = 7 (nearest-node stencils, padded
+    stencil lists), and the higher orders d = 10, 12 with M = d + 3 (Remark
+    3.5; four stars per lane): classes and STRIP list bit-exact, matching
+    values, the extension and (power-of-two grids) its spectrum against the
+    oracle."""
     from paper_2010_03901_amd import fc2d
     torch = torch_mod
     case, opl = oracle_plan(builder.__name__, builder)
@@ -249,17 +264,29 @@ def test_generic_d_and_M(torch_mod, builder):
     fc2d.fc2d_matching(gpl, dfg, dfb, fD)
     out = torch.empty_like(dfg)
     fc2d.fc2d_extend(gpl, dfg, dfb, out)
+    pow2 = case.n & (case.n - 1) == 0
     spec = torch.zeros((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
-    fc2d.fc2d_extend_fft(gpl, dfg, dfb, torch.empty_like(dfg), spec)
+    if pow2:
+        fc2d.fc2d_extend_fft(gpl, dfg, dfb, torch.empty_like(dfg), spec)
     torch.cuda.synchronize()
     out = out.cpu().numpy()
+    rng = np.random.default_rng(11)
     for k in range(nf):
         assert rel_err(fD[k].cpu().numpy(), OE.matching_values(opl, fg[k], fbo[k])) < 1e-13
         ref = OE.extend(opl, fg[k], fbo[k])
+        # the continuation amplifies rounding more with the order: for d >= 10
+        # the bar is ten times the oracle's own change under a relative
+        # perturbation of 1e-16 of its inputs (at least the d = 5 bar 1e-11)
+        bar = 1e-11
+        if case.d >= 10:
+            pert = OE.extend(opl, fg[k] * (1 + 1e-16 * rng.standard_normal(fg[k].shape)),
+                             fbo[k] * (1 + 1e-16 * rng.standard_normal(fbo[k].shape)))
+            bar = max(bar, 10 * rel_err(pert, ref))
         e = rel_err(out[k], ref)
-        print("[parity] generic", case.name, "field", k, "rel err %.3e" % e)
-        assert e < 1e-11
-        assert rel_err(spec[k].cpu().numpy(), np.fft.rfft2(ref)) < 1e-11
+        print("[parity] generic", case.name, "field", k, "rel err %.3e (bar %.1e)" % (e, bar))
+        assert e < bar
+        if pow2:
+            assert rel_err(spec[k].cpu().numpy(), np.fft.rfft2(ref)) < bar
 
 
 def test_strip_window_fallback(torch_mod):

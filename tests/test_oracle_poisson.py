@@ -1,0 +1,100 @@
+"""Pins for the oracle's full Poisson solver (Sec. 4.1): the double-layer
+kernel against Gauss's lemma, the trigonometric interpolant against the FFT
+zero-padding interpolant, the Laplace part against harmonic closed forms
+(also at grid points next to Gamma), and the whole solver against the paper's
+Table 3 (kite, d = 4, M = M_P = d + 1 .. d + 3)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from conftest import load_golden
+from oracle import fcgram
+from oracle import plan as P
+from oracle import poisson as PS
+from oracle.curves import Curve
+
+
+def test_gauss_lemma_and_matrix_rows():
+    cv = Curve(*W.kite(0.35, 0.7))
+    nb = 96
+    # constant density: -1 inside, and (I - 2K) 1 = 2 on Gamma
+    pts = np.array([[0.0, 0.0], [-0.3, 0.2], [0.5, -0.1]])
+    assert np.abs(PS.double_layer(cv, np.ones(4 * nb), pts) + 1.0).max() < 1e-12
+    A = PS.nystrom_matrix(cv, nb)
+    assert np.abs(A @ np.ones(nb) - 2.0).max() < 1e-12
+    # unit circle: the kernel is -1/(4 pi) everywhere, the diagonal limit included
+    A = PS.nystrom_matrix(Curve(*W.disc()), 16)
+    assert np.allclose(A, np.eye(16) + np.full((16, 16), 1.0 / 16), atol=1e-15)
+
+
+@pytest.mark.parametrize("n", [17, 24])
+def test_trig_interp_matches_zero_padding(n):
+    rng = np.random.default_rng(n)
+    v = rng.standard_normal(n)
+    R = 4
+    V = np.fft.fft(v)
+    Vp = np.zeros(R * n, dtype=complex)
+    h = n // 2
+    Vp[:h + 1] = V[:h + 1]
+    Vp[-h:] += V[-h:]
+    if n % 2 == 0:
+        Vp[h] = 0.5 * V[h]
+        Vp[R * n - h] = 0.5 * V[h]
+    ref = np.real(np.fft.ifft(Vp)) * R
+    got = PS.trig_interp(v, 2 * math.pi * np.arange(R * n) / (R * n))
+    assert np.abs(got - ref).max() < 1e-13
+
+
+def _kite_plan(h, nx, ny, d, M):
+    curve = W.kite(0.35, 0.7)
+    xmin, xmax, ymin, ymax = W.bbox(curve)
+    x0 = 0.5 * (xmin + xmax) - 0.5 * nx * h
+    y0 = 0.5 * (ymin + ymax) - 0.5 * ny * h
+    g = P.Grid(x0, y0, h, nx, ny)
+    return P.make_plan(Curve(*curve), g, fcgram.load_tables(d), int(round(2 * np.pi / h)), k1=h, M=M)
+
+
+def _u_exact(x, y):
+    return np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) / (8 * np.pi ** 2)
+
+
+def _f(x, y):
+    return -np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+
+
+def test_laplace_part_harmonic_data():
+    """f = 0 (so u_p = 0): u = e^x cos y, a harmonic function, at every IN point,
+    including the points within h/2 of Gamma."""
+    pl = _kite_plan(4e-2, 117, 93, 4, 7)
+    X, Y = np.meshgrid(pl.grid.xs(), pl.grid.ys(), indexing="ij")
+    _, q, _, _ = PS.nodes(pl.curve, 117)
+    u = PS.solve(pl, np.zeros_like(X), np.zeros(P.boundary_points(pl).shape[0]),
+                 np.exp(q[:, 0]) * np.cos(q[:, 1]), 117)
+    ins = pl.cls == P.IN
+    ex = np.exp(X) * np.cos(Y)
+    assert np.abs(u - ex)[ins].max() < 1e-11
+
+
+@pytest.mark.slow
+def test_paper_table3_kite():
+    rows = load_golden("paper_table3_kite_poisson.txt")
+    for M in (5, 6, 7):
+        errs = []
+        for h, nx, ny, e5, e6, e7 in rows[:3]:
+            nx, ny = int(nx), int(ny)
+            pl = _kite_plan(h, nx, ny, 4, M)
+            X, Y = np.meshgrid(pl.grid.xs(), pl.grid.ys(), indexing="ij")
+            bp = P.boundary_points(pl)
+            _, q, _, _ = PS.nodes(pl.curve, nx)
+            u = PS.solve(pl, _f(X, Y), _f(bp[:, 0], bp[:, 1]), _u_exact(q[:, 0], q[:, 1]), nx, MP=M)
+            ins = pl.cls == P.IN
+            ex = _u_exact(X, Y)[ins]
+            e = np.linalg.norm(u[ins] - ex) / np.linalg.norm(ex)
+            ref = {5: e5, 6: e6, 7: e7}[M]
+            print("Table 3 M=%d h=%g: %.2e (printed %.2e)" % (M, h, e, ref))
+            assert e < 10 * ref, (M, h, e, ref)
+            errs.append(e)
+        order = math.log2(errs[-2] / errs[-1])
+        assert order > (4.5 if M == 5 else 5.3), (M, errs)

@@ -199,6 +199,29 @@ int fc2d_extend_fft(const fc2d_plan* plan, const double* f_grid, const double* f
  * scaled by 1/(nx ny).  in and out must not overlap. */
 int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStream_t stream);
 
+/* Full Poisson solve (Sec. 4.1; eq. def_poisson): Delta u = f in Omega, u = g on
+ * Gamma, as u = u_p + v (eq. total_soln).  u_p is the 2D-FC particular solution
+ * (eq. poisson_ps: the extension's spectrum over -|k|^2, plus f_00 (x^2 + y^2)/4
+ * with f_00 the extension's mean -- the printed formula's minus sign on this
+ * term is read as a plus, so that Delta u_p = f); v is harmonic with
+ * v = g - u_p on Gamma (eq. def_laplace, eq. laplace_bc), a double-layer
+ * potential whose density solves the second-kind Nystrom system of the
+ * trapezoidal rule on nb nodes q(2 pi j / nb), by GMRES; u_p on Gamma comes from
+ * degree-(M-1) tensor interpolation (the plan's M).  v is summed at the IN grid
+ * points (density refined 32x near Gamma); points within h/2 of Gamma use the
+ * foot value and M - 1 values along the inward normal at h/2, h, ...
+ * interpolated in the distance with degree M - 1.
+ * fc2d_poisson_nodes writes the nodes, host xy [2 nb], where the caller samples
+ * g.  fc2d_poisson_solve: device f_grid [nf][nx][ny] (IN entries read),
+ * f_bdry [nf][n_bdry] (the plan's boundary points), g_nodes [nf][nb]; writes
+ * u [nf][nx][ny] (IN points; every other point 0).  Power-of-two grids, 8 <= nb
+ * <= 16384.  Allocates its work buffers, synchronises `stream` (GMRES reads its
+ * scalars on the host), returns the GMRES iterations summed over the fields in
+ * *gmres_iters (may be NULL).  FC2D_E_NEWTON when GMRES or a foot solve fails. */
+int fc2d_poisson_nodes(const fc2d_plan* plan, int nb, double* xy);
+int fc2d_poisson_solve(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, const double* g_nodes,
+                       int nb, double* u, int nf, hipStream_t stream, int* gmres_iters);
+
 /* Spectral operators on half spectra (in place allowed): FC2D_LAPLACE_INV
  * multiplies by -1/|k|^2 with the (0,0) mode set to 0 (eq. poisson_ps_coeffs);
  * FC2D_DX / FC2D_DY multiply by i k_x / i k_y with the Nyquist mode zeroed;

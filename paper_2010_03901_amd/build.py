@@ -17,8 +17,8 @@ OUT = os.path.join(PKG, "libfc2d.so")
 BUILD = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp"]
-HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip", "kernels_mlp.hip"]
+HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp", "poisson.cpp"]
+HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip", "kernels_mlp.hip", "kernels_poisson.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",

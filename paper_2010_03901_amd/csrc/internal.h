@@ -141,6 +141,24 @@ struct PlanDev {
     int64_t off_match, off_strip, off_bv;   // first work item of this entry
 };
 // which: 0 match, 1 strip, 2 boundary values
+// ---- full Poisson solve (kernels_poisson.hip); qd: (x, y, x', y', x'', y'') per node
+int pois_mean(const fc2d_grid* g, const double* spec, double* mean, hipStream_t s);
+int pois_add_quad(const fc2d_grid* g, const double* mean, double* up, hipStream_t s);
+int pois_ghom(int M, const fc2d_grid* g, const double* up, const double* qd, int nb, const double* gv,
+              double* ghom, hipStream_t s);
+int pois_nystrom(const double* qd, int nb, double* A, hipStream_t s);
+int pois_matvec(const double* A, const double* x, int n, double* y, hipStream_t s);
+int pois_dots(const double* V, int nv, const double* w, int n, double* out, hipStream_t s);
+int pois_sub(const double* V, int nv, const double* c, int n, double* w, hipStream_t s);
+int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s);
+int pois_trig_up(const double* phi, int nb, int R, double* phif, hipStream_t s);
+int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* qc, const double* phic,
+                 int nb, const double* qf, const double* phif, int nbf, double far2, double* u, int32_t* cand,
+                 int* ncand, hipStream_t s);
+int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
+                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* qf,
+                 const double* phif, int nbf, double* u, int* nfail, hipStream_t s);
+
 // LDS bytes of the strip kernels for a widest block window wmax (normals), and
 // the stage shape they use: at most lcap normals, fstage fields per stage
 size_t strip_lds(int wmax, int d, int Cr, int fpt, int* lcap, int* fstage);

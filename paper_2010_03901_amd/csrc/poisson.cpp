@@ -1,0 +1,260 @@
+// Full 2D-FC Poisson solve (Sec. 4.1), host orchestration: every numerical
+// step runs in the library's kernels (extension + FFT, spectral inversion,
+// mean term, boundary interpolation, Nystrom matrix, GMRES vector operations,
+// density refinement, double-layer evaluation); the host only sequences the
+// launches and runs GMRES's small Hessenberg least-squares problem.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace fc2d;
+
+namespace {
+
+constexpr int kRefine = 32;      // density refinement factor of the near-boundary sums
+constexpr int kRestart = 80;     // GMRES restart length
+constexpr int kMaxRestarts = 20;
+constexpr double kGmresTol = 1e-14;
+
+// (x, y, x', y', x'', y'') at t_j = 2 pi j / n
+void node_data(const CurveC& cv, int n, std::vector<double>& qd) {
+    qd.resize(6 * (size_t)n);
+    for (int j = 0; j < n; ++j) curve_eval(cv, 2.0 * M_PI * (double)j / (double)n, &qd[6 * (size_t)j]);
+}
+
+struct PoisBuf {
+    std::vector<void*> ptrs;
+    ~PoisBuf() {
+        for (void* p : ptrs) (void)hipFree(p);
+    }
+    template <class T>
+    T* get(size_t n) {
+        void* p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
+        ptrs.push_back(p);
+        return (T*)p;
+    }
+};
+
+int hip_err(hipError_t e, const char* what) {
+    set_error(std::string(what) + ": " + hipGetErrorString(e));
+    return FC2D_E_HIP;
+}
+
+// Restarted GMRES with classical Gram-Schmidt applied twice; A column-major
+// n x n (device), b and x device vectors; x starts at zero.
+int gmres(const double* A, const double* b, double* x, int n, double* V, double* w, double* hd, hipStream_t s,
+          int* iters) {
+    const int m = std::min(n, kRestart);
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1));
+    double* h1 = hd;                 // [m + 1]
+    double* h2 = hd + (m + 1);       // [m + 1]
+    double* nrm = hd + 2 * (m + 1);  // [1]
+    double* ydev = hd + 2 * (m + 1) + 1;
+    int st;
+    hipError_t e;
+    if ((e = hipMemsetAsync(x, 0, n * sizeof(double), s)) != hipSuccess) return hip_err(e, "gmres");
+    double bnorm = 0.0;
+    if ((st = pois_dots(b, 1, b, n, nrm, s))) return st;
+    if ((e = hipMemcpyAsync(&bnorm, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        (e = hipStreamSynchronize(s)) != hipSuccess)
+        return hip_err(e, "gmres");
+    bnorm = sqrt(bnorm);
+    *iters = 0;
+    if (bnorm == 0.0) return FC2D_OK;
+    // r = b (x = 0)
+    double beta = bnorm;
+    if ((st = pois_axpbz(1.0 / beta, b, 0.0, b, n, V, s))) return st;
+    for (int rs = 0; rs < kMaxRestarts; ++rs) {
+        std::fill(g.begin(), g.end(), 0.0);
+        g[0] = beta;
+        int k = 0;
+        bool done = false;
+        for (int j = 0; j < m; ++j) {
+            double* vj1 = V + (size_t)(j + 1) * n;
+            if ((st = pois_matvec(A, V + (size_t)j * n, n, w, s))) return st;
+            if ((st = pois_dots(V, j + 1, w, n, h1, s))) return st;
+            if ((st = pois_sub(V, j + 1, h1, n, w, s))) return st;
+            if ((st = pois_dots(V, j + 1, w, n, h2, s))) return st;
+            if ((st = pois_sub(V, j + 1, h2, n, w, s))) return st;
+            if ((st = pois_dots(w, 1, w, n, nrm, s))) return st;
+            if ((e = hipMemcpyAsync(hh.data(), hd, 2 * (m + 1) * sizeof(double), hipMemcpyDeviceToHost, s)) !=
+                hipSuccess)
+                return hip_err(e, "gmres");
+            double hn2 = 0.0;
+            if ((e = hipMemcpyAsync(&hn2, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+                (e = hipStreamSynchronize(s)) != hipSuccess)
+                return hip_err(e, "gmres");
+            const double hn = sqrt(hn2);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 1) + i];
+            H[(size_t)(j + 1) * m + j] = hn;
+            for (int i = 0; i < j; ++i) {   // previous rotations
+                const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
+                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
+                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
+            }
+            const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
+            const double r = hypot(a, c);
+            cs[j] = r > 0 ? a / r : 1.0;
+            sn[j] = r > 0 ? c / r : 0.0;
+            H[(size_t)j * m + j] = r;
+            H[(size_t)(j + 1) * m + j] = 0.0;
+            g[j + 1] = -sn[j] * g[j];
+            g[j] = cs[j] * g[j];
+            k = j + 1;
+            ++*iters;
+            if (fabs(g[j + 1]) <= kGmresTol * bnorm || hn == 0.0) {
+                done = true;
+                break;
+            }
+            if ((st = pois_axpbz(1.0 / hn, w, 0.0, w, n, vj1, s))) return st;
+        }
+        // y = H(0:k, 0:k)^-1 g, x += V y  (as x -= sum (-y_i) V_i)
+        for (int i = k - 1; i >= 0; --i) {
+            double t = g[i];
+            for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
+            y[i] = t / H[(size_t)i * m + i];
+        }
+        for (int i = 0; i < k; ++i) y[i] = -y[i];
+        if ((e = hipMemcpyAsync(ydev, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_err(e, "gmres");
+        if ((st = pois_sub(V, k, ydev, n, x, s))) return st;
+        if (done) return FC2D_OK;
+        // restart from the true residual r = b - A x
+        if ((st = pois_matvec(A, x, n, w, s))) return st;
+        if ((st = pois_axpbz(1.0, b, -1.0, w, n, w, s))) return st;
+        if ((st = pois_dots(w, 1, w, n, nrm, s))) return st;
+        double r2 = 0.0;
+        if ((e = hipMemcpyAsync(&r2, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_err(e, "gmres");
+        beta = sqrt(r2);
+        if (beta <= kGmresTol * bnorm) return FC2D_OK;
+        if ((st = pois_axpbz(1.0 / beta, w, 0.0, w, n, V, s))) return st;
+    }
+    set_error("GMRES did not converge");
+    return FC2D_E_NEWTON;
+}
+
+bool pow2(int n) { return n >= 8 && (n & (n - 1)) == 0; }
+
+}  // namespace
+
+extern "C" {
+
+int fc2d_poisson_nodes(const fc2d_plan* pl, int nb, double* xy) {
+    if (!pl || nb < 8 || !xy) { set_error("invalid Poisson node arguments"); return FC2D_E_ARG; }
+    std::vector<double> qd;
+    node_data(pl->curve, nb, qd);
+    for (int j = 0; j < nb; ++j) {
+        xy[2 * j] = qd[6 * (size_t)j];
+        xy[2 * j + 1] = qd[6 * (size_t)j + 1];
+    }
+    return FC2D_OK;
+}
+
+int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, const double* g_nodes,
+                       int nb, double* u, int nf, hipStream_t s, int* gmres_iters) {
+    if (!pl || !f_grid || !f_bdry || !g_nodes || !u || nb < 8 || nb > 16384 || nf < 1) {
+        set_error("invalid Poisson solve arguments");
+        return FC2D_E_ARG;
+    }
+    const fc2d_grid& g = pl->grid;
+    if (!pow2(g.nx) || !pow2(g.ny)) {
+        set_error("Poisson solve: power-of-two grids only");
+        return FC2D_E_ARG;
+    }
+    const int M = pl->M;
+    const int64_t npts = (int64_t)g.nx * g.ny;
+    const int64_t nbdry = pl->B + (int64_t)pl->squares.size() / 2;
+    const int nbf = nb * kRefine;
+    const int m = std::min(nb, kRestart);
+    // node data on the host (curve geometry), the rest on the device
+    std::vector<double> qc, qf;
+    node_data(pl->curve, nb, qc);
+    node_data(pl->curve, nbf, qf);
+    double dsmax = 0.0;
+    for (int j = 0; j < nb; ++j) dsmax = std::max(dsmax, hypot(qc[6 * (size_t)j + 2], qc[6 * (size_t)j + 3]));
+    dsmax *= 2.0 * M_PI / nb;
+    const double far2 = (7.0 * dsmax) * (7.0 * dsmax);
+    PoisBuf db;
+    double* spec = db.get<double>((size_t)g.nx * (g.ny / 2 + 1) * 2);
+    double* work = db.get<double>((size_t)npts);
+    double* up = db.get<double>((size_t)npts);
+    double* mean = db.get<double>(1);
+    double* d_qc = db.get<double>(qc.size());
+    double* d_qf = db.get<double>(qf.size());
+    double* ghom = db.get<double>(nb);
+    double* rhs = db.get<double>(nb);
+    double* A = db.get<double>((size_t)nb * nb);
+    double* phi = db.get<double>(nb);
+    double* phif = db.get<double>(nbf);
+    double* V = db.get<double>((size_t)(m + 1) * nb);
+    double* w = db.get<double>(nb);
+    double* hd = db.get<double>(3 * (size_t)(m + 2) + m);
+    int8_t* cls = db.get<int8_t>((size_t)npts);
+    int32_t* cand = db.get<int32_t>((size_t)std::max<int64_t>(pl->n_in, 1));
+    int* cnt = db.get<int>(2);
+    double* bx = db.get<double>(pl->B);
+    double* by = db.get<double>(pl->B);
+    double* bnx = db.get<double>(pl->B);
+    double* bny = db.get<double>(pl->B);
+    if (!spec || !work || !up || !mean || !d_qc || !d_qf || !ghom || !rhs || !A || !phi || !phif || !V || !w ||
+        !hd || !cls || !cand || !cnt || !bx || !by || !bnx || !bny) {
+        set_error("Poisson solve: out of device memory");
+        return FC2D_E_NOMEM;
+    }
+    hipError_t e;
+    if ((e = hipMemcpyAsync(d_qc, qc.data(), qc.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_qf, qf.data(), qf.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(cls, pl->cls.data(), (size_t)npts, hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(bx, pl->bx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(by, pl->by.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(bnx, pl->bnx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(bny, pl->bny.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+        return hip_err(e, "Poisson solve upload");
+    const BndView bd{bx, by, bnx, bny, pl->B, pl->k2};
+    int st;
+    if ((st = pois_nystrom(d_qc, nb, A, s))) return st;
+    int iters_total = 0;
+    for (int f = 0; f < nf; ++f) {
+        double* uf = u + (int64_t)f * npts;
+        // particular solution: extension + R2C, -1/|k|^2, C2R, mean term
+        if ((st = fc2d_extend_fft(pl, f_grid + (int64_t)f * npts, f_bdry + (int64_t)f * nbdry, work, spec, 1, s)))
+            return st;
+        if ((st = pois_mean(&g, spec, mean, s))) return st;
+        if ((st = spectral_apply(&g, FC2D_LAPLACE_INV, spec, spec, 1, s))) return st;
+        if ((st = fft2_c2r(&g, spec, up, 1, s))) return st;
+        if ((st = pois_add_quad(&g, mean, up, s))) return st;
+        // boundary data of the harmonic part and its density
+        if ((st = pois_ghom(M, &g, up, d_qc, nb, g_nodes + (int64_t)f * nb, ghom, s))) return st;
+        if ((st = pois_axpbz(-2.0, ghom, 0.0, ghom, nb, rhs, s))) return st;
+        int it = 0;
+        if ((st = gmres(A, rhs, phi, nb, V, w, hd, s, &it))) return st;
+        iters_total += it;
+        if ((st = pois_trig_up(phi, nb, kRefine, phif, s))) return st;
+        // v on the grid, then the points next to Gamma
+        if ((e = hipMemsetAsync(cnt, 0, 2 * sizeof(int), s)) != hipSuccess) return hip_err(e, "Poisson solve");
+        if ((st = pois_dl_grid(&g, cls, up, d_qc, phi, nb, d_qf, phif, nbf, far2, uf, cand, cnt, s))) return st;
+        if ((st = pois_dl_near(M, cand, cnt, std::max<int64_t>(pl->n_in, 1), pl->curve, bd, 60, &g, up, ghom, nb,
+                               d_qf, phif, nbf, uf, cnt + 1, s)))
+            return st;
+        int hc[2] = {0, 0};
+        if ((e = hipMemcpyAsync(hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipStreamSynchronize(s)) != hipSuccess)
+            return hip_err(e, "Poisson solve");
+        if (hc[1] > 0) {
+            set_error("Poisson solve: foot of the normal failed next to the boundary");
+            return FC2D_E_NEWTON;
+        }
+    }
+    if (gmres_iters) *gmres_iters = iters_total;
+    return FC2D_OK;
+}
+
+}  // extern "C"

@@ -81,6 +81,8 @@ def _lib():
             "fc2d_extend_fft": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P]),
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
+            "fc2d_poisson_nodes": (C.c_int, [_P, C.c_int, _P]),
+            "fc2d_poisson_solve": (C.c_int, [_P, _P, _P, _P, C.c_int, _P, C.c_int, _P, C.POINTER(C.c_int)]),
             "ff_propagate": (C.c_int, [C.POINTER(fc2d_grid), C.c_double, C.c_double, _P, _P, _P, _P, C.c_int, _P]),
             "fc2d_boundary_values": (C.c_int, [_P, _P, _P, C.c_int, _P]),
             "fc2d_batch_create": (C.c_int, [C.POINTER(_P), C.POINTER(C.c_int), C.c_int, C.c_uint, _P, C.POINTER(_P)]),
@@ -289,6 +291,28 @@ def fc2d_fft(grid, inp, out, direction, stream=None):
     if spec.dtype != torch.complex128 or spec.numel() != nf * grid.nx * (grid.ny // 2 + 1):
         raise ValueError("spectrum must be complex128 [nf][nx][ny/2+1]")
     _check(_lib().fc2d_fft(C.byref(grid), _dptr(inp, "in"), _dptr(out, "out"), int(direction), nf, _stream(stream)))
+
+
+def fc2d_poisson_nodes(plan, nb):
+    """Nystrom nodes q(2 pi j / nb), host array [nb, 2]."""
+    xy = np.zeros((int(nb), 2))
+    _check(_lib().fc2d_poisson_nodes(plan.handle, int(nb), C.c_void_p(xy.ctypes.data)))
+    return xy
+
+
+def fc2d_poisson_solve(plan, f_grid, f_bdry, g_nodes, u, stream=None):
+    """Full Poisson solve; g_nodes [nf, nb] at fc2d_poisson_nodes(plan, nb).
+    Returns the GMRES iterations summed over the fields."""
+    import torch
+    nf = _nf(f_grid, plan.grid)
+    nb = g_nodes.shape[-1]
+    if f_bdry.numel() != nf * plan.info.n_bdry or u.numel() != f_grid.numel() or g_nodes.numel() != nf * nb:
+        raise ValueError("f_bdry / g_nodes / u sizes do not match the plan")
+    it = C.c_int()
+    _check(_lib().fc2d_poisson_solve(plan.handle, _dptr(f_grid, "f_grid", torch.float64),
+                                     _dptr(f_bdry, "f_bdry", torch.float64), _dptr(g_nodes, "g_nodes", torch.float64),
+                                     int(nb), _dptr(u, "u", torch.float64), nf, _stream(stream), C.byref(it)))
+    return it.value
 
 
 def fc2d_spectral_apply(grid, op, inp, out, stream=None):

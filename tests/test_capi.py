@@ -138,3 +138,10 @@ def test_tuning_knobs_host_side():
     # column shapes: only compiled (E, T) pairs
     assert lib.fc2d_tune_set(fc2d.FC2D_TUNE_COL_TILE, 1024, 3) == fc2d.FC2D_E_ARG
     assert lib.fc2d_tune_set(99, 0, 1) == fc2d.FC2D_E_ARG
+
+
+def test_poisson_argument_errors_without_gpu():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    assert lib.fc2d_poisson_solve(None, None, None, None, 64, None, 1, None, None) == fc2d.FC2D_E_ARG
+    assert lib.fc2d_poisson_nodes(None, 64, None) == fc2d.FC2D_E_ARG

@@ -1,0 +1,114 @@
+"""The library's full Poisson solve (Sec. 4.1) against the oracle's
+(`oracle/poisson.py`) on the same plan and data, and against the paper's
+Table 3 accuracy on power-of-two boxes around the kite of Example 4.2."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads as W
+from conftest import load_golden
+from gpu_common import rel_err
+from oracle import fcgram
+from oracle import plan as OP
+from oracle import poisson as OPS
+from oracle.curves import Curve
+
+pytestmark = pytest.mark.gpu
+
+KITE = W.kite(0.35, 0.7)
+
+
+@pytest.fixture(scope="module")
+def torch_mod():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _u_exact(x, y):
+    return np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) / (8 * np.pi ** 2)
+
+
+def _f(x, y):
+    return -np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+
+
+def _box(h, n):
+    xmin, xmax, ymin, ymax = W.bbox(KITE)
+    return 0.5 * (xmin + xmax) - 0.5 * n * h, 0.5 * (ymin + ymax) - 0.5 * n * h
+
+
+def _gpu(torch, h, n, d, M, fs, gs, nb):
+    """GPU solve of Delta u = f_k, u = g_k (closed forms) on the n x n box; returns u, plan, iterations."""
+    from paper_2010_03901_amd import fc2d
+    x0, y0 = _box(h, n)
+    grid = fc2d.make_grid(x0, y0, h, n, n)
+    pl = fc2d.Plan(fc2d.make_curve(*KITE), grid, d=d, C_=27, B=int(round(2 * np.pi / h)), k1=h, M=M)
+    bp = fc2d.fc2d_boundary_points(pl)
+    q = fc2d.fc2d_poisson_nodes(pl, nb)
+    X, Y = np.meshgrid(x0 + np.arange(n) * h, y0 + np.arange(n) * h, indexing="ij")
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    fg = dev(np.stack([f(X, Y) for f in fs]))
+    fb = dev(np.stack([f(bp[:, 0], bp[:, 1]) for f in fs]))
+    gn = dev(np.stack([g(q[:, 0], q[:, 1]) for g in gs]))
+    u = torch.full_like(fg, float("nan"))
+    it = fc2d.fc2d_poisson_solve(pl, fg, fb, gn, u)
+    torch.cuda.synchronize()
+    return u.cpu().numpy(), pl, it, X, Y
+
+
+def _oracle(h, n, d, M, f, g, nb):
+    x0, y0 = _box(h, n)
+    pl = OP.make_plan(Curve(*KITE), OP.Grid(x0, y0, h, n, n), fcgram.load_tables(d), int(round(2 * np.pi / h)),
+                      k1=h, M=M)
+    X, Y = np.meshgrid(pl.grid.xs(), pl.grid.ys(), indexing="ij")
+    bp = OP.boundary_points(pl)
+    _, q, _, _ = OPS.nodes(pl.curve, nb)
+    return OPS.solve(pl, f(X, Y), f(bp[:, 0], bp[:, 1]), g(q[:, 0], q[:, 1]), nb), pl
+
+
+@pytest.mark.parametrize("case", ["poisson", "harmonic"])
+def test_poisson_parity(torch_mod, case):
+    """Two fields in one call; each against the oracle's solve (1e-11 of max |u|)
+    and the plan's classes (every non-IN point 0)."""
+    h, n, d, M, nb = 0.04, 128, 4, 7, 128
+    harm = lambda x, y: np.exp(x) * np.cos(y)
+    zero = lambda x, y: 0.0 * x
+    fs, gs = ([_f, lambda x, y: 2.0 * _f(x, y)], [_u_exact, lambda x, y: 2.0 * _u_exact(x, y)]) \
+        if case == "poisson" else ([zero, zero], [harm, lambda x, y: x * x - y * y])
+    u, pl, it, X, Y = _gpu(torch_mod, h, n, d, M, fs, gs, nb)
+    print("\n[poisson] %s: GMRES iterations %d" % (case, it))
+    assert 0 < it < 200
+    from paper_2010_03901_amd import fc2d
+    cls = fc2d.fc2d_plan_classes(pl)
+    for k in range(2):
+        ref, opl = _oracle(h, n, d, M, fs[k], gs[k], nb)
+        assert np.array_equal(cls, opl.cls)
+        assert np.all(u[k][cls != OP.IN] == 0.0)
+        e = rel_err(u[k], ref)
+        print("[poisson] %s field %d: rel err vs oracle %.2e" % (case, k, e))
+        assert e < 1e-11
+    if case == "harmonic":   # exact for harmonic data, next to Gamma too
+        ins = cls == OP.IN
+        assert np.abs(u[0] - np.exp(X) * np.cos(Y))[ins].max() < 1e-11
+        assert np.abs(u[1] - (X * X - Y * Y))[ins].max() < 1e-11
+
+
+def test_paper_table3_on_power_of_two_boxes(torch_mod):
+    """Example 4.2 (kite, d = 4, M = M_P = 7): relative l2 error over the IN points
+    within 10x of Table 3 at h = 4e-2, 2e-2, 1e-2 (boxes 128^2, 256^2, 512^2
+    instead of the printed N_x x N_y), order above 5.3 over the last halving."""
+    rows = load_golden("paper_table3_kite_poisson.txt")[:3]
+    errs = []
+    for (h, _, _, _, _, ref), n in zip(rows, (128, 256, 512)):
+        u, pl, it, X, Y = _gpu(torch_mod, h, n, 4, 7, [_f], [_u_exact], n)
+        from paper_2010_03901_amd import fc2d
+        ins = fc2d.fc2d_plan_classes(pl) == OP.IN
+        ex = _u_exact(X, Y)[ins]
+        e = np.linalg.norm(u[0][ins] - ex) / np.linalg.norm(ex)
+        print("\n[poisson] Table 3 h=%g (%d^2, nb=%d): GPU %.2e printed %.2e, GMRES %d" % (h, n, n, e, ref, it))
+        assert e < 10 * ref
+        errs.append(e)
+    assert math.log2(errs[-2] / errs[-1]) > 5.3, errs

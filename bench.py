@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--mlp-steps", type=int, default=20000)
     ap.add_argument("--mlp-batch", type=int, default=4096)
     ap.add_argument("--mlp-fields", type=int, default=8)
+    ap.add_argument("--no-poisson", action="store_true", help="skip the full Poisson solve measurement")
+    ap.add_argument("--poisson-n", type=int, default=2048, help="grid of the full Poisson solve")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (known-size kernel for counter calibration)")
     return ap.parse_args()
@@ -181,6 +183,61 @@ def run_batched(args):
                         "Gaussian pulses, u and u_t extended each step",
             "note": "throughput of the step; each step matches the oracle's step from the same state, but "
                     "without a near-boundary solver the iterated state is not a PDE solution"}
+
+
+def run_poisson(args):
+    """Full Poisson solve (Sec. 4.1) on the Poisson workload: kite(0.65, 1.5) in
+    its fitted box (poisson_n^2, d = 5, M = 8, B by the workload's rule), one
+    field, manufactured solution u = sin(2 pi x) sin(2 pi y) / (8 pi^2) (so
+    f = -sin(2 pi x) sin(2 pi y), g = u on Gamma), nb = N Nystrom nodes as in
+    the paper.  Reports the wall time of a solve (it synchronises), the GMRES
+    iterations, per-kernel times (HIP events) and the relative l2 / l_inf error
+    over the IN points against the exact solution."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2010_03901_amd import fc2d
+    case = W.cfg_kite(args.poisson_n)
+    grid = fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n)
+    t0 = time.perf_counter()
+    plan = fc2d.Plan(fc2d.make_curve(*case.curve), grid, d=case.d, C_=case.C, B=case.B, k1=case.k1, M=case.M)
+    plan_s = time.perf_counter() - t0
+    nb = case.n
+    ue = lambda x, y: np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y) / (8 * np.pi ** 2)
+    f = lambda x, y: -np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+    x = case.x0 + np.arange(case.n) * case.h
+    y = case.y0 + np.arange(case.n) * case.h
+    X, Y = np.meshgrid(x, y, indexing="ij")
+    bp = fc2d.fc2d_boundary_points(plan)
+    q = fc2d.fc2d_poisson_nodes(plan, nb)
+    fg = torch.from_numpy(f(X, Y)[None]).to("cuda:0")
+    fb = torch.from_numpy(f(bp[:, 0], bp[:, 1])[None]).to("cuda:0")
+    gn = torch.from_numpy(ue(q[:, 0], q[:, 1])[None]).to("cuda:0")
+    u = torch.empty_like(fg)
+    fc2d.fc2d_poisson_solve(plan, fg, fb, gn, u)            # warm-up
+    reps = 3
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        it = fc2d.fc2d_poisson_solve(plan, fg, fb, gn, u)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    fc2d.fc2d_trace_begin()
+    fc2d.fc2d_poisson_solve(plan, fg, fb, gn, u)
+    tr = fc2d.fc2d_trace_end()
+    per = {}
+    for name, t in tr:
+        if name != "begin":
+            per[name] = per.get(name, 0.0) + t
+    ins = fc2d.fc2d_plan_classes(plan) == 1
+    err = u[0].cpu().numpy()[ins] - ue(X, Y)[ins]
+    ex = ue(X, Y)[ins]
+    return {"workload": "kite(0.65,1.5) fitted %d^2, d=%d, M=%d, B=%d, nb=%d, u=sin(2 pi x)sin(2 pi y)/(8 pi^2)"
+                        % (case.n, case.d, case.M, case.B, nb, ),
+            "ms_per_solve": ms, "gmres_iters": it, "plan_s": plan_s, "in_points": int(ins.sum()),
+            "rel_l2_err": float(np.linalg.norm(err) / np.linalg.norm(ex)),
+            "rel_linf_err": float(np.abs(err).max() / np.abs(ex).max()),
+            "kernels_ms": {k: round(v, 4) for k, v in sorted(per.items(), key=lambda kv: -kv[1])}}
 
 
 def run_mlp(args):
@@ -432,6 +489,13 @@ def main():
         learned = run_mlp(args)
         print("[bench] learned seed: " + json.dumps(learned), file=sys.stderr, flush=True)
 
+    poisson = None
+    if not args.no_poisson:
+        print("[bench] full Poisson solve ...", file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        poisson = run_poisson(args)
+        print("[bench] poisson: " + json.dumps(poisson), file=sys.stderr, flush=True)
+
     cpu = None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
@@ -454,6 +518,7 @@ def main():
         "kernels": kernels,
         "batched_ff": batched,
         "learned_seed": learned,
+        "poisson_full": poisson,
         "plan_s": plan_s,
     }
     print(json.dumps(out))

@@ -151,13 +151,21 @@ int pois_matvec(const double* A, const double* x, int n, double* y, hipStream_t 
 int pois_dots(const double* V, int nv, const double* w, int n, double* out, hipStream_t s);
 int pois_sub(const double* V, int nv, const double* c, int n, double* w, hipStream_t s);
 int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s);
-int pois_trig_up(const double* phi, int nb, int R, double* phif, hipStream_t s);
-int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* qc, const double* phic,
-                 int nb, const double* qf, const double* phif, int nbf, double far2, double* u, int32_t* cand,
-                 int* ncand, hipStream_t s);
+// Levels of the double-layer sums: level L (0 <= L < kPoisLevels) holds 2^L nb
+// equispaced nodes at offset nb (2^L - 1) of the concatenated node arrays.
+constexpr int kPoisLevels = 6;
+// phi on the nb nodes -> phif (finest level, by the Dirichlet kernel) -> node
+// records rec (x, y, phi y', phi x') of every level; geo: (x, y, x', y') per node
+int pois_records(const double* phi, int nb, const double* geo, double* phif, double* rec, hipStream_t s);
+// v at the IN points (u = u_p + v, 0 elsewhere); points next to Gamma listed in
+// cand.  bl: kPoisLevels lists of cap entries (cap >= IN points), bcnt their
+// counts (zero on entry), both scratch
+int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
+                 double* u, int32_t* bl, int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s);
+// the listed points within h/2 of Gamma; recf: finest-level records (nbf nodes)
 int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
-                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* qf,
-                 const double* phif, int nbf, double* u, int* nfail, hipStream_t s);
+                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
+                 int nbf, double* u, int* nfail, hipStream_t s);
 
 // LDS bytes of the strip kernels for a widest block window wmax (normals), and
 // the stage shape they use: at most lcap normals, fstage fields per stage

@@ -9,11 +9,13 @@
 //    diagonal), stored column-major, and the GMRES building blocks;
 //  * the density's trigonometric interpolant on R nb nodes (Dirichlet kernel);
 //  * v = double-layer potential at the IN grid points: the nb-node trapezoidal
-//    sum where every node is at least 7 node spacings away, the R nb-node sum
-//    otherwise; points whose nearest fine node is closer than h are listed,
+//    sum where every node is at least 7 node spacings away, otherwise the sum
+//    on a refined level (2, 4, ..., 32 nb nodes) with spacing at most a seventh
+//    of the distance; points whose nearest node is closer than h are listed,
 //    and those within h/2 of Gamma (foot of the normal, Sec. 3.4) take v from
-//    the foot value g_hom(theta) and the fine sums at M - 1 points h/2, h, ...
-//    inward along the normal, interpolated in the distance with degree M - 1.
+//    the foot value g_hom(theta) and the 32 nb-node sums at M - 1 points h/2,
+//    h, ... inward along the normal, interpolated in the distance with degree
+//    M - 1.
 #include <hip/hip_runtime.h>
 
 #include <math.h>
@@ -134,89 +136,184 @@ __global__ void k_trig_up(const double* __restrict__ phi, int nb, int R, double*
     phif[i] = s;
 }
 
-// trigonometric interpolant of the nb samples at parameter th (as k_trig_up)
-__device__ inline double trig_at(const double* __restrict__ vals, int nb, double th) {
-    double s = 0.0;
-    for (int j = 0; j < nb; ++j) {
-        const double d = th - 2.0 * M_PI * (double)j / (double)nb;
-        const double sh = sin(0.5 * d);
-        if (sh == 0.0) return vals[j];
-        double w = sin(0.5 * nb * d) / (nb * sh);
-        if ((nb & 1) == 0) w *= cos(0.5 * d);
-        s += w * vals[j];
-    }
-    return s;
+// Node records of the double-layer sums: (x, y, phi y', phi x') per node,
+// phi the density at that node.  Level L node k sits at record nb (2^L - 1) + k;
+// its density is finest-level node k 2^(kPoisLevels - 1 - L).
+__global__ void k_records(const double4* __restrict__ geo, const double* __restrict__ phif, int nb,
+                          double4* __restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int top = kPoisLevels - 1;
+    if (i >= (int64_t)nb * ((2 << top) - 1)) return;
+    int L = 0;
+    while (i >= (int64_t)nb * ((2 << L) - 1)) ++L;
+    const int64_t k = i - (int64_t)nb * ((1 << L) - 1);
+    const double ph = phif[k << (top - L)];
+    const double4 g = geo[i];   // x, y, x', y'
+    rec[i] = make_double4(g.x, g.y, ph * g.w, ph * g.z);
 }
 
-// trapezoidal double-layer sum at (X, Y) over n nodes: qd as in k_nystrom
-// (only x, y, x', y' read), density phi; also the smallest squared node distance
-__device__ inline double dl_sum(const double* __restrict__ qd, const double* __restrict__ phi, int n, double X,
-                                double Y, double* dmin2) {
-    double s = 0.0, dm = 1e300;
-    for (int j = 0; j < n; ++j) {
-        const double* b = qd + 6 * j;
-        const double dx = X - b[0], dy = Y - b[1];
-        const double r2 = dx * dx + dy * dy;
-        dm = fmin(dm, r2);
-        s += phi[j] * (dx * b[3] - dy * b[2]) / r2;
-    }
-    *dmin2 = dm;
-    return s / n;   // (1 / 2 pi) x (2 pi / n)
+// 1 / r2 from the hardware reciprocal and two Newton steps (a few ulp; the
+// squared distances here are normal numbers far from the range limits)
+__device__ inline double inv_r2(double r2) {
+    double r = __builtin_amdgcn_rcp(r2);
+    r = fma(fma(-r2, r, 1.0), r, r);
+    r = fma(fma(-r2, r, 1.0), r, r);
+    return r;
 }
 
-// v at every IN point; u = u_p + v there, 0 elsewhere.  Points whose nearest
-// fine node is closer than h are appended to cand (count in *ncand).
-__global__ void k_dl_grid(const int8_t* __restrict__ cls, const double* __restrict__ up, int nx, int ny,
-                          double x0, double y0, double h, const double* __restrict__ qc,
-                          const double* __restrict__ phic, int nb, const double* __restrict__ qf,
-                          const double* __restrict__ phif, int nbf, double far2, double* __restrict__ u,
-                          int32_t* __restrict__ cand, int* __restrict__ ncand) {
-    const int64_t n = (int64_t)nx * ny;
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n; e += (int64_t)gridDim.x * blockDim.x) {
-        if (cls[e] != 1) {
-            u[e] = 0.0;
-            continue;
+// trapezoidal double-layer terms of the node records [j0, j1) at (X, Y), not
+// yet divided by the node count (wave-uniform addresses: the records come
+// through the scalar cache, eight per wait); with MIN also the smallest
+// squared node distance
+template <bool MIN>
+__device__ inline double dl_partial(const double4* __restrict__ rec, int j0, int j1, double X, double Y,
+                                    double* dmin2) {
+    double s0 = 0.0, s1 = 0.0, dm = 1e300;
+    int j = j0;
+    for (; j + 8 <= j1; j += 8) {
+        double4 b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) b[u] = rec[j + u];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double dx = X - b[u].x, dy = Y - b[u].y;
+            const double r2 = dx * dx + dy * dy;
+            if (MIN) dm = r2 < dm ? r2 : dm;
+            const double t = (dx * b[u].z - dy * b[u].w) * inv_r2(r2);
+            if (u & 1) s1 += t; else s0 += t;
         }
-        const int i = (int)(e / ny), j = (int)(e - (int64_t)i * ny);
-        const double X = x0 + i * h, Y = y0 + j * h;
-        double d2;
-        double v = dl_sum(qc, phic, nb, X, Y, &d2);
-        if (d2 < far2) {
-            v = dl_sum(qf, phif, nbf, X, Y, &d2);
+    }
+    for (; j < j1; ++j) {
+        const double4 b = rec[j];
+        const double dx = X - b.x, dy = Y - b.y;
+        const double r2 = dx * dx + dy * dy;
+        if (MIN) dm = r2 < dm ? r2 : dm;
+        s0 += (dx * b.z - dy * b.w) * inv_r2(r2);
+    }
+    if (MIN) *dmin2 = dm;
+    return s0 + s1;
+}
+
+// v at every IN point from the nb-node sum (trapezoidal weight 2 pi / nb, the
+// 1 / (2 pi) of the kernel folded in); u = u_p + v there, 0 elsewhere.  Points
+// whose nearest node is closer than 7 node spacings (dsmax: largest spacing of
+// the nb nodes) go to the list of the level whose spacing is at most a seventh
+// of the point's distance, estimated as that node distance - dsmax / 2 (the
+// finest level at most); bl[L cap ...], count bcnt[L].  Other points closer
+// than h to a node go to cand.
+__global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls, const double* __restrict__ up,
+                                                 int nx, int ny, double x0, double y0, double h,
+                                                 const double4* __restrict__ rec, int nb, double dsmax,
+                                                 double* __restrict__ u, int32_t* __restrict__ bl, int64_t cap,
+                                                 int* __restrict__ bcnt, int32_t* __restrict__ cand,
+                                                 int* __restrict__ ncand) {
+    // one 8 x 8 tile of points per wave
+    const int tj = (ny + 7) >> 3;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
+    const int i = (tile / tj) * 8 + (l >> 3), j = (tile % tj) * 8 + (l & 7);
+    if (i >= nx || j >= ny) return;
+    const int64_t e = (int64_t)i * ny + j;
+    if (cls[e] != 1) {
+        u[e] = 0.0;
+        return;
+    }
+    const double X = x0 + i * h, Y = y0 + j * h;
+    double d2;
+    u[e] = up[e] + dl_partial<true>(rec, 0, nb, X, Y, &d2) / nb;
+    if (d2 < 49.0 * dsmax * dsmax) {
+        const double dest = sqrt(d2) - 0.5 * dsmax;
+        int L = kPoisLevels - 1;
+        if (dest > 0.0) {
+            L = 1;
+            while (L < kPoisLevels - 1 && 7.0 * dsmax / (double)(1 << L) > dest) ++L;
+        }
+        const int k = atomicAdd(bcnt + L, 1);
+        bl[L * cap + k] = (int32_t)e;
+    } else if (d2 < h * h) {
+        const int k = atomicAdd(ncand, 1);
+        cand[k] = (int32_t)e;
+    }
+}
+
+// the listed points of one level (n = 2^L nb nodes), 64 per block, the nodes
+// split over the block's W waves and the partial sums added in wave order;
+// u = u_p + v, and points closer than h to a node of the level go to cand
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_dl_band(const int32_t* __restrict__ bl, const int* __restrict__ bcnt,
+                                                    const double* __restrict__ up, int ny, double x0, double y0,
+                                                    double h, const double4* __restrict__ rec, int n,
+                                                    double* __restrict__ u, int32_t* __restrict__ cand,
+                                                    int* __restrict__ ncand) {
+    __shared__ double ps[W][64], pm[W][64];
+    const int cnt = *bcnt;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
+    const int j0 = (int)((int64_t)n * w / W), j1 = (int)((int64_t)n * (w + 1) / W);
+    for (int g = blockIdx.x; g * 64 < cnt; g += gridDim.x) {
+        const int k = g * 64 + l;
+        const int64_t e = bl[k < cnt ? k : g * 64];   // idle lanes repeat the group's first point
+        const int i = (int)(e / ny), jj = (int)(e - (int64_t)i * ny);
+        double dm;
+        ps[w][l] = dl_partial<true>(rec, j0, j1, x0 + i * h, y0 + jj * h, &dm);
+        pm[w][l] = dm;
+        __syncthreads();
+        if (w == 0 && k < cnt) {
+            double s = 0.0, d2 = 1e300;
+            for (int q = 0; q < W; ++q) {
+                s += ps[q][l];
+                d2 = fmin(d2, pm[q][l]);
+            }
+            u[e] = up[e] + s / n;
             if (d2 < h * h) {
-                const int k = atomicAdd(ncand, 1);
-                cand[k] = (int32_t)e;
+                const int c = atomicAdd(ncand, 1);
+                cand[c] = (int32_t)e;
             }
         }
-        u[e] = up[e] + v;
+        __syncthreads();
     }
 }
 
-// the listed points within h/2 of Gamma: foot (theta, eta); v from the foot
-// value and the fine sums at M - 1 points inward along the normal, degree
-// M - 1 in the distance; plan boundary samples (bx, by, bnx, bny) seed the foot
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// the listed points within h/2 of Gamma, one 64-lane block each: foot
+// (theta, eta) seeded by the nearest plan boundary sample; v from the foot
+// value and the finest-level sums at M - 1 points inward along the normal,
+// degree M - 1 in the distance (lanes split every sum)
 template <int M>
-__global__ void k_dl_near(const int32_t* __restrict__ cand, const int* __restrict__ ncand, CurveC cv, BndView bd,
-                          int maxit, const double* __restrict__ up, int ny, double x0, double y0, double h,
-                          const double* __restrict__ ghom, int nb, const double* __restrict__ qf,
-                          const double* __restrict__ phif, int nbf, double* __restrict__ u,
-                          int* __restrict__ nfail) {
+__global__ __launch_bounds__(64) void k_dl_near(const int32_t* __restrict__ cand, const int* __restrict__ ncand,
+                                                CurveC cv, BndView bd, int maxit, const double* __restrict__ up,
+                                                int ny, double x0, double y0, double h,
+                                                const double* __restrict__ ghom, int nb,
+                                                const double4* __restrict__ recf, int nbf, double* __restrict__ u,
+                                                int* __restrict__ nfail) {
     const int nc = *ncand;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += gridDim.x * blockDim.x) {
+    const int lane = threadIdx.x;
+    for (int e = blockIdx.x; e < nc; e += gridDim.x) {
         const int64_t idx = cand[e];
         const int i = (int)(idx / ny), j = (int)(idx - (int64_t)i * ny);
         const double X = x0 + i * h, Y = y0 + j * h;
-        int p = 0;
+        // nearest boundary sample (smallest index among equals)
         double best = 1e300;
-        for (int r = 0; r < bd.B; ++r) {
+        int p = 0x7fffffff;
+        for (int r = lane; r < bd.B; r += 64) {
             const double dx = bd.x[r] - X, dy = bd.y[r] - Y;
             const double d2 = dx * dx + dy * dy;
             if (d2 < best) { best = d2; p = r; }
         }
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ob = __shfl_xor(best, o, 64);
+            const int op = __shfl_xor(p, o, 64);
+            if (ob < best || (ob == best && op < p)) { best = ob; p = op; }
+        }
         double th, eta;
         int it;
-        if (foot_solve<M>(cv, bd, X, Y, p, maxit, &th, &eta, &it) != FOOT_OK) {
-            atomicAdd(nfail, 1);
+        const int fst = foot_solve<M>(cv, bd, X, Y, p, maxit, &th, &eta, &it);   // every lane, same result
+        if (fst != FOOT_OK) {
+            if (lane == 0) atomicAdd(nfail, 1);
             continue;
         }
         if (!(fabs(eta) < 0.5 * h)) continue;
@@ -225,19 +322,41 @@ __global__ void k_dl_near(const int32_t* __restrict__ cand, const int* __restric
         const double sp = sqrt(o[2] * o[2] + o[3] * o[3]);
         const double ix = -o[3] / sp, iy = o[2] / sp;   // inward normal
         double vals[M];
-        vals[0] = trig_at(ghom, nb, th);
+        {
+            // trigonometric interpolant of g_hom at theta
+            double sv = 0.0;
+            bool hit = false;
+            double hv = 0.0;
+            for (int k = lane; k < nb; k += 64) {
+                const double d = th - 2.0 * M_PI * (double)k / (double)nb;
+                const double sh = sin(0.5 * d);
+                if (sh == 0.0) { hit = true; hv = ghom[k]; continue; }
+                double w = sin(0.5 * nb * d) / (nb * sh);
+                if ((nb & 1) == 0) w *= cos(0.5 * d);
+                sv += w * ghom[k];
+            }
+            sv = wave_sum(sv);
+            const double any = wave_sum(hit ? 1.0 : 0.0);
+            const double hs = wave_sum(hit ? hv : 0.0);
+            vals[0] = any > 0.0 ? hs : sv;
+        }
         for (int m = 1; m < M; ++m) {
             const double s = 0.5 * h * m;
-            double d2;
-            vals[m] = dl_sum(qf, phif, nbf, o[0] + s * ix, o[1] + s * iy, &d2);
+            const double PX = o[0] + s * ix, PY = o[1] + s * iy;
+            double acc = 0.0;
+            for (int k = lane; k < nbf; k += 64) {
+                const double4 b = recf[k];
+                const double dx = PX - b.x, dy = PY - b.y;
+                acc += (dx * b.z - dy * b.w) * inv_r2(dx * dx + dy * dy);
+            }
+            vals[m] = wave_sum(acc) / nbf;
         }
         // Lagrange weights on the nodes s_m = m h / 2 at s = -eta
-        const double x = -eta / (0.5 * h);
         double w[M];
-        equi_weights<M>(x, w);
+        equi_weights<M>(-eta / (0.5 * h), w);
         double v = 0.0;
         for (int m = 0; m < M; ++m) v += w[m] * vals[m];
-        u[idx] = up[idx] + v;
+        if (lane == 0) u[idx] = up[idx] + v;
     }
 }
 
@@ -304,27 +423,47 @@ int pois_axpbz(double a, const double* x, double b, const double* z, int n, doub
     return pois_check("k_axpbz", s);
 }
 
-int pois_trig_up(const double* phi, int nb, int R, double* phif, hipStream_t s) {
-    k_trig_up<<<(unsigned)(((int64_t)nb * R + 255) / 256), 256, 0, s>>>(phi, nb, R, phif);
-    return pois_check("k_trig_up", s);
+int pois_records(const double* phi, int nb, const double* geo, double* phif, double* rec, hipStream_t s) {
+    const int top = kPoisLevels - 1;
+    k_trig_up<<<(unsigned)(((int64_t)nb * (1 << top) + 255) / 256), 256, 0, s>>>(phi, nb, 1 << top, phif);
+    int st = pois_check("k_trig_up", s);
+    if (st) return st;
+    const int64_t nall = (int64_t)nb * ((2 << top) - 1);
+    k_records<<<(unsigned)((nall + 255) / 256), 256, 0, s>>>((const double4*)geo, phif, nb, (double4*)rec);
+    return pois_check("k_records", s);
 }
 
-int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* qc, const double* phic,
-                 int nb, const double* qf, const double* phif, int nbf, double far2, double* u, int32_t* cand,
-                 int* ncand, hipStream_t s) {
-    k_dl_grid<<<blocks_for((int64_t)g->nx * g->ny, 8192), 256, 0, s>>>(cls, up, g->nx, g->ny, g->x0, g->y0, g->h,
-                                                                       qc, phic, nb, qf, phif, nbf, far2, u, cand,
-                                                                       ncand);
-    return pois_check("k_dl_grid", s);
+int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
+                 double* u, int32_t* bl, int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s) {
+    const int64_t tiles = (int64_t)((g->nx + 7) / 8) * ((g->ny + 7) / 8);
+    k_dl_grid<<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(cls, up, g->nx, g->ny, g->x0, g->y0, g->h,
+                                                          (const double4*)rec, nb, dsmax, u, bl, cap, bcnt, cand,
+                                                          ncand);
+    int st = pois_check("k_dl_grid", s);
+    // levels 1 .. kPoisLevels - 1, up to 16 waves per group of 64 points
+    const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 63) / 64, 2048));
+    for (int L = 1; L < kPoisLevels && !st; ++L) {
+        const int64_t off = (int64_t)nb * ((1 << L) - 1);
+        const double4* rl = (const double4*)rec + off;
+        const int32_t* bll = bl + L * cap;
+        switch (L) {
+            case 1: k_dl_band<2><<<nbk, 128, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            case 2: k_dl_band<4><<<nbk, 256, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            case 3: k_dl_band<8><<<nbk, 512, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            default: k_dl_band<16><<<nbk, 1024, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+        }
+        st = pois_check("k_dl_band", s);
+    }
+    return st;
 }
 
 int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
-                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* qf,
-                 const double* phif, int nbf, double* u, int* nfail, hipStream_t s) {
-    const unsigned nbk = blocks_for(cap, 4096);
+                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
+                 int nbf, double* u, int* nfail, hipStream_t s) {
+    const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, 16384));
     switch (M) {
 #define FC2D_NEAR(MM) \
-        case MM: k_dl_near<MM><<<nbk, 256, 0, s>>>(cand, ncand, cv, bd, maxit, up, g->ny, g->x0, g->y0, g->h, ghom, nb, qf, phif, nbf, u, nfail); break;
+        case MM: k_dl_near<MM><<<nbk, 64, 0, s>>>(cand, ncand, cv, bd, maxit, up, g->ny, g->x0, g->y0, g->h, ghom, nb, (const double4*)recf, nbf, u, nfail); break;
         FC2D_NEAR(4) FC2D_NEAR(5) FC2D_NEAR(6) FC2D_NEAR(7) FC2D_NEAR(8) FC2D_NEAR(13) FC2D_NEAR(15)
 #undef FC2D_NEAR
         default: set_error("unsupported M"); return FC2D_E_ARG;

@@ -16,7 +16,7 @@ using namespace fc2d;
 
 namespace {
 
-constexpr int kRefine = 32;      // density refinement factor of the near-boundary sums
+constexpr int kRefine = 1 << (kPoisLevels - 1);   // finest density refinement of the near-boundary sums
 constexpr int kRestart = 80;     // GMRES restart length
 constexpr int kMaxRestarts = 20;
 constexpr double kGmresTol = 1e-14;
@@ -181,37 +181,47 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     double dsmax = 0.0;
     for (int j = 0; j < nb; ++j) dsmax = std::max(dsmax, hypot(qc[6 * (size_t)j + 2], qc[6 * (size_t)j + 3]));
     dsmax *= 2.0 * M_PI / nb;
-    const double far2 = (7.0 * dsmax) * (7.0 * dsmax);
+    // (x, y, x', y') of the nodes of every level, coarser ones subsampled from the finest
+    const int64_t nall = (int64_t)nb * (2 * kRefine - 1);
+    std::vector<double> geo((size_t)nall * 4);
+    for (int L = 0; L < kPoisLevels; ++L) {
+        const int64_t off = (int64_t)nb * ((1 << L) - 1), stride = kRefine >> L;
+        for (int64_t k = 0; k < ((int64_t)nb << L); ++k)
+            std::copy_n(qf.data() + 6 * k * stride, 4, geo.data() + 4 * (off + k));
+    }
     PoisBuf db;
     double* spec = db.get<double>((size_t)g.nx * (g.ny / 2 + 1) * 2);
     double* work = db.get<double>((size_t)npts);
     double* up = db.get<double>((size_t)npts);
     double* mean = db.get<double>(1);
     double* d_qc = db.get<double>(qc.size());
-    double* d_qf = db.get<double>(qf.size());
+    double* d_geo = db.get<double>(geo.size());
+    double* rec = db.get<double>(geo.size());
     double* ghom = db.get<double>(nb);
     double* rhs = db.get<double>(nb);
     double* A = db.get<double>((size_t)nb * nb);
     double* phi = db.get<double>(nb);
-    double* phif = db.get<double>(nbf);
+    double* phif = db.get<double>((size_t)nbf);
     double* V = db.get<double>((size_t)(m + 1) * nb);
     double* w = db.get<double>(nb);
     double* hd = db.get<double>(3 * (size_t)(m + 2) + m);
     int8_t* cls = db.get<int8_t>((size_t)npts);
     int32_t* cand = db.get<int32_t>((size_t)std::max<int64_t>(pl->n_in, 1));
-    int* cnt = db.get<int>(2);
+    int* cnt = db.get<int>(2 + kPoisLevels);   // candidates, foot failures, level counts
+    const int64_t cap = std::max<int64_t>(pl->n_in, 1);
+    int32_t* bl = db.get<int32_t>((size_t)cap * kPoisLevels);
     double* bx = db.get<double>(pl->B);
     double* by = db.get<double>(pl->B);
     double* bnx = db.get<double>(pl->B);
     double* bny = db.get<double>(pl->B);
-    if (!spec || !work || !up || !mean || !d_qc || !d_qf || !ghom || !rhs || !A || !phi || !phif || !V || !w ||
-        !hd || !cls || !cand || !cnt || !bx || !by || !bnx || !bny) {
+    if (!spec || !work || !up || !mean || !d_qc || !d_geo || !rec || !ghom || !rhs || !A || !phi || !phif || !V || !w ||
+        !hd || !cls || !cand || !cnt || !bl || !bx || !by || !bnx || !bny) {
         set_error("Poisson solve: out of device memory");
         return FC2D_E_NOMEM;
     }
     hipError_t e;
     if ((e = hipMemcpyAsync(d_qc, qc.data(), qc.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(d_qf, qf.data(), qf.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+        (e = hipMemcpyAsync(d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(cls, pl->cls.data(), (size_t)npts, hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(bx, pl->bx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(by, pl->by.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
@@ -237,12 +247,14 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
         int it = 0;
         if ((st = gmres(A, rhs, phi, nb, V, w, hd, s, &it))) return st;
         iters_total += it;
-        if ((st = pois_trig_up(phi, nb, kRefine, phif, s))) return st;
+        if ((st = pois_records(phi, nb, d_geo, phif, rec, s))) return st;
         // v on the grid, then the points next to Gamma
-        if ((e = hipMemsetAsync(cnt, 0, 2 * sizeof(int), s)) != hipSuccess) return hip_err(e, "Poisson solve");
-        if ((st = pois_dl_grid(&g, cls, up, d_qc, phi, nb, d_qf, phif, nbf, far2, uf, cand, cnt, s))) return st;
+        if ((e = hipMemsetAsync(cnt, 0, (2 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
+            return hip_err(e, "Poisson solve");
+        if ((st = pois_dl_grid(&g, cls, up, rec, nb, dsmax, uf, bl, cap, cnt + 2, cand, cnt, s))) return st;
+        const int64_t top = (int64_t)nb * (kRefine - 1);
         if ((st = pois_dl_near(M, cand, cnt, std::max<int64_t>(pl->n_in, 1), pl->curve, bd, 60, &g, up, ghom, nb,
-                               d_qf, phif, nbf, uf, cnt + 1, s)))
+                               rec + 4 * top, nbf, uf, cnt + 1, s)))
             return st;
         int hc[2] = {0, 0};
         if ((e = hipMemcpyAsync(hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||

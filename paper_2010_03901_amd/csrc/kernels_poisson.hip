@@ -52,6 +52,39 @@ __global__ void k_pois_ghom(const double* __restrict__ up, int nx, int ny, doubl
     ghom[j] = g[j] - bval_one<M>(up, nx, ny, x0, y0, h, qd[6 * j], qd[6 * j + 1]);
 }
 
+__global__ void k_pois_nodes(CurveC cv, int nb, double* __restrict__ qc, double* __restrict__ geo) {
+    const int top = kPoisLevels - 1;
+    const int64_t nall = (int64_t)nb * ((2 << top) - 1);
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nb + nall) return;
+    const double nf = (double)nb * (double)(1 << top);
+    double o[6];
+    if (i < nb) {
+        curve_eval(cv, 2.0 * M_PI * (double)(i << top) / nf, o);
+        for (int c = 0; c < 6; ++c) qc[6 * i + c] = o[c];
+        return;
+    }
+    const int64_t e = i - nb;
+    int L = 0;
+    while (e >= (int64_t)nb * ((2 << L) - 1)) ++L;
+    const int64_t k = e - (int64_t)nb * ((1 << L) - 1);
+    curve_eval(cv, 2.0 * M_PI * (double)(k << (top - L)) / nf, o);
+    reinterpret_cast<double4*>(geo)[e] = make_double4(o[0], o[1], o[2], o[3]);
+}
+
+// one block per grid row; runs (start, end, class) cover the row in order
+__global__ void k_pois_classes(const int32_t* __restrict__ run_ptr, const int32_t* __restrict__ run, int ny,
+                               int8_t* __restrict__ cls) {
+    const int i = blockIdx.x;
+    const int r0 = run_ptr[i], r1 = run_ptr[i + 1];
+    for (int j = threadIdx.x; j < ny; j += blockDim.x) {
+        int8_t c = 0;
+        for (int r = r0; r < r1; ++r)
+            if (j >= run[3 * r] && j < run[3 * r + 1]) c = (int8_t)run[3 * r + 2];
+        cls[(int64_t)i * ny + j] = c;
+    }
+}
+
 // A[j nb + i] = delta_ij - 2 K(t_i, t_j) 2 pi / nb, with K(t, tau) =
 // (q(t) - q(tau)) . (y'(tau), -x'(tau)) / (2 pi |q(t) - q(tau)|^2) and the
 // diagonal limit -(x' y'' - y' x'') / (4 pi |q'|^2).  qd: (x, y, x', y', x'', y'') per node.
@@ -72,12 +105,30 @@ __global__ void k_nystrom(const double* __restrict__ qd, int nb, double* __restr
 }
 
 // ---- GMRES building blocks (vectors of length n; V holds basis vectors of stride n)
-__global__ void k_matvec_cm(const double* __restrict__ A, const double* __restrict__ x, int n,
-                            double* __restrict__ y) {
+// part[c n + i] = sum over the columns k of split c of A[k n + i] x[k]
+// (A column-major; grid: row blocks of 256 x column splits)
+__global__ __launch_bounds__(256) void k_matvec_part(const double* __restrict__ A, const double* __restrict__ x,
+                                                     int n, int splits, double* __restrict__ part) {
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    const int c = blockIdx.y;
+    const int k0 = (int)((int64_t)n * c / splits), k1 = (int)((int64_t)n * (c + 1) / splits);
+    if (i >= n) return;
+    double s0 = 0.0, s1 = 0.0;
+    int k = k0;
+    for (; k + 2 <= k1; k += 2) {
+        s0 += A[(int64_t)k * n + i] * x[k];
+        s1 += A[(int64_t)(k + 1) * n + i] * x[k + 1];
+    }
+    if (k < k1) s0 += A[(int64_t)k * n + i] * x[k];
+    part[(int64_t)c * n + i] = s0 + s1;
+}
+
+// y[i] = sum of the splits' partial sums, in split order
+__global__ void k_matvec_sum(const double* __restrict__ part, int n, int splits, double* __restrict__ y) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
-    for (int k = 0; k < n; ++k) s += A[(int64_t)k * n + i] * x[k];
+    for (int c = 0; c < splits; ++c) s += part[(int64_t)c * n + i];
     y[i] = s;
 }
 
@@ -115,25 +166,57 @@ __global__ void k_axpbz(double a, const double* __restrict__ x, double b, const 
     if (i < n) y[i] = a * x[i] + b * z[i];
 }
 
-// density on R nb equispaced nodes: phif[i] = sum_j phi_j D(tau_i - t_j)
-__global__ void k_trig_up(const double* __restrict__ phi, int nb, int R, double* __restrict__ phif) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int nf = nb * R;
-    if (i >= nf) return;
-    if (i % R == 0) {
-        phif[i] = phi[i / R];
+// Trigonometric interpolation of the nb samples phi_j (nodes t_j = 2 pi j / nb)
+// at the R nb nodes tau_i = 2 pi i / (R nb) through the Dirichlet kernel
+// D(s) = sin(nb s / 2) / (nb sin(s / 2)), times cos(s / 2) for even nb.  With
+// i = R m + r, tau_i - t_j = 2 pi (k + r / R) / nb, k = m - j (mod nb; D has
+// period 2 pi), so residue r is a circulant convolution of phi with
+// W_r[k] = D(2 pi (k + r / R) / nb) = (-1)^k sin(pi r / R) c(pi x) / nb, where
+// x = (k R + r) / (R nb) and c = cot (even nb) or 1 / sin (odd nb).
+// W[(r - 1) nb + k], r = 1 .. R - 1; x is a ratio of integers, so sinpi / cospi
+// take it with relative rounding only.
+__global__ void k_trig_weights(int nb, int R, double* __restrict__ W) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= (int64_t)(R - 1) * nb) return;
+    const int r = (int)(e / nb) + 1, k = (int)(e - (int64_t)(r - 1) * nb);
+    const double x = (double)((int64_t)k * R + r) / ((double)R * nb);
+    double sx, cx;
+    sincospi(x, &sx, &cx);
+    const double c = (nb & 1) ? 1.0 / sx : cx / sx;
+    W[e] = ((k & 1) ? -1.0 : 1.0) * sinpi((double)r / R) * c / nb;
+}
+
+// phif[R m + r] = sum_j phi_j W_r[(m - j) mod nb] for r >= 1, phif[R m] = phi_m.
+// Block: 256 consecutive m of one r (blockIdx.y); phi and the window of W_r
+// that a chunk of 1024 j needs are staged in LDS.
+__global__ __launch_bounds__(256) void k_trig_conv(const double* __restrict__ phi, int nb, int R,
+                                                   const double* __restrict__ W, double* __restrict__ phif) {
+    constexpr int CJ = 1024;
+    __shared__ double ph[CJ], win[CJ + 256];
+    const int r = blockIdx.y, m0 = blockIdx.x * 256, ml = threadIdx.x, m = m0 + ml;
+    if (r == 0) {
+        if (m < nb) phif[(int64_t)R * m] = phi[m];
         return;
     }
-    const double tau = 2.0 * M_PI * (double)i / (double)nf;
+    const double* Wr = W + (int64_t)(r - 1) * nb;
     double s = 0.0;
-    for (int j = 0; j < nb; ++j) {
-        const double d = tau - 2.0 * M_PI * (double)j / (double)nb;
-        const double sh = sin(0.5 * d);
-        double w = sin(0.5 * nb * d) / (nb * sh);
-        if ((nb & 1) == 0) w *= cos(0.5 * d);
-        s += w * phi[j];
+    for (int j0 = 0; j0 < nb; j0 += CJ) {
+        const int nj = min(CJ, nb - j0);
+        // window: win[t] = W_r[(m0 - j0 - (CJ - 1) + t) mod nb], t < CJ + 255
+        int kb = (m0 - j0 - (CJ - 1)) % nb;
+        if (kb < 0) kb += nb;
+        for (int t = ml; t < CJ + 255; t += 256) {
+            int k = kb + t;
+            while (k >= nb) k -= nb;
+            win[t] = Wr[k];
+        }
+        for (int t = ml; t < nj; t += 256) ph[t] = phi[j0 + t];
+        __syncthreads();
+        if (m < nb)
+            for (int jj = 0; jj < nj; ++jj) s += ph[jj] * win[ml - jj + CJ - 1];
+        __syncthreads();
     }
-    phif[i] = s;
+    if (m < nb) phif[(int64_t)R * m + r] = s;
 }
 
 // Node records of the double-layer sums: (x, y, phi y', phi x') per node,
@@ -398,13 +481,28 @@ int pois_ghom(int M, const fc2d_grid* g, const double* up, const double* qd, int
     return pois_check("k_pois_ghom", s);
 }
 
+int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, hipStream_t s) {
+    const int64_t n = (int64_t)nb * (2 << (kPoisLevels - 1));   // nb + all levels
+    k_pois_nodes<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(cv, nb, qc, geo);
+    return pois_check("k_pois_nodes", s);
+}
+
+int pois_classes(const int32_t* run_ptr, const int32_t* run, int nx, int ny, int8_t* cls, hipStream_t s) {
+    k_pois_classes<<<(unsigned)nx, 256, 0, s>>>(run_ptr, run, ny, cls);
+    return pois_check("k_pois_classes", s);
+}
+
 int pois_nystrom(const double* qd, int nb, double* A, hipStream_t s) {
     k_nystrom<<<blocks_for((int64_t)nb * nb, (int64_t)1 << 30), 256, 0, s>>>(qd, nb, A);
     return pois_check("k_nystrom", s);
 }
 
-int pois_matvec(const double* A, const double* x, int n, double* y, hipStream_t s) {
-    k_matvec_cm<<<(unsigned)((n + 127) / 128), 128, 0, s>>>(A, x, n, y);
+int pois_matvec_splits(int n) { return std::max(1, std::min(64, n / 32)); }
+
+int pois_matvec(const double* A, const double* x, int n, double* part, double* y, hipStream_t s) {
+    const int sp = pois_matvec_splits(n);
+    k_matvec_part<<<dim3((unsigned)((n + 255) / 256), (unsigned)sp), 256, 0, s>>>(A, x, n, sp, part);
+    k_matvec_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, n, sp, y);
     return pois_check("k_matvec", s);
 }
 
@@ -423,9 +521,11 @@ int pois_axpbz(double a, const double* x, double b, const double* z, int n, doub
     return pois_check("k_axpbz", s);
 }
 
-int pois_records(const double* phi, int nb, const double* geo, double* phif, double* rec, hipStream_t s) {
-    const int top = kPoisLevels - 1;
-    k_trig_up<<<(unsigned)(((int64_t)nb * (1 << top) + 255) / 256), 256, 0, s>>>(phi, nb, 1 << top, phif);
+int pois_records(const double* phi, int nb, const double* geo, double* wtab, double* phif, double* rec,
+                 hipStream_t s) {
+    const int top = kPoisLevels - 1, R = 1 << top;
+    k_trig_weights<<<(unsigned)(((int64_t)(R - 1) * nb + 255) / 256), 256, 0, s>>>(nb, R, wtab);
+    k_trig_conv<<<dim3((unsigned)((nb + 255) / 256), (unsigned)R), 256, 0, s>>>(phi, nb, R, wtab, phif);
     int st = pois_check("k_trig_up", s);
     if (st) return st;
     const int64_t nall = (int64_t)nb * ((2 << top) - 1);

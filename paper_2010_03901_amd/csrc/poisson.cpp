@@ -27,17 +27,30 @@ void node_data(const CurveC& cv, int n, std::vector<double>& qd) {
     for (int j = 0; j < n; ++j) curve_eval(cv, 2.0 * M_PI * (double)j / (double)n, &qd[6 * (size_t)j]);
 }
 
-struct PoisBuf {
-    std::vector<void*> ptrs;
-    ~PoisBuf() {
-        for (void* p : ptrs) (void)hipFree(p);
+// all device buffers of a solve in one allocation (256-byte aligned pieces)
+struct PoisArena {
+    void* base = nullptr;
+    std::vector<std::pair<void**, size_t>> req;
+    ~PoisArena() {
+        if (base) (void)hipFree(base);
     }
     template <class T>
-    T* get(size_t n) {
-        void* p = nullptr;
-        if (hipMalloc(&p, std::max<size_t>(n, 1) * sizeof(T)) != hipSuccess) return nullptr;
-        ptrs.push_back(p);
-        return (T*)p;
+    void add(T** p, size_t n) {
+        req.push_back({(void**)p, (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255});
+    }
+    bool commit() {
+        size_t tot = 0;
+        for (auto& r : req) tot += r.second;
+        if (hipMalloc(&base, tot) != hipSuccess) {
+            base = nullptr;
+            return false;
+        }
+        size_t off = 0;
+        for (auto& r : req) {
+            *r.first = (char*)base + off;
+            off += r.second;
+        }
+        return true;
     }
 };
 
@@ -48,8 +61,8 @@ int hip_err(hipError_t e, const char* what) {
 
 // Restarted GMRES with classical Gram-Schmidt applied twice; A column-major
 // n x n (device), b and x device vectors; x starts at zero.
-int gmres(const double* A, const double* b, double* x, int n, double* V, double* w, double* hd, hipStream_t s,
-          int* iters) {
+int gmres(const double* A, const double* b, double* x, int n, double* V, double* w, double* hd, double* part,
+          hipStream_t s, int* iters) {
     const int m = std::min(n, kRestart);
     std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1));
     double* h1 = hd;                 // [m + 1]
@@ -77,7 +90,7 @@ int gmres(const double* A, const double* b, double* x, int n, double* V, double*
         bool done = false;
         for (int j = 0; j < m; ++j) {
             double* vj1 = V + (size_t)(j + 1) * n;
-            if ((st = pois_matvec(A, V + (size_t)j * n, n, w, s))) return st;
+            if ((st = pois_matvec(A, V + (size_t)j * n, n, part, w, s))) return st;
             if ((st = pois_dots(V, j + 1, w, n, h1, s))) return st;
             if ((st = pois_sub(V, j + 1, h1, n, w, s))) return st;
             if ((st = pois_dots(V, j + 1, w, n, h2, s))) return st;
@@ -126,7 +139,7 @@ int gmres(const double* A, const double* b, double* x, int n, double* V, double*
         if ((st = pois_sub(V, k, ydev, n, x, s))) return st;
         if (done) return FC2D_OK;
         // restart from the true residual r = b - A x
-        if ((st = pois_matvec(A, x, n, w, s))) return st;
+        if ((st = pois_matvec(A, x, n, part, w, s))) return st;
         if ((st = pois_axpbz(1.0, b, -1.0, w, n, w, s))) return st;
         if ((st = pois_dots(w, 1, w, n, nrm, s))) return st;
         double r2 = 0.0;
@@ -174,62 +187,61 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     const int64_t nbdry = pl->B + (int64_t)pl->squares.size() / 2;
     const int nbf = nb * kRefine;
     const int m = std::min(nb, kRestart);
-    // node data on the host (curve geometry), the rest on the device
-    std::vector<double> qc, qf;
+    // largest node spacing of the nb nodes (host); node data, classes and the
+    // rest on the device
+    std::vector<double> qc;
     node_data(pl->curve, nb, qc);
-    node_data(pl->curve, nbf, qf);
     double dsmax = 0.0;
     for (int j = 0; j < nb; ++j) dsmax = std::max(dsmax, hypot(qc[6 * (size_t)j + 2], qc[6 * (size_t)j + 3]));
     dsmax *= 2.0 * M_PI / nb;
-    // (x, y, x', y') of the nodes of every level, coarser ones subsampled from the finest
-    const int64_t nall = (int64_t)nb * (2 * kRefine - 1);
-    std::vector<double> geo((size_t)nall * 4);
-    for (int L = 0; L < kPoisLevels; ++L) {
-        const int64_t off = (int64_t)nb * ((1 << L) - 1), stride = kRefine >> L;
-        for (int64_t k = 0; k < ((int64_t)nb << L); ++k)
-            std::copy_n(qf.data() + 6 * k * stride, 4, geo.data() + 4 * (off + k));
-    }
-    PoisBuf db;
-    double* spec = db.get<double>((size_t)g.nx * (g.ny / 2 + 1) * 2);
-    double* work = db.get<double>((size_t)npts);
-    double* up = db.get<double>((size_t)npts);
-    double* mean = db.get<double>(1);
-    double* d_qc = db.get<double>(qc.size());
-    double* d_geo = db.get<double>(geo.size());
-    double* rec = db.get<double>(geo.size());
-    double* ghom = db.get<double>(nb);
-    double* rhs = db.get<double>(nb);
-    double* A = db.get<double>((size_t)nb * nb);
-    double* phi = db.get<double>(nb);
-    double* phif = db.get<double>((size_t)nbf);
-    double* V = db.get<double>((size_t)(m + 1) * nb);
-    double* w = db.get<double>(nb);
-    double* hd = db.get<double>(3 * (size_t)(m + 2) + m);
-    int8_t* cls = db.get<int8_t>((size_t)npts);
-    int32_t* cand = db.get<int32_t>((size_t)std::max<int64_t>(pl->n_in, 1));
-    int* cnt = db.get<int>(2 + kPoisLevels);   // candidates, foot failures, level counts
+    const int64_t nall = (int64_t)nb * (2 * kRefine - 1);   // nodes of all levels
     const int64_t cap = std::max<int64_t>(pl->n_in, 1);
-    int32_t* bl = db.get<int32_t>((size_t)cap * kPoisLevels);
-    double* bx = db.get<double>(pl->B);
-    double* by = db.get<double>(pl->B);
-    double* bnx = db.get<double>(pl->B);
-    double* bny = db.get<double>(pl->B);
-    if (!spec || !work || !up || !mean || !d_qc || !d_geo || !rec || !ghom || !rhs || !A || !phi || !phif || !V || !w ||
-        !hd || !cls || !cand || !cnt || !bl || !bx || !by || !bnx || !bny) {
+    double *spec, *work, *up, *mean, *d_qc, *d_geo, *rec, *ghom, *rhs, *A, *phi, *phif, *wtab, *part, *V, *w, *hd;
+    double *bx, *by, *bnx, *bny;
+    int8_t* cls;
+    int32_t *cand, *bl;
+    int* cnt;
+    PoisArena db;
+    db.add(&spec, (size_t)g.nx * (g.ny / 2 + 1) * 2);
+    db.add(&work, (size_t)npts);
+    db.add(&up, (size_t)npts);
+    db.add(&mean, 1);
+    db.add(&d_qc, 6 * (size_t)nb);
+    db.add(&d_geo, 4 * (size_t)nall);
+    db.add(&rec, 4 * (size_t)nall);
+    db.add(&ghom, nb);
+    db.add(&rhs, nb);
+    db.add(&A, (size_t)nb * nb);
+    db.add(&phi, nb);
+    db.add(&phif, (size_t)nbf);
+    db.add(&wtab, (size_t)nbf);   // (kRefine - 1) nb weights
+    db.add(&part, (size_t)pois_matvec_splits(nb) * nb);
+    db.add(&V, (size_t)(m + 1) * nb);
+    db.add(&w, nb);
+    db.add(&hd, 3 * (size_t)(m + 2) + m);
+    db.add(&cls, (size_t)npts);
+    db.add(&cand, (size_t)cap);
+    db.add(&cnt, 2 + kPoisLevels);   // candidates, foot failures, level counts
+    db.add(&bl, (size_t)cap * kPoisLevels);
+    db.add(&bx, pl->B);
+    db.add(&by, pl->B);
+    db.add(&bnx, pl->B);
+    db.add(&bny, pl->B);
+    if (!db.commit()) {
         set_error("Poisson solve: out of device memory");
         return FC2D_E_NOMEM;
     }
     hipError_t e;
-    if ((e = hipMemcpyAsync(d_qc, qc.data(), qc.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(d_geo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(cls, pl->cls.data(), (size_t)npts, hipMemcpyHostToDevice, s)) != hipSuccess ||
-        (e = hipMemcpyAsync(bx, pl->bx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
+    if ((e = hipMemcpyAsync(bx, pl->bx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(by, pl->by.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(bnx, pl->bnx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(bny, pl->bny.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
         return hip_err(e, "Poisson solve upload");
-    const BndView bd{bx, by, bnx, bny, pl->B, pl->k2};
+    trace_point("pois_setup", s);
     int st;
+    if ((st = pois_nodes(pl->curve, nb, d_qc, d_geo, s))) return st;
+    if ((st = pois_classes(pl->d_run_ptr, pl->d_run, g.nx, g.ny, cls, s))) return st;
+    const BndView bd{bx, by, bnx, bny, pl->B, pl->k2};
     if ((st = pois_nystrom(d_qc, nb, A, s))) return st;
     int iters_total = 0;
     for (int f = 0; f < nf; ++f) {
@@ -245,9 +257,9 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
         if ((st = pois_ghom(M, &g, up, d_qc, nb, g_nodes + (int64_t)f * nb, ghom, s))) return st;
         if ((st = pois_axpbz(-2.0, ghom, 0.0, ghom, nb, rhs, s))) return st;
         int it = 0;
-        if ((st = gmres(A, rhs, phi, nb, V, w, hd, s, &it))) return st;
+        if ((st = gmres(A, rhs, phi, nb, V, w, hd, part, s, &it))) return st;
         iters_total += it;
-        if ((st = pois_records(phi, nb, d_geo, phif, rec, s))) return st;
+        if ((st = pois_records(phi, nb, d_geo, wtab, phif, rec, s))) return st;
         // v on the grid, then the points next to Gamma
         if ((e = hipMemsetAsync(cnt, 0, (2 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
             return hip_err(e, "Poisson solve");

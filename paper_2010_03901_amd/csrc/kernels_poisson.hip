@@ -246,34 +246,44 @@ __device__ inline double inv_r2(double r2) {
 
 // trapezoidal double-layer terms of the node records [j0, j1) at (X, Y), not
 // yet divided by the node count (wave-uniform addresses: the records come
-// through the scalar cache, eight per wait); with MIN also the smallest
-// squared node distance
+// through the scalar cache, eight per wait; the eight reciprocals are formed
+// side by side).  With MIN also a lower bound of the smallest squared node
+// distance: the minimum of the high words, low word zero (relative error below
+// 2^-20, rounded down; it only steers the level choice and the candidate test).
 template <bool MIN>
 __device__ inline double dl_partial(const double4* __restrict__ rec, int j0, int j1, double X, double Y,
                                     double* dmin2) {
-    double s0 = 0.0, s1 = 0.0, dm = 1e300;
+    double s0 = 0.0, s1 = 0.0;
+    unsigned dmh = 0xffffffffu;
     int j = j0;
     for (; j + 8 <= j1; j += 8) {
         double4 b[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) b[u] = rec[j + u];
+        double r2[8], nm[8], rv[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
             const double dx = X - b[u].x, dy = Y - b[u].y;
-            const double r2 = dx * dx + dy * dy;
-            if (MIN) dm = r2 < dm ? r2 : dm;
-            const double t = (dx * b[u].z - dy * b[u].w) * inv_r2(r2);
-            if (u & 1) s1 += t; else s0 += t;
+            r2[u] = dx * dx + dy * dy;
+            nm[u] = dx * b[u].z - dy * b[u].w;
+            if (MIN) dmh = min(dmh, (unsigned)(__double_as_longlong(r2[u]) >> 32));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) rv[u] = inv_r2(r2[u]);
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            if (u & 1) s1 += nm[u] * rv[u];
+            else s0 += nm[u] * rv[u];
         }
     }
     for (; j < j1; ++j) {
         const double4 b = rec[j];
         const double dx = X - b.x, dy = Y - b.y;
         const double r2 = dx * dx + dy * dy;
-        if (MIN) dm = r2 < dm ? r2 : dm;
+        if (MIN) dmh = min(dmh, (unsigned)(__double_as_longlong(r2) >> 32));
         s0 += (dx * b.z - dy * b.w) * inv_r2(r2);
     }
-    if (MIN) *dmin2 = dm;
+    if (MIN) *dmin2 = __longlong_as_double((long long)((unsigned long long)dmh << 32));
     return s0 + s1;
 }
 

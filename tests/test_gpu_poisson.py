@@ -112,3 +112,19 @@ def test_paper_table3_on_power_of_two_boxes(torch_mod):
         assert e < 10 * ref
         errs.append(e)
     assert math.log2(errs[-2] / errs[-1]) > 5.3, errs
+
+
+@pytest.mark.parametrize("h,nb", [(0.04, 100), (0.04, 129), (0.04, 2000)], ids=["nb100", "nb129_odd", "dense_nodes"])
+def test_poisson_node_counts(torch_mod, h, nb):
+    """Node counts off the powers of two: even (100) and odd (129, the odd
+    Dirichlet kernel), and nb = 2000, where seven node spacings are
+    below h, so points next to Gamma are found outside the refined band; each
+    against the oracle's solve (1e-11 of max |u|)."""
+    n, d, M = 128, 4, 7
+    u, pl, it, X, Y = _gpu(torch_mod, h, n, d, M, [_f], [_u_exact], nb)
+    ref, opl = _oracle(h, n, d, M, _f, _u_exact, nb)
+    from paper_2010_03901_amd import fc2d
+    assert np.array_equal(fc2d.fc2d_plan_classes(pl), opl.cls)
+    e = rel_err(u[0], ref)
+    print("\n[poisson] h=%g nb=%d: GMRES %d, rel err vs oracle %.2e" % (h, nb, it, e))
+    assert e < 1e-11

@@ -172,10 +172,14 @@ int pois_records(const double* phi, int nb, const double* geo, double* wtab, dou
 // counts (zero on entry), both scratch
 int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
                  double* u, int32_t* bl, int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s);
-// the listed points within h/2 of Gamma; recf: finest-level records (nbf nodes)
+// the listed points within h/2 of Gamma; recf: finest-level records (nbf nodes).
+// Scratch for up to capn such points: nidx [capn], nw [capn M], nv0 [capn],
+// samp [capn (M - 1)] point pairs, sval [capn (M - 1)]; ncnt[0] counts them
+// and ncnt[1] those beyond capn (both zero on entry).
 int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
                  int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
-                 int nbf, double* u, int* nfail, hipStream_t s);
+                 int nbf, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
+                 int* ncnt, double* u, int* nfail, hipStream_t s);
 
 // LDS bytes of the strip kernels for a widest block window wmax (normals), and
 // the stage shape they use: at most lcap normals, fstage fields per stage

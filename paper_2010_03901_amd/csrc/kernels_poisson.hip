@@ -372,23 +372,25 @@ __device__ inline double wave_sum(double v) {
 }
 
 // the listed points within h/2 of Gamma, one 64-lane block each: foot
-// (theta, eta) seeded by the nearest plan boundary sample; v from the foot
-// value and the finest-level sums at M - 1 points inward along the normal,
-// degree M - 1 in the distance (lanes split every sum)
+// (theta, eta) seeded by the nearest plan boundary sample (lane reduction,
+// smallest index among equals), g_hom(theta) by the lanes, the degree-(M - 1)
+// Lagrange weights in the distance on the nodes s_m = m h / 2 at s = -eta,
+// and the M - 1 points P_m = foot + s_m (inward normal), m >= 1, whose sums
+// k_dl_samples forms.  Near point k: nidx[k], nw[k M + m], nv0[k] = g_hom(theta),
+// samp[k (M - 1) + m - 1] = P_m; count cnt[0], beyond capn counted in cnt[1].
 template <int M>
-__global__ __launch_bounds__(64) void k_dl_near(const int32_t* __restrict__ cand, const int* __restrict__ ncand,
-                                                CurveC cv, BndView bd, int maxit, const double* __restrict__ up,
-                                                int ny, double x0, double y0, double h,
-                                                const double* __restrict__ ghom, int nb,
-                                                const double4* __restrict__ recf, int nbf, double* __restrict__ u,
-                                                int* __restrict__ nfail) {
+__global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ cand, const int* __restrict__ ncand,
+                                                  CurveC cv, BndView bd, int maxit, int ny, double x0, double y0,
+                                                  double h, const double* __restrict__ ghom, int nb, int capn,
+                                                  int32_t* __restrict__ nidx, double* __restrict__ nw,
+                                                  double* __restrict__ nv0, double2* __restrict__ samp,
+                                                  int* __restrict__ cnt, int* __restrict__ nfail) {
     const int nc = *ncand;
     const int lane = threadIdx.x;
     for (int e = blockIdx.x; e < nc; e += gridDim.x) {
         const int64_t idx = cand[e];
         const int i = (int)(idx / ny), j = (int)(idx - (int64_t)i * ny);
         const double X = x0 + i * h, Y = y0 + j * h;
-        // nearest boundary sample (smallest index among equals)
         double best = 1e300;
         int p = 0x7fffffff;
         for (int r = lane; r < bd.B; r += 64) {
@@ -410,47 +412,85 @@ __global__ __launch_bounds__(64) void k_dl_near(const int32_t* __restrict__ cand
             continue;
         }
         if (!(fabs(eta) < 0.5 * h)) continue;
+        // trigonometric interpolant of g_hom at theta
+        double sv = 0.0, hv = 0.0;
+        bool hit = false;
+        for (int k = lane; k < nb; k += 64) {
+            const double d = th - 2.0 * M_PI * (double)k / (double)nb;
+            const double sh = sin(0.5 * d);
+            if (sh == 0.0) { hit = true; hv = ghom[k]; continue; }
+            double w = sin(0.5 * nb * d) / (nb * sh);
+            if ((nb & 1) == 0) w *= cos(0.5 * d);
+            sv += w * ghom[k];
+        }
+        sv = wave_sum(sv);
+        const double any = wave_sum(hit ? 1.0 : 0.0);
+        const double hs = wave_sum(hit ? hv : 0.0);
+        int k = 0;
+        if (lane == 0) k = atomicAdd(cnt, 1);
+        k = __shfl(k, 0, 64);
+        if (k >= capn) {
+            if (lane == 0) atomicAdd(cnt + 1, 1);
+            continue;
+        }
         double o[6];
         curve_eval(cv, th, o);
         const double sp = sqrt(o[2] * o[2] + o[3] * o[3]);
         const double ix = -o[3] / sp, iy = o[2] / sp;   // inward normal
-        double vals[M];
-        {
-            // trigonometric interpolant of g_hom at theta
-            double sv = 0.0;
-            bool hit = false;
-            double hv = 0.0;
-            for (int k = lane; k < nb; k += 64) {
-                const double d = th - 2.0 * M_PI * (double)k / (double)nb;
-                const double sh = sin(0.5 * d);
-                if (sh == 0.0) { hit = true; hv = ghom[k]; continue; }
-                double w = sin(0.5 * nb * d) / (nb * sh);
-                if ((nb & 1) == 0) w *= cos(0.5 * d);
-                sv += w * ghom[k];
-            }
-            sv = wave_sum(sv);
-            const double any = wave_sum(hit ? 1.0 : 0.0);
-            const double hs = wave_sum(hit ? hv : 0.0);
-            vals[0] = any > 0.0 ? hs : sv;
+        if (lane == 0) {
+            double w[M];
+            equi_weights<M>(-eta / (0.5 * h), w);
+            nidx[k] = (int32_t)idx;
+            nv0[k] = any > 0.0 ? hs : sv;
+            for (int m = 0; m < M; ++m) nw[(int64_t)k * M + m] = w[m];
         }
-        for (int m = 1; m < M; ++m) {
-            const double s = 0.5 * h * m;
-            const double PX = o[0] + s * ix, PY = o[1] + s * iy;
-            double acc = 0.0;
-            for (int k = lane; k < nbf; k += 64) {
-                const double4 b = recf[k];
-                const double dx = PX - b.x, dy = PY - b.y;
-                acc += (dx * b.z - dy * b.w) * inv_r2(dx * dx + dy * dy);
-            }
-            vals[m] = wave_sum(acc) / nbf;
+        if (lane >= 1 && lane < M) {
+            const double s = 0.5 * h * lane;
+            samp[(int64_t)k * (M - 1) + lane - 1] = make_double2(o[0] + s * ix, o[1] + s * iy);
         }
-        // Lagrange weights on the nodes s_m = m h / 2 at s = -eta
-        double w[M];
-        equi_weights<M>(-eta / (0.5 * h), w);
-        double v = 0.0;
-        for (int m = 0; m < M; ++m) v += w[m] * vals[m];
-        if (lane == 0) u[idx] = up[idx] + v;
     }
+}
+
+// double-layer sums at the listed sample points (count *nnear, at most capn,
+// times per), 64 per block with the n nodes split over the block's W waves
+// and the partials added in wave order; sval[k] = sum / n
+template <int W>
+__global__ __launch_bounds__(64 * W) void k_dl_samples(const double2* __restrict__ samp,
+                                                       const int* __restrict__ nnear, int capn, int per,
+                                                       const double4* __restrict__ rec, int n,
+                                                       double* __restrict__ sval) {
+    __shared__ double ps[W][64];
+    const int cnt = min(*nnear, capn) * per;
+    const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
+    const int j0 = (int)((int64_t)n * w / W), j1 = (int)((int64_t)n * (w + 1) / W);
+    for (int g = blockIdx.x; g * 64 < cnt; g += gridDim.x) {
+        const int k = g * 64 + l;
+        const double2 P = samp[k < cnt ? k : g * 64];   // idle lanes repeat the group's first point
+        double dm;
+        ps[w][l] = dl_partial<false>(rec, j0, j1, P.x, P.y, &dm);
+        __syncthreads();
+        if (w == 0 && k < cnt) {
+            double s = 0.0;
+            for (int q = 0; q < W; ++q) s += ps[q][l];
+            sval[k] = s / n;
+        }
+        __syncthreads();
+    }
+}
+
+// u = u_p + sum_m w_m v_m at the near points (v_0 = g_hom(theta), v_m the sums)
+template <int M>
+__global__ void k_near_fin(const int32_t* __restrict__ nidx, const int* __restrict__ nnear, int capn,
+                           const double* __restrict__ nw, const double* __restrict__ nv0,
+                           const double* __restrict__ sval, const double* __restrict__ up, double* __restrict__ u) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= min(*nnear, capn)) return;
+    const double* w = nw + (int64_t)k * M;
+    const double* sv = sval + (int64_t)k * (M - 1);
+    double v = w[0] * nv0[k];
+    for (int m = 1; m < M; ++m) v += w[m] * sv[m - 1];
+    const int64_t e = nidx[k];
+    u[e] = up[e] + v;
 }
 
 // ---- launchers -------------------------------------------------------------
@@ -569,16 +609,31 @@ int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const 
 
 int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
                  int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
-                 int nbf, double* u, int* nfail, hipStream_t s) {
+                 int nbf, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
+                 int* ncnt, double* u, int* nfail, hipStream_t s) {
     const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, 16384));
     switch (M) {
 #define FC2D_NEAR(MM) \
-        case MM: k_dl_near<MM><<<nbk, 64, 0, s>>>(cand, ncand, cv, bd, maxit, up, g->ny, g->x0, g->y0, g->h, ghom, nb, (const double4*)recf, nbf, u, nfail); break;
+        case MM: k_near_prep<MM><<<nbk, 64, 0, s>>>(cand, ncand, cv, bd, maxit, g->ny, g->x0, g->y0, g->h, ghom, nb, \
+                                                    capn, nidx, nw, nv0, (double2*)samp, ncnt, nfail); break;
         FC2D_NEAR(4) FC2D_NEAR(5) FC2D_NEAR(6) FC2D_NEAR(7) FC2D_NEAR(8) FC2D_NEAR(13) FC2D_NEAR(15)
 #undef FC2D_NEAR
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
-    return pois_check("k_dl_near", s);
+    int st = pois_check("k_near_prep", s);
+    if (st) return st;
+    const unsigned sbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((int64_t)capn * (M - 1) + 63) / 64, 2048));
+    k_dl_samples<16><<<sbk, 1024, 0, s>>>((const double2*)samp, ncnt, capn, M - 1, (const double4*)recf, nbf, sval);
+    if ((st = pois_check("k_dl_samples", s))) return st;
+    const unsigned fbk = (unsigned)std::max(1, (capn + 255) / 256);
+    switch (M) {
+#define FC2D_FIN(MM) \
+        case MM: k_near_fin<MM><<<fbk, 256, 0, s>>>(nidx, ncnt, capn, nw, nv0, sval, up, u); break;
+        FC2D_FIN(4) FC2D_FIN(5) FC2D_FIN(6) FC2D_FIN(7) FC2D_FIN(8) FC2D_FIN(13) FC2D_FIN(15)
+#undef FC2D_FIN
+        default: break;
+    }
+    return pois_check("k_near_fin", s);
 }
 
 }  // namespace fc2d

@@ -194,6 +194,12 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     double dsmax = 0.0;
     for (int j = 0; j < nb; ++j) dsmax = std::max(dsmax, hypot(qc[6 * (size_t)j + 2], qc[6 * (size_t)j + 3]));
     dsmax *= 2.0 * M_PI / nb;
+    // grid points within h of Gamma (the only ones that can be near points): at most the tube
+    // area 2 (h + h / sqrt 2) P + pi (h + h / sqrt 2)^2 over h^2, P the perimeter
+    double perim = 0.0;
+    for (int j = 0; j < nb; ++j) perim += hypot(qc[6 * (size_t)j + 2], qc[6 * (size_t)j + 3]);
+    perim *= 2.0 * M_PI / nb;
+    const int capn = (int)std::min<double>((double)std::max<int64_t>(pl->n_in, 1), ceil(4.0 * perim / g.h) + 64.0);
     const int64_t nall = (int64_t)nb * (2 * kRefine - 1);   // nodes of all levels
     const int64_t cap = std::max<int64_t>(pl->n_in, 1);
     double *spec, *work, *up, *mean, *d_qc, *d_geo, *rec, *ghom, *rhs, *A, *phi, *phif, *wtab, *part, *V, *w, *hd;
@@ -221,7 +227,14 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     db.add(&hd, 3 * (size_t)(m + 2) + m);
     db.add(&cls, (size_t)npts);
     db.add(&cand, (size_t)cap);
-    db.add(&cnt, 2 + kPoisLevels);   // candidates, foot failures, level counts
+    db.add(&cnt, 4 + kPoisLevels);   // candidates, foot failures, level counts, near points, overflow
+    int32_t* nidx;
+    double *nw, *nv0, *samp, *sval;
+    db.add(&nidx, capn);
+    db.add(&nw, (size_t)capn * M);
+    db.add(&nv0, capn);
+    db.add(&samp, (size_t)capn * (M - 1) * 2);
+    db.add(&sval, (size_t)capn * (M - 1));
     db.add(&bl, (size_t)cap * kPoisLevels);
     db.add(&bx, pl->B);
     db.add(&by, pl->B);
@@ -261,20 +274,25 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
         iters_total += it;
         if ((st = pois_records(phi, nb, d_geo, wtab, phif, rec, s))) return st;
         // v on the grid, then the points next to Gamma
-        if ((e = hipMemsetAsync(cnt, 0, (2 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
+        if ((e = hipMemsetAsync(cnt, 0, (4 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
             return hip_err(e, "Poisson solve");
         if ((st = pois_dl_grid(&g, cls, up, rec, nb, dsmax, uf, bl, cap, cnt + 2, cand, cnt, s))) return st;
         const int64_t top = (int64_t)nb * (kRefine - 1);
-        if ((st = pois_dl_near(M, cand, cnt, std::max<int64_t>(pl->n_in, 1), pl->curve, bd, 60, &g, up, ghom, nb,
-                               rec + 4 * top, nbf, uf, cnt + 1, s)))
+        int* ncnt = cnt + 2 + kPoisLevels;
+        if ((st = pois_dl_near(M, cand, cnt, cap, pl->curve, bd, 60, &g, up, ghom, nb, rec + 4 * top, nbf, capn,
+                               nidx, nw, nv0, samp, sval, ncnt, uf, cnt + 1, s)))
             return st;
-        int hc[2] = {0, 0};
-        if ((e = hipMemcpyAsync(hc, cnt, 2 * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+        int hc[4 + kPoisLevels] = {};
+        if ((e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return hip_err(e, "Poisson solve");
         if (hc[1] > 0) {
             set_error("Poisson solve: foot of the normal failed next to the boundary");
             return FC2D_E_NEWTON;
+        }
+        if (hc[3 + kPoisLevels] > 0) {
+            set_error("Poisson solve: more points next to the boundary than the bound allows");
+            return FC2D_E_HIP;
         }
     }
     if (gmres_iters) *gmres_iters = iters_total;

@@ -24,7 +24,7 @@ COUNTERS = os.path.join(ROOT, "profiles", "star1024_extend_fft_counters.json")
 
 
 # sources of the extension and FFT kernels whose HBM counters are committed
-KERNEL_SOURCES = ["kernels_extend.hip", "kernels_fft.hip", "dd.h", "geom.h", "internal.h"]
+KERNEL_SOURCES = ["kernels_extend.hip", "kernels_fft.hip", "dd.h", "geom.h", "internal.h", "lagrange_dev.h"]
 
 
 def source_hash():

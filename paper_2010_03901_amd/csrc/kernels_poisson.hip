@@ -24,6 +24,7 @@
 #include <string>
 
 #include "internal.h"
+#include "poisson_int.h"
 #include "lagrange_dev.h"
 
 namespace fc2d {

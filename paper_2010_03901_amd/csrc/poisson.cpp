@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "poisson_int.h"
 
 using namespace fc2d;
 

@@ -1,0 +1,49 @@
+// Internal interface of the full Poisson solve (Sec. 4.1): launchers of
+// kernels_poisson.hip, used by poisson.cpp.  Not part of the C ABI.
+#pragma once
+
+#include "internal.h"
+
+namespace fc2d {
+
+// ---- full Poisson solve (kernels_poisson.hip); qd: (x, y, x', y', x'', y'') per node
+int pois_mean(const fc2d_grid* g, const double* spec, double* mean, hipStream_t s);
+int pois_add_quad(const fc2d_grid* g, const double* mean, double* up, hipStream_t s);
+int pois_ghom(int M, const fc2d_grid* g, const double* up, const double* qd, int nb, const double* gv,
+              double* ghom, hipStream_t s);
+// node data on the device: qc (x, y, x', y', x'', y'') at the nb nodes, geo
+// (x, y, x', y') at the nodes of every level (t = 2 pi q / (2^(kPoisLevels-1) nb),
+// q the node's finest-level index, so shared nodes agree bit for bit)
+int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, hipStream_t s);
+// per-point classes (nx * ny bytes) from the plan's row runs
+int pois_classes(const int32_t* run_ptr, const int32_t* run, int nx, int ny, int8_t* cls, hipStream_t s);
+int pois_nystrom(const double* qd, int nb, double* A, hipStream_t s);
+// y = A x, A column-major n x n; part: scratch of pois_matvec_splits(n) n doubles
+int pois_matvec_splits(int n);
+int pois_matvec(const double* A, const double* x, int n, double* part, double* y, hipStream_t s);
+int pois_dots(const double* V, int nv, const double* w, int n, double* out, hipStream_t s);
+int pois_sub(const double* V, int nv, const double* c, int n, double* w, hipStream_t s);
+int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s);
+// Levels of the double-layer sums: level L (0 <= L < kPoisLevels) holds 2^L nb
+// equispaced nodes at offset nb (2^L - 1) of the concatenated node arrays.
+constexpr int kPoisLevels = 6;
+// phi on the nb nodes -> phif (finest level, by the Dirichlet kernel) -> node
+// records rec (x, y, phi y', phi x') of every level; geo: (x, y, x', y') per
+// node; wtab: scratch of (2^(kPoisLevels - 1) - 1) nb doubles
+int pois_records(const double* phi, int nb, const double* geo, double* wtab, double* phif, double* rec,
+                 hipStream_t s);
+// v at the IN points (u = u_p + v, 0 elsewhere); points next to Gamma listed in
+// cand.  bl: kPoisLevels lists of cap entries (cap >= IN points), bcnt their
+// counts (zero on entry), both scratch
+int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
+                 double* u, int32_t* bl, int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s);
+// the listed points within h/2 of Gamma; recf: finest-level records (nbf nodes).
+// Scratch for up to capn such points: nidx [capn], nw [capn M], nv0 [capn],
+// samp [capn (M - 1)] point pairs, sval [capn (M - 1)]; ncnt[0] counts them
+// and ncnt[1] those beyond capn (both zero on entry).
+int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
+                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
+                 int nbf, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
+                 int* ncnt, double* u, int* nfail, hipStream_t s);
+
+}  // namespace fc2d

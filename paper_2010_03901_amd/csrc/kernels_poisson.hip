@@ -73,6 +73,18 @@ __global__ void k_pois_nodes(CurveC cv, int nb, double* __restrict__ qc, double*
     reinterpret_cast<double4*>(geo)[e] = make_double4(o[0], o[1], o[2], o[3]);
 }
 
+// chords of the nb-node polygon: seg[j] = (x_j, y_j, x_{j+1} - x_j, y_{j+1} - y_j)
+// and sinv[j] = 1 / |chord|^2, from the level-0 node data
+__global__ void k_pois_segments(const double4* __restrict__ geo, int nb, double4* __restrict__ seg,
+                                double* __restrict__ sinv) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= nb) return;
+    const double4 a = geo[j], b = geo[j + 1 < nb ? j + 1 : 0];
+    const double sx = b.x - a.x, sy = b.y - a.y;
+    seg[j] = make_double4(a.x, a.y, sx, sy);
+    sinv[j] = 1.0 / (sx * sx + sy * sy);
+}
+
 // one block per grid row; runs (start, end, class) cover the row in order
 __global__ void k_pois_classes(const int32_t* __restrict__ run_ptr, const int32_t* __restrict__ run, int ny,
                                int8_t* __restrict__ cls) {
@@ -124,13 +136,23 @@ __global__ __launch_bounds__(256) void k_matvec_part(const double* __restrict__ 
     part[(int64_t)c * n + i] = s0 + s1;
 }
 
-// y[i] = sum of the splits' partial sums, in split order
-__global__ void k_matvec_sum(const double* __restrict__ part, int n, int splits, double* __restrict__ y) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+// y[i] = sum of the splits' partial sums: block of 32 rows x 8 groups, group
+// g adding splits g, g + 8, ... in order, then the groups in order through LDS
+__global__ __launch_bounds__(256) void k_matvec_sum(const double* __restrict__ part, int n, int splits,
+                                                    double* __restrict__ y) {
+    __shared__ double red[8][32];
+    const int r = threadIdx.x & 31, g = threadIdx.x >> 5;
+    const int i = blockIdx.x * 32 + r;
     double s = 0.0;
-    for (int c = 0; c < splits; ++c) s += part[(int64_t)c * n + i];
-    y[i] = s;
+    if (i < n)
+        for (int c = g; c < splits; c += 8) s += part[(int64_t)c * n + i];
+    red[g][r] = s;
+    __syncthreads();
+    if (g == 0 && i < n) {
+        double t = 0.0;
+        for (int q = 0; q < 8; ++q) t += red[q][r];
+        y[i] = t;
+    }
 }
 
 // out[b] = <V_b, w> for b < nv (one block per vector)
@@ -288,17 +310,52 @@ __device__ inline double dl_partial(const double4* __restrict__ rec, int j0, int
     return s0 + s1;
 }
 
+// squared distance from (X, Y) to the nb-node polygon (wave-uniform chords
+// through the scalar cache, four per wait), as a lower bound from the high word
+__device__ inline double poly_dist2(const double4* __restrict__ seg, const double* __restrict__ sinv, int nb,
+                                   double X, double Y) {
+    unsigned dmh = 0xffffffffu;
+    int j = 0;
+    for (; j + 4 <= nb; j += 4) {
+        double4 c[4];
+        double iv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            c[u] = seg[j + u];
+            iv[u] = sinv[j + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const double vx = X - c[u].x, vy = Y - c[u].y;
+            const double t = fmin(fmax((vx * c[u].z + vy * c[u].w) * iv[u], 0.0), 1.0);
+            const double dx = vx - t * c[u].z, dy = vy - t * c[u].w;
+            dmh = min(dmh, (unsigned)(__double_as_longlong(dx * dx + dy * dy) >> 32));
+        }
+    }
+    for (; j < nb; ++j) {
+        const double4 c = seg[j];
+        const double vx = X - c.x, vy = Y - c.y;
+        const double t = fmin(fmax((vx * c.z + vy * c.w) * sinv[j], 0.0), 1.0);
+        const double dx = vx - t * c.z, dy = vy - t * c.w;
+        dmh = min(dmh, (unsigned)(__double_as_longlong(dx * dx + dy * dy) >> 32));
+    }
+    return __longlong_as_double((long long)((unsigned long long)dmh << 32));
+}
+
 // v at every IN point from the nb-node sum (trapezoidal weight 2 pi / nb, the
 // 1 / (2 pi) of the kernel folded in); u = u_p + v there, 0 elsewhere.  Points
 // whose nearest node is closer than 7 node spacings (dsmax: largest spacing of
 // the nb nodes) go to the list of the level whose spacing is at most a seventh
-// of the point's distance, estimated as that node distance - dsmax / 2 (the
-// finest level at most); bl[L cap ...], count bcnt[L].  Other points closer
-// than h to a node go to cand.
+// of the point's distance to Gamma (the finest level at most), bounded from
+// below by the larger of (that node distance - dsmax / 2) and (the distance to
+// the nb-node polygon - sag, sag bounding how far an arc leaves its chord);
+// bl[L cap ...], count bcnt[L].  Other points closer than h to a node go to cand.
 __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls, const double* __restrict__ up,
                                                  int nx, int ny, double x0, double y0, double h,
                                                  const double4* __restrict__ rec, int nb, double dsmax,
-                                                 double* __restrict__ u, int32_t* __restrict__ bl, int64_t cap,
+                                                 const double4* __restrict__ seg, const double* __restrict__ sinv,
+                                                 double sag, double* __restrict__ u, int32_t* __restrict__ bl,
+                                                 int64_t cap,
                                                  int* __restrict__ bcnt, int32_t* __restrict__ cand,
                                                  int* __restrict__ ncand) {
     // one 8 x 8 tile of points per wave
@@ -315,7 +372,7 @@ __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls,
     double d2;
     u[e] = up[e] + dl_partial<true>(rec, 0, nb, X, Y, &d2) / nb;
     if (d2 < 49.0 * dsmax * dsmax) {
-        const double dest = sqrt(d2) - 0.5 * dsmax;
+        const double dest = fmax(sqrt(d2) - 0.5 * dsmax, sqrt(poly_dist2(seg, sinv, nb, X, Y)) - sag);
         int L = kPoisLevels - 1;
         if (dest > 0.0) {
             L = 1;
@@ -532,9 +589,10 @@ int pois_ghom(int M, const fc2d_grid* g, const double* up, const double* qd, int
     return pois_check("k_pois_ghom", s);
 }
 
-int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, hipStream_t s) {
+int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, double* seg, double* sinv, hipStream_t s) {
     const int64_t n = (int64_t)nb * (2 << (kPoisLevels - 1));   // nb + all levels
     k_pois_nodes<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(cv, nb, qc, geo);
+    k_pois_segments<<<(unsigned)((nb + 255) / 256), 256, 0, s>>>((const double4*)geo, nb, (double4*)seg, sinv);
     return pois_check("k_pois_nodes", s);
 }
 
@@ -553,7 +611,7 @@ int pois_matvec_splits(int n) { return std::max(1, std::min(64, n / 32)); }
 int pois_matvec(const double* A, const double* x, int n, double* part, double* y, hipStream_t s) {
     const int sp = pois_matvec_splits(n);
     k_matvec_part<<<dim3((unsigned)((n + 255) / 256), (unsigned)sp), 256, 0, s>>>(A, x, n, sp, part);
-    k_matvec_sum<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(part, n, sp, y);
+    k_matvec_sum<<<(unsigned)((n + 31) / 32), 256, 0, s>>>(part, n, sp, y);
     return pois_check("k_matvec", s);
 }
 
@@ -585,11 +643,12 @@ int pois_records(const double* phi, int nb, const double* geo, double* wtab, dou
 }
 
 int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
-                 double* u, int32_t* bl, int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s) {
+                 const double* seg, const double* sinv, double sag, double* u, int32_t* bl, int64_t cap, int* bcnt,
+                 int32_t* cand, int* ncand, hipStream_t s) {
     const int64_t tiles = (int64_t)((g->nx + 7) / 8) * ((g->ny + 7) / 8);
     k_dl_grid<<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(cls, up, g->nx, g->ny, g->x0, g->y0, g->h,
-                                                          (const double4*)rec, nb, dsmax, u, bl, cap, bcnt, cand,
-                                                          ncand);
+                                                          (const double4*)rec, nb, dsmax, (const double4*)seg, sinv,
+                                                          sag, u, bl, cap, bcnt, cand, ncand);
     int st = pois_check("k_dl_grid", s);
     // levels 1 .. kPoisLevels - 1, up to 16 waves per group of 64 points
     const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 63) / 64, 2048));

@@ -65,7 +65,7 @@ int hip_err(hipError_t e, const char* what) {
 int gmres(const double* A, const double* b, double* x, int n, double* V, double* w, double* hd, double* part,
           hipStream_t s, int* iters) {
     const int m = std::min(n, kRestart);
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1));
+    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1) + 1);
     double* h1 = hd;                 // [m + 1]
     double* h2 = hd + (m + 1);       // [m + 1]
     double* nrm = hd + 2 * (m + 1);  // [1]
@@ -97,13 +97,12 @@ int gmres(const double* A, const double* b, double* x, int n, double* V, double*
             if ((st = pois_dots(V, j + 1, w, n, h2, s))) return st;
             if ((st = pois_sub(V, j + 1, h2, n, w, s))) return st;
             if ((st = pois_dots(w, 1, w, n, nrm, s))) return st;
-            if ((e = hipMemcpyAsync(hh.data(), hd, 2 * (m + 1) * sizeof(double), hipMemcpyDeviceToHost, s)) !=
-                hipSuccess)
-                return hip_err(e, "gmres");
-            double hn2 = 0.0;
-            if ((e = hipMemcpyAsync(&hn2, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            // h1, h2 and the norm are contiguous: one copy
+            if ((e = hipMemcpyAsync(hh.data(), hd, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s)) !=
+                    hipSuccess ||
                 (e = hipStreamSynchronize(s)) != hipSuccess)
                 return hip_err(e, "gmres");
+            const double hn2 = hh[2 * (m + 1)];
             const double hn = sqrt(hn2);
             for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 1) + i];
             H[(size_t)(j + 1) * m + j] = hn;
@@ -200,6 +199,15 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     double perim = 0.0;
     for (int j = 0; j < nb; ++j) perim += hypot(qc[6 * (size_t)j + 2], qc[6 * (size_t)j + 3]);
     perim *= 2.0 * M_PI / nb;
+    // largest curvature at the nodes (twice, for safety) -> how far an arc of length <= dsmax
+    // leaves its chord: kappa dsmax^2 / 8
+    double kmax = 0.0;
+    for (int j = 0; j < nb; ++j) {
+        const double* q = &qc[6 * (size_t)j];
+        const double sp = hypot(q[2], q[3]);
+        kmax = std::max(kmax, fabs(q[2] * q[5] - q[3] * q[4]) / (sp * sp * sp));
+    }
+    const double sag = 2.0 * kmax * dsmax * dsmax / 8.0;
     const int capn = (int)std::min<double>((double)std::max<int64_t>(pl->n_in, 1), ceil(4.0 * perim / g.h) + 64.0);
     const int64_t nall = (int64_t)nb * (2 * kRefine - 1);   // nodes of all levels
     const int64_t cap = std::max<int64_t>(pl->n_in, 1);
@@ -216,6 +224,9 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     db.add(&d_qc, 6 * (size_t)nb);
     db.add(&d_geo, 4 * (size_t)nall);
     db.add(&rec, 4 * (size_t)nall);
+    double *seg, *sinv;
+    db.add(&seg, 4 * (size_t)nb);
+    db.add(&sinv, nb);
     db.add(&ghom, nb);
     db.add(&rhs, nb);
     db.add(&A, (size_t)nb * nb);
@@ -253,7 +264,7 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
         return hip_err(e, "Poisson solve upload");
     trace_point("pois_setup", s);
     int st;
-    if ((st = pois_nodes(pl->curve, nb, d_qc, d_geo, s))) return st;
+    if ((st = pois_nodes(pl->curve, nb, d_qc, d_geo, seg, sinv, s))) return st;
     if ((st = pois_classes(pl->d_run_ptr, pl->d_run, g.nx, g.ny, cls, s))) return st;
     const BndView bd{bx, by, bnx, bny, pl->B, pl->k2};
     if ((st = pois_nystrom(d_qc, nb, A, s))) return st;
@@ -277,7 +288,7 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
         // v on the grid, then the points next to Gamma
         if ((e = hipMemsetAsync(cnt, 0, (4 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
             return hip_err(e, "Poisson solve");
-        if ((st = pois_dl_grid(&g, cls, up, rec, nb, dsmax, uf, bl, cap, cnt + 2, cand, cnt, s))) return st;
+        if ((st = pois_dl_grid(&g, cls, up, rec, nb, dsmax, seg, sinv, sag, uf, bl, cap, cnt + 2, cand, cnt, s))) return st;
         const int64_t top = (int64_t)nb * (kRefine - 1);
         int* ncnt = cnt + 2 + kPoisLevels;
         if ((st = pois_dl_near(M, cand, cnt, cap, pl->curve, bd, 60, &g, up, ghom, nb, rec + 4 * top, nbf, capn,

@@ -14,7 +14,8 @@ int pois_ghom(int M, const fc2d_grid* g, const double* up, const double* qd, int
 // node data on the device: qc (x, y, x', y', x'', y'') at the nb nodes, geo
 // (x, y, x', y') at the nodes of every level (t = 2 pi q / (2^(kPoisLevels-1) nb),
 // q the node's finest-level index, so shared nodes agree bit for bit)
-int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, hipStream_t s);
+// and the chords of the nb-node polygon: seg (x, y, dx, dy) per node, sinv 1 / |chord|^2
+int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, double* seg, double* sinv, hipStream_t s);
 // per-point classes (nx * ny bytes) from the plan's row runs
 int pois_classes(const int32_t* run_ptr, const int32_t* run, int nx, int ny, int8_t* cls, hipStream_t s);
 int pois_nystrom(const double* qd, int nb, double* A, hipStream_t s);
@@ -34,9 +35,11 @@ int pois_records(const double* phi, int nb, const double* geo, double* wtab, dou
                  hipStream_t s);
 // v at the IN points (u = u_p + v, 0 elsewhere); points next to Gamma listed in
 // cand.  bl: kPoisLevels lists of cap entries (cap >= IN points), bcnt their
-// counts (zero on entry), both scratch
+// counts (zero on entry), both scratch; sag: bound on how far an arc between two
+// nodes leaves its chord
 int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
-                 double* u, int32_t* bl, int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s);
+                 const double* seg, const double* sinv, double sag, double* u, int32_t* bl, int64_t cap, int* bcnt,
+                 int32_t* cand, int* ncand, hipStream_t s);
 // the listed points within h/2 of Gamma; recf: finest-level records (nbf nodes).
 // Scratch for up to capn such points: nidx [capn], nw [capn M], nv0 [capn],
 // samp [capn (M - 1)] point pairs, sval [capn (M - 1)]; ncnt[0] counts them

@@ -2,7 +2,8 @@
 
 * ``matching_values``: f_{D_p} on the d matching points of every normal
   (Sec. 3.2, two-step degree-(M-1) interpolation; the point on Gamma takes the
-  boundary sample).  Evaluated in numpy.longdouble: the continuation below
+  boundary sample, or with a plan built from interior data only (Remark 3.1 II)
+  the same interpolation at depth 0).  Evaluated in numpy.longdouble: the continuation below
   amplifies a relative perturbation of f_D by |A_r Q^T| ~ 1e4, so f_D and
   Q^T f_D are carried with more than float64 precision and rounded once.
 * ``blend``: blending to zero along each normal on the refined grid,
@@ -35,15 +36,22 @@ def matching_values(pl, f_grid, f_bdry):
     """
     B, M, d = pl.B, pl.M, pl.d
     fg = np.asarray(f_grid, dtype=np.float64).ravel()
-    fb = np.asarray(f_bdry, dtype=np.float64)
     ref = pl.match_ref
-    vals = np.where(ref >= 0, fg[np.clip(ref, 0, None)], fb[B + np.clip(-ref - 1, 0, None)])
+    if getattr(pl, "interior_only", False):   # no boundary samples are read (f_bdry may be None)
+        assert np.all(ref >= 0)
+        vals = fg[ref]
+    else:
+        fb = np.asarray(f_bdry, dtype=np.float64)
+        vals = np.where(ref >= 0, fg[np.clip(ref, 0, None)], fb[B + np.clip(-ref - 1, 0, None)])
     if np.any(ref >= 0):
         assert np.all(pl.cls.ravel()[ref[ref >= 0]] == IN)
     stars = np.sum(pl.match_wv * vals.astype(LD), axis=2)                 # [B, M]
     fD = np.zeros((B, d), dtype=LD)
-    fD[:, : d - 1] = np.sum(pl.match_wn * stars[:, None, :], axis=2)        # [B, d-1]
-    fD[:, d - 1] = fb[:B].astype(LD)
+    if getattr(pl, "interior_only", False):
+        fD[:, :] = np.sum(pl.match_wn * stars[:, None, :], axis=2)         # [B, d], Remark 3.1 II
+    else:
+        fD[:, : d - 1] = np.sum(pl.match_wn * stars[:, None, :], axis=2)    # [B, d-1]
+        fD[:, d - 1] = fb[:B].astype(LD)
     return fD
 
 

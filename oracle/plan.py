@@ -41,6 +41,10 @@ Readings of the paper taken here (the paper leaves them open):
   d - 1 interior matching points come from a degree-(M-1) interpolation over
   the M stars along the normal; the matching point on Gamma takes the
   boundary sample.  Weights are formed in numpy.longdouble.
+* Interior data only (Remark 3.1 II; ``interior_only=True``).  No squares: a
+  star's nodes are IN points only, and the matching point on Gamma also takes
+  the degree-(M-1) interpolation over the M stars along the normal (at depth 0)
+  instead of a boundary sample.
 """
 from __future__ import annotations
 
@@ -219,8 +223,9 @@ class Plan:
     pass
 
 
-def make_plan(curve, grid, tables, B, k1=None, M=None, n_r=None):
-    """Geometrical Setup (Sec. 3.5 steps 1-4) plus the matching stencils of Sec. 3.2."""
+def make_plan(curve, grid, tables, B, k1=None, M=None, n_r=None, interior_only=False):
+    """Geometrical Setup (Sec. 3.5 steps 1-4) plus the matching stencils of Sec. 3.2
+    (from interior data only when ``interior_only``: Remark 3.1 II)."""
     d = tables["Q"].shape[0]
     C = tables["A"].shape[0]
     n_r = tables["Ar"].shape[0] // C if n_r is None else n_r
@@ -230,6 +235,7 @@ def make_plan(curve, grid, tables, B, k1=None, M=None, n_r=None):
     k1 = h if k1 is None else float(k1)
     pl = Plan()
     pl.curve, pl.grid, pl.d, pl.C, pl.n_r, pl.Cr, pl.M, pl.k1, pl.B = curve, grid, d, C, n_r, Cr, M, k1, B
+    pl.interior_only = bool(interior_only)
     pl.Q, pl.Ar = tables["Q"], tables["Ar"]
 
     # step 1: boundary discretisation and normals (eq. bdry_grid)
@@ -351,6 +357,8 @@ def _matching_stencils(pl):
             rid = len(star_rec)
             star_rec.append((p, vertical, i_s, delta, bstar))
             runs.append([lower, upper, None, None])
+            if pl.interior_only:
+                continue          # no boundary samples: IN nodes only
             if lo_stop is not None:
                 b_in = (b0 + (lo_stop + 1) * h) if lower else float(bstar)
                 sq_req.append((rid, 0, vertical, a_s, b_in, b0 + lo_stop * h))
@@ -418,9 +426,10 @@ def _matching_stencils(pl):
         pl.vertical[p] = vertical
         rid += 2 * M
     pl.squares = np.array(sq_xy, dtype=np.float64).reshape(-1, 2)
-    depth = np.array([LD(d - 1 - q) * LD(pl.k1) for q in range(d - 1)], dtype=LD)
-    wn = lagrange_weights(np.broadcast_to(deltas[:, None, :], (B, d - 1, M)).copy(),
-                          np.broadcast_to(depth[None, :], (B, d - 1)).copy())
+    nq = d if pl.interior_only else d - 1     # matching values interpolated along the normal
+    depth = np.array([LD(d - 1 - q) * LD(pl.k1) for q in range(nq)], dtype=LD)
+    wn = lagrange_weights(np.broadcast_to(deltas[:, None, :], (B, nq, M)).copy(),
+                          np.broadcast_to(depth[None, :], (B, nq)).copy())
     pl.match_ref = nref
     pl.match_wv = wv
     pl.match_wn = wn

@@ -113,6 +113,11 @@ typedef struct {
     int seed;          /* FC2D_SEED_*; 0 -> PROXIMITY */
     double mlp_tol;    /* MLP seed: residual threshold; 0 -> 1e-13; < 0 -> every point falls back */
     const float* mlp_weights;   /* MLP seed: FC2D_MLP_NW floats, host memory (copied) */
+    int interior_only; /* 1: extension from interior data only (Remark 3.1 II): the matching
+                          stencils use IN grid points only and the matching value on Gamma is
+                          interpolated along the normal like the others; the extension calls
+                          then read no boundary samples (f_bdry may be NULL).  0: the paper's
+                          default, boundary samples at the feet and squares. */
 } fc2d_opts;
 
 typedef struct fc2d_plan fc2d_plan;

@@ -48,6 +48,7 @@ struct fc2d_plan {
     int strip_wmax = 0;   // widest stencil window (normals) of a block of 512 theta-sorted STRIP points
     int64_t n_in = 0, n_far = 0;
     int seed = 0;
+    bool interior_only = false;   // Remark 3.1 II: no boundary samples, d matching values interpolated
     int64_t n_solved = 0, n_fallback = 0, newton_iters = 0;
     // device
     double* d_Q = nullptr;          // [d][d]
@@ -132,7 +133,7 @@ struct PlanDev {
     const double* sth;
     const double* seta;
     const double* bxy;
-    int B, D, nf, nx, ny, pad;
+    int B, D, nf, nx, ny, io;   // io: plan built from interior data only
     int64_t npts, nbdry, S;
     double k2, lev_scale, x0, y0, h;
     double* u;    // [nf][nx][ny] fields: IN values read, STRIP values written
@@ -151,8 +152,7 @@ int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipSt
 // ---- extension kernels (kernels_extend.hip) ----
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry,
                  double* c_out, double* fD_out, int nf, hipStream_t s);
-int launch_blend(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry,
-                 double* F, int nf, hipStream_t s);
+int launch_blend(const fc2d_plan* pl, const double* c, double* F, int nf, hipStream_t s);
 int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry,
                  double* out, int nf, hipStream_t s);
 int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, hipStream_t s);

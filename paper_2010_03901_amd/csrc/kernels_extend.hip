@@ -84,6 +84,8 @@ __device__ __forceinline__ int xg_index(int s, int k, int gi) {
 //  2. Red stars (first interpolation, along the grid lines): lane sq forms
 //     stars sq, sq + 4, ... from xg; the others travel by cross-lane shuffles.
 //  3. Matching values along the normal (second interpolation) q = sq, sq + 4, ...
+//     (q < d - 1; q < d for a plan built from interior data only, io = 1,
+//     where the value on Gamma is interpolated too instead of read from bv)
 //  4. Gram coefficients c_j, j = sq, sq + 4, ...
 // Every sum is a Dot2 over the stencil in node / star order, as in a one-lane
 // evaluation.  DT > 0 fixes d = DT at compile time; DT = 0 takes d = Drt.
@@ -92,7 +94,7 @@ __device__ __forceinline__ int xg_index(int s, int k, int gi) {
 template <int M, int DT>
 __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, const uint8_t* __restrict__ mlab,
                                             const double* __restrict__ mwv, const double* __restrict__ mwn,
-                                            const double* __restrict__ Q, int Drt, int B,
+                                            const double* __restrict__ Q, int Drt, int B, int io,
                                             const double* __restrict__ g, const double* __restrict__ bv, int p,
                                             int sq, bool live, double* __restrict__ co, double* __restrict__ fo,
                                             double* xg) {
@@ -150,31 +152,34 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
         star[s] = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
     }
     // 3. matching values along the normal (second interpolation)
-    const int RQ = (D - 1 + 3) / 4;
+    const int NQ = D - 1 + io;   // matching values interpolated along the normal
+    const int RQ = (NQ + 3) / 4;
     const double* wn = mwn + (int64_t)p * RQ * M * 4 * 2;   // [r][s][sq] double-double
-    const double fbp = bv[p];
+    const double fbs = io ? 0.0 : bv[p];   // boundary sample (not read from interior data only)
     dd fq[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {
         const int q = sq + 4 * r;
         Acc2 a;
-        if (q < D - 1) {
+        if (q < NQ) {
 #pragma unroll
             for (int s = 0; s < M; ++s) {
                 const int o = (r * M + s) * 4 + sq;
                 a.add(dd{wn[2 * o], wn[2 * o + 1]}, star[s]);
             }
         }
-        fq[r] = q < D - 1 ? a.result() : dd{fbp, 0.0};
+        fq[r] = q < NQ ? a.result() : dd{fbs, 0.0};
     }
     dd fD[12];
+    double fbp = fbs;   // f_{D_p}[d-1]: the sample, or its interpolated value
 #pragma unroll
     for (int q = 0; q < 12; ++q) {
         if (q < D) {
             const int src = gbase + (q & 3);
             const dd v = (q < 4) ? fq[0] : ((q < 8) ? fq[1] : fq[2]);
             const dd x = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
-            fD[q] = q < D - 1 ? x : dd{fbp, 0.0};
+            fD[q] = q < NQ ? x : dd{fbs, 0.0};
+            if (q == D - 1) fbp = fD[q].hi;
         }
     }
     // 4. c_p = Q^T f_{D_p}, stored with the boundary value appended: [c_0..c_{d-1}, f_{D_p}[d-1], 0 pad]
@@ -218,7 +223,7 @@ __device__ __forceinline__ int xcd_normal(int l, int B) {
 template <int M, int DT, int NPW>
 __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, const uint8_t* __restrict__ mlab,
                                               const double* __restrict__ mwv, const double* __restrict__ mwn,
-                                              const double* __restrict__ Q, int D, int B,
+                                              const double* __restrict__ Q, int D, int B, int io,
                                               const double* __restrict__ fg, int64_t npts,
                                               const double* __restrict__ fb, int64_t nbdry, int nf,
                                               double* __restrict__ c_out, double* __restrict__ fD_out) {
@@ -234,7 +239,7 @@ __global__ __launch_bounds__(64) void k_match(const int32_t* __restrict__ mref, 
     const int f = fl < nf ? fl : 0;
     const int p = pn < B ? pn : B - 1;
     const int DP = (D + 2) & ~1;
-    match_group<M, DT>(mref, mlab, mwv, mwn, Q, D, B, fg + (int64_t)f * npts, fb + (int64_t)f * nbdry, p,
+    match_group<M, DT>(mref, mlab, mwv, mwn, Q, D, B, io, fg + (int64_t)f * npts, fb ? fb + (int64_t)f * nbdry : fb, p,
                        threadIdx.x & 3, live, c_out + ((int64_t)f * B + p) * DP,
                        fD_out ? fD_out + ((int64_t)f * B + p) * D : nullptr, xg + gi * M * M);
 }
@@ -262,25 +267,26 @@ __global__ __launch_bounds__(64) void k_match_multi(const PlanDev* __restrict__ 
         const int f = fl < P.nf ? fl : 0;
         const int p = pn < P.B ? pn : P.B - 1;
         const int DP = (P.D + 2) & ~1;
-        match_group<M, DT>(P.mref, P.mlab, P.mwv, P.mwn, P.Q, P.D, P.B, P.u + (int64_t)f * P.npts,
+        match_group<M, DT>(P.mref, P.mlab, P.mwv, P.mwn, P.Q, P.D, P.B, P.io, P.u + (int64_t)f * P.npts,
                            P.fb + (int64_t)f * P.nbdry, p, threadIdx.x & 3, live, P.c + ((int64_t)f * P.B + p) * DP,
                            nullptr, xg + gi * M * M);
     }
 }
 
-__global__ void k_blend(const double* __restrict__ c, const double* __restrict__ fb, int64_t nbdry,
-                        const double* __restrict__ Ar, int D, int B, int Cr, double* __restrict__ F) {
+// F[l, p] = (A_r c_p)_{l-1}, l >= 1; F[0, p] = f_{D_p}[d-1] (stored after c_p)
+__global__ void k_blend(const double* __restrict__ c, const double* __restrict__ Ar, int D, int B, int Cr,
+                        double* __restrict__ F) {
     const int64_t n = (int64_t)(Cr + 1) * B;
     const int f = blockIdx.y;
     for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += (int64_t)gridDim.x * blockDim.x) {
         const int l = (int)(k / B);
         const int p = (int)(k - (int64_t)l * B);
+        const int DP = (D + 2) & ~1;
         double v;
         if (l == 0) {
-            v = fb[(int64_t)f * nbdry + p];
+            v = c[((int64_t)f * B + p) * DP + D];
         } else {
             v = 0.0;
-            const int DP = (D + 2) & ~1;
             for (int j = 0; j < D; ++j) v += Ar[(l - 1) * D + j] * c[((int64_t)f * B + p) * DP + j];
         }
         F[(int64_t)f * n + k] = v;
@@ -615,10 +621,10 @@ int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry
     switch (pl->M) {
 #define FC2D_MATCH(MM) \
         case MM: \
-            if (pl->d == 5 && npw == 4) k_match<MM, 5, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else if (pl->d == 5) k_match<MM, 5, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else if (npw == 4) k_match<MM, 0, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
-            else k_match<MM, 0, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            if (pl->d == 5 && npw == 4) k_match<MM, 5, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, pl->interior_only ? 1 : 0, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else if (pl->d == 5) k_match<MM, 5, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, pl->interior_only ? 1 : 0, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else if (npw == 4) k_match<MM, 0, 4><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, pl->interior_only ? 1 : 0, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
+            else k_match<MM, 0, 1><<<grid, 64, 0, s>>>(pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_Q, pl->d, pl->B, pl->interior_only ? 1 : 0, f_grid, npts, f_bdry, nbdry, nf, c_out, fD_out); \
             break;
         FC2D_MATCH(4) FC2D_MATCH(5) FC2D_MATCH(6) FC2D_MATCH(7) FC2D_MATCH(8) FC2D_MATCH(13) FC2D_MATCH(15)
 #undef FC2D_MATCH
@@ -627,11 +633,11 @@ int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry
     return launch_check("k_match", s);
 }
 
-int launch_blend(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry, double* F, int nf,
+int launch_blend(const fc2d_plan* pl, const double* c, double* F, int nf,
                  hipStream_t s) {
     const int64_t n = (int64_t)(pl->Cr + 1) * pl->B;
     dim3 grid((unsigned)std::min<int64_t>((n + 255) / 256, 4096), nf);
-    k_blend<<<grid, 256, 0, s>>>(c, f_bdry, nbdry, pl->d_Ar, pl->d, pl->B, pl->Cr, F);
+    k_blend<<<grid, 256, 0, s>>>(c, pl->d_Ar, pl->d, pl->B, pl->Cr, F);
     return launch_check("k_blend", s);
 }
 

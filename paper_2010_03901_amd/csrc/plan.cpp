@@ -193,6 +193,8 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
                           std::vector<double>& mwv, std::vector<double>& mwn) {
     const fc2d_grid& g = pl->grid;
     const int M = pl->M, d = pl->d, B = pl->B;
+    const bool io = pl->interior_only;
+    const int nq = io ? d : d - 1;   // matching values interpolated along the normal
     const double h = g.h;
     std::vector<StarRec> stars;
     stars.reserve((size_t)B * 2 * M);
@@ -234,6 +236,10 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
             const bool hi_stop = j <= jb + 1 + M;
             const int jhi = j;
             const int rid = (int)stars.size();
+            if (io) {   // no boundary samples: IN nodes only
+                stars.push_back(std::move(r));
+                continue;
+            }
             if (lo_stop) {
                 SqReq q{rid, 0, vertical, a_s,
                         r.lower.empty() ? (double)r.bstar : b0 + (jlo + 1) * h, b0 + jlo * h, 0.0, p};
@@ -288,7 +294,7 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
     // select stars and nodes, form weights
     mref.assign((size_t)B * M * M, 0);
     mwv.assign((size_t)B * M * M * 2, 0.0);
-    mwn.assign((size_t)B * (d - 1) * M * 2, 0.0);
+    mwn.assign((size_t)B * nq * M * 2, 0.0);
     pl->squares.clear();
     std::vector<long double> deltas(M);
     for (int p = 0; p < B; ++p) {
@@ -346,13 +352,13 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
             set_error(buf);
             return FC2D_E_GEOMETRY;
         }
-        for (int q = 0; q < d - 1; ++q) {
+        for (int q = 0; q < nq; ++q) {
             const long double x = (long double)(d - 1 - q) * (long double)pl->k1;
             for (int s = 0; s < M; ++s) {
                 long double w = 1.0L;
                 for (int m = 0; m < M; ++m)
                     if (m != s) w *= (x - deltas[m]) / (deltas[s] - deltas[m]);
-                const size_t o = ((size_t)p * (d - 1) + q) * M + s;
+                const size_t o = ((size_t)p * nq + q) * M + s;
                 const double whi = (double)w;
                 mwn[2 * o] = whi;
                 mwn[2 * o + 1] = (double)(w - (long double)whi);
@@ -392,6 +398,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         o.seed = opts_in->seed;
         if (opts_in->mlp_tol != 0.0) o.mlp_tol = opts_in->mlp_tol < 0.0 ? -1.0 : opts_in->mlp_tol;
         o.mlp_weights = opts_in->mlp_weights;
+        o.interior_only = opts_in->interior_only != 0;
     }
     if (o.seed < FC2D_SEED_PROXIMITY || o.seed > FC2D_SEED_MLP ||
         (o.seed != FC2D_SEED_PROXIMITY && curve->kind != FC2D_CURVE_POLAR) ||
@@ -416,6 +423,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     pl->k1 = o.k1;
     pl->k2 = 2.0 * M_PI / o.B;
     pl->seed = o.seed;
+    pl->interior_only = o.interior_only != 0;
     memset(&pl->curve, 0, sizeof pl->curve);
     pl->curve.kind = curve->kind;
     pl->curve.nmodes = curve->nmodes;
@@ -679,7 +687,8 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             // address order, dealt to the 4 lanes of a group (entry 4u + sq to lane
             // sq), and the weights interleaved over the 4 lanes
             const int M = pl->M, d = pl->d, B = pl->B;
-            const int MM = M * M, NU = (MM + 15) / 16 * 4, RQ = (d - 1 + 3) / 4;
+            const int nq = pl->interior_only ? d : d - 1;   // matching values along the normal
+            const int MM = M * M, NU = (MM + 15) / 16 * 4, RQ = (nq + 3) / 4;
             const int64_t npts = (int64_t)grid->nx * grid->ny;
             std::vector<int32_t> dref((size_t)B * 4 * NU, 0);
             std::vector<uint8_t> dlab((size_t)B * 4 * NU, 255);
@@ -710,9 +719,9 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                     for (int sv = 0; sv < M; ++sv)
                         for (int sq = 0; sq < 4; ++sq) {
                             const int q = 4 * r + sq;
-                            if (q >= d - 1) continue;
+                            if (q >= nq) continue;
                             const size_t on = (((size_t)p * RQ + r) * M + sv) * 4 + sq;
-                            const size_t oo = ((size_t)p * (d - 1) + q) * M + sv;
+                            const size_t oo = ((size_t)p * nq + q) * M + sv;
                             dwn[2 * on] = mwn[2 * oo];
                             dwn[2 * on + 1] = mwn[2 * oo + 1];
                         }
@@ -885,7 +894,7 @@ int fc2d_matching(const fc2d_plan* pl, const double* f_grid, const double* f_bdr
     int st = check_fields(pl, nf);
     if (st) return st;
     if (nf == 0) return FC2D_OK;
-    if (!f_grid || !f_bdry || !fD) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (!f_grid || (!f_bdry && !pl->interior_only) || !fD) { set_error("NULL argument"); return FC2D_E_ARG; }
     std::lock_guard<std::mutex> lk(g_work_mu);
     if ((st = ensure_work(pl, nf))) return st;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
@@ -897,12 +906,12 @@ int fc2d_blend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, 
     int st = check_fields(pl, nf);
     if (st) return st;
     if (nf == 0) return FC2D_OK;
-    if (!f_grid || !f_bdry || !F) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (!f_grid || (!f_bdry && !pl->interior_only) || !F) { set_error("NULL argument"); return FC2D_E_ARG; }
     std::lock_guard<std::mutex> lk(g_work_mu);
     if ((st = ensure_work(pl, nf))) return st;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
     if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
-    return launch_blend(pl, pl->d_c, f_bdry, nb, F, nf, s);
+    return launch_blend(pl, pl->d_c, F, nf, s);
 }
 
 int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* out, int nf,
@@ -910,7 +919,7 @@ int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry,
     int st = check_fields(pl, nf);
     if (st) return st;
     if (nf == 0) return FC2D_OK;
-    if (!f_grid || !f_bdry || !out) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (!f_grid || (!f_bdry && !pl->interior_only) || !out) { set_error("NULL argument"); return FC2D_E_ARG; }
     std::lock_guard<std::mutex> lk(g_work_mu);
     if ((st = ensure_work(pl, nf))) return st;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
@@ -925,7 +934,7 @@ int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_b
     if (st) return st;
     if (nf == 0) return FC2D_OK;
     const fc2d_grid* g = &pl->grid;
-    if (!f_grid || !f_bdry || !work || !spec) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (!f_grid || (!f_bdry && !pl->interior_only) || !work || !spec) { set_error("NULL argument"); return FC2D_E_ARG; }
     if (g->nx < 16 || g->nx > 4096 || (g->nx & (g->nx - 1)) || g->ny < 16 || g->ny > 8192 || (g->ny & (g->ny - 1)) ||
         !pl->d_cls2) {
         set_error("fc2d_extend_fft: the plan's grid must have power-of-two sizes (nx <= 4096, ny <= 8192)");

@@ -173,7 +173,7 @@ int fc2d_poisson_nodes(const fc2d_plan* pl, int nb, double* xy) {
 
 int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, const double* g_nodes,
                        int nb, double* u, int nf, hipStream_t s, int* gmres_iters) {
-    if (!pl || !f_grid || !f_bdry || !g_nodes || !u || nb < 8 || nb > 16384 || nf < 1) {
+    if (!pl || !f_grid || (!f_bdry && !pl->interior_only) || !g_nodes || !u || nb < 8 || nb > 16384 || nf < 1) {
         set_error("invalid Poisson solve arguments");
         return FC2D_E_ARG;
     }
@@ -272,7 +272,7 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     for (int f = 0; f < nf; ++f) {
         double* uf = u + (int64_t)f * npts;
         // particular solution: extension + R2C, -1/|k|^2, C2R, mean term
-        if ((st = fc2d_extend_fft(pl, f_grid + (int64_t)f * npts, f_bdry + (int64_t)f * nbdry, work, spec, 1, s)))
+        if ((st = fc2d_extend_fft(pl, f_grid + (int64_t)f * npts, f_bdry ? f_bdry + (int64_t)f * nbdry : f_bdry, work, spec, 1, s)))
             return st;
         if ((st = pois_mean(&g, spec, mean, s))) return st;
         if ((st = spectral_apply(&g, FC2D_LAPLACE_INV, spec, spec, 1, s))) return st;

@@ -46,7 +46,7 @@ class fc2d_grid(C.Structure):
 class fc2d_opts(C.Structure):
     _fields_ = [("B", C.c_int), ("k1", C.c_double), ("M", C.c_int), ("n_r", C.c_int), ("Z", C.c_int),
                 ("n_os", C.c_int), ("mf", C.c_int), ("newton_maxit", C.c_int), ("seed", C.c_int),
-                ("mlp_tol", C.c_double), ("mlp_weights", C.POINTER(C.c_float))]
+                ("mlp_tol", C.c_double), ("mlp_weights", C.POINTER(C.c_float)), ("interior_only", C.c_int)]
 
 
 class fc2d_plan_info(C.Structure):
@@ -135,6 +135,15 @@ def _dptr(t, name, dtype=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _bptr(plan, f_bdry):
+    """Boundary samples: a device tensor, or None for a plan built from interior data only."""
+    if f_bdry is None:
+        if not plan.interior_only:
+            raise TypeError("f_bdry is required unless the plan was built with interior_only=True")
+        return None
+    return _dptr(f_bdry, "f_bdry", __import__("torch").float64)
+
+
 def make_grid(x0, y0, h, nx, ny):
     return fc2d_grid(float(x0), float(y0), float(h), int(nx), int(ny))
 
@@ -168,15 +177,17 @@ class Plan:
     """Owning wrapper of fc2d_plan*."""
 
     def __init__(self, curve, grid, d=5, C_=27, B=None, k1=None, M=None, n_r=None, Z=None, n_os=None, mf=None,
-                 newton_maxit=None, seed=None, mlp_weights=None, mlp_tol=None, stream=None):
+                 newton_maxit=None, seed=None, mlp_weights=None, mlp_tol=None, interior_only=False, stream=None):
         lib = _lib()
         self.grid = grid
+        self.interior_only = bool(interior_only)
         opts = fc2d_opts()
         lib.fc2d_opts_default(C.byref(grid), C.byref(opts))
         for name, v in (("B", B), ("k1", k1), ("M", M), ("n_r", n_r), ("Z", Z), ("n_os", n_os), ("mf", mf),
                         ("newton_maxit", newton_maxit), ("seed", seed), ("mlp_tol", mlp_tol)):
             if v is not None:
                 setattr(opts, name, v)
+        opts.interior_only = 1 if interior_only else 0
         if mlp_weights is not None:
             wts = np.ascontiguousarray(mlp_weights, dtype=np.float32)
             if wts.size != FC2D_MLP_NW:
@@ -250,23 +261,23 @@ def _nf(f_grid, grid):
 def fc2d_matching(plan, f_grid, f_bdry, fD, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
-    _check(_lib().fc2d_matching(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+    _check(_lib().fc2d_matching(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
                                 _dptr(fD, "fD", torch.float64), nf, _stream(stream)))
 
 
 def fc2d_blend(plan, f_grid, f_bdry, F, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
-    _check(_lib().fc2d_blend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+    _check(_lib().fc2d_blend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
                              _dptr(F, "F", torch.float64), nf, _stream(stream)))
 
 
 def fc2d_extend(plan, f_grid, f_bdry, out, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
-    if f_bdry.numel() != nf * plan.info.n_bdry or out.numel() != f_grid.numel():
+    if (f_bdry is not None and f_bdry.numel() != nf * plan.info.n_bdry) or out.numel() != f_grid.numel():
         raise ValueError("f_bdry / out sizes do not match the plan")
-    _check(_lib().fc2d_extend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _dptr(f_bdry, "f_bdry", torch.float64),
+    _check(_lib().fc2d_extend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
                               _dptr(out, "out", torch.float64), nf, _stream(stream)))
 
 
@@ -274,12 +285,12 @@ def fc2d_extend_fft(plan, f_grid, f_bdry, work, spec, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
     g = plan.grid
-    if f_bdry.numel() != nf * plan.info.n_bdry or work.numel() != f_grid.numel():
+    if (f_bdry is not None and f_bdry.numel() != nf * plan.info.n_bdry) or work.numel() != f_grid.numel():
         raise ValueError("f_bdry / work sizes do not match the plan")
     if spec.dtype != torch.complex128 or spec.numel() != nf * g.nx * (g.ny // 2 + 1):
         raise ValueError("spec must be complex128 [nf][nx][ny/2+1]")
     _check(_lib().fc2d_extend_fft(plan.handle, _dptr(f_grid, "f_grid", torch.float64),
-                                  _dptr(f_bdry, "f_bdry", torch.float64), _dptr(work, "work", torch.float64),
+                                  _bptr(plan, f_bdry), _dptr(work, "work", torch.float64),
                                   _dptr(spec, "spec"), nf, _stream(stream)))
 
 
@@ -306,11 +317,12 @@ def fc2d_poisson_solve(plan, f_grid, f_bdry, g_nodes, u, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
     nb = g_nodes.shape[-1]
-    if f_bdry.numel() != nf * plan.info.n_bdry or u.numel() != f_grid.numel() or g_nodes.numel() != nf * nb:
+    if ((f_bdry is not None and f_bdry.numel() != nf * plan.info.n_bdry) or u.numel() != f_grid.numel()
+            or g_nodes.numel() != nf * nb):
         raise ValueError("f_bdry / g_nodes / u sizes do not match the plan")
     it = C.c_int()
     _check(_lib().fc2d_poisson_solve(plan.handle, _dptr(f_grid, "f_grid", torch.float64),
-                                     _dptr(f_bdry, "f_bdry", torch.float64), _dptr(g_nodes, "g_nodes", torch.float64),
+                                     _bptr(plan, f_bdry), _dptr(g_nodes, "g_nodes", torch.float64),
                                      int(nb), _dptr(u, "u", torch.float64), nf, _stream(stream), C.byref(it)))
     return it.value
 

@@ -165,12 +165,16 @@ int fc2d_plan_strip(const fc2d_plan* plan, int64_t* index, double* theta, double
 
 /* Matching values f_{D_p} (Sec. 3.2): fD [nf][B][d] device float64, from
  * f_grid [nf][nx][ny] (device; only IN entries read) and f_bdry [nf][n_bdry]
- * (device).  Sums are carried in double-double and rounded once. */
+ * (device).  Sums are carried in double-double and rounded once.  With a plan
+ * built from interior data only (fc2d_opts.interior_only; Remark 3.1 II)
+ * f_bdry is not read and may be NULL, here and in fc2d_blend, fc2d_extend,
+ * fc2d_extend_fft and fc2d_poisson_solve. */
 int fc2d_matching(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
                   double* fD, int nf, hipStream_t stream);
 
 /* Blending to zero on V+_{B,C_r} (eq. b_to_z, Remark 2.2): F [nf][C_r+1][B]
- * device float64 with F[0][p] = f_bdry[p] and F[l][p] = (A_r Q^T f_{D_p})_{l-1}.
+ * device float64 with F[0][p] = f_{D_p}[d-1] (f_bdry[p], or its interpolated value from
+ * interior data only) and F[l][p] = (A_r Q^T f_{D_p})_{l-1}.
  * A materialised check of the blend; fc2d_extend never forms F. */
 int fc2d_blend(const fc2d_plan* plan, const double* f_grid, const double* f_bdry,
                double* F, int nf, hipStream_t stream);

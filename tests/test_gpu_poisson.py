@@ -97,21 +97,28 @@ def test_poisson_parity(torch_mod, case):
 
 
 def test_paper_table3_on_power_of_two_boxes(torch_mod):
-    """Example 4.2 (kite, d = 4, M = M_P = 7): relative l2 error over the IN points
-    within 10x of Table 3 at h = 4e-2, 2e-2, 1e-2 (boxes 128^2, 256^2, 512^2
-    instead of the printed N_x x N_y), order above 5.3 over the last halving."""
-    rows = load_golden("paper_table3_kite_poisson.txt")[:3]
-    errs = []
-    for (h, _, _, _, _, ref), n in zip(rows, (128, 256, 512)):
-        u, pl, it, X, Y = _gpu(torch_mod, h, n, 4, 7, [_f], [_u_exact], n)
-        from paper_2010_03901_amd import fc2d
-        ins = fc2d.fc2d_plan_classes(pl) == OP.IN
-        ex = _u_exact(X, Y)[ins]
-        e = np.linalg.norm(u[0][ins] - ex) / np.linalg.norm(ex)
-        print("\n[poisson] Table 3 h=%g (%d^2, nb=%d): GPU %.2e printed %.2e, GMRES %d" % (h, n, n, e, ref, it))
-        assert e < 10 * ref
-        errs.append(e)
-    assert math.log2(errs[-2] / errs[-1]) > 5.3, errs
+    """Example 4.2 (kite, d = 4): the whole of Table 3, M = M_P = 5, 6, 7 at
+    h = 4e-2 .. 4e-3 (boxes 128^2 .. 1024^2 instead of the printed N_x x N_y,
+    nb = N): relative l2 error over the IN points within a factor 2 of each
+    printed value (measured 0.75 - 1.06), and the printed orders over the
+    halvings (about 5 for M_P = d + 1, 6 for d + 2 and d + 3) within 0.7."""
+    from paper_2010_03901_amd import fc2d
+    rows = load_golden("paper_table3_kite_poisson.txt")
+    errs = {5: [], 6: [], 7: []}
+    for h, _, _, r5, r6, r7 in rows:
+        n = 128 if h >= 0.04 else 256 if h >= 0.02 else 512 if h >= 0.01 else 1024
+        for M, ref in ((5, r5), (6, r6), (7, r7)):
+            u, pl, it, X, Y = _gpu(torch_mod, h, n, 4, M, [_f], [_u_exact], n)
+            ins = fc2d.fc2d_plan_classes(pl) == OP.IN
+            ex = _u_exact(X, Y)[ins]
+            e = np.linalg.norm(u[0][ins] - ex) / np.linalg.norm(ex)
+            print("\n[poisson] Table 3 h=%g M=%d (%d^2): GPU %.2e printed %.2e (x%.2f), GMRES %d"
+                  % (h, M, n, e, ref, e / ref, it), end="")
+            assert 0.5 * ref < e < 2.0 * ref
+            errs[M].append((h, e))
+    for M, order in ((5, 5.0), (6, 6.0), (7, 6.0)):
+        (h0, e0), (h1, e1) = errs[M][2], errs[M][3]          # h = 1e-2 -> 5e-3
+        assert abs(math.log(e0 / e1) / math.log(h0 / h1) - order) < 0.7, (M, errs[M])
 
 
 @pytest.mark.parametrize("h,nb", [(0.04, 100), (0.04, 129), (0.04, 2000)], ids=["nb100", "nb129_odd", "dense_nodes"])
@@ -133,9 +140,9 @@ def test_poisson_node_counts(torch_mod, h, nb):
 def test_paper_table4_oscillatory_d10(torch_mod):
     """Example 4.3 (kite, f = -sin(40 pi x) sin(40 pi y), d = 10, M = M_P = 13,
     nb = N, boxes 1024^2 and 2048^2 instead of the printed N_x x N_y): relative
-    l_inf and l2 errors over the IN points farther than 0.2 from Gamma within 10x
-    of Table 4 at h = 2.5e-3 and 1.25e-3, order above d + 2 = 12 over that
-    halving.  (The coarsest row, h = 5e-3, is left out: there the d = 10 tables
+    l_inf and l2 errors over the IN points farther than 0.2 from Gamma within 5x
+    of Table 4 at h = 2.5e-3 and 1.25e-3 (measured 2.1 - 3.3x), order above
+    d + 2 = 12 over that halving.  (The coarsest row, h = 5e-3, is left out: there the d = 10 tables
     built here differ from the paper's by more than 10x, as in Table 1.)"""
     from scipy.spatial import cKDTree
     from oracle.curves import Curve
@@ -158,6 +165,6 @@ def test_paper_table4_oscillatory_d10(torch_mod):
         e_l2 = np.linalg.norm(err) / np.linalg.norm(ex)
         print("\n[poisson] Table 4 h=%g (%d^2): l_inf %.2e (printed %.2e), l2 %.2e (printed %.2e), GMRES %d"
               % (h, n, e_inf, ref_inf, e_l2, ref_l2, it))
-        assert e_inf < 10 * ref_inf and e_l2 < 10 * ref_l2
+        assert e_inf < 5 * ref_inf and e_l2 < 5 * ref_l2
         errs.append((e_inf, e_l2))
     assert math.log2(errs[0][0] / errs[1][0]) > 12 and math.log2(errs[0][1] / errs[1][1]) > 12, errs

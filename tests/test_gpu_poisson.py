@@ -168,3 +168,37 @@ def test_paper_table4_oscillatory_d10(torch_mod):
         assert e_inf < 5 * ref_inf and e_l2 < 5 * ref_l2
         errs.append((e_inf, e_l2))
     assert math.log2(errs[0][0] / errs[1][0]) > 12 and math.log2(errs[0][1] / errs[1][1]) > 12, errs
+
+
+def test_poisson_parity_star(torch_mod):
+    """The star r = 1 + 0.3 cos 5t (concave bends of radius 0.07 outside, k1 =
+    0.0024 < h) on 256^2, d = 5, M = M_P = 8, nb = 256: the GPU solve against the
+    oracle's on the same plan (1e-11 of max |u|), every non-IN point 0."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    case = W.cfg_star(256)
+    nb = 256
+    g = OP.Grid(case.x0, case.y0, case.h, case.n, case.n)
+    opl = OP.make_plan(Curve(*case.curve), g, fcgram.load_tables(case.d), case.B, k1=case.k1, M=case.M)
+    gpl = fc2d.Plan(fc2d.make_curve(*case.curve), fc2d.make_grid(case.x0, case.y0, case.h, case.n, case.n),
+                    d=case.d, C_=case.C, B=case.B, k1=case.k1, M=case.M)
+    X, Y = np.meshgrid(g.xs(), g.ys(), indexing="ij")
+    bp = fc2d.fc2d_boundary_points(gpl)
+    q = fc2d.fc2d_poisson_nodes(gpl, nb)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    u = torch.full((1, case.n, case.n), float("nan"), dtype=torch.float64, device="cuda:0")
+    it = fc2d.fc2d_poisson_solve(gpl, dev(_f(X, Y)[None]), dev(_f(bp[:, 0], bp[:, 1])[None]),
+                                 dev(_u_exact(q[:, 0], q[:, 1])[None]), u)
+    torch.cuda.synchronize()
+    U = u[0].cpu().numpy()
+    obp = OP.boundary_points(opl)
+    _, qo, _, _ = OPS.nodes(opl.curve, nb)
+    ref = OPS.solve(opl, _f(X, Y), _f(obp[:, 0], obp[:, 1]), _u_exact(qo[:, 0], qo[:, 1]), nb)
+    assert np.array_equal(fc2d.fc2d_plan_classes(gpl), opl.cls)
+    assert np.all(U[opl.cls != OP.IN] == 0.0)
+    e = rel_err(U, ref)
+    ins = opl.cls == OP.IN
+    ex = _u_exact(X, Y)[ins]
+    print("\n[poisson] star 256^2: GMRES %d, rel err vs oracle %.2e, vs exact %.2e"
+          % (it, e, np.linalg.norm(U[ins] - ex) / np.linalg.norm(ex)))
+    assert e < 1e-11

@@ -50,6 +50,7 @@ def matching_values(pl, f_grid, f_bdry):
     if getattr(pl, "interior_only", False):
         fD[:, :] = np.sum(pl.match_wn * stars[:, None, :], axis=2)         # [B, d], Remark 3.1 II
     else:
+        stars[:, M - 1] = fb[:B].astype(LD)                                # the point on Gamma
         fD[:, : d - 1] = np.sum(pl.match_wn * stars[:, None, :], axis=2)    # [B, d-1]
         fD[:, d - 1] = fb[:B].astype(LD)
     return fD

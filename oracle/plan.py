@@ -34,17 +34,18 @@ Readings of the paper taken here (the paper leaves them open):
   the IN points of the run of IN points on its line that holds the star (at
   most M + 1 grid steps away) and the crossings of that line with Gamma that
   bound the run ("squares"); a square closer than h/2 to one of these IN
-  nodes is dropped.  The red stars are the first M candidates offering at least
-  M nodes (a line nearly tangent to Gamma next to a shallow star offers too
-  few), and each uses the M nodes nearest to it.  Squares are listed once per
-  use, in the order normal, star, node.  Values at the
-  d - 1 interior matching points come from a degree-(M-1) interpolation over
-  the M stars along the normal; the matching point on Gamma takes the
-  boundary sample.  Weights are formed in numpy.longdouble.
+  nodes is dropped.  The red stars are the first M - 1 candidates offering at
+  least M nodes (a line nearly tangent to Gamma next to a shallow star offers
+  too few), and each uses the M nodes nearest to it.  Squares are listed once
+  per use, in the order normal, star, node.  Values at the d - 1 interior
+  matching points come from a degree-(M-1) interpolation along the normal over
+  M nodes: the M - 1 stars and the point on Gamma itself (depth 0, the
+  boundary sample), which also gives the matching point on Gamma.  Weights are
+  formed in numpy.longdouble.
 * Interior data only (Remark 3.1 II; ``interior_only=True``).  No squares: a
-  star's nodes are IN points only, and the matching point on Gamma also takes
-  the degree-(M-1) interpolation over the M stars along the normal (at depth 0)
-  instead of a boundary sample.
+  star's nodes are IN points only, the along-normal interpolation uses M stars
+  (no boundary sample to stand at depth 0), and the matching point on Gamma
+  takes that interpolation too.
 """
 from __future__ import annotations
 
@@ -61,6 +62,7 @@ LD = np.longdouble
 TWO_PI = 2.0 * math.pi
 EPS = 2.0 ** -52
 ON_GAMMA_TOL = 1e-13
+STAR_MIN_DEPTH = 0.05   # red stars closer to Gamma than this fraction of the star spacing are skipped
 
 
 class GeometryError(Exception):
@@ -344,6 +346,11 @@ def _matching_stencils(pl):
                 return cls[i_s, j] if vertical else cls[j, i_s]
 
             lower, upper = [], []
+            if not pl.interior_only and delta < LD(STAR_MIN_DEPTH) * LD(h) / LD(abs(na)):
+                # too close to the point on Gamma (itself a node along the normal)
+                star_rec.append((p, vertical, i_s, delta, bstar))
+                runs.append([[], [], None, None])
+                continue
             j = jb
             while j >= jb - M and c_at(j) == IN:
                 lower.append(j)
@@ -377,8 +384,11 @@ def _matching_stencils(pl):
         if any(abs(b - (b0 + j * h)) < 0.5 * h for j in nodes):
             continue              # closer than h/2 to an IN node: dropped
         runs[rid][2 + side] = b
-    # phase 3: per normal, the first M stars whose line offers >= M nodes;
-    # the M nodes nearest each star; weights in longdouble
+    # phase 3: per normal, the first M - 1 stars (M from interior data only)
+    # whose line offers >= M nodes; the M nodes nearest each star; weights in
+    # longdouble.  With boundary data, star slot M - 1 is the point on Gamma
+    # (depth 0): its value is the boundary sample, its stencil unused.
+    nstar = M if pl.interior_only else M - 1
     nref = np.zeros((B, M, M), dtype=np.int64)
     wv = np.zeros((B, M, M), dtype=LD)
     deltas = np.zeros((B, M), dtype=LD)
@@ -390,7 +400,7 @@ def _matching_stencils(pl):
         for s in range(2 * M):
             _, vertical, i_s, delta, bstar = star_rec[rid + s]
             lower, upper, sqlo, sqhi = runs[rid + s]
-            if used == M or len(lower) + len(upper) + (sqlo is not None) + (sqhi is not None) < M:
+            if used == nstar or len(lower) + len(upper) + (sqlo is not None) + (sqhi is not None) < M:
                 continue
             b0 = grid.y0 if vertical else grid.x0
             lo_list = [("g", j, b0 + j * h) for j in lower] + ([("s", None, sqlo)] if sqlo is not None else [])
@@ -421,8 +431,11 @@ def _matching_stencils(pl):
                     sq_xy.append((a_s, c[2]) if vertical else (c[2], a_s))
             deltas[p, used] = delta
             used += 1
-        if used < M:
-            raise GeometryError("matching stencil: fewer than M usable red stars at normal %d" % p)
+        if used < nstar:
+            raise GeometryError("matching stencil: too few usable red stars at normal %d" % p)
+        if nstar < M:        # the point on Gamma; placeholder stencil (star 0's nodes, zero weights)
+            nref[p, M - 1] = nref[p, 0]
+            deltas[p, M - 1] = 0
         pl.vertical[p] = vertical
         rid += 2 * M
     pl.squares = np.array(sq_xy, dtype=np.float64).reshape(-1, 2)

@@ -143,41 +143,43 @@ def test_paper_table1_disc():
         for r in [r for r in rows if r[0] == d]:
             e = _disc_error(d, r[1], int(r[3]))
             errs.append(e)
-            assert e < 10 * r[4], (d, r, e)
+            assert r[4] / 2 < e < 2 * r[4], (d, r, e)        # measured 0.82 - 1.07
         orders = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
         assert orders[-1] > d - 0.7, (d, errs)
 
 
-@pytest.mark.slow
-def test_paper_table2_kite():
-    """Kite of Example 3.2 on the printed N_x x N_y grids (M = d + 3)."""
-    rows = [r for r in load_golden("paper_table2_kite.txt") if r[1] >= 5e-3]
+def _kite_error(d, M, h, nx, ny):
     curve = W.kite(0.35, 0.7)
     xmin, xmax, ymin, ymax = W.bbox(curve)
     f = W.f_paper_kite
-    for d, h, nx, ny, ref in rows:
+    x0 = 0.5 * (xmin + xmax) - 0.5 * nx * h
+    y0 = 0.5 * (ymin + ymax) - 0.5 * ny * h
+    g = P.Grid(x0, y0, h, nx, ny)
+    pl = P.make_plan(Curve(*curve), g, fcgram.load_tables(d), int(round(2 * np.pi / h)), k1=h, M=M)
+    bp = P.boundary_points(pl)
+    X, Y = np.meshgrid(g.xs(), g.ys(), indexing="ij")
+    ext = E.extend(pl, f(X, Y), f(bp[:, 0], bp[:, 1]))
+    U = np.fft.fft2(ext)
+    # values on the h/2 grid by zero padding
+    P2 = np.zeros((2 * nx, 2 * ny), dtype=complex)
+    hx, hy = nx // 2, ny // 2
+    P2[:hx + 1, :hy + 1] = U[:hx + 1, :hy + 1]
+    P2[-hx:, :hy + 1] = U[-hx:, :hy + 1]
+    P2[:hx + 1, -hy:] = U[:hx + 1, -hy:]
+    P2[-hx:, -hy:] = U[-hx:, -hy:]
+    up = np.real(np.fft.ifft2(P2)) * 4
+    X2, Y2 = np.meshgrid(x0 + np.arange(2 * nx) * h / 2, y0 + np.arange(2 * ny) * h / 2, indexing="ij")
+    ins = P.column_parity_inside(Curve(*curve), P.Grid(x0, y0, h / 2, 2 * nx, 2 * ny), 16384)
+    return np.abs(up - f(X2, Y2))[ins].max()
+
+
+@pytest.mark.slow
+def test_paper_table2_kite():
+    """Kite of Example 3.2 on the printed N_x x N_y grids, every M column
+    (M = d + 1, d + 2, d + 3) of the rows h = 1e-2, 5e-3: each error within a
+    factor 3 of the printed one (measured 0.48 - 2.1)."""
+    for d, h, nx, ny, *refs in [r for r in load_golden("paper_table2_kite.txt") if r[1] >= 5e-3]:
         d, nx, ny = int(d), int(nx), int(ny)
-        tab = fcgram.load_tables(d)
-        x0 = 0.5 * (xmin + xmax) - 0.5 * nx * h
-        y0 = 0.5 * (ymin + ymax) - 0.5 * ny * h
-        g = P.Grid(x0, y0, h, nx, ny)
-        B = int(round(2 * np.pi / h))
-        pl = P.make_plan(Curve(*curve), g, tab, B, k1=h, M=d + 3)
-        bp = P.boundary_points(pl)
-        X, Y = np.meshgrid(g.xs(), g.ys(), indexing="ij")
-        ext = E.extend(pl, f(X, Y), f(bp[:, 0], bp[:, 1]))
-        U = np.fft.fft2(ext)
-        # values on the h/2 grid by zero padding
-        P2 = np.zeros((2 * nx, 2 * ny), dtype=complex)
-        hx, hy = nx // 2, ny // 2
-        P2[:hx + 1, :hy + 1] = U[:hx + 1, :hy + 1]
-        P2[-hx:, :hy + 1] = U[-hx:, :hy + 1]
-        P2[:hx + 1, -hy:] = U[:hx + 1, -hy:]
-        P2[-hx:, -hy:] = U[-hx:, -hy:]
-        up = np.real(np.fft.ifft2(P2)) * 4
-        x2 = x0 + np.arange(2 * nx) * h / 2
-        y2 = y0 + np.arange(2 * ny) * h / 2
-        X2, Y2 = np.meshgrid(x2, y2, indexing="ij")
-        ins = P.column_parity_inside(Curve(*curve), P.Grid(x0, y0, h / 2, 2 * nx, 2 * ny), 16384)
-        err = np.abs(up - f(X2, Y2))[ins].max()
-        assert err < 10 * ref, (d, h, err, ref)
+        for M, ref in zip((d + 1, d + 2, d + 3), refs):
+            err = _kite_error(d, M, h, nx, ny)
+            assert ref / 3 < err < 3 * ref, (d, M, h, err, ref)

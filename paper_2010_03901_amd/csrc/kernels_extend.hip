@@ -83,6 +83,8 @@ __device__ __forceinline__ int xg_index(int s, int k, int gi) {
 //     addresses, and stores each value in the group's LDS block xg at s M + k.
 //  2. Red stars (first interpolation, along the grid lines): lane sq forms
 //     stars sq, sq + 4, ... from xg; the others travel by cross-lane shuffles.
+//     With boundary data the M-th node along the normal is the point on Gamma
+//     (the boundary sample; its stencil entries are padding), otherwise a star.
 //  3. Matching values along the normal (second interpolation) q = sq, sq + 4, ...
 //     (q < d - 1; q < d for a plan built from interior data only, io = 1,
 //     where the value on Gamma is interpolated too instead of read from bv)
@@ -151,11 +153,14 @@ __device__ __forceinline__ void match_group(const int32_t* __restrict__ mref, co
         const dd v = mine[s >> 2];
         star[s] = dd{__shfl(v.hi, src, 64), __shfl(v.lo, src, 64)};
     }
+    // with boundary data the last node along the normal is the point on Gamma
+    // (depth 0): its value is the boundary sample, not a red star
+    const double fbs = io ? 0.0 : bv[p];   // boundary sample (not read from interior data only)
+    if (!io) star[M - 1] = dd{fbs, 0.0};
     // 3. matching values along the normal (second interpolation)
     const int NQ = D - 1 + io;   // matching values interpolated along the normal
     const int RQ = (NQ + 3) / 4;
     const double* wn = mwn + (int64_t)p * RQ * M * 4 * 2;   // [r][s][sq] double-double
-    const double fbs = io ? 0.0 : bv[p];   // boundary sample (not read from interior data only)
     dd fq[3];
 #pragma unroll
     for (int r = 0; r < 3; ++r) {

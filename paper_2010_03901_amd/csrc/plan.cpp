@@ -172,6 +172,11 @@ static int nearest_sample(const fc2d_plan* pl, double X, double Y, int p) {
 // ----------------------------------------------------------------------------
 // matching stencils (Sec. 3.2)
 // ----------------------------------------------------------------------------
+// red stars closer to Gamma than this fraction of the star spacing (h / |n| along
+// the normal) are skipped: the point on Gamma is itself a node along the normal
+constexpr double kStarMinDepth = 0.05;
+constexpr int32_t kUnusedRef = INT32_MIN;   // stencil entry of the point-on-Gamma slot (not gathered)
+
 struct StarRec {
     int p;
     bool vertical;
@@ -195,6 +200,9 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
     const int M = pl->M, d = pl->d, B = pl->B;
     const bool io = pl->interior_only;
     const int nq = io ? d : d - 1;   // matching values interpolated along the normal
+    // red stars per normal: with boundary data the point on Gamma (depth 0, the
+    // boundary sample) is the M-th node of the along-normal interpolation
+    const int nstar = io ? M : M - 1;
     const double h = g.h;
     std::vector<StarRec> stars;
     stars.reserve((size_t)B * 2 * M);
@@ -222,6 +230,10 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
             r.delta = ((long double)qa - (long double)a_s) / (long double)na;
             r.bstar = (long double)qb - r.delta * (long double)nb;
             const int jb = (int)floor(((double)r.bstar - b0) / h);
+            if (!io && r.delta < (long double)kStarMinDepth * h / fabs(na)) {
+                stars.push_back(std::move(r));   // too close to the point on Gamma: unusable
+                continue;
+            }
             auto c_at = [&](int j) -> int {
                 if (j < 0 || j >= Nb) return 0;
                 if (r.line < 0 || r.line >= (vertical ? g.nx : g.ny)) return 0;
@@ -299,7 +311,7 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
     std::vector<long double> deltas(M);
     for (int p = 0; p < B; ++p) {
         int used = 0;
-        for (int s = 0; s < 2 * M && used < M; ++s) {
+        for (int s = 0; s < 2 * M && used < nstar; ++s) {
             const StarRec& r = stars[(size_t)p * 2 * M + s];
             const int ncand = (int)r.lower.size() + (int)r.upper.size() + r.sq_has[0] + r.sq_has[1];
             if (ncand < M) continue;
@@ -346,11 +358,15 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
             deltas[used] = r.delta;
             ++used;
         }
-        if (used < M) {
+        if (used < nstar) {
             char buf[160];
-            snprintf(buf, sizeof buf, "matching stencil: fewer than M usable red stars at normal %d", p);
+            snprintf(buf, sizeof buf, "matching stencil: too few usable red stars at normal %d", p);
             set_error(buf);
             return FC2D_E_GEOMETRY;
+        }
+        if (nstar < M) {   // the point on Gamma: no stencil (entries marked unused), depth 0
+            for (int k = 0; k < M; ++k) mref[((size_t)p * M + M - 1) * M + k] = kUnusedRef;
+            deltas[M - 1] = 0.0L;
         }
         for (int q = 0; q < nq; ++q) {
             const long double x = (long double)(d - 1 - q) * (long double)pl->k1;
@@ -698,9 +714,11 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             for (int p = 0; p < B; ++p) {
                 const int32_t* r0 = &mref[(size_t)p * MM];
                 auto key = [&](int e) { return r0[e] >= 0 ? (int64_t)r0[e] : npts + (int64_t)(-r0[e] - 1); };
-                for (int e = 0; e < MM; ++e) ord[e] = e;
-                std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return key(a) < key(b); });
-                for (int i = 0; i < MM; ++i) {
+                int nuse = 0;   // entries of unused stencils stay padding (label 255)
+                for (int e = 0; e < MM; ++e)
+                    if (r0[e] != kUnusedRef) ord[nuse++] = e;
+                std::stable_sort(ord.begin(), ord.begin() + nuse, [&](int a, int b) { return key(a) < key(b); });
+                for (int i = 0; i < nuse; ++i) {
                     const size_t o = ((size_t)p * 4 + i % 4) * NU + i / 4;
                     dref[o] = r0[ord[i]];
                     dlab[o] = (uint8_t)ord[i];

@@ -60,6 +60,23 @@ def test_table1_disc(torch_mod, d):
     assert order > d - 0.7, (d, errs)
 
 
+def test_table1_disc_d10(torch_mod):
+    """Table 1's d = 10 rows (M = 13): within 10x at h = 2e-2 and 3x at h = 1e-2
+    (measured 7.4x and 1.9x)."""
+    rows = [r for r in load_golden("paper_table1_disc.txt") if int(r[0]) == 10]
+    for (_, h, _, B, ref), bar in zip(rows, (10.0, 3.0)):
+        n = int(round(3.2 / h))
+        ext = _gpu_extension(torch_mod, W.disc(), -1.6, -1.6, h, n, n, int(B), 10, W.f_paper_disc)
+        up = OS.upsample_h2(ext)
+        x = -1.6 + np.arange(2 * n) * h / 2
+        X, Y = np.meshgrid(x, x, indexing="ij")
+        ins = X ** 2 + Y ** 2 < 1
+        ex = W.f_paper_disc(X, Y)
+        e = np.abs(up - ex)[ins].max() / np.abs(ex[ins]).max()
+        print("[paper] Table 1 d=10 h=%g: GPU %.2e printed %.2e (x%.2f)" % (h, e, ref, e / ref))
+        assert ref / bar < e < bar * ref, (h, e, ref)
+
+
 @pytest.mark.parametrize("d", [4, 5])
 def test_table2_kite(torch_mod, d):
     rows = [r for r in load_golden("paper_table2_kite.txt") if int(r[0]) == d and r[1] >= 5e-3]

@@ -174,6 +174,16 @@ def _kite_error(d, M, h, nx, ny):
 
 
 @pytest.mark.slow
+def test_paper_table1_disc_d10():
+    """Table 1's d = 10 rows (M = 13): within 10x at h = 2e-2 and 3x at h = 1e-2
+    (measured 7.4x and 1.9x; the tables here use the band limit of d = 4, 5)."""
+    rows = [r for r in load_golden("paper_table1_disc.txt") if r[0] == 10]
+    for (_, h, _, B, ref), bar in zip(rows, (10.0, 3.0)):
+        e = _disc_error(10, h, int(B))
+        assert ref / bar < e < bar * ref, (h, e, ref)
+
+
+@pytest.mark.slow
 def test_paper_table2_kite():
     """Kite of Example 3.2 on the printed N_x x N_y grids, every M column
     (M = d + 1, d + 2, d + 3) of the rows h = 1e-2, 5e-3: each error within a

@@ -139,11 +139,11 @@ def test_poisson_node_counts(torch_mod, h, nb):
 
 def test_paper_table4_oscillatory_d10(torch_mod):
     """Example 4.3 (kite, f = -sin(40 pi x) sin(40 pi y), d = 10, M = M_P = 13,
-    nb = N, boxes 1024^2 and 2048^2 instead of the printed N_x x N_y): relative
-    l_inf and l2 errors over the IN points farther than 0.2 from Gamma within 5x
-    of Table 4 at h = 2.5e-3 and 1.25e-3 (measured 2.1 - 3.3x), order above
-    d + 2 = 12 over that halving.  (The coarsest row, h = 5e-3, is left out: there the d = 10 tables
-    built here differ from the paper's by more than 10x, as in Table 1.)"""
+    nb = N, boxes 512^2 .. 2048^2 instead of the printed N_x x N_y): relative
+    l_inf and l2 errors over the IN points farther than 0.2 from Gamma within a
+    factor 2 of Table 4 at h = 5e-3 (measured 0.99 and 0.86), at most 5x the
+    printed ones at h = 2.5e-3 and 1.25e-3 (measured 0.13 - 0.24x: smaller), and
+    order above d + 2 = 12 over the last halving."""
     from scipy.spatial import cKDTree
     from oracle.curves import Curve
     from paper_2010_03901_amd import fc2d
@@ -152,9 +152,9 @@ def test_paper_table4_oscillatory_d10(torch_mod):
     f = lambda x, y: -np.sin(k * x) * np.sin(k * y)
     x, y, _, _, _, _ = Curve(*KITE).eval_vec(np.linspace(0, 2 * np.pi, 20000, endpoint=False))
     tree = cKDTree(np.stack([x, y], 1))
-    rows = load_golden("paper_table4_kite_poisson_d10.txt")[1:]
+    rows = load_golden("paper_table4_kite_poisson_d10.txt")
     errs = []
-    for (h, _, _, ref_inf, ref_l2), n in zip(rows, (1024, 2048)):
+    for (h, _, _, ref_inf, ref_l2), n in zip(rows, (512, 1024, 2048)):
         u, pl, it, X, Y = _gpu(torch_mod, h, n, 10, 13, [f], [ue], n)
         ins = fc2d.fc2d_plan_classes(pl) == OP.IN
         dist, _ = tree.query(np.stack([X[ins], Y[ins]], 1), distance_upper_bound=0.25)
@@ -165,9 +165,12 @@ def test_paper_table4_oscillatory_d10(torch_mod):
         e_l2 = np.linalg.norm(err) / np.linalg.norm(ex)
         print("\n[poisson] Table 4 h=%g (%d^2): l_inf %.2e (printed %.2e), l2 %.2e (printed %.2e), GMRES %d"
               % (h, n, e_inf, ref_inf, e_l2, ref_l2, it))
-        assert e_inf < 5 * ref_inf and e_l2 < 5 * ref_l2
+        if n == 512:
+            assert ref_inf / 2 < e_inf < 2 * ref_inf and ref_l2 / 2 < e_l2 < 2 * ref_l2
+        else:
+            assert e_inf < 5 * ref_inf and e_l2 < 5 * ref_l2
         errs.append((e_inf, e_l2))
-    assert math.log2(errs[0][0] / errs[1][0]) > 12 and math.log2(errs[0][1] / errs[1][1]) > 12, errs
+    assert math.log2(errs[1][0] / errs[2][0]) > 12 and math.log2(errs[1][1] / errs[2][1]) > 12, errs
 
 
 def test_poisson_parity_star(torch_mod):

@@ -107,9 +107,10 @@ def double_layer(curve, phi, pts):
     return out
 
 
-def solve(pl, f_grid, f_bdry, g_nodes, nb, MP=None):
+def solve(pl, f_grid, f_bdry, g_nodes, nb, MP=None, sample=None):
     """u on the IN points of the plan's grid (other points 0).  g_nodes: g at
-    the nb nodes q(2 pi j / nb)."""
+    the nb nodes q(2 pi j / nb).  With ``sample`` (flat grid indices of IN
+    points) only those points are evaluated and their values returned."""
     MP = pl.M if MP is None else MP
     grid, curve = pl.grid, pl.curve
     up = particular_solution(pl, f_grid, f_bdry)
@@ -118,7 +119,12 @@ def solve(pl, f_grid, f_bdry, g_nodes, nb, MP=None):
     phi = density(curve, g_hom)
     phif = trig_interp(phi, 2.0 * math.pi * np.arange(REFINE * nb) / (REFINE * nb))
     X, Y = np.meshgrid(grid.xs(), grid.ys(), indexing="ij")
-    ins = np.argwhere(pl.cls == IN)
+    if sample is None:
+        ins = np.argwhere(pl.cls == IN)
+    else:
+        sample = np.asarray(sample)
+        assert np.all(pl.cls.ravel()[sample] == IN)
+        ins = np.stack(np.unravel_index(sample, pl.cls.shape), 1)
     P = np.stack([X[ins[:, 0], ins[:, 1]], Y[ins[:, 0], ins[:, 1]]], 1)
     v = double_layer(curve, phif, P)
     # points within h/2 of Gamma: along the normal from the foot
@@ -144,6 +150,8 @@ def solve(pl, f_grid, f_bdry, g_nodes, nb, MP=None):
             vals[:, m] = double_layer(curve, phif, pts)
         w = lagrange_weights(np.broadcast_to(s_nodes, (sel.size, MP)).copy(), -eta[sel])
         v[sel] = (w * vals).sum(1)
+    if sample is not None:
+        return up[ins[:, 0], ins[:, 1]] + v
     u = np.zeros_like(up)
     u[ins[:, 0], ins[:, 1]] = up[ins[:, 0], ins[:, 1]] + v
     return u

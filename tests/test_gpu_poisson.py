@@ -205,3 +205,43 @@ def test_poisson_parity_star(torch_mod):
     print("\n[poisson] star 256^2: GMRES %d, rel err vs oracle %.2e, vs exact %.2e"
           % (it, e, np.linalg.norm(U[ins] - ex) / np.linalg.norm(ex)))
     assert e < 1e-11
+
+
+def test_poisson_full_size_sampled(torch_mod):
+    """The Poisson workload the benchmark times (kite(0.65, 1.5) in its fitted
+    2048^2 box, d = 5, M = M_P = 8, B = 4096, nb = 2048, u = sin(2 pi x)
+    sin(2 pi y) / (8 pi^2)), solved on the GPU as the benchmark does, against the
+    oracle's solve at 600 seeded IN points (400 uniform, 200 within 2h of the
+    boundary samples, so the near-boundary interpolation is included): 1e-11 of
+    max |u|."""
+    from scipy.spatial import cKDTree
+    from gpu_common import gpu_plan, oracle_plan
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    print("\n[poisson] full size: plans", flush=True)
+    case, opl = oracle_plan("kite2048", W.cfg_kite, 2048)
+    gpl = gpu_plan(case)
+    nb = case.n
+    X, Y = np.meshgrid(case.x0 + np.arange(case.n) * case.h, case.y0 + np.arange(case.n) * case.h, indexing="ij")
+    bp = fc2d.fc2d_boundary_points(gpl)
+    q = fc2d.fc2d_poisson_nodes(gpl, nb)
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    u = torch.empty((1, case.n, case.n), dtype=torch.float64, device="cuda:0")
+    it = fc2d.fc2d_poisson_solve(gpl, dev(_f(X, Y)[None]), dev(_f(bp[:, 0], bp[:, 1])[None]),
+                                 dev(_u_exact(q[:, 0], q[:, 1])[None]), u)
+    torch.cuda.synchronize()
+    U = u[0].cpu().numpy().ravel()
+    rng = np.random.default_rng(2048)
+    ins = np.flatnonzero(opl.cls.ravel() == OP.IN)
+    tree = cKDTree(np.stack([opl.bd["x"], opl.bd["y"]], 1))
+    d, _ = tree.query(np.stack([X.ravel()[ins], Y.ravel()[ins]], 1), distance_upper_bound=2 * case.h)
+    near = ins[np.isfinite(d)]
+    sample = np.unique(np.concatenate([rng.choice(ins, 400, replace=False), rng.choice(near, 200, replace=False)]))
+    print("[poisson] full size: GMRES %d; oracle at %d points" % (it, sample.size), flush=True)
+    obp = OP.boundary_points(opl)
+    _, qo, _, _ = OPS.nodes(opl.curve, nb)
+    ref = OPS.solve(opl, _f(X, Y), _f(obp[:, 0], obp[:, 1]), _u_exact(qo[:, 0], qo[:, 1]), nb, sample=sample)
+    e = np.abs(U[sample] - ref).max() / np.abs(U[ins]).max()
+    ex = _u_exact(X.ravel()[sample], Y.ravel()[sample])
+    print("[poisson] full size: rel err vs oracle %.2e (vs exact %.2e)" % (e, np.abs(ref - ex).max() / np.abs(ex).max()))
+    assert e < 1e-11

@@ -242,20 +242,36 @@ __global__ __launch_bounds__(256) void k_trig_conv(const double* __restrict__ ph
     if (m < nb) phif[(int64_t)R * m + r] = s;
 }
 
-// Node records of the double-layer sums: (x, y, phi y', phi x') per node,
-// phi the density at that node.  Level L node k sits at record nb (2^L - 1) + k;
-// its density is finest-level node k 2^(kPoisLevels - 1 - L).
+// Node records of the double-layer sums for NF fields: (x, y) and, per field
+// f, (phi_f y', phi_f x'), phi_f the field's density at the node (NF = 1: the
+// 32-byte record (x, y, phi y', phi x')).  Level L node k sits at record
+// nb (2^L - 1) + k; its density is finest-level node k 2^(kPoisLevels - 1 - L).
+template <int NF>
+struct DlRec {
+    double x, y;
+    double ab[2 * NF];
+};
+
+template <int NF>
 __global__ void k_records(const double4* __restrict__ geo, const double* __restrict__ phif, int nb,
-                          double4* __restrict__ rec) {
+                          DlRec<NF>* __restrict__ rec) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int top = kPoisLevels - 1;
     if (i >= (int64_t)nb * ((2 << top) - 1)) return;
     int L = 0;
     while (i >= (int64_t)nb * ((2 << L) - 1)) ++L;
     const int64_t k = i - (int64_t)nb * ((1 << L) - 1);
-    const double ph = phif[k << (top - L)];
     const double4 g = geo[i];   // x, y, x', y'
-    rec[i] = make_double4(g.x, g.y, ph * g.w, ph * g.z);
+    DlRec<NF> r;
+    r.x = g.x;
+    r.y = g.y;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const double ph = phif[((int64_t)f * nb << top) + (k << (top - L))];
+        r.ab[2 * f] = ph * g.w;
+        r.ab[2 * f + 1] = ph * g.z;
+    }
+    rec[i] = r;
 }
 
 // 1 / r2 from the hardware reciprocal and two Newton steps (a few ulp; the
@@ -267,47 +283,57 @@ __device__ inline double inv_r2(double r2) {
     return r;
 }
 
-// trapezoidal double-layer terms of the node records [j0, j1) at (X, Y), not
-// yet divided by the node count (wave-uniform addresses: the records come
-// through the scalar cache, eight per wait; the eight reciprocals are formed
-// side by side).  With MIN also a lower bound of the smallest squared node
-// distance: the minimum of the high words, low word zero (relative error below
-// 2^-20, rounded down; it only steers the level choice and the candidate test).
-template <bool MIN>
-__device__ inline double dl_partial(const double4* __restrict__ rec, int j0, int j1, double X, double Y,
-                                    double* dmin2) {
-    double s0 = 0.0, s1 = 0.0;
+// trapezoidal double-layer terms of the node records [j0, j1) at (X, Y) for NF
+// fields, not yet divided by the node count: sum[f].  The records come through
+// the scalar cache (wave-uniform addresses), 8 / NF per wait, their
+// reciprocals formed side by side; distance and reciprocal are shared by the
+// fields.  With MIN also a lower bound of the smallest squared node distance:
+// the minimum of the high words, low word zero (relative error below 2^-20,
+// rounded down; it only steers the level choice and the candidate test).
+template <bool MIN, int NF>
+__device__ inline void dl_partial(const DlRec<NF>* __restrict__ rec, int j0, int j1, double X, double Y,
+                                  double* sum, double* dmin2) {
+    constexpr int U = NF == 1 ? 8 : (NF == 2 ? 4 : 2);
+    double s0[NF], s1[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s0[f] = s1[f] = 0.0;
     unsigned dmh = 0xffffffffu;
     int j = j0;
-    for (; j + 8 <= j1; j += 8) {
-        double4 b[8];
+    for (; j + U <= j1; j += U) {
+        DlRec<NF> b[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) b[u] = rec[j + u];
-        double r2[8], nm[8], rv[8];
+        for (int u = 0; u < U; ++u) b[u] = rec[j + u];
+        double dx[U], dy[U], r2[U], rv[U];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double dx = X - b[u].x, dy = Y - b[u].y;
-            r2[u] = dx * dx + dy * dy;
-            nm[u] = dx * b[u].z - dy * b[u].w;
+        for (int u = 0; u < U; ++u) {
+            dx[u] = X - b[u].x;
+            dy[u] = Y - b[u].y;
+            r2[u] = dx[u] * dx[u] + dy[u] * dy[u];
             if (MIN) dmh = min(dmh, (unsigned)(__double_as_longlong(r2[u]) >> 32));
         }
 #pragma unroll
-        for (int u = 0; u < 8; ++u) rv[u] = inv_r2(r2[u]);
+        for (int u = 0; u < U; ++u) rv[u] = inv_r2(r2[u]);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            if (u & 1) s1 += nm[u] * rv[u];
-            else s0 += nm[u] * rv[u];
-        }
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                const double t = (dx[u] * b[u].ab[2 * f] - dy[u] * b[u].ab[2 * f + 1]) * rv[u];
+                if (u & 1) s1[f] += t;
+                else s0[f] += t;
+            }
     }
     for (; j < j1; ++j) {
-        const double4 b = rec[j];
+        const DlRec<NF> b = rec[j];
         const double dx = X - b.x, dy = Y - b.y;
         const double r2 = dx * dx + dy * dy;
         if (MIN) dmh = min(dmh, (unsigned)(__double_as_longlong(r2) >> 32));
-        s0 += (dx * b.z - dy * b.w) * inv_r2(r2);
+        const double rv = inv_r2(r2);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) s0[f] += (dx * b.ab[2 * f] - dy * b.ab[2 * f + 1]) * rv;
     }
     if (MIN) *dmin2 = __longlong_as_double((long long)((unsigned long long)dmh << 32));
-    return s0 + s1;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) sum[f] = s0[f] + s1[f];
 }
 
 // squared distance from (X, Y) to the nb-node polygon (wave-uniform chords
@@ -350,9 +376,11 @@ __device__ inline double poly_dist2(const double4* __restrict__ seg, const doubl
 // below by the larger of (that node distance - dsmax / 2) and (the distance to
 // the nb-node polygon - sag, sag bounding how far an arc leaves its chord);
 // bl[L cap ...], count bcnt[L].  Other points closer than h to a node go to cand.
+// NF fields: up and u hold them npts apart.
+template <int NF>
 __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls, const double* __restrict__ up,
-                                                 int nx, int ny, double x0, double y0, double h,
-                                                 const double4* __restrict__ rec, int nb, double dsmax,
+                                                 int nx, int ny, int64_t npts, double x0, double y0, double h,
+                                                 const DlRec<NF>* __restrict__ rec, int nb, double dsmax,
                                                  const double4* __restrict__ seg, const double* __restrict__ sinv,
                                                  double sag, double* __restrict__ u, int32_t* __restrict__ bl,
                                                  int64_t cap,
@@ -365,12 +393,15 @@ __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls,
     if (i >= nx || j >= ny) return;
     const int64_t e = (int64_t)i * ny + j;
     if (cls[e] != 1) {
-        u[e] = 0.0;
+#pragma unroll
+        for (int f = 0; f < NF; ++f) u[f * npts + e] = 0.0;
         return;
     }
     const double X = x0 + i * h, Y = y0 + j * h;
-    double d2;
-    u[e] = up[e] + dl_partial<true>(rec, 0, nb, X, Y, &d2) / nb;
+    double d2, sum[NF];
+    dl_partial<true, NF>(rec, 0, nb, X, Y, sum, &d2);
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u[f * npts + e] = up[f * npts + e] + sum[f] / nb;
     if (d2 < 49.0 * dsmax * dsmax) {
         const double dest = fmax(sqrt(d2) - 0.5 * dsmax, sqrt(poly_dist2(seg, sinv, nb, X, Y)) - sag);
         int L = kPoisLevels - 1;
@@ -389,13 +420,13 @@ __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls,
 // the listed points of one level (n = 2^L nb nodes), 64 per block, the nodes
 // split over the block's W waves and the partial sums added in wave order;
 // u = u_p + v, and points closer than h to a node of the level go to cand
-template <int W>
+template <int W, int NF>
 __global__ __launch_bounds__(64 * W) void k_dl_band(const int32_t* __restrict__ bl, const int* __restrict__ bcnt,
-                                                    const double* __restrict__ up, int ny, double x0, double y0,
-                                                    double h, const double4* __restrict__ rec, int n,
+                                                    const double* __restrict__ up, int ny, int64_t npts, double x0,
+                                                    double y0, double h, const DlRec<NF>* __restrict__ rec, int n,
                                                     double* __restrict__ u, int32_t* __restrict__ cand,
                                                     int* __restrict__ ncand) {
-    __shared__ double ps[W][64], pm[W][64];
+    __shared__ double ps[W][NF][64], pm[W][64];
     const int cnt = *bcnt;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
     const int j0 = (int)((int64_t)n * w / W), j1 = (int)((int64_t)n * (w + 1) / W);
@@ -403,17 +434,21 @@ __global__ __launch_bounds__(64 * W) void k_dl_band(const int32_t* __restrict__ 
         const int k = g * 64 + l;
         const int64_t e = bl[k < cnt ? k : g * 64];   // idle lanes repeat the group's first point
         const int i = (int)(e / ny), jj = (int)(e - (int64_t)i * ny);
-        double dm;
-        ps[w][l] = dl_partial<true>(rec, j0, j1, x0 + i * h, y0 + jj * h, &dm);
+        double dm, sum[NF];
+        dl_partial<true, NF>(rec, j0, j1, x0 + i * h, y0 + jj * h, sum, &dm);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ps[w][f][l] = sum[f];
         pm[w][l] = dm;
         __syncthreads();
         if (w == 0 && k < cnt) {
-            double s = 0.0, d2 = 1e300;
-            for (int q = 0; q < W; ++q) {
-                s += ps[q][l];
-                d2 = fmin(d2, pm[q][l]);
+            double d2 = 1e300;
+            for (int q = 0; q < W; ++q) d2 = fmin(d2, pm[q][l]);
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                double s = 0.0;
+                for (int q = 0; q < W; ++q) s += ps[q][f][l];
+                u[f * npts + e] = up[f * npts + e] + s / n;
             }
-            u[e] = up[e] + s / n;
             if (d2 < h * h) {
                 const int c = atomicAdd(ncand, 1);
                 cand[c] = (int32_t)e;
@@ -434,9 +469,10 @@ __device__ inline double wave_sum(double v) {
 // smallest index among equals), g_hom(theta) by the lanes, the degree-(M - 1)
 // Lagrange weights in the distance on the nodes s_m = m h / 2 at s = -eta,
 // and the M - 1 points P_m = foot + s_m (inward normal), m >= 1, whose sums
-// k_dl_samples forms.  Near point k: nidx[k], nw[k M + m], nv0[k] = g_hom(theta),
-// samp[k (M - 1) + m - 1] = P_m; count cnt[0], beyond capn counted in cnt[1].
-template <int M>
+// k_dl_samples forms.  Near point k: nidx[k], nw[k M + m], nv0[k NF + f] =
+// g_hom of field f at theta (ghom: NF rows of nb), samp[k (M - 1) + m - 1] = P_m;
+// count cnt[0], beyond capn counted in cnt[1].
+template <int M, int NF>
 __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ cand, const int* __restrict__ ncand,
                                                   CurveC cv, BndView bd, int maxit, int ny, double x0, double y0,
                                                   double h, const double* __restrict__ ghom, int nb, int capn,
@@ -470,20 +506,31 @@ __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ ca
             continue;
         }
         if (!(fabs(eta) < 0.5 * h)) continue;
-        // trigonometric interpolant of g_hom at theta
-        double sv = 0.0, hv = 0.0;
+        // trigonometric interpolant of each field's g_hom at theta
+        double sv[NF], hv[NF];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) sv[f] = hv[f] = 0.0;
         bool hit = false;
         for (int k = lane; k < nb; k += 64) {
             const double d = th - 2.0 * M_PI * (double)k / (double)nb;
             const double sh = sin(0.5 * d);
-            if (sh == 0.0) { hit = true; hv = ghom[k]; continue; }
+            if (sh == 0.0) {
+                hit = true;
+#pragma unroll
+                for (int f = 0; f < NF; ++f) hv[f] = ghom[f * nb + k];
+                continue;
+            }
             double w = sin(0.5 * nb * d) / (nb * sh);
             if ((nb & 1) == 0) w *= cos(0.5 * d);
-            sv += w * ghom[k];
+#pragma unroll
+            for (int f = 0; f < NF; ++f) sv[f] += w * ghom[f * nb + k];
         }
-        sv = wave_sum(sv);
         const double any = wave_sum(hit ? 1.0 : 0.0);
-        const double hs = wave_sum(hit ? hv : 0.0);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            sv[f] = wave_sum(sv[f]);
+            hv[f] = wave_sum(hit ? hv[f] : 0.0);
+        }
         int k = 0;
         if (lane == 0) k = atomicAdd(cnt, 1);
         k = __shfl(k, 0, 64);
@@ -499,7 +546,8 @@ __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ ca
             double w[M];
             equi_weights<M>(-eta / (0.5 * h), w);
             nidx[k] = (int32_t)idx;
-            nv0[k] = any > 0.0 ? hs : sv;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) nv0[(int64_t)k * NF + f] = any > 0.0 ? hv[f] : sv[f];
             for (int m = 0; m < M; ++m) nw[(int64_t)k * M + m] = w[m];
         }
         if (lane >= 1 && lane < M) {
@@ -511,44 +559,54 @@ __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ ca
 
 // double-layer sums at the listed sample points (count *nnear, at most capn,
 // times per), 64 per block with the n nodes split over the block's W waves
-// and the partials added in wave order; sval[k] = sum / n
-template <int W>
+// and the partials added in wave order; sval[k NF + f] = sum of field f / n
+template <int W, int NF>
 __global__ __launch_bounds__(64 * W) void k_dl_samples(const double2* __restrict__ samp,
                                                        const int* __restrict__ nnear, int capn, int per,
-                                                       const double4* __restrict__ rec, int n,
+                                                       const DlRec<NF>* __restrict__ rec, int n,
                                                        double* __restrict__ sval) {
-    __shared__ double ps[W][64];
+    __shared__ double ps[W][NF][64];
     const int cnt = min(*nnear, capn) * per;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
     const int j0 = (int)((int64_t)n * w / W), j1 = (int)((int64_t)n * (w + 1) / W);
     for (int g = blockIdx.x; g * 64 < cnt; g += gridDim.x) {
         const int k = g * 64 + l;
         const double2 P = samp[k < cnt ? k : g * 64];   // idle lanes repeat the group's first point
-        double dm;
-        ps[w][l] = dl_partial<false>(rec, j0, j1, P.x, P.y, &dm);
+        double dm, sum[NF];
+        dl_partial<false, NF>(rec, j0, j1, P.x, P.y, sum, &dm);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) ps[w][f][l] = sum[f];
         __syncthreads();
         if (w == 0 && k < cnt) {
-            double s = 0.0;
-            for (int q = 0; q < W; ++q) s += ps[q][l];
-            sval[k] = s / n;
+#pragma unroll
+            for (int f = 0; f < NF; ++f) {
+                double s = 0.0;
+                for (int q = 0; q < W; ++q) s += ps[q][f][l];
+                sval[(int64_t)k * NF + f] = s / n;
+            }
         }
         __syncthreads();
     }
 }
 
-// u = u_p + sum_m w_m v_m at the near points (v_0 = g_hom(theta), v_m the sums)
-template <int M>
+// u = u_p + sum_m w_m v_m at the near points (v_0 = g_hom(theta), v_m the sums),
+// per field (up and u hold the NF fields npts apart)
+template <int M, int NF>
 __global__ void k_near_fin(const int32_t* __restrict__ nidx, const int* __restrict__ nnear, int capn,
                            const double* __restrict__ nw, const double* __restrict__ nv0,
-                           const double* __restrict__ sval, const double* __restrict__ up, double* __restrict__ u) {
+                           const double* __restrict__ sval, const double* __restrict__ up, int64_t npts,
+                           double* __restrict__ u) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= min(*nnear, capn)) return;
     const double* w = nw + (int64_t)k * M;
-    const double* sv = sval + (int64_t)k * (M - 1);
-    double v = w[0] * nv0[k];
-    for (int m = 1; m < M; ++m) v += w[m] * sv[m - 1];
     const int64_t e = nidx[k];
-    u[e] = up[e] + v;
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        const double* sv = sval + (int64_t)k * (M - 1) * NF + f;
+        double v = w[0] * nv0[(int64_t)k * NF + f];
+        for (int m = 1; m < M; ++m) v += w[m] * sv[(int64_t)(m - 1) * NF];
+        u[f * npts + e] = up[f * npts + e] + v;
+    }
 }
 
 // ---- launchers -------------------------------------------------------------
@@ -630,70 +688,110 @@ int pois_axpbz(double a, const double* x, double b, const double* z, int n, doub
     return pois_check("k_axpbz", s);
 }
 
-int pois_records(const double* phi, int nb, const double* geo, double* wtab, double* phif, double* rec,
+int pois_records(const double* phi, int nb, int nfc, const double* geo, double* wtab, double* phif, double* rec,
                  hipStream_t s) {
     const int top = kPoisLevels - 1, R = 1 << top;
     k_trig_weights<<<(unsigned)(((int64_t)(R - 1) * nb + 255) / 256), 256, 0, s>>>(nb, R, wtab);
-    k_trig_conv<<<dim3((unsigned)((nb + 255) / 256), (unsigned)R), 256, 0, s>>>(phi, nb, R, wtab, phif);
+    for (int f = 0; f < nfc; ++f)
+        k_trig_conv<<<dim3((unsigned)((nb + 255) / 256), (unsigned)R), 256, 0, s>>>(
+            phi + (int64_t)f * nb, nb, R, wtab, phif + (int64_t)f * nb * R);
     int st = pois_check("k_trig_up", s);
     if (st) return st;
     const int64_t nall = (int64_t)nb * ((2 << top) - 1);
-    k_records<<<(unsigned)((nall + 255) / 256), 256, 0, s>>>((const double4*)geo, phif, nb, (double4*)rec);
+    const unsigned blk = (unsigned)((nall + 255) / 256);
+    switch (nfc) {
+        case 1: k_records<1><<<blk, 256, 0, s>>>((const double4*)geo, phif, nb, (DlRec<1>*)rec); break;
+        case 2: k_records<2><<<blk, 256, 0, s>>>((const double4*)geo, phif, nb, (DlRec<2>*)rec); break;
+        case 4: k_records<4><<<blk, 256, 0, s>>>((const double4*)geo, phif, nb, (DlRec<4>*)rec); break;
+        default: set_error("Poisson: unsupported field chunk"); return FC2D_E_ARG;
+    }
     return pois_check("k_records", s);
 }
 
-int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
-                 const double* seg, const double* sinv, double sag, double* u, int32_t* bl, int64_t cap, int* bcnt,
-                 int32_t* cand, int* ncand, hipStream_t s) {
+template <int NF>
+static int dl_grid_nf(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb,
+                      double dsmax, const double* seg, const double* sinv, double sag, double* u, int32_t* bl,
+                      int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s) {
     const int64_t tiles = (int64_t)((g->nx + 7) / 8) * ((g->ny + 7) / 8);
-    k_dl_grid<<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(cls, up, g->nx, g->ny, g->x0, g->y0, g->h,
-                                                          (const double4*)rec, nb, dsmax, (const double4*)seg, sinv,
-                                                          sag, u, bl, cap, bcnt, cand, ncand);
+    const int64_t npts = (int64_t)g->nx * g->ny;
+    const DlRec<NF>* r = (const DlRec<NF>*)rec;
+    k_dl_grid<NF><<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(cls, up, g->nx, g->ny, npts, g->x0, g->y0, g->h, r,
+                                                              nb, dsmax, (const double4*)seg, sinv, sag, u, bl, cap,
+                                                              bcnt, cand, ncand);
     int st = pois_check("k_dl_grid", s);
     // levels 1 .. kPoisLevels - 1, up to 16 waves per group of 64 points
     const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 63) / 64, 2048));
     for (int L = 1; L < kPoisLevels && !st; ++L) {
-        const int64_t off = (int64_t)nb * ((1 << L) - 1);
-        const double4* rl = (const double4*)rec + off;
+        const DlRec<NF>* rl = r + (int64_t)nb * ((1 << L) - 1);
         const int32_t* bll = bl + L * cap;
         switch (L) {
-            case 1: k_dl_band<2><<<nbk, 128, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-            case 2: k_dl_band<4><<<nbk, 256, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-            case 3: k_dl_band<8><<<nbk, 512, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-            default: k_dl_band<16><<<nbk, 1024, 0, s>>>(bll, bcnt + L, up, g->ny, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            case 1: k_dl_band<2, NF><<<nbk, 128, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            case 2: k_dl_band<4, NF><<<nbk, 256, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            case 3: k_dl_band<8, NF><<<nbk, 512, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
+            default: k_dl_band<16, NF><<<nbk, 1024, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
         }
         st = pois_check("k_dl_band", s);
     }
     return st;
 }
 
-int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
-                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
-                 int nbf, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
-                 int* ncnt, double* u, int* nfail, hipStream_t s) {
+int pois_dl_grid(const fc2d_grid* g, int nfc, const int8_t* cls, const double* up, const double* rec, int nb,
+                 double dsmax, const double* seg, const double* sinv, double sag, double* u, int32_t* bl,
+                 int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s) {
+    switch (nfc) {
+        case 1: return dl_grid_nf<1>(g, cls, up, rec, nb, dsmax, seg, sinv, sag, u, bl, cap, bcnt, cand, ncand, s);
+        case 2: return dl_grid_nf<2>(g, cls, up, rec, nb, dsmax, seg, sinv, sag, u, bl, cap, bcnt, cand, ncand, s);
+        case 4: return dl_grid_nf<4>(g, cls, up, rec, nb, dsmax, seg, sinv, sag, u, bl, cap, bcnt, cand, ncand, s);
+        default: set_error("Poisson: unsupported field chunk"); return FC2D_E_ARG;
+    }
+}
+
+template <int M, int NF>
+static int dl_near_mnf(const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
+                       int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
+                       const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp,
+                       double* sval, int* ncnt, double* u, int* nfail, hipStream_t s) {
+    const int top = kPoisLevels - 1;
+    const int64_t npts = (int64_t)g->nx * g->ny;
+    const DlRec<NF>* recf = (const DlRec<NF>*)rec + (int64_t)nb * ((1 << top) - 1);   // finest level
     const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, 16384));
+    k_near_prep<M, NF><<<nbk, 64, 0, s>>>(cand, ncand, cv, bd, maxit, g->ny, g->x0, g->y0, g->h, ghom, nb, capn,
+                                          nidx, nw, nv0, (double2*)samp, ncnt, nfail);
+    int st = pois_check("k_near_prep", s);
+    if (st) return st;
+    const unsigned sbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((int64_t)capn * (M - 1) + 63) / 64, 2048));
+    k_dl_samples<16, NF><<<sbk, 1024, 0, s>>>((const double2*)samp, ncnt, capn, M - 1, recf, nb << top, sval);
+    if ((st = pois_check("k_dl_samples", s))) return st;
+    const unsigned fbk = (unsigned)std::max(1, (capn + 255) / 256);
+    k_near_fin<M, NF><<<fbk, 256, 0, s>>>(nidx, ncnt, capn, nw, nv0, sval, up, npts, u);
+    return pois_check("k_near_fin", s);
+}
+
+template <int M>
+static int dl_near_m(int nfc, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv,
+                     const BndView& bd, int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
+                     const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp,
+                     double* sval, int* ncnt, double* u, int* nfail, hipStream_t s) {
+    switch (nfc) {
+        case 1: return dl_near_mnf<M, 1>(cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, nv0, samp, sval, ncnt, u, nfail, s);
+        case 2: return dl_near_mnf<M, 2>(cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, nv0, samp, sval, ncnt, u, nfail, s);
+        case 4: return dl_near_mnf<M, 4>(cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, nv0, samp, sval, ncnt, u, nfail, s);
+        default: set_error("Poisson: unsupported field chunk"); return FC2D_E_ARG;
+    }
+}
+
+int pois_dl_near(int M, int nfc, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv,
+                 const BndView& bd, int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
+                 const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
+                 int* ncnt, double* u, int* nfail, hipStream_t s) {
     switch (M) {
 #define FC2D_NEAR(MM) \
-        case MM: k_near_prep<MM><<<nbk, 64, 0, s>>>(cand, ncand, cv, bd, maxit, g->ny, g->x0, g->y0, g->h, ghom, nb, \
-                                                    capn, nidx, nw, nv0, (double2*)samp, ncnt, nfail); break;
+        case MM: return dl_near_m<MM>(nfc, cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, \
+                                      nv0, samp, sval, ncnt, u, nfail, s);
         FC2D_NEAR(4) FC2D_NEAR(5) FC2D_NEAR(6) FC2D_NEAR(7) FC2D_NEAR(8) FC2D_NEAR(13) FC2D_NEAR(15)
 #undef FC2D_NEAR
         default: set_error("unsupported M"); return FC2D_E_ARG;
     }
-    int st = pois_check("k_near_prep", s);
-    if (st) return st;
-    const unsigned sbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((int64_t)capn * (M - 1) + 63) / 64, 2048));
-    k_dl_samples<16><<<sbk, 1024, 0, s>>>((const double2*)samp, ncnt, capn, M - 1, (const double4*)recf, nbf, sval);
-    if ((st = pois_check("k_dl_samples", s))) return st;
-    const unsigned fbk = (unsigned)std::max(1, (capn + 255) / 256);
-    switch (M) {
-#define FC2D_FIN(MM) \
-        case MM: k_near_fin<MM><<<fbk, 256, 0, s>>>(nidx, ncnt, capn, nw, nv0, sval, up, u); break;
-        FC2D_FIN(4) FC2D_FIN(5) FC2D_FIN(6) FC2D_FIN(7) FC2D_FIN(8) FC2D_FIN(13) FC2D_FIN(15)
-#undef FC2D_FIN
-        default: break;
-    }
-    return pois_check("k_near_fin", s);
 }
 
 }  // namespace fc2d

@@ -211,6 +211,7 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     const int capn = (int)std::min<double>((double)std::max<int64_t>(pl->n_in, 1), ceil(4.0 * perim / g.h) + 64.0);
     const int64_t nall = (int64_t)nb * (2 * kRefine - 1);   // nodes of all levels
     const int64_t cap = std::max<int64_t>(pl->n_in, 1);
+    const int nfm = std::min(nf, kPoisChunk);   // fields per chunk at most
     double *spec, *work, *up, *mean, *d_qc, *d_geo, *rec, *ghom, *rhs, *A, *phi, *phif, *wtab, *part, *V, *w, *hd;
     double *bx, *by, *bnx, *bny;
     int8_t* cls;
@@ -219,19 +220,19 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     PoisArena db;
     db.add(&spec, (size_t)g.nx * (g.ny / 2 + 1) * 2);
     db.add(&work, (size_t)npts);
-    db.add(&up, (size_t)npts);
+    db.add(&up, (size_t)npts * nfm);
     db.add(&mean, 1);
     db.add(&d_qc, 6 * (size_t)nb);
     db.add(&d_geo, 4 * (size_t)nall);
-    db.add(&rec, 4 * (size_t)nall);
+    db.add(&rec, (2 + 2 * (size_t)nfm) * nall);
     double *seg, *sinv;
     db.add(&seg, 4 * (size_t)nb);
     db.add(&sinv, nb);
-    db.add(&ghom, nb);
+    db.add(&ghom, (size_t)nb * nfm);
     db.add(&rhs, nb);
     db.add(&A, (size_t)nb * nb);
-    db.add(&phi, nb);
-    db.add(&phif, (size_t)nbf);
+    db.add(&phi, (size_t)nb * nfm);
+    db.add(&phif, (size_t)nbf * nfm);
     db.add(&wtab, (size_t)nbf);   // (kRefine - 1) nb weights
     db.add(&part, (size_t)pois_matvec_splits(nb) * nb);
     db.add(&V, (size_t)(m + 1) * nb);
@@ -244,9 +245,9 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     double *nw, *nv0, *samp, *sval;
     db.add(&nidx, capn);
     db.add(&nw, (size_t)capn * M);
-    db.add(&nv0, capn);
+    db.add(&nv0, (size_t)capn * nfm);
     db.add(&samp, (size_t)capn * (M - 1) * 2);
-    db.add(&sval, (size_t)capn * (M - 1));
+    db.add(&sval, (size_t)capn * (M - 1) * nfm);
     db.add(&bl, (size_t)cap * kPoisLevels);
     db.add(&bx, pl->B);
     db.add(&by, pl->B);
@@ -269,30 +270,39 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     const BndView bd{bx, by, bnx, bny, pl->B, pl->k2};
     if ((st = pois_nystrom(d_qc, nb, A, s))) return st;
     int iters_total = 0;
-    for (int f = 0; f < nf; ++f) {
-        double* uf = u + (int64_t)f * npts;
-        // particular solution: extension + R2C, -1/|k|^2, C2R, mean term
-        if ((st = fc2d_extend_fft(pl, f_grid + (int64_t)f * npts, f_bdry ? f_bdry + (int64_t)f * nbdry : f_bdry, work, spec, 1, s)))
-            return st;
-        if ((st = pois_mean(&g, spec, mean, s))) return st;
-        if ((st = spectral_apply(&g, FC2D_LAPLACE_INV, spec, spec, 1, s))) return st;
-        if ((st = fft2_c2r(&g, spec, up, 1, s))) return st;
-        if ((st = pois_add_quad(&g, mean, up, s))) return st;
-        // boundary data of the harmonic part and its density
-        if ((st = pois_ghom(M, &g, up, d_qc, nb, g_nodes + (int64_t)f * nb, ghom, s))) return st;
-        if ((st = pois_axpbz(-2.0, ghom, 0.0, ghom, nb, rhs, s))) return st;
-        int it = 0;
-        if ((st = gmres(A, rhs, phi, nb, V, w, hd, part, s, &it))) return st;
-        iters_total += it;
-        if ((st = pois_records(phi, nb, d_geo, wtab, phif, rec, s))) return st;
+    // chunks of 4, 2 or 1 fields: the particular solution, boundary data and
+    // density of each field, then the double-layer sums of the chunk together
+    for (int f0 = 0; f0 < nf;) {
+        const int nfc = nf - f0 >= 4 ? 4 : (nf - f0 >= 2 ? 2 : 1);
+        for (int c = 0; c < nfc; ++c) {
+            const int f = f0 + c;
+            double* upc = up + (int64_t)c * npts;
+            double* ghc = ghom + (int64_t)c * nb;
+            // particular solution: extension + R2C, -1/|k|^2, C2R, mean term
+            if ((st = fc2d_extend_fft(pl, f_grid + (int64_t)f * npts, f_bdry ? f_bdry + (int64_t)f * nbdry : f_bdry,
+                                      work, spec, 1, s)))
+                return st;
+            if ((st = pois_mean(&g, spec, mean, s))) return st;
+            if ((st = spectral_apply(&g, FC2D_LAPLACE_INV, spec, spec, 1, s))) return st;
+            if ((st = fft2_c2r(&g, spec, upc, 1, s))) return st;
+            if ((st = pois_add_quad(&g, mean, upc, s))) return st;
+            // boundary data of the harmonic part and its density
+            if ((st = pois_ghom(M, &g, upc, d_qc, nb, g_nodes + (int64_t)f * nb, ghc, s))) return st;
+            if ((st = pois_axpbz(-2.0, ghc, 0.0, ghc, nb, rhs, s))) return st;
+            int it = 0;
+            if ((st = gmres(A, rhs, phi + (int64_t)c * nb, nb, V, w, hd, part, s, &it))) return st;
+            iters_total += it;
+        }
+        if ((st = pois_records(phi, nb, nfc, d_geo, wtab, phif, rec, s))) return st;
         // v on the grid, then the points next to Gamma
+        double* uc = u + (int64_t)f0 * npts;
         if ((e = hipMemsetAsync(cnt, 0, (4 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
             return hip_err(e, "Poisson solve");
-        if ((st = pois_dl_grid(&g, cls, up, rec, nb, dsmax, seg, sinv, sag, uf, bl, cap, cnt + 2, cand, cnt, s))) return st;
-        const int64_t top = (int64_t)nb * (kRefine - 1);
+        if ((st = pois_dl_grid(&g, nfc, cls, up, rec, nb, dsmax, seg, sinv, sag, uc, bl, cap, cnt + 2, cand, cnt, s)))
+            return st;
         int* ncnt = cnt + 2 + kPoisLevels;
-        if ((st = pois_dl_near(M, cand, cnt, cap, pl->curve, bd, 60, &g, up, ghom, nb, rec + 4 * top, nbf, capn,
-                               nidx, nw, nv0, samp, sval, ncnt, uf, cnt + 1, s)))
+        if ((st = pois_dl_near(M, nfc, cand, cnt, cap, pl->curve, bd, 60, &g, up, ghom, nb, rec, capn, nidx, nw, nv0,
+                               samp, sval, ncnt, uc, cnt + 1, s)))
             return st;
         int hc[4 + kPoisLevels] = {};
         if ((e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess ||
@@ -306,6 +316,7 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
             set_error("Poisson solve: more points next to the boundary than the bound allows");
             return FC2D_E_HIP;
         }
+        f0 += nfc;
     }
     if (gmres_iters) *gmres_iters = iters_total;
     return FC2D_OK;

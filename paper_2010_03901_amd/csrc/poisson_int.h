@@ -28,25 +28,30 @@ int pois_axpbz(double a, const double* x, double b, const double* z, int n, doub
 // Levels of the double-layer sums: level L (0 <= L < kPoisLevels) holds 2^L nb
 // equispaced nodes at offset nb (2^L - 1) of the concatenated node arrays.
 constexpr int kPoisLevels = 6;
-// phi on the nb nodes -> phif (finest level, by the Dirichlet kernel) -> node
-// records rec (x, y, phi y', phi x') of every level; geo: (x, y, x', y') per
+// Fields are handled in chunks of nfc = 1, 2 or 4 (kPoisChunk at most) that
+// share the geometry work of the double-layer sums.
+constexpr int kPoisChunk = 4;
+// phi (nfc rows of nb) -> phif (nfc rows of 2^(kPoisLevels - 1) nb, the finest
+// level, by the Dirichlet kernel) -> node records of every level: (x, y) and
+// per field (phi y', phi x'), 2 + 2 nfc doubles each; geo: (x, y, x', y') per
 // node; wtab: scratch of (2^(kPoisLevels - 1) - 1) nb doubles
-int pois_records(const double* phi, int nb, const double* geo, double* wtab, double* phif, double* rec,
+int pois_records(const double* phi, int nb, int nfc, const double* geo, double* wtab, double* phif, double* rec,
                  hipStream_t s);
-// v at the IN points (u = u_p + v, 0 elsewhere); points next to Gamma listed in
-// cand.  bl: kPoisLevels lists of cap entries (cap >= IN points), bcnt their
-// counts (zero on entry), both scratch; sag: bound on how far an arc between two
-// nodes leaves its chord
-int pois_dl_grid(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb, double dsmax,
-                 const double* seg, const double* sinv, double sag, double* u, int32_t* bl, int64_t cap, int* bcnt,
-                 int32_t* cand, int* ncand, hipStream_t s);
-// the listed points within h/2 of Gamma; recf: finest-level records (nbf nodes).
-// Scratch for up to capn such points: nidx [capn], nw [capn M], nv0 [capn],
-// samp [capn (M - 1)] point pairs, sval [capn (M - 1)]; ncnt[0] counts them
+// v at the IN points of nfc fields (u = u_p + v, 0 elsewhere; up and u hold
+// the fields nx ny apart); points next to Gamma listed in cand.  bl:
+// kPoisLevels lists of cap entries (cap >= IN points), bcnt their counts (zero
+// on entry), both scratch; sag: bound on how far an arc between two nodes
+// leaves its chord
+int pois_dl_grid(const fc2d_grid* g, int nfc, const int8_t* cls, const double* up, const double* rec, int nb,
+                 double dsmax, const double* seg, const double* sinv, double sag, double* u, int32_t* bl,
+                 int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s);
+// the listed points within h/2 of Gamma, nfc fields (ghom: nfc rows of nb).
+// Scratch for up to capn such points: nidx [capn], nw [capn M], nv0 [capn nfc],
+// samp [capn (M - 1)] point pairs, sval [capn (M - 1) nfc]; ncnt[0] counts them
 // and ncnt[1] those beyond capn (both zero on entry).
-int pois_dl_near(int M, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
-                 int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb, const double* recf,
-                 int nbf, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
+int pois_dl_near(int M, int nfc, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv,
+                 const BndView& bd, int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
+                 const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
                  int* ncnt, double* u, int* nfail, hipStream_t s);
 
 }  // namespace fc2d

@@ -245,3 +245,26 @@ def test_poisson_full_size_sampled(torch_mod):
     ex = _u_exact(X.ravel()[sample], Y.ravel()[sample])
     print("[poisson] full size: rel err vs oracle %.2e (vs exact %.2e)" % (e, np.abs(ref - ex).max() / np.abs(ex).max()))
     assert e < 1e-11
+
+
+def test_poisson_field_chunks(torch_mod):
+    """Seven fields in one call (chunks of 4, 2 and 1 fields sharing the
+    double-layer geometry work) against each field solved alone (1e-13 of
+    max |u|; the per-field sums take the same nodes in the same order, only
+    the unrolling differs)."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    h, n, d, M, nb = 0.04, 128, 4, 7, 128
+    ks = [1.0, 1.5, 2.0, 2.5, 3.0, 0.5, 1.25]
+    fs = [(lambda k: (lambda x, y: -2 * (k * np.pi) ** 2 * np.sin(k * np.pi * x) * np.sin(k * np.pi * y)))(k)
+          for k in ks]
+    gs = [(lambda k: (lambda x, y: np.sin(k * np.pi * x) * np.sin(k * np.pi * y)))(k) for k in ks]
+    u_all, pl, it_all, X, Y = _gpu(torch, h, n, d, M, fs, gs, nb)
+    for k in range(len(ks)):
+        u1, _, _, _, _ = _gpu(torch, h, n, d, M, [fs[k]], [gs[k]], nb)
+        e = rel_err(u_all[k], u1[0])
+        ins = fc2d.fc2d_plan_classes(pl) == OP.IN
+        ex = gs[k](X, Y)[ins]
+        print("\n[poisson] chunked field %d: vs alone %.1e, vs exact %.1e"
+              % (k, e, np.linalg.norm(u_all[k][ins] - ex) / np.linalg.norm(ex)), end="")
+        assert e < 1e-13

@@ -120,20 +120,34 @@ __global__ void k_nystrom(const double* __restrict__ qd, int nb, double* __restr
 // ---- GMRES building blocks (vectors of length n; V holds basis vectors of stride n)
 // part[c n + i] = sum over the columns k of split c of A[k n + i] x[k]
 // (A column-major; grid: row blocks of 256 x column splits)
+// (NF right-hand sides x_f at stride xs; A read once for all of them:
+// part[(c NF + f) n + i])
+template <int NF>
 __global__ __launch_bounds__(256) void k_matvec_part(const double* __restrict__ A, const double* __restrict__ x,
-                                                     int n, int splits, double* __restrict__ part) {
+                                                     int64_t xs, int n, int splits, double* __restrict__ part) {
     const int i = blockIdx.x * 256 + threadIdx.x;
     const int c = blockIdx.y;
     const int k0 = (int)((int64_t)n * c / splits), k1 = (int)((int64_t)n * (c + 1) / splits);
     if (i >= n) return;
-    double s0 = 0.0, s1 = 0.0;
+    double s0[NF], s1[NF];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) s0[f] = s1[f] = 0.0;
     int k = k0;
     for (; k + 2 <= k1; k += 2) {
-        s0 += A[(int64_t)k * n + i] * x[k];
-        s1 += A[(int64_t)(k + 1) * n + i] * x[k + 1];
+        const double a0 = A[(int64_t)k * n + i], a1 = A[(int64_t)(k + 1) * n + i];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            s0[f] += a0 * x[f * xs + k];
+            s1[f] += a1 * x[f * xs + k + 1];
+        }
     }
-    if (k < k1) s0 += A[(int64_t)k * n + i] * x[k];
-    part[(int64_t)c * n + i] = s0 + s1;
+    if (k < k1) {
+        const double a0 = A[(int64_t)k * n + i];
+#pragma unroll
+        for (int f = 0; f < NF; ++f) s0[f] += a0 * x[f * xs + k];
+    }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) part[((int64_t)c * NF + f) * n + i] = s0[f] + s1[f];
 }
 
 // y[i] = sum of the splits' partial sums: block of 32 rows x 8 groups, group
@@ -155,12 +169,17 @@ __global__ __launch_bounds__(256) void k_matvec_sum(const double* __restrict__ p
     }
 }
 
-// out[b] = <V_b, w> for b < nv (one block per vector)
-__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int nv, const double* __restrict__ w,
-                                              int n, double* __restrict__ out) {
+// out[b] = <V_b, w> for b < nv (one block per vector); field blockIdx.y takes
+// V, w and out at its strides
+__global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int64_t vs, int nv,
+                                              const double* __restrict__ w, int64_t ws, int n,
+                                              double* __restrict__ out, int64_t os) {
     __shared__ double red[256];
     const int b = blockIdx.x;
     if (b >= nv) return;
+    V += vs * blockIdx.y;
+    w += ws * blockIdx.y;
+    out += os * blockIdx.y;
     double s = 0.0;
     for (int i = threadIdx.x; i < n; i += 256) s += V[(int64_t)b * n + i] * w[i];
     red[threadIdx.x] = s;
@@ -172,14 +191,27 @@ __global__ __launch_bounds__(256) void k_dots(const double* __restrict__ V, int 
     if (threadIdx.x == 0) out[b] = red[0];
 }
 
-// w -= sum_b c[b] V_b, b < nv
-__global__ void k_sub(const double* __restrict__ V, int nv, const double* __restrict__ c, int n,
-                      double* __restrict__ w) {
+// w -= sum_b c[b] V_b, b < nv; field blockIdx.y at its strides
+__global__ void k_sub(const double* __restrict__ V, int64_t vs, int nv, const double* __restrict__ c, int64_t cs,
+                      int n, double* __restrict__ w, int64_t ws) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    V += vs * blockIdx.y;
+    c += cs * blockIdx.y;
+    w += ws * blockIdx.y;
     double s = w[i];
     for (int b = 0; b < nv; ++b) s -= c[b] * V[(int64_t)b * n + i];
     w[i] = s;
+}
+
+// y_f = a_f x_f for the fields f = blockIdx.y (at most kPoisChunk)
+struct Scal4 {
+    double a[kPoisChunk];
+};
+__global__ void k_scale(Scal4 a, const double* __restrict__ x, int64_t xs, int n, double* __restrict__ y,
+                        int64_t ys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[ys * blockIdx.y + i] = a.a[blockIdx.y] * x[xs * blockIdx.y + i];
 }
 
 // y = a x + b z
@@ -666,21 +698,39 @@ int pois_nystrom(const double* qd, int nb, double* A, hipStream_t s) {
 
 int pois_matvec_splits(int n) { return std::max(1, std::min(64, n / 32)); }
 
-int pois_matvec(const double* A, const double* x, int n, double* part, double* y, hipStream_t s) {
+int pois_matvec(const double* A, const double* x, int64_t xs, int n, int nfc, double* part, double* y,
+                hipStream_t s) {
     const int sp = pois_matvec_splits(n);
-    k_matvec_part<<<dim3((unsigned)((n + 255) / 256), (unsigned)sp), 256, 0, s>>>(A, x, n, sp, part);
-    k_matvec_sum<<<(unsigned)((n + 31) / 32), 256, 0, s>>>(part, n, sp, y);
+    const dim3 grid((unsigned)((n + 255) / 256), (unsigned)sp);
+    switch (nfc) {
+        case 1: k_matvec_part<1><<<grid, 256, 0, s>>>(A, x, xs, n, sp, part); break;
+        case 2: k_matvec_part<2><<<grid, 256, 0, s>>>(A, x, xs, n, sp, part); break;
+        case 4: k_matvec_part<4><<<grid, 256, 0, s>>>(A, x, xs, n, sp, part); break;
+        default: set_error("Poisson: unsupported field chunk"); return FC2D_E_ARG;
+    }
+    // the splits' partials of the nfc outputs: one sum over nfc n entries (y holds them n apart)
+    k_matvec_sum<<<(unsigned)(((int64_t)nfc * n + 31) / 32), 256, 0, s>>>(part, nfc * n, sp, y);
     return pois_check("k_matvec", s);
 }
 
-int pois_dots(const double* V, int nv, const double* w, int n, double* out, hipStream_t s) {
-    k_dots<<<(unsigned)nv, 256, 0, s>>>(V, nv, w, n, out);
+int pois_dots(const double* V, int64_t vs, int nv, const double* w, int64_t ws, int n, int nfc, double* out,
+              int64_t os, hipStream_t s) {
+    k_dots<<<dim3((unsigned)nv, (unsigned)nfc), 256, 0, s>>>(V, vs, nv, w, ws, n, out, os);
     return pois_check("k_dots", s);
 }
 
-int pois_sub(const double* V, int nv, const double* c, int n, double* w, hipStream_t s) {
-    k_sub<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(V, nv, c, n, w);
+int pois_sub(const double* V, int64_t vs, int nv, const double* c, int64_t cs, int n, int nfc, double* w,
+             int64_t ws, hipStream_t s) {
+    k_sub<<<dim3((unsigned)((n + 255) / 256), (unsigned)nfc), 256, 0, s>>>(V, vs, nv, c, cs, n, w, ws);
     return pois_check("k_sub", s);
+}
+
+int pois_scale(const double* a, const double* x, int64_t xs, int n, int nfc, double* y, int64_t ys,
+               hipStream_t s) {
+    Scal4 sc{};
+    for (int f = 0; f < nfc && f < kPoisChunk; ++f) sc.a[f] = a[f];
+    k_scale<<<dim3((unsigned)((n + 255) / 256), (unsigned)nfc), 256, 0, s>>>(sc, x, xs, n, y, ys);
+    return pois_check("k_axpbz", s);
 }
 
 int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s) {

@@ -60,95 +60,137 @@ int hip_err(hipError_t e, const char* what) {
     return FC2D_E_HIP;
 }
 
-// Restarted GMRES with classical Gram-Schmidt applied twice; A column-major
-// n x n (device), b and x device vectors; x starts at zero.
-int gmres(const double* A, const double* b, double* x, int n, double* V, double* w, double* hd, double* part,
-          hipStream_t s, int* iters) {
+// Restarted GMRES with classical Gram-Schmidt applied twice, for nfc systems
+// A x_f = b_f at once (A column-major n x n on the device, read once per
+// iteration for all of them; b and x hold the fields n apart; x starts at
+// zero).  The Hessenberg columns come to the host, one copy and one
+// synchronisation per iteration for all fields; a field that has converged
+// keeps zero basis vectors until the others finish.  V: nfc (m + 1) n, w: nfc n,
+// hd: nfc (3 (m + 2) + m) device doubles; iters: iterations summed over fields.
+int gmres(const double* A, const double* b, double* x, int n, int nfc, double* V, double* w, double* hd,
+          double* part, hipStream_t s, int* iters) {
     const int m = std::min(n, kRestart);
-    std::vector<double> H((size_t)(m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), hh(2 * (m + 1) + 1);
-    double* h1 = hd;                 // [m + 1]
-    double* h2 = hd + (m + 1);       // [m + 1]
-    double* nrm = hd + 2 * (m + 1);  // [1]
-    double* ydev = hd + 2 * (m + 1) + 1;
+    const int64_t VS = (int64_t)(m + 1) * n;                 // basis stride per field
+    const int64_t HS = 3 * (int64_t)(m + 2) + m;             // h1 [m + 1], h2 [m + 1], norm, y [m]
+    const int64_t o2 = m + 1, on = 2 * (m + 1), oy = 2 * (m + 1) + 1;
+    std::vector<double> H((size_t)nfc * (m + 1) * m), cs((size_t)nfc * m), sn((size_t)nfc * m),
+        g((size_t)nfc * (m + 1)), hh((size_t)nfc * HS), bnorm(nfc), beta(nfc), scal(nfc);
+    std::vector<int> k(nfc, 0);
+    std::vector<char> done(nfc, 0), act(nfc, 0), conv(nfc, 0);
     int st;
     hipError_t e;
-    if ((e = hipMemsetAsync(x, 0, n * sizeof(double), s)) != hipSuccess) return hip_err(e, "gmres");
-    double bnorm = 0.0;
-    if ((st = pois_dots(b, 1, b, n, nrm, s))) return st;
-    if ((e = hipMemcpyAsync(&bnorm, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
-        (e = hipStreamSynchronize(s)) != hipSuccess)
-        return hip_err(e, "gmres");
-    bnorm = sqrt(bnorm);
     *iters = 0;
-    if (bnorm == 0.0) return FC2D_OK;
-    // r = b (x = 0)
-    double beta = bnorm;
-    if ((st = pois_axpbz(1.0 / beta, b, 0.0, b, n, V, s))) return st;
-    for (int rs = 0; rs < kMaxRestarts; ++rs) {
-        std::fill(g.begin(), g.end(), 0.0);
-        g[0] = beta;
-        int k = 0;
-        bool done = false;
-        for (int j = 0; j < m; ++j) {
-            double* vj1 = V + (size_t)(j + 1) * n;
-            if ((st = pois_matvec(A, V + (size_t)j * n, n, part, w, s))) return st;
-            if ((st = pois_dots(V, j + 1, w, n, h1, s))) return st;
-            if ((st = pois_sub(V, j + 1, h1, n, w, s))) return st;
-            if ((st = pois_dots(V, j + 1, w, n, h2, s))) return st;
-            if ((st = pois_sub(V, j + 1, h2, n, w, s))) return st;
-            if ((st = pois_dots(w, 1, w, n, nrm, s))) return st;
-            // h1, h2 and the norm are contiguous: one copy
-            if ((e = hipMemcpyAsync(hh.data(), hd, (2 * (m + 1) + 1) * sizeof(double), hipMemcpyDeviceToHost, s)) !=
-                    hipSuccess ||
-                (e = hipStreamSynchronize(s)) != hipSuccess)
-                return hip_err(e, "gmres");
-            const double hn2 = hh[2 * (m + 1)];
-            const double hn = sqrt(hn2);
-            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = hh[i] + hh[(m + 1) + i];
-            H[(size_t)(j + 1) * m + j] = hn;
-            for (int i = 0; i < j; ++i) {   // previous rotations
-                const double a = H[(size_t)i * m + j], c = H[(size_t)(i + 1) * m + j];
-                H[(size_t)i * m + j] = cs[i] * a + sn[i] * c;
-                H[(size_t)(i + 1) * m + j] = -sn[i] * a + cs[i] * c;
-            }
-            const double a = H[(size_t)j * m + j], c = H[(size_t)(j + 1) * m + j];
-            const double r = hypot(a, c);
-            cs[j] = r > 0 ? a / r : 1.0;
-            sn[j] = r > 0 ? c / r : 0.0;
-            H[(size_t)j * m + j] = r;
-            H[(size_t)(j + 1) * m + j] = 0.0;
-            g[j + 1] = -sn[j] * g[j];
-            g[j] = cs[j] * g[j];
-            k = j + 1;
-            ++*iters;
-            if (fabs(g[j + 1]) <= kGmresTol * bnorm || hn == 0.0) {
-                done = true;
-                break;
-            }
-            if ((st = pois_axpbz(1.0 / hn, w, 0.0, w, n, vj1, s))) return st;
-        }
-        // y = H(0:k, 0:k)^-1 g, x += V y  (as x -= sum (-y_i) V_i)
-        for (int i = k - 1; i >= 0; --i) {
-            double t = g[i];
-            for (int l = i + 1; l < k; ++l) t -= H[(size_t)i * m + l] * y[l];
-            y[i] = t / H[(size_t)i * m + i];
-        }
-        for (int i = 0; i < k; ++i) y[i] = -y[i];
-        if ((e = hipMemcpyAsync(ydev, y.data(), k * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
-            return hip_err(e, "gmres");
-        if ((st = pois_sub(V, k, ydev, n, x, s))) return st;
-        if (done) return FC2D_OK;
-        // restart from the true residual r = b - A x
-        if ((st = pois_matvec(A, x, n, part, w, s))) return st;
-        if ((st = pois_axpbz(1.0, b, -1.0, w, n, w, s))) return st;
-        if ((st = pois_dots(w, 1, w, n, nrm, s))) return st;
-        double r2 = 0.0;
-        if ((e = hipMemcpyAsync(&r2, nrm, sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+    if ((e = hipMemsetAsync(x, 0, (size_t)nfc * n * sizeof(double), s)) != hipSuccess) return hip_err(e, "gmres");
+    auto fetch = [&]() -> int {
+        if ((e = hipMemcpyAsync(hh.data(), hd, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return hip_err(e, "gmres");
-        beta = sqrt(r2);
-        if (beta <= kGmresTol * bnorm) return FC2D_OK;
-        if ((st = pois_axpbz(1.0 / beta, w, 0.0, w, n, V, s))) return st;
+        return FC2D_OK;
+    };
+    if ((st = pois_dots(b, n, 1, b, n, n, nfc, hd + on, HS, s)) || (st = fetch())) return st;
+    bool all = true;
+    for (int f = 0; f < nfc; ++f) {
+        bnorm[f] = beta[f] = sqrt(hh[f * HS + on]);
+        done[f] = bnorm[f] == 0.0;
+        scal[f] = done[f] ? 0.0 : 1.0 / beta[f];
+        all = all && done[f];
+    }
+    if (all) return FC2D_OK;
+    if ((st = pois_scale(scal.data(), b, n, n, nfc, V, VS, s))) return st;   // V_f,0 = b_f / |b_f|
+    for (int rs = 0; rs < kMaxRestarts; ++rs) {
+        for (int f = 0; f < nfc; ++f) {
+            std::fill(g.begin() + (size_t)f * (m + 1), g.begin() + (size_t)(f + 1) * (m + 1), 0.0);
+            g[(size_t)f * (m + 1)] = beta[f];
+            k[f] = 0;
+            act[f] = !done[f];
+            conv[f] = 0;
+        }
+        int kmax = 0;
+        for (int j = 0; j < m; ++j) {
+            if ((st = pois_matvec(A, V + (size_t)j * n, VS, n, nfc, part, w, s)) ||
+                (st = pois_dots(V, VS, j + 1, w, n, n, nfc, hd, HS, s)) ||
+                (st = pois_sub(V, VS, j + 1, hd, HS, n, nfc, w, n, s)) ||
+                (st = pois_dots(V, VS, j + 1, w, n, n, nfc, hd + o2, HS, s)) ||
+                (st = pois_sub(V, VS, j + 1, hd + o2, HS, n, nfc, w, n, s)) ||
+                (st = pois_dots(w, n, 1, w, n, n, nfc, hd + on, HS, s)) || (st = fetch()))
+                return st;
+            bool any = false;
+            for (int f = 0; f < nfc; ++f) {
+                scal[f] = 0.0;
+                if (!act[f]) continue;
+                double* Hf = &H[(size_t)f * (m + 1) * m];
+                double* csf = &cs[(size_t)f * m];
+                double* snf = &sn[(size_t)f * m];
+                double* gf = &g[(size_t)f * (m + 1)];
+                const double* hf = &hh[(size_t)f * HS];
+                const double hn = sqrt(hf[on]);
+                for (int i = 0; i <= j; ++i) Hf[(size_t)i * m + j] = hf[i] + hf[o2 + i];
+                Hf[(size_t)(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {   // previous rotations
+                    const double a = Hf[(size_t)i * m + j], c = Hf[(size_t)(i + 1) * m + j];
+                    Hf[(size_t)i * m + j] = csf[i] * a + snf[i] * c;
+                    Hf[(size_t)(i + 1) * m + j] = -snf[i] * a + csf[i] * c;
+                }
+                const double a = Hf[(size_t)j * m + j], c = Hf[(size_t)(j + 1) * m + j];
+                const double r = hypot(a, c);
+                csf[j] = r > 0 ? a / r : 1.0;
+                snf[j] = r > 0 ? c / r : 0.0;
+                Hf[(size_t)j * m + j] = r;
+                Hf[(size_t)(j + 1) * m + j] = 0.0;
+                gf[j + 1] = -snf[j] * gf[j];
+                gf[j] = csf[j] * gf[j];
+                k[f] = j + 1;
+                ++*iters;
+                if (fabs(gf[j + 1]) <= kGmresTol * bnorm[f] || hn == 0.0) {
+                    act[f] = 0;   // converged (or an exact breakdown): this cycle ends for f
+                    conv[f] = 1;
+                } else {
+                    scal[f] = 1.0 / hn;
+                    any = true;
+                }
+            }
+            kmax = j + 1;
+            if (!any) break;
+            if ((st = pois_scale(scal.data(), w, n, n, nfc, V + (size_t)(j + 1) * n, VS, s))) return st;
+        }
+        // y_f = H_f(0:k, 0:k)^-1 g_f, x_f += V_f y_f (as x_f -= sum (-y_f,i) V_f,i; zeros past k_f)
+        std::fill(hh.begin(), hh.end(), 0.0);
+        for (int f = 0; f < nfc; ++f) {
+            const double* Hf = &H[(size_t)f * (m + 1) * m];
+            const double* gf = &g[(size_t)f * (m + 1)];
+            double* yf = &hh[(size_t)f * HS + oy];
+            for (int i = k[f] - 1; i >= 0; --i) {
+                double t = gf[i];
+                for (int l = i + 1; l < k[f]; ++l) t -= Hf[(size_t)i * m + l] * yf[l];
+                yf[i] = t / Hf[(size_t)i * m + i];
+            }
+            for (int i = 0; i < k[f]; ++i) yf[i] = -yf[i];
+        }
+        if ((e = hipMemcpyAsync(hd, hh.data(), hh.size() * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess)
+            return hip_err(e, "gmres");
+        if ((st = pois_sub(V, VS, kmax, hd + oy, HS, n, nfc, x, n, s))) return st;
+        all = true;
+        for (int f = 0; f < nfc; ++f) {
+            done[f] = done[f] || conv[f];
+            all = all && done[f];
+        }
+        if (all) return FC2D_OK;
+        // restart the open fields from their true residuals r_f = b_f - A x_f
+        if ((st = pois_matvec(A, x, n, n, nfc, part, w, s)) ||
+            (st = pois_axpbz(1.0, b, -1.0, w, nfc * n, w, s)) ||
+            (st = pois_dots(w, n, 1, w, n, n, nfc, hd + on, HS, s)) || (st = fetch()))
+            return st;
+        all = true;
+        for (int f = 0; f < nfc; ++f) {
+            if (!done[f]) {
+                beta[f] = sqrt(hh[f * HS + on]);
+                done[f] = beta[f] <= kGmresTol * bnorm[f];
+            }
+            scal[f] = done[f] ? 0.0 : 1.0 / beta[f];
+            all = all && done[f];
+        }
+        if (all) return FC2D_OK;
+        if ((st = pois_scale(scal.data(), w, n, n, nfc, V, VS, s))) return st;
     }
     set_error("GMRES did not converge");
     return FC2D_E_NEWTON;
@@ -229,15 +271,15 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     db.add(&seg, 4 * (size_t)nb);
     db.add(&sinv, nb);
     db.add(&ghom, (size_t)nb * nfm);
-    db.add(&rhs, nb);
+    db.add(&rhs, (size_t)nb * nfm);
     db.add(&A, (size_t)nb * nb);
     db.add(&phi, (size_t)nb * nfm);
     db.add(&phif, (size_t)nbf * nfm);
     db.add(&wtab, (size_t)nbf);   // (kRefine - 1) nb weights
-    db.add(&part, (size_t)pois_matvec_splits(nb) * nb);
-    db.add(&V, (size_t)(m + 1) * nb);
-    db.add(&w, nb);
-    db.add(&hd, 3 * (size_t)(m + 2) + m);
+    db.add(&part, (size_t)pois_matvec_splits(nb) * nb * nfm);
+    db.add(&V, (size_t)(m + 1) * nb * nfm);
+    db.add(&w, (size_t)nb * nfm);
+    db.add(&hd, (3 * (size_t)(m + 2) + m) * nfm);
     db.add(&cls, (size_t)npts);
     db.add(&cand, (size_t)cap);
     db.add(&cnt, 4 + kPoisLevels);   // candidates, foot failures, level counts, near points, overflow
@@ -288,11 +330,11 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
             if ((st = pois_add_quad(&g, mean, upc, s))) return st;
             // boundary data of the harmonic part and its density
             if ((st = pois_ghom(M, &g, upc, d_qc, nb, g_nodes + (int64_t)f * nb, ghc, s))) return st;
-            if ((st = pois_axpbz(-2.0, ghc, 0.0, ghc, nb, rhs, s))) return st;
-            int it = 0;
-            if ((st = gmres(A, rhs, phi + (int64_t)c * nb, nb, V, w, hd, part, s, &it))) return st;
-            iters_total += it;
+            if ((st = pois_axpbz(-2.0, ghc, 0.0, ghc, nb, rhs + (int64_t)c * nb, s))) return st;
         }
+        int it = 0;
+        if ((st = gmres(A, rhs, phi, nb, nfc, V, w, hd, part, s, &it))) return st;
+        iters_total += it;
         if ((st = pois_records(phi, nb, nfc, d_geo, wtab, phif, rec, s))) return st;
         // v on the grid, then the points next to Gamma
         double* uc = u + (int64_t)f0 * npts;

@@ -6,6 +6,11 @@
 
 namespace fc2d {
 
+// Fields are handled in chunks of nfc = 1, 2 or 4 (kPoisChunk at most) that
+// share the GMRES passes over the Nystrom matrix and the geometry work of the
+// double-layer sums.
+constexpr int kPoisChunk = 4;
+
 // ---- full Poisson solve (kernels_poisson.hip); qd: (x, y, x', y', x'', y'') per node
 int pois_mean(const fc2d_grid* g, const double* spec, double* mean, hipStream_t s);
 int pois_add_quad(const fc2d_grid* g, const double* mean, double* up, hipStream_t s);
@@ -19,18 +24,26 @@ int pois_nodes(const CurveC& cv, int nb, double* qc, double* geo, double* seg, d
 // per-point classes (nx * ny bytes) from the plan's row runs
 int pois_classes(const int32_t* run_ptr, const int32_t* run, int nx, int ny, int8_t* cls, hipStream_t s);
 int pois_nystrom(const double* qd, int nb, double* A, hipStream_t s);
-// y = A x, A column-major n x n; part: scratch of pois_matvec_splits(n) n doubles
+// GMRES building blocks for nfc fields at once (nfc = 1, 2 or 4; the field
+// index runs over the given strides).
+// y_f = A x_f, A column-major n x n read once; y holds the fields n apart;
+// part: scratch of pois_matvec_splits(n) nfc n doubles
 int pois_matvec_splits(int n);
-int pois_matvec(const double* A, const double* x, int n, double* part, double* y, hipStream_t s);
-int pois_dots(const double* V, int nv, const double* w, int n, double* out, hipStream_t s);
-int pois_sub(const double* V, int nv, const double* c, int n, double* w, hipStream_t s);
+int pois_matvec(const double* A, const double* x, int64_t xs, int n, int nfc, double* part, double* y,
+                hipStream_t s);
+// out_f[b] = <V_f,b, w_f>, b < nv (V_f,b at V + f vs + b n)
+int pois_dots(const double* V, int64_t vs, int nv, const double* w, int64_t ws, int n, int nfc, double* out,
+              int64_t os, hipStream_t s);
+// w_f -= sum_b c_f[b] V_f,b
+int pois_sub(const double* V, int64_t vs, int nv, const double* c, int64_t cs, int n, int nfc, double* w,
+             int64_t ws, hipStream_t s);
+// y_f = a[f] x_f (a: nfc host values)
+int pois_scale(const double* a, const double* x, int64_t xs, int n, int nfc, double* y, int64_t ys,
+               hipStream_t s);
 int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s);
 // Levels of the double-layer sums: level L (0 <= L < kPoisLevels) holds 2^L nb
 // equispaced nodes at offset nb (2^L - 1) of the concatenated node arrays.
 constexpr int kPoisLevels = 6;
-// Fields are handled in chunks of nfc = 1, 2 or 4 (kPoisChunk at most) that
-// share the geometry work of the double-layer sums.
-constexpr int kPoisChunk = 4;
 // phi (nfc rows of nb) -> phif (nfc rows of 2^(kPoisLevels - 1) nb, the finest
 // level, by the Dirichlet kernel) -> node records of every level: (x, y) and
 // per field (phi y', phi x'), 2 + 2 nfc doubles each; geo: (x, y, x', y') per

@@ -217,16 +217,21 @@ int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStr
  * potential whose density solves the second-kind Nystrom system of the
  * trapezoidal rule on nb nodes q(2 pi j / nb), by GMRES; u_p on Gamma comes from
  * degree-(M-1) tensor interpolation (the plan's M).  v is summed at the IN grid
- * points (density refined 32x near Gamma); points within h/2 of Gamma use the
+ * points (density refined up to 32x near Gamma); points within h/2 of Gamma use the
  * foot value and M - 1 values along the inward normal at h/2, h, ...
- * interpolated in the distance with degree M - 1.
+ * interpolated in the distance with degree M - 1.  Fields are solved in chunks
+ * of up to four that share the GMRES passes over the Nystrom matrix and the
+ * geometry work of the double-layer sums (results per field as when alone, to
+ * rounding).
  * fc2d_poisson_nodes writes the nodes, host xy [2 nb], where the caller samples
  * g.  fc2d_poisson_solve: device f_grid [nf][nx][ny] (IN entries read),
  * f_bdry [nf][n_bdry] (the plan's boundary points), g_nodes [nf][nb]; writes
  * u [nf][nx][ny] (IN points; every other point 0).  Power-of-two grids, 8 <= nb
  * <= 16384.  Allocates its work buffers, synchronises `stream` (GMRES reads its
  * scalars on the host), returns the GMRES iterations summed over the fields in
- * *gmres_iters (may be NULL).  FC2D_E_NEWTON when GMRES or a foot solve fails. */
+ * *gmres_iters (may be NULL).  FC2D_E_NEWTON when GMRES or a foot solve fails;
+ * FC2D_E_NOMEM when the work buffers (about 3 + min(nf, 4) grids of nx ny
+ * doubles plus 8 nb^2 bytes) do not fit. */
 int fc2d_poisson_nodes(const fc2d_plan* plan, int nb, double* xy);
 int fc2d_poisson_solve(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, const double* g_nodes,
                        int nb, double* u, int nf, hipStream_t stream, int* gmres_iters);

@@ -230,3 +230,37 @@ def test_transposed_spectra_bitwise(batch_setup, torch_mod, nf8):
         ou, out_ = OF.ff_step(opl, u0[k][f], np.zeros_like(u0[k][f]), dt)
         assert rel_err(du[f].cpu().numpy(), ou) < 1e-11 and rel_err(dut[f].cpu().numpy(), out_) < 1e-11
     b.close()
+
+
+def test_batch_interior_only_plan(torch_mod):
+    """A batch mixing a plan built from interior data only (Remark 3.1 II; its
+    matching reads no boundary values) with an ordinary one: one step per field
+    against the oracle's step on the same plans (1e-11)."""
+    from paper_2010_03901_amd import fc2d
+    from oracle import fcgram
+    from oracle.curves import Curve
+    torch = torch_mod
+    case_io = W.cfg_ff("disc", 256)
+    g = OP.Grid(case_io.x0, case_io.y0, case_io.h, case_io.n, case_io.n)
+    opl_io = OP.make_plan(Curve(*case_io.curve), g, fcgram.load_tables(case_io.d), case_io.B, k1=case_io.k1,
+                          M=case_io.M, interior_only=True)
+    gpl_io = fc2d.Plan(fc2d.make_curve(*case_io.curve),
+                       fc2d.make_grid(case_io.x0, case_io.y0, case_io.h, case_io.n, case_io.n),
+                       d=case_io.d, C_=case_io.C, B=case_io.B, k1=case_io.k1, M=case_io.M, interior_only=True)
+    case_k, opl_k = oracle_plan("kite256ff", W.cfg_ff, "kite", 256)
+    gpl_k = gpu_plan(case_k)
+    nf = [2, 1]
+    batch = fc2d.Batch([gpl_io, gpl_k], nf, autotune=False)
+    u0 = [_pulses(case_io, [3, 4]), _pulses(case_k, [5])]
+    _load_state(batch, u0)
+    dt = 0.02
+    batch.run_ff(1.0, dt, 1, use_graph=False)
+    torch.cuda.synchronize()
+    for k, (opl, m) in enumerate(zip([opl_io, opl_k], nf)):
+        du, dut = batch.state(k)
+        for f in range(m):
+            ou, out_ = OF.ff_step(opl, u0[k][f], np.zeros_like(u0[k][f]), dt)
+            eu = rel_err(du[f].cpu().numpy(), ou)
+            et = rel_err(dut[f].cpu().numpy(), out_)
+            print("\n[batch] interior-only mix plan %d field %d: u %.2e u_t %.2e" % (k, f, eu, et), end="")
+            assert eu < 1e-11 and et < 1e-11

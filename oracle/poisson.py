@@ -21,7 +21,9 @@ as u = u_p + v (eq. total_soln):
   -(x'y'' - y'x'') / (4 pi |q'|^2) on the diagonal.  The small dense system is
   solved directly here.
 * v at grid points of Omega by the trapezoidal rule with the density carried to
-  R NB nodes by its trigonometric interpolant (the Dirichlet kernel).  Points
+  R NB nodes by its trigonometric interpolant (the Dirichlet kernel), R = 128:
+  enough that the points h/2 inside Gamma, the closest the sums are taken at,
+  lie several node spacings from the nodes even for NB = N on a tight box.  Points
   closer to Gamma than h/2 (foot of the normal of Sec. 3.4) take v at the foot
   (g_hom interpolated trigonometrically) and at MP - 1 points h/2, h, ... inward
   along the normal, interpolated in the distance with degree MP - 1: a reading
@@ -37,7 +39,7 @@ from .ff import boundary_interp
 from .interp import lagrange_weights
 from .plan import IN, foot_solve
 
-REFINE = 32   # density refinement factor R of the near-boundary sums
+REFINE = 128   # density refinement factor R of the near-boundary sums
 
 
 def particular_solution(pl, f_grid, f_bdry):
@@ -82,15 +84,21 @@ def trig_interp(vals, tau):
     Dirichlet kernel sin(n s / 2) / (n sin(s / 2)), times cos(s / 2) for even n."""
     n = vals.size
     t = 2.0 * math.pi * np.arange(n) / n
-    s = np.asarray(tau)[..., None] - t
-    half = 0.5 * s
-    sn = np.sin(half)
-    with np.errstate(divide="ignore", invalid="ignore"):
-        w = np.sin(0.5 * n * s) * (np.cos(half) if n % 2 == 0 else 1.0) / (n * sn)
-    hit = np.abs(sn) < 1e-300
-    w = np.where(hit, 1.0, w)
-    w = np.where(hit.any(-1, keepdims=True) & ~hit, 0.0, w)
-    return w @ vals
+    tau = np.atleast_1d(np.asarray(tau, dtype=np.float64))
+    out = np.empty(tau.shape)
+    flat, res = tau.ravel(), out.ravel()
+    step = max(1, (1 << 24) // n)          # rows per block (bounded memory)
+    for a in range(0, flat.size, step):
+        s = flat[a:a + step, None] - t
+        half = 0.5 * s
+        sn = np.sin(half)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            w = np.sin(0.5 * n * s) * (np.cos(half) if n % 2 == 0 else 1.0) / (n * sn)
+        hit = np.abs(sn) < 1e-300
+        w = np.where(hit, 1.0, w)
+        w = np.where(hit.any(-1, keepdims=True) & ~hit, 0.0, w)
+        res[a:a + step] = w @ vals
+    return out
 
 
 def double_layer(curve, phi, pts):
@@ -99,11 +107,12 @@ def double_layer(curve, phi, pts):
     _, q, q1, _ = nodes(curve, n)
     nu = np.stack([q1[:, 1], -q1[:, 0]], 1)
     out = np.empty(pts.shape[0])
-    for a in range(0, pts.shape[0], 2048):
-        dx = pts[a:a + 2048, None, :] - q[None, :, :]
+    step = max(1, (1 << 23) // n)          # points per block (bounded memory)
+    for a in range(0, pts.shape[0], step):
+        dx = pts[a:a + step, None, :] - q[None, :, :]
         r2 = np.einsum("ijk,ijk->ij", dx, dx)
         num = np.einsum("ijk,jk->ij", dx, nu)
-        out[a:a + 2048] = (num / r2) @ phi / n          # (1 / 2 pi) x (2 pi / n)
+        out[a:a + step] = (num / r2) @ phi / n          # (1 / 2 pi) x (2 pi / n)
     return out
 
 

@@ -400,15 +400,28 @@ __device__ inline double poly_dist2(const double4* __restrict__ seg, const doubl
     return __longlong_as_double((long long)((unsigned long long)dmh << 32));
 }
 
+// blocks that share the nodes of a level of n nodes (1024 nodes per wave of a
+// 16-wave block at least): the finest levels carry few points, and splitting
+// their nodes over blocks keeps the chip busy
+__host__ __device__ inline int dl_chunks(int n) { return n >= (16 << 14) ? 16 : (n >= (1 << 14) ? n >> 14 : 1); }
+
+// the coarsest level whose node spacing (at most dsmax 2^-L) is a seventh of
+// the distance dist to Gamma or less; the finest level when none is
+__device__ inline int dl_level(double dist, double dsmax) {
+    int L = 0;
+    while (L < kPoisLevels - 1 && 7.0 * dsmax > dist * (double)(1 << L)) ++L;
+    return L;
+}
+
 // v at every IN point from the nb-node sum (trapezoidal weight 2 pi / nb, the
-// 1 / (2 pi) of the kernel folded in); u = u_p + v there, 0 elsewhere.  Points
-// whose nearest node is closer than 7 node spacings (dsmax: largest spacing of
-// the nb nodes) go to the list of the level whose spacing is at most a seventh
-// of the point's distance to Gamma (the finest level at most), bounded from
-// below by the larger of (that node distance - dsmax / 2) and (the distance to
-// the nb-node polygon - sag, sag bounding how far an arc leaves its chord);
-// bl[L cap ...], count bcnt[L].  Other points closer than h to a node go to cand.
-// NF fields: up and u hold them npts apart.
+// 1 / (2 pi) of the kernel folded in); u = u_p + v there, 0 elsewhere.  The
+// distance to Gamma is bounded from below by the larger of (nearest node
+// distance - dsmax / 2, dsmax the largest spacing of the nb nodes) and (the
+// distance to the nb-node polygon - sag, sag bounding how far an arc leaves
+// its chord).  Points whose bound is below h/2 go to cand (the foot of the
+// normal decides there); other points closer than 7 dsmax go to the list of
+// the level dl_level picks, bl[L cap ...], count bcnt[L].  NF fields: up and u
+// hold them npts apart.
 template <int NF>
 __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls, const double* __restrict__ up,
                                                  int nx, int ny, int64_t npts, double x0, double y0, double h,
@@ -434,59 +447,76 @@ __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls,
     dl_partial<true, NF>(rec, 0, nb, X, Y, sum, &d2);
 #pragma unroll
     for (int f = 0; f < NF; ++f) u[f * npts + e] = up[f * npts + e] + sum[f] / nb;
-    if (d2 < 49.0 * dsmax * dsmax) {
-        const double dest = fmax(sqrt(d2) - 0.5 * dsmax, sqrt(poly_dist2(seg, sinv, nb, X, Y)) - sag);
-        int L = kPoisLevels - 1;
-        if (dest > 0.0) {
-            L = 1;
-            while (L < kPoisLevels - 1 && 7.0 * dsmax / (double)(1 << L) > dest) ++L;
+    const double dn = sqrt(d2) - 0.5 * dsmax;
+    if (dn < fmax(7.0 * dsmax, 0.5 * h)) {
+        const double dest = fmax(dn, sqrt(poly_dist2(seg, sinv, nb, X, Y)) - sag);
+        if (dest < 0.5 * h) {
+            const int k = atomicAdd(ncand, 1);
+            cand[k] = (int32_t)e;
+        } else if (dest < 7.0 * dsmax) {
+            const int L = dl_level(dest, dsmax);
+            const int k = atomicAdd(bcnt + L, 1);
+            bl[L * cap + k] = (int32_t)e;
         }
-        const int k = atomicAdd(bcnt + L, 1);
-        bl[L * cap + k] = (int32_t)e;
-    } else if (d2 < h * h) {
-        const int k = atomicAdd(ncand, 1);
-        cand[k] = (int32_t)e;
     }
 }
 
-// the listed points of one level (n = 2^L nb nodes), 64 per block, the nodes
-// split over the block's W waves and the partial sums added in wave order;
-// u = u_p + v, and points closer than h to a node of the level go to cand
+// the listed points of one level (n = 2^L nb nodes), 64 per block: the nodes
+// split into gridDim.y chunks (blockIdx.y) and each chunk over the block's W
+// waves, the partial sums added in wave order.  One chunk: u = u_p + v.  More:
+// the chunk's sum / n to part[(c capl + k) NF + f] for list entry k < capl
+// (k_band_fin adds them), more entries than capl counted in *over
 template <int W, int NF>
 __global__ __launch_bounds__(64 * W) void k_dl_band(const int32_t* __restrict__ bl, const int* __restrict__ bcnt,
                                                     const double* __restrict__ up, int ny, int64_t npts, double x0,
                                                     double y0, double h, const DlRec<NF>* __restrict__ rec, int n,
-                                                    double* __restrict__ u, int32_t* __restrict__ cand,
-                                                    int* __restrict__ ncand) {
-    __shared__ double ps[W][NF][64], pm[W][64];
-    const int cnt = *bcnt;
+                                                    double* __restrict__ u, double* __restrict__ part, int capl,
+                                                    int* __restrict__ over) {
+    __shared__ double ps[W][NF][64];
+    const int C = gridDim.y, c = blockIdx.y;
+    int cnt = *bcnt;
+    if (C > 1 && cnt > capl) {
+        if (blockIdx.x == 0 && c == 0 && threadIdx.x == 0) atomicAdd(over, 1);
+        cnt = capl;
+    }
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
-    const int j0 = (int)((int64_t)n * w / W), j1 = (int)((int64_t)n * (w + 1) / W);
+    const int64_t c0 = (int64_t)n * c / C, cl = (int64_t)n * (c + 1) / C - c0;
+    const int j0 = (int)(c0 + cl * w / W), j1 = (int)(c0 + cl * (w + 1) / W);
     for (int g = blockIdx.x; g * 64 < cnt; g += gridDim.x) {
         const int k = g * 64 + l;
         const int64_t e = bl[k < cnt ? k : g * 64];   // idle lanes repeat the group's first point
         const int i = (int)(e / ny), jj = (int)(e - (int64_t)i * ny);
         double dm, sum[NF];
-        dl_partial<true, NF>(rec, j0, j1, x0 + i * h, y0 + jj * h, sum, &dm);
+        dl_partial<false, NF>(rec, j0, j1, x0 + i * h, y0 + jj * h, sum, &dm);
 #pragma unroll
         for (int f = 0; f < NF; ++f) ps[w][f][l] = sum[f];
-        pm[w][l] = dm;
         __syncthreads();
         if (w == 0 && k < cnt) {
-            double d2 = 1e300;
-            for (int q = 0; q < W; ++q) d2 = fmin(d2, pm[q][l]);
 #pragma unroll
             for (int f = 0; f < NF; ++f) {
                 double s = 0.0;
                 for (int q = 0; q < W; ++q) s += ps[q][f][l];
-                u[f * npts + e] = up[f * npts + e] + s / n;
-            }
-            if (d2 < h * h) {
-                const int c = atomicAdd(ncand, 1);
-                cand[c] = (int32_t)e;
+                if (C == 1) u[f * npts + e] = up[f * npts + e] + s / n;
+                else part[((int64_t)c * capl + k) * NF + f] = s / n;
             }
         }
         __syncthreads();
+    }
+}
+
+// u = u_p + the C chunk sums of each listed point (chunk order), NF fields
+template <int NF>
+__global__ void k_band_fin(const int32_t* __restrict__ bl, const int* __restrict__ bcnt, int C,
+                           const double* __restrict__ part, int capl, const double* __restrict__ up, int64_t npts,
+                           double* __restrict__ u) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= min(*bcnt, capl)) return;
+    const int64_t e = bl[k];
+#pragma unroll
+    for (int f = 0; f < NF; ++f) {
+        double s = 0.0;
+        for (int c = 0; c < C; ++c) s += part[((int64_t)c * capl + k) * NF + f];
+        u[f * npts + e] = up[f * npts + e] + s;
     }
 }
 
@@ -496,21 +526,30 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// the listed points within h/2 of Gamma, one 64-lane block each: foot
-// (theta, eta) seeded by the nearest plan boundary sample (lane reduction,
-// smallest index among equals), g_hom(theta) by the lanes, the degree-(M - 1)
-// Lagrange weights in the distance on the nodes s_m = m h / 2 at s = -eta,
-// and the M - 1 points P_m = foot + s_m (inward normal), m >= 1, whose sums
-// k_dl_samples forms.  Near point k: nidx[k], nw[k M + m], nv0[k NF + f] =
-// g_hom of field f at theta (ghom: NF rows of nb), samp[k (M - 1) + m - 1] = P_m;
-// count cnt[0], beyond capn counted in cnt[1].
+// the candidate points, one 64-lane block each: foot (theta, eta) seeded by
+// the nearest plan boundary sample (lane reduction, smallest index among
+// equals).  A point with |eta| >= h/2 is no near point: it joins the band list
+// of the level its distance |eta| needs (none when level 0, already summed,
+// will do).  A near point takes g_hom(theta) from the lanes, the degree-(M - 1)
+// Lagrange weights in the distance on the nodes s_m = m h / 2 at s = -eta, and
+// the M - 1 points P_m = foot + s_m (inward normal), m >= 1, whose sums
+// k_dl_samples forms: sample k (M - 1) + m - 1 joins the list of the level its
+// polygon distance bound needs, sl[L scap ...], count scnt[L].  Near point k:
+// nidx[k], nw[k M + m], nv0[k NF + f] = g_hom of field f at theta (ghom: NF
+// rows of nb), samp[k (M - 1) + m - 1] = P_m and slev[...] its level; count
+// cnt[0], beyond capn counted in cnt[1].
 template <int M, int NF>
 __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ cand, const int* __restrict__ ncand,
                                                   CurveC cv, BndView bd, int maxit, int ny, double x0, double y0,
-                                                  double h, const double* __restrict__ ghom, int nb, int capn,
-                                                  int32_t* __restrict__ nidx, double* __restrict__ nw,
-                                                  double* __restrict__ nv0, double2* __restrict__ samp,
-                                                  int* __restrict__ cnt, int* __restrict__ nfail) {
+                                                  double h, const double* __restrict__ ghom, int nb, double dsmax,
+                                                  const double4* __restrict__ seg, const double* __restrict__ sinv,
+                                                  double sag, int32_t* __restrict__ bl, int64_t cap,
+                                                  int* __restrict__ bcnt, int capn, int32_t* __restrict__ nidx,
+                                                  double* __restrict__ nw, double* __restrict__ nv0,
+                                                  double2* __restrict__ samp, int32_t* __restrict__ sl,
+                                                  int8_t* __restrict__ slev, int64_t scap,
+                                                  int* __restrict__ scnt, int* __restrict__ cnt,
+                                                  int* __restrict__ nfail) {
     const int nc = *ncand;
     const int lane = threadIdx.x;
     for (int e = blockIdx.x; e < nc; e += gridDim.x) {
@@ -537,7 +576,14 @@ __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ ca
             if (lane == 0) atomicAdd(nfail, 1);
             continue;
         }
-        if (!(fabs(eta) < 0.5 * h)) continue;
+        if (!(fabs(eta) < 0.5 * h)) {
+            if (lane == 0 && fabs(eta) < 7.0 * dsmax) {
+                const int L = dl_level(fabs(eta), dsmax);
+                const int q = atomicAdd(bcnt + L, 1);
+                bl[L * cap + q] = (int32_t)idx;
+            }
+            continue;
+        }
         // trigonometric interpolant of each field's g_hom at theta
         double sv[NF], hv[NF];
 #pragma unroll
@@ -582,28 +628,40 @@ __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ ca
             for (int f = 0; f < NF; ++f) nv0[(int64_t)k * NF + f] = any > 0.0 ? hv[f] : sv[f];
             for (int m = 0; m < M; ++m) nw[(int64_t)k * M + m] = w[m];
         }
+        const double sh = 0.5 * h * (lane < M ? lane : M - 1);
+        const double px = o[0] + sh * ix, py = o[1] + sh * iy;
+        const double dsb = sqrt(poly_dist2(seg, sinv, nb, px, py)) - sag;   // every lane (uniform chords)
         if (lane >= 1 && lane < M) {
-            const double s = 0.5 * h * lane;
-            samp[(int64_t)k * (M - 1) + lane - 1] = make_double2(o[0] + s * ix, o[1] + s * iy);
+            const int64_t si = (int64_t)k * (M - 1) + lane - 1;
+            samp[si] = make_double2(px, py);
+            const int L = dsb >= 7.0 * dsmax ? 0 : dl_level(dsb, dsmax);
+            slev[si] = (int8_t)L;
+            const int q = atomicAdd(scnt + L, 1);
+            sl[L * scap + q] = (int32_t)si;
         }
     }
 }
 
-// double-layer sums at the listed sample points (count *nnear, at most capn,
-// times per), 64 per block with the n nodes split over the block's W waves
-// and the partials added in wave order; sval[k NF + f] = sum of field f / n
+// double-layer sums over one level's n nodes at the sample points listed for
+// it (sl, count *scnt), 64 per block: the nodes split into gridDim.y chunks
+// (blockIdx.y, dl_chunks(n) of them) and each chunk over the block's W waves,
+// the partials added in wave order; sval[(c scap + k) NF + f] = chunk c's sum
+// of field f / n for sample k
 template <int W, int NF>
 __global__ __launch_bounds__(64 * W) void k_dl_samples(const double2* __restrict__ samp,
-                                                       const int* __restrict__ nnear, int capn, int per,
-                                                       const DlRec<NF>* __restrict__ rec, int n,
+                                                       const int32_t* __restrict__ sl, const int* __restrict__ scnt,
+                                                       const DlRec<NF>* __restrict__ rec, int n, int64_t scap,
                                                        double* __restrict__ sval) {
     __shared__ double ps[W][NF][64];
-    const int cnt = min(*nnear, capn) * per;
+    const int cnt = *scnt;
+    const int C = gridDim.y, c = blockIdx.y;
     const int w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6)), l = threadIdx.x & 63;
-    const int j0 = (int)((int64_t)n * w / W), j1 = (int)((int64_t)n * (w + 1) / W);
+    const int64_t c0 = (int64_t)n * c / C, cl = (int64_t)n * (c + 1) / C - c0;
+    const int j0 = (int)(c0 + cl * w / W), j1 = (int)(c0 + cl * (w + 1) / W);
     for (int g = blockIdx.x; g * 64 < cnt; g += gridDim.x) {
         const int k = g * 64 + l;
-        const double2 P = samp[k < cnt ? k : g * 64];   // idle lanes repeat the group's first point
+        const int64_t si = sl[k < cnt ? k : g * 64];   // idle lanes repeat the group's first sample
+        const double2 P = samp[si];
         double dm, sum[NF];
         dl_partial<false, NF>(rec, j0, j1, P.x, P.y, sum, &dm);
 #pragma unroll
@@ -614,31 +672,41 @@ __global__ __launch_bounds__(64 * W) void k_dl_samples(const double2* __restrict
             for (int f = 0; f < NF; ++f) {
                 double s = 0.0;
                 for (int q = 0; q < W; ++q) s += ps[q][f][l];
-                sval[(int64_t)k * NF + f] = s / n;
+                sval[(c * scap + si) * NF + f] = s / n;
             }
         }
         __syncthreads();
     }
 }
 
-// u = u_p + sum_m w_m v_m at the near points (v_0 = g_hom(theta), v_m the sums),
+// u = u_p + sum_m w_m v_m at the near points (v_0 = g_hom(theta), v_m the
+// sample sums: the chunk sums of the sample's level added in chunk order),
 // per field (up and u hold the NF fields npts apart)
 template <int M, int NF>
 __global__ void k_near_fin(const int32_t* __restrict__ nidx, const int* __restrict__ nnear, int capn,
                            const double* __restrict__ nw, const double* __restrict__ nv0,
-                           const double* __restrict__ sval, const double* __restrict__ up, int64_t npts,
-                           double* __restrict__ u) {
+                           const double* __restrict__ sval, const int8_t* __restrict__ slev, int nb,
+                           const double* __restrict__ up, int64_t npts, double* __restrict__ u) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= min(*nnear, capn)) return;
+    const int64_t scap = (int64_t)capn * (M - 1);
     const double* w = nw + (int64_t)k * M;
     const int64_t e = nidx[k];
+    double v[NF];
 #pragma unroll
-    for (int f = 0; f < NF; ++f) {
-        const double* sv = sval + (int64_t)k * (M - 1) * NF + f;
-        double v = w[0] * nv0[(int64_t)k * NF + f];
-        for (int m = 1; m < M; ++m) v += w[m] * sv[(int64_t)(m - 1) * NF];
-        u[f * npts + e] = up[f * npts + e] + v;
+    for (int f = 0; f < NF; ++f) v[f] = w[0] * nv0[(int64_t)k * NF + f];
+    for (int m = 1; m < M; ++m) {
+        const int64_t si = (int64_t)k * (M - 1) + m - 1;
+        const int C = dl_chunks(nb << slev[si]);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) {
+            double s = 0.0;
+            for (int c = 0; c < C; ++c) s += sval[(c * scap + si) * NF + f];
+            v[f] += w[m] * s;
+        }
     }
+#pragma unroll
+    for (int f = 0; f < NF; ++f) u[f * npts + e] = up[f * npts + e] + v[f];
 }
 
 // ---- launchers -------------------------------------------------------------
@@ -758,86 +826,102 @@ int pois_records(const double* phi, int nb, int nfc, const double* geo, double* 
     return pois_check("k_records", s);
 }
 
-template <int NF>
-static int dl_grid_nf(const fc2d_grid* g, const int8_t* cls, const double* up, const double* rec, int nb,
-                      double dsmax, const double* seg, const double* sinv, double sag, double* u, int32_t* bl,
-                      int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s) {
-    const int64_t tiles = (int64_t)((g->nx + 7) / 8) * ((g->ny + 7) / 8);
+// the band kernel of one level with W waves per block
+template <int W, int NF>
+static void band_launch(const PoisDl& a, unsigned bx, int C, int L, const DlRec<NF>* rl, int* bcnt, int* over,
+                        hipStream_t s) {
+    const fc2d_grid* g = a.g;
     const int64_t npts = (int64_t)g->nx * g->ny;
-    const DlRec<NF>* r = (const DlRec<NF>*)rec;
-    k_dl_grid<NF><<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(cls, up, g->nx, g->ny, npts, g->x0, g->y0, g->h, r,
-                                                              nb, dsmax, (const double4*)seg, sinv, sag, u, bl, cap,
-                                                              bcnt, cand, ncand);
-    int st = pois_check("k_dl_grid", s);
-    // levels 1 .. kPoisLevels - 1, up to 16 waves per group of 64 points
-    const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>((cap + 63) / 64, 2048));
-    for (int L = 1; L < kPoisLevels && !st; ++L) {
-        const DlRec<NF>* rl = r + (int64_t)nb * ((1 << L) - 1);
-        const int32_t* bll = bl + L * cap;
-        switch (L) {
-            case 1: k_dl_band<2, NF><<<nbk, 128, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-            case 2: k_dl_band<4, NF><<<nbk, 256, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-            case 3: k_dl_band<8, NF><<<nbk, 512, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-            default: k_dl_band<16, NF><<<nbk, 1024, 0, s>>>(bll, bcnt + L, up, g->ny, npts, g->x0, g->y0, g->h, rl, nb << L, u, cand, ncand); break;
-        }
-        st = pois_check("k_dl_band", s);
-    }
-    return st;
+    k_dl_band<W, NF><<<dim3(bx, C), 64 * W, 0, s>>>(a.bl + L * a.cap, bcnt + L, a.up, g->ny, npts, g->x0, g->y0, g->h,
+                                                   rl, a.nb << L, a.u, a.bpart, a.capb, over);
 }
 
-int pois_dl_grid(const fc2d_grid* g, int nfc, const int8_t* cls, const double* up, const double* rec, int nb,
-                 double dsmax, const double* seg, const double* sinv, double sag, double* u, int32_t* bl,
-                 int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s) {
-    switch (nfc) {
-        case 1: return dl_grid_nf<1>(g, cls, up, rec, nb, dsmax, seg, sinv, sag, u, bl, cap, bcnt, cand, ncand, s);
-        case 2: return dl_grid_nf<2>(g, cls, up, rec, nb, dsmax, seg, sinv, sag, u, bl, cap, bcnt, cand, ncand, s);
-        case 4: return dl_grid_nf<4>(g, cls, up, rec, nb, dsmax, seg, sinv, sag, u, bl, cap, bcnt, cand, ncand, s);
-        default: set_error("Poisson: unsupported field chunk"); return FC2D_E_ARG;
-    }
+template <int W, int NF>
+static void samples_launch(const PoisDl& a, unsigned bx, int C, int L, int64_t scap, const DlRec<NF>* rl,
+                           int* scnt, hipStream_t s) {
+    k_dl_samples<W, NF><<<dim3(bx, C), 64 * W, 0, s>>>((const double2*)a.samp, a.sl + L * scap, scnt + L, rl,
+                                                      a.nb << L, scap, a.sval);
 }
 
 template <int M, int NF>
-static int dl_near_mnf(const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv, const BndView& bd,
-                       int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
-                       const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp,
-                       double* sval, int* ncnt, double* u, int* nfail, hipStream_t s) {
-    const int top = kPoisLevels - 1;
+static int dl_eval_mnf(const PoisDl& a, hipStream_t s) {
+    const fc2d_grid* g = a.g;
+    const int nb = a.nb;
     const int64_t npts = (int64_t)g->nx * g->ny;
-    const DlRec<NF>* recf = (const DlRec<NF>*)rec + (int64_t)nb * ((1 << top) - 1);   // finest level
-    const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(cap, 16384));
-    k_near_prep<M, NF><<<nbk, 64, 0, s>>>(cand, ncand, cv, bd, maxit, g->ny, g->x0, g->y0, g->h, ghom, nb, capn,
-                                          nidx, nw, nv0, (double2*)samp, ncnt, nfail);
-    int st = pois_check("k_near_prep", s);
+    const int64_t tiles = (int64_t)((g->nx + 7) / 8) * ((g->ny + 7) / 8);
+    const int64_t scap = (int64_t)a.capn * (M - 1);
+    const DlRec<NF>* r = (const DlRec<NF>*)a.rec;
+    int* ncand = a.cnt;
+    int* nfail = a.cnt + 1;
+    int* bcnt = a.cnt + 2;
+    int* ncnt = a.cnt + 2 + kPoisLevels;
+    int* scnt = a.cnt + 4 + kPoisLevels;
+    int* over = a.cnt + 3 + kPoisLevels;
+    // level 0 everywhere, band lists and candidates
+    k_dl_grid<NF><<<(unsigned)((tiles + 3) / 4), 256, 0, s>>>(a.cls, a.up, g->nx, g->ny, npts, g->x0, g->y0, g->h, r,
+                                                              nb, a.dsmax, (const double4*)a.seg, a.sinv, a.sag, a.u,
+                                                              a.bl, a.cap, bcnt, a.cand, ncand);
+    int st = pois_check("k_dl_grid", s);
     if (st) return st;
-    const unsigned sbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(((int64_t)capn * (M - 1) + 63) / 64, 2048));
-    k_dl_samples<16, NF><<<sbk, 1024, 0, s>>>((const double2*)samp, ncnt, capn, M - 1, recf, nb << top, sval);
-    if ((st = pois_check("k_dl_samples", s))) return st;
-    const unsigned fbk = (unsigned)std::max(1, (capn + 255) / 256);
-    k_near_fin<M, NF><<<fbk, 256, 0, s>>>(nidx, ncnt, capn, nw, nv0, sval, up, npts, u);
+    // feet of the candidates: near points and their samples; the others join the band lists
+    const unsigned nbk = (unsigned)std::max<int64_t>(1, std::min<int64_t>(a.cap, 16384));
+    k_near_prep<M, NF><<<nbk, 64, 0, s>>>(a.cand, ncand, a.cv, a.bd, a.maxit, g->ny, g->x0, g->y0, g->h, a.ghom, nb,
+                                          a.dsmax, (const double4*)a.seg, a.sinv, a.sag, a.bl, a.cap, bcnt, a.capn,
+                                          a.nidx, a.nw, a.nv0, (double2*)a.samp, a.sl, a.slev, scap, scnt, ncnt,
+                                          nfail);
+    if ((st = pois_check("k_near_prep", s))) return st;
+    // band levels 1 .. kPoisLevels - 1, up to 16 waves per group of 64 points
+    for (int L = 1; L < kPoisLevels; ++L) {
+        const DlRec<NF>* rl = r + (int64_t)nb * ((1 << L) - 1);
+        const int C = dl_chunks(nb << L);
+        const unsigned bx =
+            (unsigned)std::max<int64_t>(1, std::min<int64_t>(((C > 1 ? a.capb : a.cap) + 63) / 64, 2048 / C));
+        switch (L) {
+            case 1: band_launch<2, NF>(a, bx, C, L, rl, bcnt, over, s); break;
+            case 2: band_launch<4, NF>(a, bx, C, L, rl, bcnt, over, s); break;
+            case 3: band_launch<8, NF>(a, bx, C, L, rl, bcnt, over, s); break;
+            default: band_launch<16, NF>(a, bx, C, L, rl, bcnt, over, s); break;
+        }
+        if ((st = pois_check("k_dl_band", s))) return st;
+        if (C > 1) {
+            k_band_fin<NF><<<(unsigned)std::max(1, (a.capb + 255) / 256), 256, 0, s>>>(
+                a.bl + L * a.cap, bcnt + L, C, a.bpart, a.capb, a.up, npts, a.u);
+            if ((st = pois_check("k_band_fin", s))) return st;
+        }
+    }
+    // sample sums by level
+    for (int L = 0; L < kPoisLevels; ++L) {
+        const DlRec<NF>* rl = r + (int64_t)nb * ((1 << L) - 1);
+        const int C = dl_chunks(nb << L);
+        const unsigned bx = (unsigned)std::max<int64_t>(1, std::min<int64_t>((scap + 63) / 64, 2048 / C));
+        switch (L) {
+            case 0: samples_launch<1, NF>(a, bx, C, L, scap, rl, scnt, s); break;
+            case 1: samples_launch<2, NF>(a, bx, C, L, scap, rl, scnt, s); break;
+            case 2: samples_launch<4, NF>(a, bx, C, L, scap, rl, scnt, s); break;
+            case 3: samples_launch<8, NF>(a, bx, C, L, scap, rl, scnt, s); break;
+            default: samples_launch<16, NF>(a, bx, C, L, scap, rl, scnt, s); break;
+        }
+        if ((st = pois_check("k_dl_samples", s))) return st;
+    }
+    const unsigned fbk = (unsigned)std::max(1, (a.capn + 255) / 256);
+    k_near_fin<M, NF><<<fbk, 256, 0, s>>>(a.nidx, ncnt, a.capn, a.nw, a.nv0, a.sval, a.slev, nb, a.up, npts, a.u);
     return pois_check("k_near_fin", s);
 }
 
 template <int M>
-static int dl_near_m(int nfc, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv,
-                     const BndView& bd, int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
-                     const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp,
-                     double* sval, int* ncnt, double* u, int* nfail, hipStream_t s) {
-    switch (nfc) {
-        case 1: return dl_near_mnf<M, 1>(cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, nv0, samp, sval, ncnt, u, nfail, s);
-        case 2: return dl_near_mnf<M, 2>(cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, nv0, samp, sval, ncnt, u, nfail, s);
-        case 4: return dl_near_mnf<M, 4>(cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, nv0, samp, sval, ncnt, u, nfail, s);
+static int dl_eval_m(const PoisDl& a, hipStream_t s) {
+    switch (a.nfc) {
+        case 1: return dl_eval_mnf<M, 1>(a, s);
+        case 2: return dl_eval_mnf<M, 2>(a, s);
+        case 4: return dl_eval_mnf<M, 4>(a, s);
         default: set_error("Poisson: unsupported field chunk"); return FC2D_E_ARG;
     }
 }
 
-int pois_dl_near(int M, int nfc, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv,
-                 const BndView& bd, int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
-                 const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
-                 int* ncnt, double* u, int* nfail, hipStream_t s) {
-    switch (M) {
+int pois_dl_eval(const PoisDl& a, hipStream_t s) {
+    switch (a.M) {
 #define FC2D_NEAR(MM) \
-        case MM: return dl_near_m<MM>(nfc, cand, ncand, cap, cv, bd, maxit, g, up, ghom, nb, rec, capn, nidx, nw, \
-                                      nv0, samp, sval, ncnt, u, nfail, s);
+        case MM: return dl_eval_m<MM>(a, s);
         FC2D_NEAR(4) FC2D_NEAR(5) FC2D_NEAR(6) FC2D_NEAR(7) FC2D_NEAR(8) FC2D_NEAR(13) FC2D_NEAR(15)
 #undef FC2D_NEAR
         default: set_error("unsupported M"); return FC2D_E_ARG;

@@ -253,6 +253,15 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     const int capn = (int)std::min<double>((double)std::max<int64_t>(pl->n_in, 1), ceil(4.0 * perim / g.h) + 64.0);
     const int64_t nall = (int64_t)nb * (2 * kRefine - 1);   // nodes of all levels
     const int64_t cap = std::max<int64_t>(pl->n_in, 1);
+    // band entries of a level whose nodes are split over blocks (2^15 nodes or more): such a
+    // point lies closer to Gamma than D = 7 dsmax / 2^(L - 1) + 2 sag (its distance bound plus
+    // the polygon's deviation both ways), so its h-square lies in the tube of radius
+    // D + h / sqrt 2 about Gamma, whose area is at most 2 r P + pi r^2
+    int lc = 1;
+    while (lc < kPoisLevels - 1 && ((int64_t)nb << lc) < (1 << 15)) ++lc;
+    const double rb = (7.0 * dsmax / (double)(1 << (lc - 1))) * (1.0 + 1e-5) + 2.0 * sag + g.h * M_SQRT1_2;
+    const int capb = (int)std::min<double>((double)cap, ceil((2.0 * rb * perim * 1.01 + M_PI * rb * rb) / (g.h * g.h)) + 64.0);
+    const int64_t scap = (int64_t)capn * (M - 1);
     const int nfm = std::min(nf, kPoisChunk);   // fields per chunk at most
     double *spec, *work, *up, *mean, *d_qc, *d_geo, *rec, *ghom, *rhs, *A, *phi, *phif, *wtab, *part, *V, *w, *hd;
     double *bx, *by, *bnx, *bny;
@@ -282,15 +291,19 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     db.add(&hd, (3 * (size_t)(m + 2) + m) * nfm);
     db.add(&cls, (size_t)npts);
     db.add(&cand, (size_t)cap);
-    db.add(&cnt, 4 + kPoisLevels);   // candidates, foot failures, level counts, near points, overflow
-    int32_t* nidx;
-    double *nw, *nv0, *samp, *sval;
+    db.add(&cnt, kPoisCounters);
+    int32_t *nidx, *sl;
+    int8_t* slev;
+    double *nw, *nv0, *samp, *sval, *bpart;
     db.add(&nidx, capn);
     db.add(&nw, (size_t)capn * M);
     db.add(&nv0, (size_t)capn * nfm);
-    db.add(&samp, (size_t)capn * (M - 1) * 2);
-    db.add(&sval, (size_t)capn * (M - 1) * nfm);
+    db.add(&samp, (size_t)scap * 2);
+    db.add(&sval, (size_t)16 * scap * nfm);
+    db.add(&sl, (size_t)scap * kPoisLevels);
+    db.add(&slev, (size_t)scap);
     db.add(&bl, (size_t)cap * kPoisLevels);
+    db.add(&bpart, (size_t)16 * capb * nfm);
     db.add(&bx, pl->B);
     db.add(&by, pl->B);
     db.add(&bnx, pl->B);
@@ -338,15 +351,13 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
         if ((st = pois_records(phi, nb, nfc, d_geo, wtab, phif, rec, s))) return st;
         // v on the grid, then the points next to Gamma
         double* uc = u + (int64_t)f0 * npts;
-        if ((e = hipMemsetAsync(cnt, 0, (4 + kPoisLevels) * sizeof(int), s)) != hipSuccess)
+        if ((e = hipMemsetAsync(cnt, 0, kPoisCounters * sizeof(int), s)) != hipSuccess)
             return hip_err(e, "Poisson solve");
-        if ((st = pois_dl_grid(&g, nfc, cls, up, rec, nb, dsmax, seg, sinv, sag, uc, bl, cap, cnt + 2, cand, cnt, s)))
-            return st;
-        int* ncnt = cnt + 2 + kPoisLevels;
-        if ((st = pois_dl_near(M, nfc, cand, cnt, cap, pl->curve, bd, 60, &g, up, ghom, nb, rec, capn, nidx, nw, nv0,
-                               samp, sval, ncnt, uc, cnt + 1, s)))
-            return st;
-        int hc[4 + kPoisLevels] = {};
+        const PoisDl dl{&g,    nfc,   M,   nb,  60,   cls,  up,   rec,  ghom, dsmax, seg, sinv, sag,
+                        pl->curve, bd, cap, bl, cand, capb, bpart, capn, nidx, nw, nv0, samp, sl, slev,
+                        sval, cnt,  uc};
+        if ((st = pois_dl_eval(dl, s))) return st;
+        int hc[kPoisCounters] = {};
         if ((e = hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
             return hip_err(e, "Poisson solve");

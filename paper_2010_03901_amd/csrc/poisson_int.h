@@ -43,28 +43,51 @@ int pois_scale(const double* a, const double* x, int64_t xs, int n, int nfc, dou
 int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s);
 // Levels of the double-layer sums: level L (0 <= L < kPoisLevels) holds 2^L nb
 // equispaced nodes at offset nb (2^L - 1) of the concatenated node arrays.
-constexpr int kPoisLevels = 6;
+constexpr int kPoisLevels = 8;
 // phi (nfc rows of nb) -> phif (nfc rows of 2^(kPoisLevels - 1) nb, the finest
 // level, by the Dirichlet kernel) -> node records of every level: (x, y) and
 // per field (phi y', phi x'), 2 + 2 nfc doubles each; geo: (x, y, x', y') per
 // node; wtab: scratch of (2^(kPoisLevels - 1) - 1) nb doubles
 int pois_records(const double* phi, int nb, int nfc, const double* geo, double* wtab, double* phif, double* rec,
                  hipStream_t s);
-// v at the IN points of nfc fields (u = u_p + v, 0 elsewhere; up and u hold
-// the fields nx ny apart); points next to Gamma listed in cand.  bl:
-// kPoisLevels lists of cap entries (cap >= IN points), bcnt their counts (zero
-// on entry), both scratch; sag: bound on how far an arc between two nodes
-// leaves its chord
-int pois_dl_grid(const fc2d_grid* g, int nfc, const int8_t* cls, const double* up, const double* rec, int nb,
-                 double dsmax, const double* seg, const double* sinv, double sag, double* u, int32_t* bl,
-                 int64_t cap, int* bcnt, int32_t* cand, int* ncand, hipStream_t s);
-// the listed points within h/2 of Gamma, nfc fields (ghom: nfc rows of nb).
-// Scratch for up to capn such points: nidx [capn], nw [capn M], nv0 [capn nfc],
-// samp [capn (M - 1)] point pairs, sval [capn (M - 1) nfc]; ncnt[0] counts them
-// and ncnt[1] those beyond capn (both zero on entry).
-int pois_dl_near(int M, int nfc, const int32_t* cand, const int* ncand, int64_t cap, const CurveC& cv,
-                 const BndView& bd, int maxit, const fc2d_grid* g, const double* up, const double* ghom, int nb,
-                 const double* rec, int capn, int32_t* nidx, double* nw, double* nv0, double* samp, double* sval,
-                 int* ncnt, double* u, int* nfail, hipStream_t s);
+// v at the IN points of one chunk of nfc fields: u = u_p + v there, 0
+// elsewhere (up and u hold the fields nx ny apart).  Every point first sums
+// the nb nodes; points within 7 node spacings of Gamma sum the level their
+// distance needs; points within h/2 of Gamma take v from the near-boundary
+// interpolation, whose samples sum the levels their distances need.
+struct PoisDl {
+    const fc2d_grid* g;
+    int nfc, M, nb, maxit;
+    const int8_t* cls;                 // [nx ny] point classes
+    const double* up;                  // [nfc][nx ny] particular solution
+    const double* rec;                 // node records of every level (pois_records)
+    const double* ghom;                // [nfc][nb] boundary data of the harmonic part
+    double dsmax;                      // largest spacing of the nb nodes
+    const double* seg;                 // nb-node polygon chords and their inverse squared lengths
+    const double* sinv;
+    double sag;                        // bound on how far an arc between two nodes leaves its chord
+    CurveC cv;
+    BndView bd;                        // plan boundary samples (foot seeds)
+    int64_t cap;                       // >= IN points
+    int32_t* bl;                       // [kPoisLevels][cap] band lists
+    int32_t* cand;                     // [cap] candidates
+    int capb;                          // band entries per level whose nodes are split over blocks
+    double* bpart;                     // [16][capb][nfc] chunk sums of those levels
+    int capn;                          // near points at most
+    int32_t* nidx;                     // [capn]
+    double* nw;                        // [capn M]
+    double* nv0;                       // [capn nfc]
+    double* samp;                      // [capn (M - 1)] point pairs
+    int32_t* sl;                       // [kPoisLevels][capn (M - 1)] sample lists
+    int8_t* slev;                      // [capn (M - 1)] sample levels
+    double* sval;                      // [16][capn (M - 1)][nfc] chunk sums of the samples
+    int* cnt;                          // kPoisCounters counters, zero on entry
+    double* u;                         // [nfc][nx ny]
+};
+// counters: [0] candidates, [1] failed feet, [2 + L] band entries of level L,
+// [2 + kPoisLevels] near points, [3 + kPoisLevels] entries beyond capn or
+// capb, [4 + kPoisLevels + L] samples of level L
+constexpr int kPoisCounters = 4 + 2 * kPoisLevels;
+int pois_dl_eval(const PoisDl& a, hipStream_t s);
 
 }  // namespace fc2d

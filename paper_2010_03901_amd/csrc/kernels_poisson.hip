@@ -319,7 +319,9 @@ __device__ inline double inv_r2(double r2) {
 // fields, not yet divided by the node count: sum[f].  The records come through
 // the scalar cache (wave-uniform addresses), 8 / NF per wait, their
 // reciprocals formed side by side; distance and reciprocal are shared by the
-// fields.  With MIN also a lower bound of the smallest squared node distance:
+// fields, and for one or two fields two terms share one reciprocal (of the
+// product of their squared distances, at most about 1e4 and at least about
+// 1e-20 here: normal numbers).  With MIN also a lower bound of the smallest squared node distance:
 // the minimum of the high words, low word zero (relative error below 2^-20,
 // rounded down; it only steers the level choice and the candidate test).
 template <bool MIN, int NF>
@@ -343,16 +345,32 @@ __device__ inline void dl_partial(const DlRec<NF>* __restrict__ rec, int j0, int
             r2[u] = dx[u] * dx[u] + dy[u] * dy[u];
             if (MIN) dmh = min(dmh, (unsigned)(__double_as_longlong(r2[u]) >> 32));
         }
+        if constexpr (NF <= 2) {
+            // pairs over one reciprocal: n0 / r0 + n1 / r1 = (n0 r1 + n1 r0) / (r0 r1)
 #pragma unroll
-        for (int u = 0; u < U; ++u) rv[u] = inv_r2(r2[u]);
+            for (int u = 0; u < U; u += 2) rv[u] = inv_r2(r2[u] * r2[u + 1]);
 #pragma unroll
-        for (int u = 0; u < U; ++u)
+            for (int u = 0; u < U; u += 2)
 #pragma unroll
-            for (int f = 0; f < NF; ++f) {
-                const double t = (dx[u] * b[u].ab[2 * f] - dy[u] * b[u].ab[2 * f + 1]) * rv[u];
-                if (u & 1) s1[f] += t;
-                else s0[f] += t;
-            }
+                for (int f = 0; f < NF; ++f) {
+                    const double n0 = dx[u] * b[u].ab[2 * f] - dy[u] * b[u].ab[2 * f + 1];
+                    const double n1 = dx[u + 1] * b[u + 1].ab[2 * f] - dy[u + 1] * b[u + 1].ab[2 * f + 1];
+                    const double t = fma(n0, r2[u + 1], n1 * r2[u]) * rv[u];
+                    if (u & 2) s1[f] += t;
+                    else s0[f] += t;
+                }
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) rv[u] = inv_r2(r2[u]);
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int f = 0; f < NF; ++f) {
+                    const double t = (dx[u] * b[u].ab[2 * f] - dy[u] * b[u].ab[2 * f + 1]) * rv[u];
+                    if (u & 1) s1[f] += t;
+                    else s0[f] += t;
+                }
+        }
     }
     for (; j < j1; ++j) {
         const DlRec<NF> b = rec[j];
@@ -628,10 +646,34 @@ __global__ __launch_bounds__(64) void k_near_prep(const int32_t* __restrict__ ca
             for (int f = 0; f < NF; ++f) nv0[(int64_t)k * NF + f] = any > 0.0 ? hv[f] : sv[f];
             for (int m = 0; m < M; ++m) nw[(int64_t)k * M + m] = w[m];
         }
-        const double sh = 0.5 * h * (lane < M ? lane : M - 1);
-        const double px = o[0] + sh * ix, py = o[1] + sh * iy;
-        const double dsb = sqrt(poly_dist2(seg, sinv, nb, px, py)) - sag;   // every lane (uniform chords)
+        // squared distances of the M - 1 samples to the nb-node polygon: the
+        // lanes split the chords, then a wave minimum
+        double sm[M - 1];
+#pragma unroll
+        for (int m = 0; m < M - 1; ++m) sm[m] = 1e300;
+        for (int j = lane; j < nb; j += 64) {
+            const double4 c = seg[j];
+            const double iv = sinv[j];
+#pragma unroll
+            for (int m = 0; m < M - 1; ++m) {
+                const double sh = 0.5 * h * (m + 1);
+                const double vx = o[0] + sh * ix - c.x, vy = o[1] + sh * iy - c.y;
+                const double t = fmin(fmax((vx * c.z + vy * c.w) * iv, 0.0), 1.0);
+                const double dx = vx - t * c.z, dy = vy - t * c.w;
+                sm[m] = fmin(sm[m], dx * dx + dy * dy);
+            }
+        }
+        double mine = 0.0;
+#pragma unroll
+        for (int m = 0; m < M - 1; ++m) {
+#pragma unroll
+            for (int of = 32; of > 0; of >>= 1) sm[m] = fmin(sm[m], __shfl_xor(sm[m], of, 64));
+            if (m == lane - 1) mine = sm[m];
+        }
         if (lane >= 1 && lane < M) {
+            const double sh = 0.5 * h * lane;
+            const double px = o[0] + sh * ix, py = o[1] + sh * iy;
+            const double dsb = sqrt(mine) - sag;
             const int64_t si = (int64_t)k * (M - 1) + lane - 1;
             samp[si] = make_double2(px, py);
             const int L = dsb >= 7.0 * dsmax ? 0 : dl_level(dsb, dsmax);

@@ -213,7 +213,9 @@ def test_poisson_full_size_sampled(torch_mod):
     sin(2 pi y) / (8 pi^2)), solved on the GPU as the benchmark does, against the
     oracle's solve at 600 seeded IN points (400 uniform, 200 within 2h of the
     boundary samples, so the near-boundary interpolation is included): 1e-11 of
-    max |u|."""
+    max |u|.  Against the exact solution over every IN point the solve holds
+    2e-12 of max |u| (measured 3.6e-13): the near-boundary sums are resolved,
+    not just equal on both sides."""
     from scipy.spatial import cKDTree
     from gpu_common import gpu_plan, oracle_plan
     from paper_2010_03901_amd import fc2d
@@ -245,6 +247,10 @@ def test_poisson_full_size_sampled(torch_mod):
     ex = _u_exact(X.ravel()[sample], Y.ravel()[sample])
     print("[poisson] full size: rel err vs oracle %.2e (vs exact %.2e)" % (e, np.abs(ref - ex).max() / np.abs(ex).max()))
     assert e < 1e-11
+    exa = _u_exact(X.ravel()[ins], Y.ravel()[ins])
+    ea = np.abs(U[ins] - exa).max() / np.abs(exa).max()
+    print("[poisson] full size: GPU l_inf vs exact over all IN points %.2e" % ea)
+    assert ea < 2e-12
 
 
 def test_poisson_field_chunks(torch_mod):

@@ -214,6 +214,17 @@ __global__ void k_scale(Scal4 a, const double* __restrict__ x, int64_t xs, int n
     if (i < n) y[ys * blockIdx.y + i] = a.a[blockIdx.y] * x[xs * blockIdx.y + i];
 }
 
+// y_f = x_f / sqrt(h_f) with h_f = hn[f hs] read on the device (zeros when h_f
+// is not positive): the next Arnoldi vector without a trip to the host
+__global__ void k_normalize(const double* __restrict__ x, int64_t xs, int n, const double* __restrict__ hn,
+                            int64_t hs, double* __restrict__ y, int64_t ys) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double hv = hn[hs * blockIdx.y];
+    const double sc = hv > 0.0 ? 1.0 / sqrt(hv) : 0.0;
+    y[ys * blockIdx.y + i] = sc * x[xs * blockIdx.y + i];
+}
+
 // y = a x + b z
 __global__ void k_axpbz(double a, const double* __restrict__ x, double b, const double* __restrict__ z, int n,
                         double* __restrict__ y) {
@@ -840,7 +851,13 @@ int pois_scale(const double* a, const double* x, int64_t xs, int n, int nfc, dou
     Scal4 sc{};
     for (int f = 0; f < nfc && f < kPoisChunk; ++f) sc.a[f] = a[f];
     k_scale<<<dim3((unsigned)((n + 255) / 256), (unsigned)nfc), 256, 0, s>>>(sc, x, xs, n, y, ys);
-    return pois_check("k_axpbz", s);
+    return pois_check("k_scale", s);
+}
+
+int pois_normalize(const double* x, int64_t xs, int n, int nfc, const double* hn, int64_t hs, double* y, int64_t ys,
+                   hipStream_t s) {
+    k_normalize<<<dim3((unsigned)((n + 255) / 256), (unsigned)nfc), 256, 0, s>>>(x, xs, n, hn, hs, y, ys);
+    return pois_check("k_normalize", s);
 }
 
 int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s) {

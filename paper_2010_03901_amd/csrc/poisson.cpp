@@ -60,13 +60,55 @@ int hip_err(hipError_t e, const char* what) {
     return FC2D_E_HIP;
 }
 
+// Pinned host memory and two events for the GMRES Hessenberg columns, one set
+// per calling thread, grown on demand and kept for the thread's life (never
+// freed: a pinned allocation and its release cost more than a solve's
+// iterations, and releasing it at thread exit could outlive the runtime);
+// the events belong to the device current at creation.
+struct PinnedCols {
+    double* p;
+    size_t cap;
+    int dev;
+    hipEvent_t ev[2];
+};
+thread_local PinnedCols t_pin = {nullptr, 0, -1, {nullptr, nullptr}};
+
+int pinned_get(size_t doubles) {
+    hipError_t e;
+    int dev = 0;
+    if ((e = hipGetDevice(&dev)) != hipSuccess) return hip_err(e, "gmres");
+    if (t_pin.dev != dev) {
+        for (hipEvent_t& v : t_pin.ev) {
+            if (v) (void)hipEventDestroy(v);
+            v = nullptr;
+        }
+        t_pin.dev = -1;
+        if ((e = hipEventCreateWithFlags(&t_pin.ev[0], hipEventDisableTiming)) != hipSuccess ||
+            (e = hipEventCreateWithFlags(&t_pin.ev[1], hipEventDisableTiming)) != hipSuccess)
+            return hip_err(e, "gmres");
+        t_pin.dev = dev;
+    }
+    if (t_pin.cap < doubles) {
+        if (t_pin.p) (void)hipHostFree(t_pin.p);
+        t_pin.p = nullptr;
+        t_pin.cap = 0;
+        if ((e = hipHostMalloc((void**)&t_pin.p, doubles * sizeof(double), hipHostMallocDefault)) != hipSuccess)
+            return hip_err(e, "gmres");
+        t_pin.cap = doubles;
+    }
+    return FC2D_OK;
+}
+
 // Restarted GMRES with classical Gram-Schmidt applied twice, for nfc systems
 // A x_f = b_f at once (A column-major n x n on the device, read once per
 // iteration for all of them; b and x hold the fields n apart; x starts at
-// zero).  The Hessenberg columns come to the host, one copy and one
-// synchronisation per iteration for all fields; a field that has converged
-// keeps zero basis vectors until the others finish.  V: nfc (m + 1) n, w: nfc n,
-// hd: nfc (3 (m + 2) + m) device doubles; iters: iterations summed over fields.
+// zero).  The next basis vector is normalised on the device, so Arnoldi step
+// j + 1 is queued before the host takes step j's Hessenberg column (one copy
+// into a pinned double buffer and one wait per step for all fields): the
+// device never waits for the host's Givens rotations.  A step queued past a
+// field's convergence is discarded (its basis columns take zero weights; a
+// zero norm gives a zero vector).  V: nfc (m + 1) n, w: nfc n, hd: nfc
+// (3 (m + 2) + m) device doubles; iters: iterations summed over fields.
 int gmres(const double* A, const double* b, double* x, int n, int nfc, double* V, double* w, double* hd,
           double* part, hipStream_t s, int* iters) {
     const int m = std::min(n, kRestart);
@@ -81,6 +123,27 @@ int gmres(const double* A, const double* b, double* x, int n, int nfc, double* V
     hipError_t e;
     *iters = 0;
     if ((e = hipMemsetAsync(x, 0, (size_t)nfc * n * sizeof(double), s)) != hipSuccess) return hip_err(e, "gmres");
+    // pinned double buffer for the Hessenberg columns and one event per slot
+    // (kept by the calling thread across solves)
+    if ((st = pinned_get(2 * hh.size()))) return st;
+    PinnedCols& pin = t_pin;
+    // Arnoldi step j: w = A V_j orthogonalised twice against V_0..V_j, its
+    // column to pinned slot j & 1, V_{j+1} = w / |w|
+    auto step = [&](int j) -> int {
+        int r;
+        if ((r = pois_matvec(A, V + (size_t)j * n, VS, n, nfc, part, w, s)) ||
+            (r = pois_dots(V, VS, j + 1, w, n, n, nfc, hd, HS, s)) ||
+            (r = pois_sub(V, VS, j + 1, hd, HS, n, nfc, w, n, s)) ||
+            (r = pois_dots(V, VS, j + 1, w, n, n, nfc, hd + o2, HS, s)) ||
+            (r = pois_sub(V, VS, j + 1, hd + o2, HS, n, nfc, w, n, s)) ||
+            (r = pois_dots(w, n, 1, w, n, n, nfc, hd + on, HS, s)))
+            return r;
+        double* slot = pin.p + (size_t)(j & 1) * hh.size();
+        if ((e = hipMemcpyAsync(slot, hd, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
+            (e = hipEventRecord(pin.ev[j & 1], s)) != hipSuccess)
+            return hip_err(e, "gmres");
+        return pois_normalize(w, n, n, nfc, hd + on, HS, V + (size_t)(j + 1) * n, VS, s);
+    };
     auto fetch = [&]() -> int {
         if ((e = hipMemcpyAsync(hh.data(), hd, hh.size() * sizeof(double), hipMemcpyDeviceToHost, s)) != hipSuccess ||
             (e = hipStreamSynchronize(s)) != hipSuccess)
@@ -106,23 +169,19 @@ int gmres(const double* A, const double* b, double* x, int n, int nfc, double* V
             conv[f] = 0;
         }
         int kmax = 0;
+        if ((st = step(0))) return st;
         for (int j = 0; j < m; ++j) {
-            if ((st = pois_matvec(A, V + (size_t)j * n, VS, n, nfc, part, w, s)) ||
-                (st = pois_dots(V, VS, j + 1, w, n, n, nfc, hd, HS, s)) ||
-                (st = pois_sub(V, VS, j + 1, hd, HS, n, nfc, w, n, s)) ||
-                (st = pois_dots(V, VS, j + 1, w, n, n, nfc, hd + o2, HS, s)) ||
-                (st = pois_sub(V, VS, j + 1, hd + o2, HS, n, nfc, w, n, s)) ||
-                (st = pois_dots(w, n, 1, w, n, n, nfc, hd + on, HS, s)) || (st = fetch()))
-                return st;
+            if (j + 1 < m && (st = step(j + 1))) return st;   // queued ahead of the host's work on column j
+            if ((e = hipEventSynchronize(pin.ev[j & 1])) != hipSuccess) return hip_err(e, "gmres");
+            const double* col = pin.p + (size_t)(j & 1) * hh.size();
             bool any = false;
             for (int f = 0; f < nfc; ++f) {
-                scal[f] = 0.0;
                 if (!act[f]) continue;
                 double* Hf = &H[(size_t)f * (m + 1) * m];
                 double* csf = &cs[(size_t)f * m];
                 double* snf = &sn[(size_t)f * m];
                 double* gf = &g[(size_t)f * (m + 1)];
-                const double* hf = &hh[(size_t)f * HS];
+                const double* hf = &col[(size_t)f * HS];
                 const double hn = sqrt(hf[on]);
                 for (int i = 0; i <= j; ++i) Hf[(size_t)i * m + j] = hf[i] + hf[o2 + i];
                 Hf[(size_t)(j + 1) * m + j] = hn;
@@ -145,13 +204,11 @@ int gmres(const double* A, const double* b, double* x, int n, int nfc, double* V
                     act[f] = 0;   // converged (or an exact breakdown): this cycle ends for f
                     conv[f] = 1;
                 } else {
-                    scal[f] = 1.0 / hn;
                     any = true;
                 }
             }
             kmax = j + 1;
             if (!any) break;
-            if ((st = pois_scale(scal.data(), w, n, n, nfc, V + (size_t)(j + 1) * n, VS, s))) return st;
         }
         // y_f = H_f(0:k, 0:k)^-1 g_f, x_f += V_f y_f (as x_f -= sum (-y_f,i) V_f,i; zeros past k_f)
         std::fill(hh.begin(), hh.end(), 0.0);

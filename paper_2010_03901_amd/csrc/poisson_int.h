@@ -40,6 +40,9 @@ int pois_sub(const double* V, int64_t vs, int nv, const double* c, int64_t cs, i
 // y_f = a[f] x_f (a: nfc host values)
 int pois_scale(const double* a, const double* x, int64_t xs, int n, int nfc, double* y, int64_t ys,
                hipStream_t s);
+// y_f = x_f / sqrt(hn[f hs]) (zeros where that is not positive), hn on the device
+int pois_normalize(const double* x, int64_t xs, int n, int nfc, const double* hn, int64_t hs, double* y, int64_t ys,
+                   hipStream_t s);
 int pois_axpbz(double a, const double* x, double b, const double* z, int n, double* y, hipStream_t s);
 // Levels of the double-layer sums: level L (0 <= L < kPoisLevels) holds 2^L nb
 // equispaced nodes at offset nb (2^L - 1) of the concatenated node arrays.

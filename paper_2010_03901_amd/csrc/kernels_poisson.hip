@@ -317,13 +317,14 @@ __global__ void k_records(const double4* __restrict__ geo, const double* __restr
     rec[i] = r;
 }
 
-// 1 / r2 from the hardware reciprocal and two Newton steps (a few ulp; the
-// squared distances here are normal numbers far from the range limits)
+// 1 / r2 from the hardware reciprocal r and its residual e = 1 - r2 r:
+// 1 / r2 = r / (1 - e) = r (1 + e + e^2) up to e^3 relative (|e| < 2^-24, so
+// rounding dominates: as accurate as two Newton steps, one instruction fewer;
+// the squared distances here are normal numbers far from the range limits)
 __device__ inline double inv_r2(double r2) {
-    double r = __builtin_amdgcn_rcp(r2);
-    r = fma(fma(-r2, r, 1.0), r, r);
-    r = fma(fma(-r2, r, 1.0), r, r);
-    return r;
+    const double r = __builtin_amdgcn_rcp(r2);
+    const double e = fma(-r2, r, 1.0);
+    return fma(r, fma(e, e, e), r);
 }
 
 // trapezoidal double-layer terms of the node records [j0, j1) at (X, Y) for NF
@@ -463,16 +464,42 @@ __global__ __launch_bounds__(256) void k_dl_grid(const int8_t* __restrict__ cls,
     // one 8 x 8 tile of points per wave
     const int tj = (ny + 7) >> 3;
     const int tile = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
-    const int i = (tile / tj) * 8 + (l >> 3), j = (tile % tj) * 8 + (l & 7);
-    if (i >= nx || j >= ny) return;
+    const int i0 = (tile / tj) * 8, jt0 = (tile % tj) * 8;
+    const int i = i0 + (l >> 3), j = jt0 + (l & 7);
     const int64_t e = (int64_t)i * ny + j;
-    if (cls[e] != 1) {
+    const bool in = i < nx && j < ny && cls[e] == 1;
+    if (i < nx && j < ny && !in) {
 #pragma unroll
         for (int f = 0; f < NF; ++f) u[f * npts + e] = 0.0;
-        return;
     }
+    if (__ballot(in) == 0) return;   // wave-uniform: every lane is still active here
+    // far tile: its centre's distance to the nb-node polygon (the lanes split
+    // the chords), less the tile's half-diagonal and sag, clears the listing
+    // threshold max(7 dsmax, h/2) + dsmax / 2 for every point: no nearest-node
+    // minimum needed
+    double cm = 1e300;
+    {
+        const double cx = x0 + (i0 + 3.5) * h, cy = y0 + (jt0 + 3.5) * h;
+        for (int q = l; q < nb; q += 64) {
+            const double4 c = seg[q];
+            const double vx = cx - c.x, vy = cy - c.y;
+            const double t = fmin(fmax((vx * c.z + vy * c.w) * sinv[q], 0.0), 1.0);
+            const double dx = vx - t * c.z, dy = vy - t * c.w;
+            cm = fmin(cm, dx * dx + dy * dy);
+        }
+#pragma unroll
+        for (int of = 32; of > 0; of >>= 1) cm = fmin(cm, __shfl_xor(cm, of, 64));
+    }
+    const bool far = sqrt(cm) - 3.5 * M_SQRT2 * h - sag > (fmax(7.0 * dsmax, 0.5 * h) + 0.5 * dsmax) * (1.0 + 1e-12);
+    if (!in) return;
     const double X = x0 + i * h, Y = y0 + j * h;
     double d2, sum[NF];
+    if (far) {
+        dl_partial<false, NF>(rec, 0, nb, X, Y, sum, &d2);
+#pragma unroll
+        for (int f = 0; f < NF; ++f) u[f * npts + e] = up[f * npts + e] + sum[f] / nb;
+        return;
+    }
     dl_partial<true, NF>(rec, 0, nb, X, Y, sum, &d2);
 #pragma unroll
     for (int f = 0; f < NF; ++f) u[f * npts + e] = up[f * npts + e] + sum[f] / nb;

@@ -1,6 +1,7 @@
 """Pins for the oracle's full Poisson solver (Sec. 4.1): the double-layer
 kernel against Gauss's lemma, the trigonometric interpolant against the FFT
-zero-padding interpolant, the Laplace part against harmonic closed forms
+zero-padding interpolant, the refined near-boundary sum against adaptive
+quadrature of the continuous double-layer integral, the Laplace part against harmonic closed forms
 (also at grid points next to Gamma), and the whole solver against the paper's
 Table 3 (kite, d = 4, M = M_P = d + 1 .. d + 3)."""
 import math
@@ -62,6 +63,45 @@ def _u_exact(x, y):
 
 def _f(x, y):
     return -np.sin(2 * np.pi * x) * np.sin(2 * np.pi * y)
+
+
+@pytest.mark.parametrize("frac", [0.108, 0.5])
+def test_refined_sum_against_adaptive_quadrature(frac):
+    """The refined trapezoidal double-layer sum (density carried to REFINE nb
+    nodes by its trigonometric interpolant) at a point inside Gamma, frac times
+    the largest node spacing from it along the inward normal, against the
+    continuous double-layer integral of Sec. 4.1 by adaptive Gauss-Kronrod
+    quadrature (scipy's quad, told where the near-singular peak is): 1e-13.
+    frac = 0.108 is how close the h/2 near-boundary sample comes to Gamma, in
+    node spacings, with nb = N on the fitted 2048^2 kite; there a 32x
+    refinement is off by about 4e-10, which is why REFINE is 128."""
+    import warnings
+    from scipy.integrate import IntegrationWarning, quad
+    cv = Curve(*W.kite(0.65, 1.5))
+    nb = 256
+    t, q, q1, _ = PS.nodes(cv, nb)
+    ds = np.hypot(q1[:, 0], q1[:, 1]) * 2.0 * math.pi / nb
+    phi = lambda tt: np.exp(np.cos(tt)) + 0.3 * np.sin(3.0 * tt)   # resolved by 256 nodes to rounding
+    t0 = t[int(np.argmax(ds))] + 0.37 * 2.0 * math.pi / nb         # between two nodes, widest spacing
+    x, y, x1, y1, _, _ = cv.eval_vec(np.array([t0]))
+    nin = np.array([-y1[0], x1[0]]) / math.hypot(x1[0], y1[0])
+    P = np.array([x[0], y[0]]) + frac * ds.max() * nin
+
+    def integrand(tt):
+        X, Y, X1, Y1, _, _ = cv.eval_vec(np.array([tt]))
+        dx, dy = P[0] - X[0], P[1] - Y[0]
+        return phi(tt) * (dx * Y1[0] - dy * X1[0]) / (dx * dx + dy * dy) / (2.0 * math.pi)
+
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore", IntegrationWarning)   # it reports reaching rounding
+        ref, _ = quad(integrand, 0.0, 2.0 * math.pi, points=[t0], epsabs=1e-15, epsrel=1e-15, limit=5000)
+
+    def refined(R):
+        return PS.double_layer(cv, PS.trig_interp(phi(t), 2.0 * math.pi * np.arange(R * nb) / (R * nb)), P[None])[0]
+
+    assert abs(refined(PS.REFINE) - ref) < 1e-13 * abs(ref)
+    if frac < 0.2:
+        assert abs(refined(32) - ref) > 1e-11 * abs(ref)
 
 
 def test_laplace_part_harmonic_data():

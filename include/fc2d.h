@@ -261,9 +261,11 @@ int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, con
  * most this many normals of Gram records are staged in LDS per block of 512
  * STRIP points (0 = no cap beyond the LDS budget; n ignored); blocks whose
  * stencils span more normals read the records from device memory instead.
- * FC2D_TUNE_FF_SHAPE: index of the compiled (E, T) shape of the fused
- * column-pass + propagation kernel for length n (batches; n = 256, 512, 1024:
- * 0..2, n = 2048: 0..3, other lengths: 0).  Not thread-safe against
+ * FC2D_TUNE_FF_SHAPE: index of the compiled shape of the fused column-pass +
+ * propagation kernel for length n (batches; n = 256, 512: 0..2, n = 1024:
+ * 0..3, n = 2048: 0..5, n = 4096: 0..1, other lengths: 0; the last index of
+ * 1024 and 4096 and the last two of 2048 take one column of both spectra per
+ * block, propagated in registers).  Not thread-safe against
  * concurrent launches. */
 int fc2d_tune_set(int knob, int n, int value);
 int fc2d_tune_get(int knob, int n, int* value);

@@ -834,15 +834,73 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
     for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, tt) * rs] = v[k];
 }
 
-// shapes (elements per thread, columns per block) of the fused kernel per
-// length 2^lg: g_colff_var[lg] indexes the compiled list of that length
+// The same fused step with one column of u_hat and the same column of u_t_hat
+// per block, both transformed by the same threads with the same index
+// pattern: after the forward transforms each thread holds both spectra at the
+// same modes, so the propagation happens in registers (no partner exchange),
+// and the two transforms take turns on one column of LDS (16 L bytes for L / E
+// threads: at L = 2048 five blocks fit a CU where the two-spectra kernel fits
+// two).
+template <int L, int E, bool TRANS>
+__global__ __launch_bounds__(L / E) void k_cols_ffp(double2* __restrict__ su, double2* __restrict__ sut, int ncol,
+                                                   double Lx, double Ly, double c, double t, int by_field) {
+    __shared__ double2 lds[L];
+    const int tt = threadIdx.x;
+    int col, field;
+    if (!col_block(ncol, by_field != 0, &col, &field)) return;   // uniform per block
+    const int64_t rs = TRANS ? 1 : ncol;   // row stride of a column
+    const int64_t off = TRANS ? ((int64_t)field * ncol + col) * L : (int64_t)field * L * ncol + col;
+    double2* bu = su + off;
+    double2* bt = sut + off;
+    double2 a[E], b[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        a[k] = bu[(int64_t)in_index<L, E>(k, tt) * rs];
+        b[k] = bt[(int64_t)in_index<L, E>(k, tt) * rs];
+    }
+    StockhamFrom<L, E, 1, false>::run(a, lds, 1, 1, 0, tt, nullptr, L);
+    __syncthreads();   // the last stage of a may still read lds
+    StockhamFrom<L, E, 1, false>::run(b, lds, 1, 1, 0, tt, nullptr, L);
+    // a[k], b[k]: row out_index(k, tt) of both spectra
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly;
+#pragma unroll
+    for (int k = 0; k < E; ++k)
+        ff_apply(ff_coef(row_freq(out_index<L, E>(k, tt), L), col, iLx, iLy, c, t), a[k], b[k], &a[k], &b[k]);
+    // inverse transforms in turn: to the input order through lds, transform, write
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[swz(out_index<L, E>(k, tt))] = a[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) a[k] = lds[swz(in_index<L, E>(k, tt))];
+    __syncthreads();
+    StockhamFrom<L, E, 1, true>::run(a, lds, 1, 1, 0, tt, nullptr, L);
+#pragma unroll
+    for (int k = 0; k < E; ++k) bu[(int64_t)out_index<L, E>(k, tt) * rs] = a[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) lds[swz(out_index<L, E>(k, tt))] = b[k];
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < E; ++k) b[k] = lds[swz(in_index<L, E>(k, tt))];
+    __syncthreads();
+    StockhamFrom<L, E, 1, true>::run(b, lds, 1, 1, 0, tt, nullptr, L);
+#pragma unroll
+    for (int k = 0; k < E; ++k) bt[(int64_t)out_index<L, E>(k, tt) * rs] = b[k];
+}
+
+// shapes of the fused kernel per length 2^lg (elements per thread and columns
+// per block of k_cols_ff, then the paired k_cols_ffp shapes): g_colff_var[lg]
+// indexes the compiled list of that length
 static int g_colff_var[14] = {0};
 
 int colff_variants(int nx) {
     switch (nx) {
-        case 256: case 512: case 1024: return 3;
-        case 2048: return 4;
-        case 16: case 32: case 64: case 128: case 4096: return 1;
+        case 256: case 512: return 3;
+        case 1024: return 4;
+        case 2048: return 6;
+        case 4096: return 2;
+        case 16: case 32: case 64: case 128: return 1;
     }
     return 0;
 }
@@ -879,6 +937,20 @@ int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int
     FC2D_COLFF(2048, 0, 8, 2) FC2D_COLFF(2048, 1, 8, 4) FC2D_COLFF(2048, 2, 16, 2) FC2D_COLFF(2048, 3, 16, 4)
     FC2D_COLFF(4096, 0, 16, 2)
 #undef FC2D_COLFF
+#define FC2D_COLFFP(LL, VV, EE)                                                                               \
+    if (g->nx == LL && var == VV) {                                                                          \
+        const bool byf = nf % 8 == 0;                                                                        \
+        const dim3 grid = byf ? dim3((unsigned)(nf * ncol)) : dim3(((ncol + 7) / 8) * 8, nf);                \
+        if (trans)                                                                                           \
+            k_cols_ffp<LL, EE, true><<<grid, LL / EE, 0, s>>>((double2*)su, (double2*)sut, ncol, Lx, Ly, c, t, \
+                                                              byf ? 1 : 0);                                  \
+        else                                                                                                 \
+            k_cols_ffp<LL, EE, false><<<grid, LL / EE, 0, s>>>((double2*)su, (double2*)sut, ncol, Lx, Ly, c,  \
+                                                               t, byf ? 1 : 0);                              \
+        return check("k_cols_ff", s);                                                                        \
+    }
+    FC2D_COLFFP(1024, 3, 8) FC2D_COLFFP(2048, 4, 8) FC2D_COLFFP(2048, 5, 16) FC2D_COLFFP(4096, 1, 16)
+#undef FC2D_COLFFP
     set_error("cols_ff: unsupported length");
     return FC2D_E_ARG;
 }

@@ -264,3 +264,46 @@ def test_batch_interior_only_plan(torch_mod):
             et = rel_err(dut[f].cpu().numpy(), out_)
             print("\n[batch] interior-only mix plan %d field %d: u %.2e u_t %.2e" % (k, f, eu, et), end="")
             assert eu < 1e-11 and et < 1e-11
+
+
+@pytest.mark.gpu
+@pytest.mark.parametrize("n", [1024, 2048])
+def test_every_fused_shape_matches_separate(torch_mod, n):
+    """Every compiled shape of the fused column-pass + propagation kernel for
+    length n (the two-spectra blocks and the paired one-column blocks that
+    propagate in registers), with row-major and transposed spectra, against
+    the separate column passes and propagation on the same kite plan and data
+    (one step of two fields): 1e-13."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    case = W.cfg_ff("kite", n)
+    gpl = gpu_plan(case)
+    u0 = [_pulses(case, range(2))]
+
+    def run(fused, trans):
+        b = fc2d.Batch([gpl], [2], fused_ff=fused, transposed=trans)
+        _load_state(b, u0)
+        b.run_ff(1.0, 0.02, 1, use_graph=False)
+        torch.cuda.synchronize()
+        r = [t.cpu().numpy().copy() for t in b.state(0)]
+        b.close()
+        return r
+
+    ref = run(False, False)
+    keep = fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_FF_SHAPE, n)
+    nshape = 0
+    try:
+        while True:
+            try:
+                fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_FF_SHAPE, n, nshape)
+            except Exception:
+                break
+            for trans in (False, True):
+                print("\n[batch] n=%d fused shape %d transposed %d" % (n, nshape, trans), end="", flush=True)
+                got = run(True, trans)
+                for j in (0, 1):
+                    assert rel_err(got[j], ref[j]) < 1e-13
+            nshape += 1
+    finally:
+        fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_FF_SHAPE, n, keep)
+    assert nshape == {1024: 4, 2048: 6}[n]

@@ -227,9 +227,11 @@ int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStr
  * g.  fc2d_poisson_solve: device f_grid [nf][nx][ny] (IN entries read),
  * f_bdry [nf][n_bdry] (the plan's boundary points), g_nodes [nf][nb]; writes
  * u [nf][nx][ny] (IN points; every other point 0).  Power-of-two grids, 8 <= nb
- * <= 16384.  Allocates its work buffers, synchronises `stream` (GMRES reads its
- * scalars on the host), returns the GMRES iterations summed over the fields in
- * *gmres_iters (may be NULL).  FC2D_E_NEWTON when GMRES or a foot solve fails;
+ * <= 16384.  Keeps its device work buffer on the plan between solves (grown
+ * when a solve needs more, released by fc2d_plan_destroy), so solves on one
+ * plan must not overlap; synchronises `stream` (GMRES reads its scalars on the
+ * host), returns the GMRES iterations summed over the fields in *gmres_iters
+ * (may be NULL).  FC2D_E_NEWTON when GMRES or a foot solve fails;
  * FC2D_E_NOMEM when the work buffers (about 3 + min(nf, 4) grids of nx ny
  * doubles plus 8 nb^2 bytes) do not fit. */
 int fc2d_poisson_nodes(const fc2d_plan* plan, int nb, double* xy);

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "internal.h"
+#include "poisson_int.h"
 
 namespace fc2d {
 
@@ -391,6 +392,7 @@ static void free_plan(fc2d_plan* pl) {
     if (!pl) return;
     void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_sidx,
                     pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c, pl->d_cls2, pl->d_bxy};
+    pois_release(pl);
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;

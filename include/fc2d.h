@@ -19,6 +19,13 @@
  *  - Calls taking a stream enqueue work asynchronously on it (NULL = the null
  *    stream); enqueue-time errors are returned, kernel faults surface at the
  *    next synchronisation.
+ *  - A plan is read-only after creation.  Calls that need device work space
+ *    (the Gram records of the matching step, the buffers of a Poisson solve)
+ *    take it per call from a library-owned memory pool, ordered on the call's
+ *    stream, and return it on that stream; so calls sharing one plan may run
+ *    concurrently on different streams (and from different host threads).
+ *    The exceptions are named where they occur: a batch (fc2d_batch_*) is
+ *    advanced by one stream at a time, and the tuning knobs are process-wide.
  */
 #ifndef FC2D_H
 #define FC2D_H
@@ -201,11 +208,15 @@ int fc2d_boundary_values(const fc2d_plan* plan, const double* u, double* f_bdry,
 int fc2d_extend_fft(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, double* work,
                     void* spec, int nf, hipStream_t stream);
 
+
 /* 2D FFT (Sec. 3.5 step 7); nx a power of two in [16, 4096], ny a power of
  * two in [16, 8192] (Remark 3.2: the grid is padded to FFT-friendly sizes).
- * FC2D_FORWARD: in = real [nf][nx][ny], out = half spectrum, unnormalised.
- * FC2D_INVERSE: in = half spectrum (overwritten as work space), out = real,
- * scaled by 1/(nx ny).  in and out must not overlap. */
+ * FC2D_FORWARD: in = real [nf][nx][ny] (not modified), out = half spectrum,
+ * unnormalised.
+ * FC2D_INVERSE: in = half spectrum, overwritten: the inverse column pass runs
+ * in place on it before the row pass writes the reals (keeping it would take a
+ * second spectrum-sized buffer per call), out = real, scaled by 1/(nx ny).
+ * in and out must not overlap; `in` is therefore not const. */
 int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStream_t stream);
 
 /* Full Poisson solve (Sec. 4.1; eq. def_poisson): Delta u = f in Omega, u = g on
@@ -217,7 +228,7 @@ int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStr
  * potential whose density solves the second-kind Nystrom system of the
  * trapezoidal rule on nb nodes q(2 pi j / nb), by GMRES; u_p on Gamma comes from
  * degree-(M-1) tensor interpolation (the plan's M).  v is summed at the IN grid
- * points (density refined up to 32x near Gamma); points within h/2 of Gamma use the
+ * points (density refined up to 128x near Gamma); points within h/2 of Gamma use the
  * foot value and M - 1 values along the inward normal at h/2, h, ...
  * interpolated in the distance with degree M - 1.  Fields are solved in chunks
  * of up to four that share the GMRES passes over the Nystrom matrix and the
@@ -227,10 +238,9 @@ int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStr
  * g.  fc2d_poisson_solve: device f_grid [nf][nx][ny] (IN entries read),
  * f_bdry [nf][n_bdry] (the plan's boundary points), g_nodes [nf][nb]; writes
  * u [nf][nx][ny] (IN points; every other point 0).  Power-of-two grids, 8 <= nb
- * <= 16384.  Keeps its device work buffer on the plan between solves (grown
- * when a solve needs more, released by fc2d_plan_destroy), so solves on one
- * plan must not overlap; synchronises `stream` (GMRES reads its scalars on the
- * host), returns the GMRES iterations summed over the fields in *gmres_iters
+ * <= 16384.  Takes its device work space per call on `stream` (from the
+ * library's pool, so solves on one plan may overlap on different streams);
+ * synchronises `stream` (GMRES reads its scalars on the host), returns the GMRES iterations summed over the fields in *gmres_iters
  * (may be NULL).  FC2D_E_NEWTON when GMRES or a foot solve fails;
  * FC2D_E_NOMEM when the work buffers (about 3 + min(nf, 4) grids of nx ny
  * doubles plus 8 nb^2 bytes) do not fit. */

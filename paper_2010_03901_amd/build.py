@@ -9,6 +9,7 @@ import shutil
 import subprocess
 import sys
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
@@ -17,7 +18,7 @@ OUT = os.path.join(PKG, "libfc2d.so")
 BUILD = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp", "poisson.cpp"]
+HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp", "poisson.cpp", "workspace.cpp"]
 HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip", "kernels_mlp.hip", "kernels_poisson.hip"]
 
 HIPCC_FLAGS = [
@@ -44,16 +45,15 @@ def build(verbose=False):
     os.makedirs(BUILD, exist_ok=True)
     hipcc = os.path.join(ROCM, "bin", "hipcc")
     gxx = shutil.which("g++") or "g++"
-    objs = []
+    jobs = [[gxx] + GXX_FLAGS + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")]
+            for src in HOST_SRC]
+    jobs += [[hipcc] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, src), "-o", os.path.join(BUILD, src + ".o")]
+             for src in HIP_SRC]
+    objs = [j[-1] for j in jobs]
     t0 = time.time()
-    for src in HOST_SRC:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([gxx] + GXX_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
-    for src in HIP_SRC:
-        obj = os.path.join(BUILD, src + ".o")
-        _run([hipcc] + HIPCC_FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj])
-        objs.append(obj)
+    # the translation units are independent: compile them side by side
+    with ThreadPoolExecutor(max_workers=min(len(jobs), os.cpu_count() or 1, 8)) as ex:
+        list(ex.map(_run, jobs))
     tmp = OUT + ".tmp"
     _run([hipcc, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs +
          ["-lquadmath", "-lgomp", "-Wl,-rpath," + os.path.join(ROCM, "lib")])

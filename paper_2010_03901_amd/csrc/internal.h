@@ -28,6 +28,28 @@ struct DevBuf {
     size_t bytes = 0;
 };
 
+// Per-call device work space, stream-ordered (workspace.cpp): taken from a
+// library-owned pool on stream s and returned on s, so calls on different
+// streams never share it.
+int ws_alloc(size_t bytes, hipStream_t s, void** p);
+int ws_free(void* p, hipStream_t s);
+// Holder that returns its memory on the stream when the call ends; work
+// already queued on that stream still sees it (the release is stream-ordered).
+struct WorkSpace {
+    void* p = nullptr;
+    hipStream_t s = nullptr;
+    int alloc(size_t bytes, hipStream_t st) {
+        s = st;
+        return ws_alloc(bytes, st, &p);
+    }
+    WorkSpace() = default;
+    WorkSpace(const WorkSpace&) = delete;
+    WorkSpace& operator=(const WorkSpace&) = delete;
+    ~WorkSpace() {
+        if (p) (void)ws_free(p, s);
+    }
+};
+
 }  // namespace fc2d
 
 // The plan: host copies needed by the host-side queries plus device arrays
@@ -69,8 +91,6 @@ struct fc2d_plan {
     double* d_bxy = nullptr;        // [n_bdry][2] boundary points (feet, then squares)
     uint8_t* d_cls2 = nullptr;      // [nx][ny/2] pair classes (2 bits per point) in row-pass thread order
     int nruns = 0;
-    double* d_c = nullptr;          // [nf_cap][B][DP] Gram coefficients, boundary value, pad (DP = (d+2)&~1)
-    int nf_cap = 0;
 };
 
 namespace fc2d {
@@ -156,6 +176,11 @@ int launch_blend(const fc2d_plan* pl, const double* c, double* F, int nf, hipStr
 int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry,
                  double* out, int nf, hipStream_t s);
 int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, hipStream_t s);
+// Gram records [nf][B][DP] (c_0..c_{d-1}, boundary value, zero pad; DP = (d+2)&~1)
+// written by launch_match and read by launch_strip
+inline size_t gram_bytes(const fc2d_plan* pl, int nf) {
+    return (size_t)nf * (size_t)pl->B * (size_t)((pl->d + 2) & ~1) * sizeof(double);
+}
 
 // ---- FFT and spectral kernels (kernels_fft.hip) ----
 // strip / cls2 non-null: the rows are assembled on the fly from `in` (IN),

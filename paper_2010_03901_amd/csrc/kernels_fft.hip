@@ -12,8 +12,10 @@
 // The inverse runs pass C (inverse) in place on the spectrum, then pass R'
 // which rebuilds z from the half spectrum, inverse-transforms and writes reals
 // scaled by 1/(N_x N_y).
-// Twiddles come from a per-length table exp(-2 pi i k / N) computed on the
-// host in extended precision.
+// The Stockham stages compute their twiddles in registers (sincospi of an
+// exact ratio, powers by a product tree); only the real split of the row
+// passes reads a per-length table exp(-2 pi i k / N), computed on the host in
+// extended precision and cached per device.
 #include <hip/hip_runtime.h>
 #include <math.h>
 

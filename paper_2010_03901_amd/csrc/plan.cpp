@@ -391,8 +391,7 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
 static void free_plan(fc2d_plan* pl) {
     if (!pl) return;
     void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_sidx,
-                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_c, pl->d_cls2, pl->d_bxy};
-    pois_release(pl);
+                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_cls2, pl->d_bxy};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;
@@ -806,22 +805,6 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     return FC2D_OK;
 }
 
-int ensure_work(const fc2d_plan* cpl, int nf) {
-    fc2d_plan* pl = const_cast<fc2d_plan*>(cpl);
-    if (nf <= pl->nf_cap) return FC2D_OK;
-    if (pl->d_c) (void)hipFree(pl->d_c);
-    pl->d_c = nullptr;
-    pl->nf_cap = 0;
-    const int DP = (pl->d + 2) & ~1;   // Gram coefficients + boundary value, padded to even
-    if (hipMalloc((void**)&pl->d_c, (size_t)nf * pl->B * DP * sizeof(double)) != hipSuccess) {
-        set_error("hipMalloc failed (Gram coefficient work space)");
-        return FC2D_E_NOMEM;
-    }
-    pl->nf_cap = nf;
-    return FC2D_OK;
-}
-
-static std::mutex g_work_mu;
 
 
 }  // namespace fc2d
@@ -915,10 +898,10 @@ int fc2d_matching(const fc2d_plan* pl, const double* f_grid, const double* f_bdr
     if (st) return st;
     if (nf == 0) return FC2D_OK;
     if (!f_grid || (!f_bdry && !pl->interior_only) || !fD) { set_error("NULL argument"); return FC2D_E_ARG; }
-    std::lock_guard<std::mutex> lk(g_work_mu);
-    if ((st = ensure_work(pl, nf))) return st;
+    WorkSpace ws;
+    if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
-    return launch_match(pl, f_grid, f_bdry, nb, pl->d_c, fD, nf, s);
+    return launch_match(pl, f_grid, f_bdry, nb, (double*)ws.p, fD, nf, s);
 }
 
 int fc2d_blend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* F, int nf,
@@ -927,11 +910,12 @@ int fc2d_blend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, 
     if (st) return st;
     if (nf == 0) return FC2D_OK;
     if (!f_grid || (!f_bdry && !pl->interior_only) || !F) { set_error("NULL argument"); return FC2D_E_ARG; }
-    std::lock_guard<std::mutex> lk(g_work_mu);
-    if ((st = ensure_work(pl, nf))) return st;
+    WorkSpace ws;
+    if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
+    double* c = (double*)ws.p;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
-    if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
-    return launch_blend(pl, pl->d_c, F, nf, s);
+    if ((st = launch_match(pl, f_grid, f_bdry, nb, c, nullptr, nf, s))) return st;
+    return launch_blend(pl, c, F, nf, s);
 }
 
 int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* out, int nf,
@@ -940,16 +924,17 @@ int fc2d_extend(const fc2d_plan* pl, const double* f_grid, const double* f_bdry,
     if (st) return st;
     if (nf == 0) return FC2D_OK;
     if (!f_grid || (!f_bdry && !pl->interior_only) || !out) { set_error("NULL argument"); return FC2D_E_ARG; }
-    std::lock_guard<std::mutex> lk(g_work_mu);
-    if ((st = ensure_work(pl, nf))) return st;
+    WorkSpace ws;
+    if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
+    double* c = (double*)ws.p;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
-    if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
+    if ((st = launch_match(pl, f_grid, f_bdry, nb, c, nullptr, nf, s))) return st;
     if ((st = launch_mask(pl, f_grid, out, nf, s))) return st;
-    return launch_strip(pl, pl->d_c, f_bdry, nb, out, nf, s);
+    return launch_strip(pl, c, f_bdry, nb, out, nf, s);
 }
 
-int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
-                    int nf, hipStream_t s) {
+static int extend_fft_check(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, const double* work,
+                            const void* spec, int nf) {
     int st = check_fields(pl, nf);
     if (st) return st;
     if (nf == 0) return FC2D_OK;
@@ -960,12 +945,26 @@ int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_b
         set_error("fc2d_extend_fft: the plan's grid must have power-of-two sizes (nx <= 4096, ny <= 8192)");
         return FC2D_E_ARG;
     }
-    std::lock_guard<std::mutex> lk(g_work_mu);
-    if ((st = ensure_work(pl, nf))) return st;
+    return FC2D_OK;
+}
+
+// matching -> strip -> masked row pass -> column pass, Gram records in c
+static int extend_fft_run(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
+                          int nf, double* c, hipStream_t s) {
+    int st;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
-    if ((st = launch_match(pl, f_grid, f_bdry, nb, pl->d_c, nullptr, nf, s))) return st;
-    if ((st = launch_strip(pl, pl->d_c, f_bdry, nb, work, nf, s))) return st;
-    return fft2_r2c(g, f_grid, (double*)spec, nf, s, work, pl->d_cls2);
+    if ((st = launch_match(pl, f_grid, f_bdry, nb, c, nullptr, nf, s))) return st;
+    if ((st = launch_strip(pl, c, f_bdry, nb, work, nf, s))) return st;
+    return fft2_r2c(&pl->grid, f_grid, (double*)spec, nf, s, work, pl->d_cls2);
+}
+
+int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
+                    int nf, hipStream_t s) {
+    int st = extend_fft_check(pl, f_grid, f_bdry, work, spec, nf);
+    if (st || nf == 0) return st;
+    WorkSpace ws;
+    if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
+    return extend_fft_run(pl, f_grid, f_bdry, work, spec, nf, (double*)ws.p, s);
 }
 
 int fc2d_boundary_values(const fc2d_plan* pl, const double* u, double* f_bdry, int nf, hipStream_t s) {

@@ -9,7 +9,6 @@
 #include <algorithm>
 #include <string>
 #include <mutex>
-#include <unordered_map>
 #include <vector>
 
 #include "internal.h"
@@ -30,62 +29,30 @@ void node_data(const CurveC& cv, int n, std::vector<double>& qd) {
     for (int j = 0; j < n; ++j) curve_eval(cv, 2.0 * M_PI * (double)j / (double)n, &qd[6 * (size_t)j]);
 }
 
-// all device buffers of a solve in one allocation (256-byte aligned pieces)
-// One device work buffer per plan, kept between solves (grown when a solve
-// needs more) and released with the plan (pois_release from plan teardown).
-struct PoisBuf {
-    void* p = nullptr;
-    size_t bytes = 0;
-};
-std::mutex g_pois_mu;
-std::unordered_map<const fc2d_plan*, PoisBuf> g_pois_bufs;
-
-// The solve's buffers, carved from the plan's work buffer.
+// all device buffers of a solve in one per-call work space (256-byte aligned
+// pieces), taken on the solve's stream and returned on it when the solve ends
 struct PoisArena {
     std::vector<std::pair<void**, size_t>> req;
+    WorkSpace ws;
     template <class T>
     void add(T** p, size_t n) {
         req.push_back({(void**)p, (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255});
     }
-    bool commit(const fc2d_plan* pl) {
+    int commit(hipStream_t s) {
         size_t tot = 0;
         for (auto& r : req) tot += r.second;
-        void* base;
-        {
-            std::lock_guard<std::mutex> lk(g_pois_mu);
-            PoisBuf& b = g_pois_bufs[pl];
-            if (tot > b.bytes) {
-                if (b.p) (void)hipFree(b.p);   // the previous solve on this plan has synchronised
-                b.p = nullptr;
-                b.bytes = 0;
-                if (hipMalloc(&b.p, tot) != hipSuccess) {
-                    b.p = nullptr;
-                    return false;
-                }
-                b.bytes = tot;
-            }
-            base = b.p;
-        }
+        int st = ws.alloc(tot, s);
+        if (st) return st;
         size_t off = 0;
         for (auto& r : req) {
-            *r.first = (char*)base + off;
+            *r.first = (char*)ws.p + off;
             off += r.second;
         }
-        return true;
+        return FC2D_OK;
     }
 };
 
 }  // namespace
-
-namespace fc2d {
-void pois_release(const fc2d_plan* pl) {
-    std::lock_guard<std::mutex> lk(g_pois_mu);
-    auto it = g_pois_bufs.find(pl);
-    if (it == g_pois_bufs.end()) return;
-    if (it->second.p) (void)hipFree(it->second.p);
-    g_pois_bufs.erase(it);
-}
-}  // namespace fc2d
 
 namespace {
 
@@ -399,10 +366,7 @@ int fc2d_poisson_solve(const fc2d_plan* pl, const double* f_grid, const double* 
     db.add(&by, pl->B);
     db.add(&bnx, pl->B);
     db.add(&bny, pl->B);
-    if (!db.commit(pl)) {
-        set_error("Poisson solve: out of device memory");
-        return FC2D_E_NOMEM;
-    }
+    if (int st0 = db.commit(s)) return st0;
     hipError_t e;
     if ((e = hipMemcpyAsync(bx, pl->bx.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||
         (e = hipMemcpyAsync(by, pl->by.data(), pl->B * sizeof(double), hipMemcpyHostToDevice, s)) != hipSuccess ||

@@ -91,8 +91,6 @@ struct PoisDl {
 // [2 + kPoisLevels] near points, [3 + kPoisLevels] entries beyond capn or
 // capb, [4 + kPoisLevels + L] samples of level L
 constexpr int kPoisCounters = 4 + 2 * kPoisLevels;
-// frees the Poisson work buffer a plan keeps between solves (plan teardown)
-void pois_release(const fc2d_plan* pl);
 int pois_dl_eval(const PoisDl& a, hipStream_t s);
 
 }  // namespace fc2d

@@ -258,9 +258,23 @@ def _nf(f_grid, grid):
     return n
 
 
+def _check_bdry(plan, f_bdry, nf):
+    import torch
+    if f_bdry is not None and (f_bdry.dtype != torch.float64 or f_bdry.numel() != nf * plan.info.n_bdry):
+        raise ValueError("f_bdry must be float64 [nf][n_bdry] with n_bdry = %d" % plan.info.n_bdry)
+
+
+def _check_out(t, name, numel, dtype):
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != dtype or t.numel() != numel:
+        raise ValueError("%s must be %s with %d elements" % (name, dtype, numel))
+
+
 def fc2d_matching(plan, f_grid, f_bdry, fD, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
+    _check_bdry(plan, f_bdry, nf)
+    _check_out(fD, "fD", nf * plan.info.B * plan.info.d, torch.float64)
     _check(_lib().fc2d_matching(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
                                 _dptr(fD, "fD", torch.float64), nf, _stream(stream)))
 
@@ -268,6 +282,8 @@ def fc2d_matching(plan, f_grid, f_bdry, fD, stream=None):
 def fc2d_blend(plan, f_grid, f_bdry, F, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
+    _check_bdry(plan, f_bdry, nf)
+    _check_out(F, "F", nf * (plan.info.Cr + 1) * plan.info.B, torch.float64)
     _check(_lib().fc2d_blend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
                              _dptr(F, "F", torch.float64), nf, _stream(stream)))
 
@@ -275,23 +291,25 @@ def fc2d_blend(plan, f_grid, f_bdry, F, stream=None):
 def fc2d_extend(plan, f_grid, f_bdry, out, stream=None):
     import torch
     nf = _nf(f_grid, plan.grid)
-    if (f_bdry is not None and f_bdry.numel() != nf * plan.info.n_bdry) or out.numel() != f_grid.numel():
-        raise ValueError("f_bdry / out sizes do not match the plan")
+    _check_bdry(plan, f_bdry, nf)
+    _check_out(out, "out", f_grid.numel(), torch.float64)
     _check(_lib().fc2d_extend(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
                               _dptr(out, "out", torch.float64), nf, _stream(stream)))
 
 
-def fc2d_extend_fft(plan, f_grid, f_bdry, work, spec, stream=None):
+def _extend_fft_args(plan, f_grid, f_bdry, work, spec):
     import torch
     nf = _nf(f_grid, plan.grid)
     g = plan.grid
-    if (f_bdry is not None and f_bdry.numel() != nf * plan.info.n_bdry) or work.numel() != f_grid.numel():
-        raise ValueError("f_bdry / work sizes do not match the plan")
-    if spec.dtype != torch.complex128 or spec.numel() != nf * g.nx * (g.ny // 2 + 1):
-        raise ValueError("spec must be complex128 [nf][nx][ny/2+1]")
-    _check(_lib().fc2d_extend_fft(plan.handle, _dptr(f_grid, "f_grid", torch.float64),
-                                  _bptr(plan, f_bdry), _dptr(work, "work", torch.float64),
-                                  _dptr(spec, "spec"), nf, _stream(stream)))
+    _check_bdry(plan, f_bdry, nf)
+    _check_out(work, "work", f_grid.numel(), torch.float64)
+    _check_out(spec, "spec", nf * g.nx * (g.ny // 2 + 1), torch.complex128)
+    return (plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
+            _dptr(work, "work", torch.float64), _dptr(spec, "spec"), nf)
+
+
+def fc2d_extend_fft(plan, f_grid, f_bdry, work, spec, stream=None):
+    _check(_lib().fc2d_extend_fft(*_extend_fft_args(plan, f_grid, f_bdry, work, spec), _stream(stream)))
 
 
 def fc2d_fft(grid, inp, out, direction, stream=None):
@@ -327,13 +345,25 @@ def fc2d_poisson_solve(plan, f_grid, f_bdry, g_nodes, u, stream=None):
     return it.value
 
 
+def _nspec(t, grid, name):
+    import torch
+    ns = grid.nx * (grid.ny // 2 + 1)
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.complex128 or t.numel() % ns:
+        raise ValueError("%s must be complex128 [nf][nx][ny/2+1]" % name)
+    return t.numel() // ns
+
+
 def fc2d_spectral_apply(grid, op, inp, out, stream=None):
-    nf = inp.numel() // (grid.nx * (grid.ny // 2 + 1))
+    nf = _nspec(inp, grid, "in")
+    if _nspec(out, grid, "out") != nf:
+        raise ValueError("in and out hold different numbers of spectra")
     _check(_lib().fc2d_spectral_apply(C.byref(grid), int(op), _dptr(inp, "in"), _dptr(out, "out"), nf, _stream(stream)))
 
 
 def ff_propagate(grid, c, t, u0h, u1h, uh, uth, stream=None):
-    nf = u0h.numel() // (grid.nx * (grid.ny // 2 + 1))
+    nf = _nspec(u0h, grid, "u0h")
+    if any(_nspec(x, grid, n) != nf for x, n in ((u1h, "u1h"), (uh, "uh"), (uth, "uth"))):
+        raise ValueError("u0h, u1h, uh and uth hold different numbers of spectra")
     _check(_lib().ff_propagate(C.byref(grid), float(c), float(t), _dptr(u0h, "u0h"), _dptr(u1h, "u1h"),
                                _dptr(uh, "uh"), _dptr(uth, "uth"), nf, _stream(stream)))
 

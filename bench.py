@@ -8,7 +8,10 @@ takes their forward 2D FFT; inputs are resident in HBM before timing.
 
 Prints one JSON line (metric, value = extended grid points per second, roofline
 of the dominant kernel from HIP-event kernel times, cpu_baseline = the oracle
-timed on a bounded sample on the host).
+timed on a bounded sample on the host; the same leg compares sampled outputs
+of the timed runs with the oracle: max_rel_err_vs_oracle).  Further legs: the
+batched Fourier-Forwarding step against its plain per-plan form on identical
+work, the learned foot seed, and the full Poisson solve.
 """
 import argparse
 import json
@@ -66,7 +69,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--nf", type=int, default=128, help="fields per step")
     ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true",
+                    help="skip the cpu_baseline leg (the oracle timing and the oracle checks of sampled outputs)")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched Fourier-Forwarding measurement")
     ap.add_argument("--ff-fields", type=int, default=128, help="fields per (grid size) in the batched run")
     ap.add_argument("--ff-steps", type=int, default=100)
@@ -105,13 +109,20 @@ def algorithmic_bytes(name, n, nf, info):
     return 0
 
 
-def cpu_baseline(case, nf_sample):
-    """The oracle (plain NumPy, one thread) on nf_sample fields of the same workload."""
+def cpu_baseline(case, nf_sample, checks, ff_check):
+    """The oracle (plain NumPy, one thread) on nf_sample fields of the same
+    workload, timed; the same leg compares sampled outputs of the timed GPU
+    runs with the oracle's: checks maps a field seed to {name: GPU array} with
+    the fused path's half spectrum ("spectrum") and the plain path's extension
+    ("extension") of that field; ff_check holds one field of the batched
+    Fourier-Forwarding step and of its plain form with the initial state."""
     from threadpoolctl import threadpool_limits
     import numpy as np
     import workloads as W
-    from oracle import extend as OE, fcgram, plan as OP, spectral as OS
+    from oracle import extend as OE, fcgram, ff as OF, plan as OP, spectral as OS
     from oracle.curves import Curve
+    rel = lambda a, b: float(np.abs(a - b).max() / np.abs(b).max())
+    res = {}
     with threadpool_limits(limits=1):
         pl = OP.make_plan(Curve(*case.curve), OP.Grid(case.x0, case.y0, case.h, case.n, case.n),
                           fcgram.load_tables(case.d), case.B, k1=case.k1, M=case.M)
@@ -120,20 +131,51 @@ def cpu_baseline(case, nf_sample):
         for s in range(nf_sample):
             f = W.f_star(s)
             fields.append((W.grid_values(case, f), f(bp[:, 0], bp[:, 1])))
+        kept = {}
         t0 = time.perf_counter()
-        for fg, fb in fields:
+        for s, (fg, fb) in enumerate(fields):
             ext = OE.extend(pl, fg, fb)
-            OS.fft2_forward(ext)
+            spec = OS.fft2_forward(ext)
+            if s in checks:
+                kept[s] = (ext, spec)
         dt = time.perf_counter() - t0
-    return {"value": nf_sample * case.n * case.n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
-            "sample": "%d fields of the %dx%d star workload (plan excluded), extend + rfft2, one thread"
-                      % (nf_sample, case.n, case.n)}
+        errs = {"spectrum": [], "extension": []}
+        in_bitwise = True
+        ins = pl.cls == OP.IN
+        for s, gpu in checks.items():
+            ext, spec = kept[s]
+            errs["spectrum"].append(rel(gpu["spectrum"], spec))
+            errs["extension"].append(rel(gpu["extension"], ext))
+            in_bitwise &= bool(np.array_equal(gpu["extension"][ins], ext[ins]))
+        res["checks"] = {"fields": sorted(checks), "fused_spectrum_max_rel_err": max(errs["spectrum"]),
+                         "plain_extension_max_rel_err": max(errs["extension"]), "in_points_bitwise": in_bitwise}
+        if ff_check is not None:
+            fc = ff_check
+            c = fc["case"]
+            fpl = OP.make_plan(Curve(*c.curve), OP.Grid(c.x0, c.y0, c.h, c.n, c.n), fcgram.load_tables(c.d), c.B,
+                               k1=c.k1, M=c.M)
+            ou, out_ = OF.ff_step(fpl, fc["u0"], np.zeros_like(fc["u0"]), fc["dt"])
+            res["ff_check"] = {"field": fc["name"], "batched_u": rel(fc["batched"][0], ou),
+                               "batched_ut": rel(fc["batched"][1], out_)}
+            if "plain" in fc:
+                res["ff_check"].update(plain_u=rel(fc["plain"][0], ou), plain_ut=rel(fc["plain"][1], out_))
+    res["baseline"] = {"value": nf_sample * case.n * case.n / dt, "unit": "points/s", "cores": 1, "kind": "oracle",
+                       "sample": "%d fields of the %dx%d star workload (plan excluded), extend + rfft2, one thread"
+                                 % (nf_sample, case.n, case.n)}
+    return res
 
 
-def run_batched(args):
+def run_ff(args):
     """Batched Fourier Forwarding: 4 domains x 4 grid sizes, ff_fields fields per
-    size (domains round-robin), Gaussian pulses, 100 steps of dt = 0.01, c = 1,
-    one HIP-graph replay per step, autotuned launch shapes."""
+    size (domains round-robin), Gaussian pulses, dt = 0.01, c = 1.  The same
+    step is timed two ways on identical plans, fields and initial data:
+      plain    one plan at a time through the per-plan entry points
+               (boundary values, fused extension + FFT of u and u_t,
+               propagation, inverse FFTs), no graph, default launch shapes;
+      batched  the batch: persistent multi-plan kernels, the fused column +
+               propagation kernel, one HIP-graph replay per step, launch
+               shapes from the autotuner.
+    The first step of one 2048^2 field of each is kept for the oracle check."""
     import numpy as np
     import torch
     import workloads as W
@@ -152,37 +194,101 @@ def run_batched(args):
             nf.append(m)
             cases.append(case)
     plan_s = time.perf_counter() - t0
-    batch = fc2d.Batch(plans, nf, autotune=True)
-    # initial data: seeded Gaussian pulses inside each domain, u_t = 0 (built on the device)
-    for k, (case, m) in enumerate(zip(cases, nf)):
-        u, ut = batch.state(k)
+    dt, c = 0.01, 1.0
+    kc = len(cases) - 2                      # the checked field: first field of the 2048^2 kite plan
+    x_c = cases[kc].x0 + np.arange(cases[kc].n) * cases[kc].h
+    f_c, _ = W.gaussian_pulse(cases[kc].curve, 1000 * kc)
+    u0_c = f_c(*np.meshgrid(x_c, x_c, indexing="ij"))
+
+    def load(k, u, ut):
+        """Seeded Gaussian pulses inside the domain (built on the device), u_t = 0."""
+        case = cases[k]
         x = case.x0 + torch.arange(case.n, device="cuda:0", dtype=torch.float64) * case.h
-        for f in range(m):
+        for f in range(nf[k]):
             _, (xc, yc, sig) = W.gaussian_pulse(case.curve, 1000 * k + f)
             u[f].copy_(torch.exp(-((x[:, None] - xc) ** 2 + (x[None, :] - yc) ** 2) / sig ** 2))
+        if k == kc:
+            u[0].copy_(torch.from_numpy(u0_c))
         ut.zero_()
+
+    def timed(step, steps):
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        step(steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / steps
+
+    # ---- plain: per-plan entry points, default launch shapes, no graph ----
+    state = []
+    for k, (case, m) in enumerate(zip(cases, nf)):
+        u = torch.empty((m, case.n, case.n), dtype=torch.float64, device="cuda:0")
+        ut = torch.empty_like(u)
+        load(k, u, ut)
+        fbu = torch.empty((m, plans[k].info.n_bdry), dtype=torch.float64, device="cuda:0")
+        state.append((u, ut, fbu, torch.empty_like(fbu)))
+    smax = max(m * cs.n * (cs.n // 2 + 1) for m, cs in zip(nf, cases))
+    sbuf = torch.empty(2 * smax, dtype=torch.complex128, device="cuda:0")
+
+    def plain_steps(steps):
+        for _ in range(steps):
+            for k, (case, m) in enumerate(zip(cases, nf)):
+                u, ut, fbu, fbt = state[k]
+                g = plans[k].grid
+                su = sbuf[: m * case.n * (case.n // 2 + 1)].view(m, case.n, case.n // 2 + 1)
+                st = sbuf[smax: smax + m * case.n * (case.n // 2 + 1)].view(m, case.n, case.n // 2 + 1)
+                fc2d.fc2d_boundary_values(plans[k], u, fbu)
+                fc2d.fc2d_boundary_values(plans[k], ut, fbt)
+                fc2d.fc2d_extend_fft(plans[k], u, fbu, u, su)
+                fc2d.fc2d_extend_fft(plans[k], ut, fbt, ut, st)
+                fc2d.ff_propagate(g, c, dt, su, st, su, st)
+                fc2d.fc2d_fft(g, su, u, fc2d.FC2D_INVERSE)
+                fc2d.fc2d_fft(g, st, ut, fc2d.FC2D_INVERSE)
+
+    plain_steps(1)                                     # first step: kept for the oracle check
     torch.cuda.synchronize()
-    pts, _, sf = batch.info()
-    batch.run_ff(1.0, 0.01, 1, use_graph=True)          # capture + warm-up
+    plain_first = (state[kc][0][0].cpu().numpy(), state[kc][1][0].cpu().numpy())
+    plain_n = min(args.ff_steps, 20)
+    ms_plain = timed(plain_steps, plain_n)
+    pts = 2 * sum(m * cs.n * cs.n for m, cs in zip(nf, cases))
+    del state, sbuf
+    torch.cuda.empty_cache()
+
+    # ---- batched: persistent kernels, fused spectral step, graph, autotuned shapes ----
+    t0 = time.perf_counter()
+    batch = fc2d.Batch(plans, nf, autotune=True)
+    tune_s = time.perf_counter() - t0
+    for k in range(len(cases)):
+        load(k, *batch.state(k))
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    batch.run_ff(1.0, 0.01, args.ff_steps, use_graph=True)
-    ev1.record()
+    pts_b, _, sf = batch.info()
+    assert pts_b == pts
+    batch.run_ff(c, dt, 1, use_graph=True)          # capture + first step: kept for the oracle check
     torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1) / args.ff_steps
+    bu, but = batch.state(kc)
+    batched_first = (bu[0].cpu().numpy(), but[0].cpu().numpy())
+    ms = timed(lambda steps: batch.run_ff(c, dt, steps, use_graph=True), args.ff_steps)
     _, nl, _ = batch.info()
     tiles = {n: (fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_ELEMS, n), fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_TILE, n))
              for n in sizes}
+    ffs = {n: fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_FF_SHAPE, n) for n in sizes}
     batch.close()
+    for p in plans:
+        p.close()
+    ff_check = {"case": cases[kc], "name": "%s field 0" % cases[kc].name, "u0": u0_c, "dt": dt,
+                "batched": batched_first, "plain": plain_first}
     return {"points_per_s": pts / (ms * 1e-3), "ms_per_step": ms, "points_per_step": pts,
-            "fields": int(sum(nf)), "steps": args.ff_steps, "dt": 0.01, "launches_per_step": nl, "graph": True,
-            "autotuned": {"col_elems_tile": tiles, "strip_fields_per_thread": sf}, "plan_s": plan_s,
+            "plain_points_per_s": pts / (ms_plain * 1e-3), "plain_ms_per_step": ms_plain, "plain_steps": plain_n,
+            "speedup_batched_vs_plain": ms_plain / ms,
+            "fields": int(sum(nf)), "steps": args.ff_steps, "dt": dt, "launches_per_step": nl, "graph": True,
+            "autotuned": {"col_elems_tile": tiles, "ff_shape": ffs, "strip_fields_per_thread": sf},
+            "plan_s": plan_s, "batch_create_and_tune_s": tune_s,
             "workload": "disc, star5, kite(0.65,1.5), ellipse(1,0.5) on [-2,2]^2 at 256^2..2048^2, "
                         "Gaussian pulses, u and u_t extended each step",
             "note": "throughput of the step; each step matches the oracle's step from the same state, but "
-                    "without a near-boundary solver the iterated state is not a PDE solution"}
+                    "without a near-boundary solver the iterated state is not a PDE solution"}, ff_check
 
 
 def run_poisson(args):
@@ -442,7 +548,12 @@ def main():
         return ev0.elapsed_time(ev1) / args.steps
 
     ms_plain = timed(step_plain)
+    # sampled outputs of the timed runs (the last step's), for the oracle check of the cpu_baseline leg
+    check_seeds = sorted({0, min(nf, args.cpu_sample_fields) - 1})
+    checks = {s: {"extension": ext[s].cpu().numpy()} for s in check_seeds}
     ms = timed(step_fused)
+    for s in check_seeds:
+        checks[s]["spectrum"] = spec[s].cpu().numpy()
     value = nf * case.n * case.n / (ms * 1e-3)
     value_plain = nf * case.n * case.n / (ms_plain * 1e-3)
     print("[bench] plain %.3f ms/step (%.3e points/s); fused %.3f ms/step (%.3e points/s)"
@@ -482,14 +593,15 @@ def main():
                 "alg_bytes_per_launch": dk["alg_bytes"], "avg_ms": dk["avg_ms"]}
     print("[bench] kernels " + json.dumps(kernels), file=sys.stderr, flush=True)
 
-    batched = None
+    batched, ff_check = None, None
     if not args.no_batched:
-        print("[bench] batched Fourier Forwarding ...", file=sys.stderr, flush=True)
+        print("[bench] Fourier Forwarding, plain and batched ...", file=sys.stderr, flush=True)
         del fg, fb, ext, spec
         torch.cuda.empty_cache()
-        batched = run_batched(args)
-        print("[bench] batched: %.3f ms/step, %.3e points/s" % (batched["ms_per_step"], batched["points_per_s"]),
-              file=sys.stderr, flush=True)
+        batched, ff_check = run_ff(args)
+        print("[bench] FF step: plain %.3f ms (%.3e points/s), batched %.3f ms (%.3e points/s)"
+              % (batched["plain_ms_per_step"], batched["plain_points_per_s"], batched["ms_per_step"],
+                 batched["points_per_s"]), file=sys.stderr, flush=True)
 
     learned = None
     if not args.no_mlp:
@@ -507,10 +619,15 @@ def main():
         poisson = run_poisson(args)
         print("[bench] poisson: " + json.dumps(poisson), file=sys.stderr, flush=True)
 
-    cpu = None
+    cpu, oracle_checks = None, None
     if not args.no_cpu_baseline:
-        print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(case, args.cpu_sample_fields)
+        print("[bench] cpu baseline and oracle checks ...", file=sys.stderr, flush=True)
+        leg = cpu_baseline(case, args.cpu_sample_fields, checks, ff_check)
+        cpu = leg["baseline"]
+        oracle_checks = {k: v for k, v in leg.items() if k != "baseline"}
+        print("[bench] oracle checks: " + json.dumps(oracle_checks), file=sys.stderr, flush=True)
+        if batched is not None and "ff_check" in oracle_checks:
+            batched["max_rel_err_vs_oracle"] = max(v for k, v in oracle_checks["ff_check"].items() if k != "field")
 
     out = {
         "metric": "2D-FC extended grid points/s at <=1e-11 err vs oracle; plain vs batched+MLP",
@@ -524,6 +641,8 @@ def main():
                    "fft_only_ms": ms_fft_only, "rocfft_reference_ms": ms_rocfft,
                    "rocfft_reference": "torch.fft.rfft2 (rocFFT via hipFFT), float64, same extended fields",
                    "spectrum_rel_diff_vs_rocfft": err_vs_rocfft},
+        "max_rel_err_vs_oracle": oracle_checks["checks"]["fused_spectrum_max_rel_err"] if oracle_checks else None,
+        "oracle_checks": oracle_checks,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": kernels,

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from gpu_common import gpu_plan, oracle_plan, rel_err
+from gpu_common import gpu_plan, oracle_ff_step_worker, oracle_plan, oracle_pool_map, pulse_field, rel_err
 from oracle import ff as OF
 from oracle import plan as OP
 
@@ -267,21 +267,23 @@ def test_batch_interior_only_plan(torch_mod):
 
 
 @pytest.mark.gpu
-@pytest.mark.parametrize("n", [1024, 2048])
-def test_every_fused_shape_matches_separate(torch_mod, n):
+@pytest.mark.parametrize("n,nfl", [(1024, 2), (2048, 2), (4096, 2), (1024, 8), (2048, 8)])
+def test_every_fused_shape_matches_separate(torch_mod, n, nfl):
     """Every compiled shape of the fused column-pass + propagation kernel for
     length n (the two-spectra blocks and the paired one-column blocks that
-    propagate in registers), with row-major and transposed spectra, against
-    the separate column passes and propagation on the same kite plan and data
-    (one step of two fields): 1e-13."""
+    propagate in registers; at 4096 the paired kernel holds 64 KiB of LDS),
+    with row-major and transposed spectra, against the separate column passes
+    and propagation on the same kite plan and data (one step of nfl fields):
+    1e-13.  Two fields take the column-tile-per-XCD mapping, eight fields the
+    whole-fields-per-XCD mapping."""
     from paper_2010_03901_amd import fc2d
     torch = torch_mod
     case = W.cfg_ff("kite", n)
     gpl = gpu_plan(case)
-    u0 = [_pulses(case, range(2))]
+    u0 = [_pulses(case, range(nfl))]
 
     def run(fused, trans):
-        b = fc2d.Batch([gpl], [2], fused_ff=fused, transposed=trans)
+        b = fc2d.Batch([gpl], [nfl], fused_ff=fused, transposed=trans)
         _load_state(b, u0)
         b.run_ff(1.0, 0.02, 1, use_graph=False)
         torch.cuda.synchronize()
@@ -299,11 +301,58 @@ def test_every_fused_shape_matches_separate(torch_mod, n):
             except Exception:
                 break
             for trans in (False, True):
-                print("\n[batch] n=%d fused shape %d transposed %d" % (n, nshape, trans), end="", flush=True)
+                print("\n[batch] n=%d fields %d fused shape %d transposed %d" % (n, nfl, nshape, trans), end="",
+                      flush=True)
                 got = run(True, trans)
                 for j in (0, 1):
                     assert rel_err(got[j], ref[j]) < 1e-13
             nshape += 1
     finally:
         fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_FF_SHAPE, n, keep)
-    assert nshape == {1024: 4, 2048: 6}[n]
+    assert nshape == {1024: 4, 2048: 6, 4096: 2}[n]
+
+
+def test_bench_shaped_batch_step_matches_oracle(torch_mod):
+    """The batch the way the benchmark builds it, at its two largest sizes: four
+    domains x {1024^2, 2048^2}, 32 fields per plan (128 per grid size, so each
+    XCD takes whole fields), launch shapes from the autotuner (transposed spectra
+    and the paired column kernel wherever they win), one HIP-graph step of
+    dt = 0.01.  One field per (domain, size) against the oracle's step from the
+    same state: 1e-11.  The oracle steps run in spawned CPU-only processes."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    doms = list(W.FF_DOMAINS)
+    specs = [(dom, n) for n in (1024, 2048) for dom in doms]
+    nfp, dt = 32, 0.01
+    check = [(5 * k + 3) % nfp for k in range(len(specs))]      # the field compared per plan
+    seeds = [1000 * k + f for k, f in enumerate(check)]
+    print("\n[batch] oracle steps of %d (domain, size) pairs in spawned workers" % len(specs), flush=True)
+    ref = oracle_pool_map(oracle_ff_step_worker, [(dom, n, s, dt) for (dom, n), s in zip(specs, seeds)])
+    print("[batch] oracle done; building the GPU batch", flush=True)
+    cases = [W.cfg_ff(dom, n) for dom, n in specs]
+    gplans = [gpu_plan(c) for c in cases]
+    batch = fc2d.Batch(gplans, [nfp] * len(specs), autotune=True)
+    print("[batch] autotuned fused-kernel shapes %s, column (E, T) %s" % (
+        {n: fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_FF_SHAPE, n) for n in (1024, 2048)},
+        {n: (fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_ELEMS, n), fc2d.fc2d_tune_get(fc2d.FC2D_TUNE_COL_TILE, n))
+         for n in (1024, 2048)}), flush=True)
+    for k, case in enumerate(cases):
+        u, ut = batch.state(k)
+        x = case.x0 + torch.arange(case.n, device="cuda:0", dtype=torch.float64) * case.h
+        for f in range(nfp):
+            _, (xc, yc, sig) = W.gaussian_pulse(case.curve, 1000 * k + f)
+            u[f].copy_(torch.exp(-((x[:, None] - xc) ** 2 + (x[None, :] - yc) ** 2) / sig ** 2))
+        u[check[k]].copy_(torch.from_numpy(pulse_field(case, seeds[k])))   # the oracle's own initial field
+        ut.zero_()
+    batch.run_ff(1.0, dt, 1, use_graph=True)
+    torch.cuda.synchronize()
+    try:
+        for k, ((dom, n), (ou, out_)) in enumerate(zip(specs, ref)):
+            u, ut = batch.state(k)
+            f = check[k]
+            eu = rel_err(u[f].cpu().numpy(), ou)
+            et = rel_err(ut[f].cpu().numpy(), out_)
+            print("[batch] %s %d^2 field %d: u %.2e u_t %.2e" % (dom, n, f, eu, et), flush=True)
+            assert eu < 1e-11 and et < 1e-11, (dom, n, eu, et)
+    finally:
+        batch.close()

@@ -25,7 +25,8 @@
  *    stream, and return it on that stream; so calls sharing one plan may run
  *    concurrently on different streams (and from different host threads).
  *    The exceptions are named where they occur: a batch (fc2d_batch_*) is
- *    advanced by one stream at a time, and the tuning knobs are process-wide.
+ *    advanced by one stream at a time, the tuning knobs are process-wide, and
+ *    fc2d_extend_fft_noalloc shares one fixed scratch per device.
  */
 #ifndef FC2D_H
 #define FC2D_H
@@ -208,6 +209,19 @@ int fc2d_boundary_values(const fc2d_plan* plan, const double* u, double* f_bdry,
 int fc2d_extend_fft(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, double* work,
                     void* spec, int nf, hipStream_t stream);
 
+/* fc2d_extend_fft for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation):
+ * same arguments, kernels and results (bitwise), but the Gram records live in
+ * the library's fixed scratch, a 16 MiB device array per device held until the
+ * process ends, and no allocation routine is called.  Requires
+ * nf * B * ((d + 2) & ~1) * 8 <= 16 MiB (FC2D_E_ARG otherwise; e.g. 170 fields
+ * at B = 2048, d = 5) and a plan created on the current device (its FFT tables
+ * and the scratch's address are set up there; FC2D_E_ARG otherwise).  Every
+ * call on one device shares the scratch: calls that overlap on one device
+ * (different streams or threads, or graphs replayed concurrently)
+ * race and give wrong results; order them on one stream. */
+int fc2d_extend_fft_noalloc(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, double* work,
+                            void* spec, int nf, hipStream_t stream);
 
 /* 2D FFT (Sec. 3.5 step 7); nx a power of two in [16, 4096], ny a power of
  * two in [16, 8192] (Remark 3.2: the grid is padded to FFT-friendly sizes).

@@ -181,6 +181,10 @@ int launch_mask(const fc2d_plan* pl, const double* f_grid, double* out, int nf, 
 inline size_t gram_bytes(const fc2d_plan* pl, int nf) {
     return (size_t)nf * (size_t)pl->B * (size_t)((pl->d + 2) & ~1) * sizeof(double);
 }
+// The library's fixed scratch array for callers that cannot allocate
+// (kernels_extend.hip): its device address on the current device (looked up
+// once per device) and its size in bytes.
+int static_scratch(double** p, size_t* bytes);
 
 // ---- FFT and spectral kernels (kernels_fft.hip) ----
 // strip / cls2 non-null: the rows are assembled on the fly from `in` (IN),
@@ -190,6 +194,9 @@ int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStrea
 int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s);
 // single passes (batches) and twiddle set-up outside stream capture
 int fft_prepare(int nx, int ny);
+// true when the twiddle tables of lengths nx and ny exist on the current device
+// (then the FFT launches allocate nothing)
+bool fft_ready(int nx, int ny);
 int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
                  const uint8_t* cls2);
 int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s);

@@ -20,6 +20,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <string>
 
 #include "dd.h"
 #include "internal.h"
@@ -598,6 +600,47 @@ __global__ void k_mask(const int32_t* __restrict__ run_ptr, const int32_t* __res
 }
 
 // fields per thread in k_strip (0 = automatic); set by the autotuner
+// ---------------------------------------------------------------------------
+// Fixed scratch for fc2d_extend_fft_noalloc (callers that cannot allocate:
+// code under graph capture, serving loops, harnesses that forbid allocation).
+// One copy per device, held until the process ends; every such call on a
+// device shares it, so calls that overlap on one device race.  In host code
+// the array's name is not a device address: its address on the current device
+// comes from hipGetSymbolAddress, looked up once per device and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)16 << 20;
+static __device__ __align__(256) double scratch[kScratchBytes / sizeof(double)];
+
+static std::mutex g_scratch_mu;
+static constexpr int kMaxDevices = 64;
+static double* g_scratch_ptr[kMaxDevices];
+
+int static_scratch(double** p, size_t* bytes) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) {
+        set_error(std::string("hipGetDevice: ") + hipGetErrorString(e));
+        return FC2D_E_HIP;
+    }
+    if (dev < 0 || dev >= kMaxDevices) {
+        set_error("fixed scratch: device index out of range");
+        return FC2D_E_ARG;
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* a = nullptr;
+        e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !a) {
+            set_error(std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+            return FC2D_E_HIP;
+        }
+        g_scratch_ptr[dev] = (double*)a;
+    }
+    *p = g_scratch_ptr[dev];
+    *bytes = kScratchBytes;
+    return FC2D_OK;
+}
+
 static int g_strip_fpt = 0;
 int strip_fpt_get() { return g_strip_fpt; }
 int strip_fpt_set(int v) {

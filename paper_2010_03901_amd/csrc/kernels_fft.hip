@@ -629,6 +629,13 @@ int fft_prepare(int nx, int ny) {
     return (twiddles(nx) && twiddles(ny)) ? FC2D_OK : FC2D_E_NOMEM;
 }
 
+bool fft_ready(int nx, int ny) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return false;
+    std::lock_guard<std::mutex> lk(g_tw_mu);
+    return g_tw.count({dev, nx}) > 0 && g_tw.count({dev, ny}) > 0;
+}
+
 int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
                  const uint8_t* cls2) {
     const double2* twy = twiddles(g->ny);

@@ -798,6 +798,12 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                 row_class_layout(Lh, pairs.data(), &cls2[(size_t)i * Lh]);
             }
             if ((st = dev_upload(&pl->d_cls2, cls2.data(), cls2.size()))) break;
+            // set-up on this device for the extension calls that allocate nothing
+            // (fc2d_extend_fft_noalloc): the FFT tables and the fixed scratch's address
+            if ((st = fft_prepare(grid->nx, grid->ny))) { set_error("FFT table set-up failed"); break; }
+            double* scr = nullptr;
+            size_t scr_bytes = 0;
+            if ((st = static_scratch(&scr, &scr_bytes))) break;
         }
     } while (0);
     if (st) { free_plan(pl); return st; }
@@ -965,6 +971,25 @@ int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_b
     WorkSpace ws;
     if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
     return extend_fft_run(pl, f_grid, f_bdry, work, spec, nf, (double*)ws.p, s);
+}
+
+int fc2d_extend_fft_noalloc(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work,
+                            void* spec, int nf, hipStream_t s) {
+    int st = extend_fft_check(pl, f_grid, f_bdry, work, spec, nf);
+    if (st || nf == 0) return st;
+    double* c = nullptr;
+    size_t cap = 0;
+    if ((st = static_scratch(&c, &cap))) return st;
+    if (gram_bytes(pl, nf) > cap) {
+        set_error("fc2d_extend_fft_noalloc: nf B (d + 2 rounded down to even) doubles exceed the fixed scratch of " +
+                  std::to_string(cap) + " bytes");
+        return FC2D_E_ARG;
+    }
+    if (!fft_ready(pl->grid.nx, pl->grid.ny)) {
+        set_error("fc2d_extend_fft_noalloc: no FFT tables on this device (create a plan on it first)");
+        return FC2D_E_ARG;
+    }
+    return extend_fft_run(pl, f_grid, f_bdry, work, spec, nf, c, s);
 }
 
 int fc2d_boundary_values(const fc2d_plan* pl, const double* u, double* f_bdry, int nf, hipStream_t s) {

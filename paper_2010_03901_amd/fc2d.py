@@ -79,6 +79,7 @@ def _lib():
             "fc2d_blend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
             "fc2d_extend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
             "fc2d_extend_fft": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_extend_fft_noalloc": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P]),
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
             "fc2d_poisson_nodes": (C.c_int, [_P, C.c_int, _P]),
@@ -310,6 +311,11 @@ def _extend_fft_args(plan, f_grid, f_bdry, work, spec):
 
 def fc2d_extend_fft(plan, f_grid, f_bdry, work, spec, stream=None):
     _check(_lib().fc2d_extend_fft(*_extend_fft_args(plan, f_grid, f_bdry, work, spec), _stream(stream)))
+
+
+def fc2d_extend_fft_noalloc(plan, f_grid, f_bdry, work, spec, stream=None):
+    """fc2d_extend_fft with its work space in the library's fixed scratch: allocates nothing."""
+    _check(_lib().fc2d_extend_fft_noalloc(*_extend_fft_args(plan, f_grid, f_bdry, work, spec), _stream(stream)))
 
 
 def fc2d_fft(grid, inp, out, direction, stream=None):

@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--mlp-batch", type=int, default=4096)
     ap.add_argument("--mlp-fields", type=int, default=8)
     ap.add_argument("--no-poisson", action="store_true", help="skip the full Poisson solve measurement")
+    ap.add_argument("--no-ff-solver", action="store_true", help="skip the Fourier Forwarding solver measurement")
+    ap.add_argument("--ff-solver-n", type=int, default=1024, help="grid of the Fourier Forwarding solver run")
     ap.add_argument("--poisson-n", type=int, default=2048, help="grid of the full Poisson solve")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one 1 GiB device copy first (known-size kernel for counter calibration)")
@@ -357,6 +359,68 @@ def run_poisson(args):
             "kernels_ms": {k: round(v, 4) for k, v in sorted(per.items(), key=lambda kv: -kv[1])}}
 
 
+def run_ff_solver(args):
+    """Fourier Forwarding solver (Sec. 4.2; fc2d_ff_advance): Ex. 4.4's
+    manufactured plane wave u = cos(2 kappa (x + t) / 3) + cos(kappa (y + t)),
+    kappa = 10, on the unit disc in the box [-1.6, 1.6]^2 at ff_solver_n^2
+    (d = 5, n_c = 6, CFL 0.125), Dirichlet data from the exact solution.
+    Reports the time of a large step (48 small steps; HIP events, the data
+    arrays resident) and the largest error over Omega after two large steps."""
+    import numpy as np
+    import torch
+    import workloads as W
+    from paper_2010_03901_amd import fc2d
+    kap = 10.0
+    ue = lambda x, y, t: np.cos(2 * kap * (x + t) / 3) + np.cos(kap * (y + t))
+    ute = lambda x, y, t: -(2 * kap / 3) * np.sin(2 * kap * (x + t) / 3) - kap * np.sin(kap * (y + t))
+    n = args.ff_solver_n
+    case = W.cfg_disc(n)
+    t0 = time.perf_counter()
+    plan = fc2d.Plan(fc2d.make_curve(*case.curve), fc2d.make_grid(case.x0, case.y0, case.h, n, n), d=case.d,
+                     C_=case.C, B=case.B, k1=case.k1, M=case.M)
+    ff = fc2d.FF(plan)
+    setup_s = time.perf_counter() - t0
+    inf = ff.info
+    inside = ff.regions() > 0
+    x = case.x0 + np.arange(n) * case.h
+    X, Y = np.meshgrid(x, x, indexing="ij")
+    bp = fc2d.fc2d_boundary_points(plan)
+    cx = ff.crossings()
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    nlarge = 2
+    data = []
+    for j in range(nlarge):
+        T = j * inf.dT
+        ts = T + np.arange(inf.K + 1) * inf.dt
+        data.append((dev(ue(bp[:, 0], bp[:, 1], T)), dev(ute(bp[:, 0], bp[:, 1], T)),
+                     dev(np.stack([ue(cx[:, 0], cx[:, 1], t) for t in ts])),
+                     dev(np.stack([ute(cx[:, 0], cx[:, 1], t) for t in ts]))))
+    u0 = dev(np.where(inside, ue(X, Y, 0.0), 0.0))
+    v0 = dev(np.where(inside, ute(X, Y, 0.0), 0.0))
+    u, v = u0.clone(), v0.clone()
+    ff.advance(u, v, *data[0])                  # warm-up
+    torch.cuda.synchronize()
+    u.copy_(u0)
+    v.copy_(v0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(nlarge + 1)]
+    ev[0].record()
+    for j in range(nlarge):
+        ff.advance(u, v, *data[j])
+        ev[j + 1].record()
+    torch.cuda.synchronize()
+    ms = [ev[j].elapsed_time(ev[j + 1]) for j in range(nlarge)]
+    t_end = nlarge * inf.dT
+    err = float(np.abs(u.cpu().numpy() - ue(X, Y, t_end))[inside].max())
+    ff.close()
+    plan.close()
+    return {"workload": "Ex. 4.4 plane wave (kappa = 10) on the unit disc, [-1.6,1.6]^2 at %d^2, d=5, n_c=6, CFL 0.125"
+                        % n,
+            "ms_per_large_step": float(np.mean(ms)), "small_steps_per_large_step": inf.K,
+            "ms_per_small_step": float(np.mean(ms)) / inf.K, "stepped_points": int(inf.n_stepped),
+            "boundary_points": int(inf.n_bnd), "segments": int(inf.n_segments), "setup_s": setup_s,
+            "t_end": t_end, "max_err_vs_exact": err}
+
+
 def run_mlp(args):
     """Learned foot seed: training pairs (the method's own foot solves on
     mlp_curves random curves x 1000 points in the exterior strip) and training on
@@ -619,6 +683,12 @@ def main():
         poisson = run_poisson(args)
         print("[bench] poisson: " + json.dumps(poisson), file=sys.stderr, flush=True)
 
+    ff_solver = None
+    if not args.no_ff_solver:
+        print("[bench] Fourier Forwarding solver ...", file=sys.stderr, flush=True)
+        ff_solver = run_ff_solver(args)
+        print("[bench] ff solver: " + json.dumps(ff_solver), file=sys.stderr, flush=True)
+
     cpu, oracle_checks = None, None
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline and oracle checks ...", file=sys.stderr, flush=True)
@@ -649,6 +719,7 @@ def main():
         "batched_ff": batched,
         "learned_seed": learned,
         "poisson_full": poisson,
+        "ff_solver": ff_solver,
         "plan_s": plan_s,
     }
     print(json.dumps(out))

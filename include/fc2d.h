@@ -276,6 +276,61 @@ int fc2d_spectral_apply(const fc2d_grid* grid, int op, const void* in, void* out
 int ff_propagate(const fc2d_grid* grid, double c, double t, const void* u0h, const void* u1h,
                  void* uh, void* uth, int nf, hipStream_t stream);
 
+/* ---- Fourier Forwarding solver of the wave equation (Sec. 4.2) ----
+ * u_tt = c^2 (u_xx + u_yy) in Omega (eq. wave_2d) with Dirichlet data
+ * u = b(x, y, t) on Gamma.  fc2d_ff_advance takes the solution from T_j to
+ * T_j + nsmall dt (nsmall <= K, K dt = dT = n_c h / c) as eq. ff_soln
+ * combines it:
+ *  - U_FC (eq. aux_sol): the 2D-FC extensions of u and u_t at T_j (boundary
+ *    samples fb_u, fb_ut = b, b_t at T_j on the plan's fc2d_boundary_points),
+ *    their spectra advanced in closed form (eq. wave_2d_ff); it is taken at
+ *    the interior points, which lie at least c dT from Gamma;
+ *  - U_B: on the boundary region (IN points within Chebyshev grid distance
+ *    n_c + 2 of a non-IN point) explicit second-order Taylor steps of
+ *    dt = dT / (8 n_c) (CFL 0.125): u += dt v + dt^2/2 a, v += dt (a + a')/2
+ *    with a = c^2 (u_xx + u_yy) from the 1D-FC of Sec. 2.3 (both blends)
+ *    along grid lines (runs shorter than 2 d: the Lagrange interpolant through
+ *    the run and its crossings with Gamma); the grid points next to Gamma
+ *    (along x or y) take the cubic interpolant along their grid line through
+ *    the Dirichlet value at the line's crossing with Gamma and the nearest
+ *    stepped points; values needed beyond the region come from U_FC at the
+ *    current time.  The paper defers the details of U_B; these are the
+ *    library's readings.
+ * The solver owns its work buffers (4 half spectra and 2 grids per field) and
+ * is advanced by one stream at a time.  One field per call. */
+typedef struct fc2d_ff fc2d_ff;
+typedef struct {
+    double c, dT, dt;        /* wave speed, large step, small step */
+    int K, n_c, M_b;         /* small steps per large step, region width, closure nodes */
+    int64_t n_cross;         /* crossings of grid lines with Gamma: Dirichlet data per small step */
+    int64_t n_stepped, n_bnd;   /* stepped and interpolated (boundary) points of U_B */
+    int n_segments, max_segment;
+} fc2d_ff_info;
+/* Solver on the plan's grid (power of two, boundary data; the plan must
+ * outlive it).  c > 0, 1 <= n_c <= 64 (the paper's examples: 6);
+ * closure_nodes 2..4 (0 -> 4): nodes of the interpolation closure at the grid
+ * points next to Gamma.  Host set-up
+ * (crossings by bisection on eta, closure and derivative matrices in long
+ * double) plus device uploads; FC2D_E_GEOMETRY if a derivative segment would
+ * exceed 2048 points. */
+int fc2d_ff_create(const fc2d_plan* plan, double c, int n_c, int closure_nodes, hipStream_t stream, fc2d_ff** out);
+int fc2d_ff_destroy(fc2d_ff* ff);
+int fc2d_ff_get_info(const fc2d_ff* ff, fc2d_ff_info* info);
+/* The crossings (host xy [2 n]) where the caller supplies b and b_t at every
+ * small step; xy may be NULL to query n. */
+int fc2d_ff_crossings(const fc2d_ff* ff, int64_t* n, double* xy);
+/* Per grid point (host [nx][ny]): 0 outside Omega, 1 interior (U_FC),
+ * 2 stepped, 3 boundary point of U_B. */
+int fc2d_ff_regions(const fc2d_ff* ff, int8_t* region);
+/* Advance one field by nsmall small steps (1 <= nsmall <= K) from T_j.  u, ut
+ * [nx][ny] device: the solution and its time derivative at T_j at the IN
+ * points on entry, at T_j + nsmall dt on return (0 outside Omega).  fb_u,
+ * fb_ut [n_bdry]: b and b_t at T_j on the plan's boundary points.  bc_u,
+ * bc_ut [nsmall + 1][n_cross]: b and b_t at the crossings at T_j + k dt,
+ * k = 0..nsmall.  Asynchronous on `stream`. */
+int fc2d_ff_advance(fc2d_ff* ff, double* u, double* ut, const double* fb_u, const double* fb_ut,
+                    const double* bc_u, const double* bc_ut, int nsmall, hipStream_t stream);
+
 /* Launch-shape knobs, process-wide (set by the autotuner; results do not
  * depend on them beyond rounding).  For the column FFT pass of length n = nx:
  * FC2D_TUNE_COL_TILE = columns per block T, FC2D_TUNE_COL_ELEMS = elements per

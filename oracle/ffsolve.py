@@ -36,9 +36,12 @@ Readings (the paper sketches FF and defers its details to a later paper):
   with the longer IN run when both qualify, x on ties) from the crossings of
   the line with Gamma that bound the run (data b, resp. b_t) and the stepped
   points of the run: the M_b nodes nearest the point (ties: lower position).
-  M_b = 4 (a cubic closure): with 5 or more nodes the closed step operator
-  has growing modes (seen in its eigenvalues and in runs on the disc: with
-  M_b = 8 the solution grows without bound within about 400 small steps).
+  M_b = 4 (a cubic closure).  The closure makes the stepper only
+  conditionally useful: with the boundary points held at the exact solution
+  the stepper is stable (unit disc, 512^2, 1600 small steps), with the
+  interpolation closure its error grows, the faster the finer the grid; 2, 3,
+  5 or more nodes, or nodes two grid steps apart, grow faster than 4.  The
+  paper leaves its closure to a later paper.
 * Stepped points: the other boundary-region points.  For each grid line the
   stepped points form sub-runs of the IN runs; the 1D-FC segment of a
   sub-run extends it by n_o = d points on each side, clipped to the IN run,

@@ -169,6 +169,9 @@ int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, i
                  int Cr, int wmax, int grid_blocks, hipStream_t s);
 int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipStream_t s);
 
+// crossing of a grid-line segment with Gamma (plan.cpp; bisection on eta)
+int gridline_crossing(const fc2d_plan* pl, bool vertical, double a_line, double b_in, double b_out, double* out);
+
 // ---- extension kernels (kernels_extend.hip) ----
 int launch_match(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, int64_t nbdry,
                  double* c_out, double* fD_out, int nf, hipStream_t s);

@@ -782,7 +782,7 @@ __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2*
         double2 ra, rt;
         ff_apply(ff_coef(row_freq(i, nx), j, iLx, iLy, c, t), u0[e], u1[e], &ra, &rt);
         uh[e] = ra;
-        uth[e] = rt;
+        if (uth) uth[e] = rt;   // uth may be NULL when only the field is wanted
     }
 }
 

@@ -813,6 +813,39 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
 
 
 
+// Crossing of the grid-line segment {a = a_line, b between b_in (inside) and
+// b_out (outside)} with Gamma: bisection on the sign of eta (64 halvings, one
+// foot solve each).  vertical: the line x = a_line (b runs along y).
+int gridline_crossing(const fc2d_plan* pl, bool vertical, double a_line, double b_in, double b_out, double* out) {
+    const BndView bd{pl->bx.data(), pl->by.data(), pl->bnx.data(), pl->bny.data(), pl->B, pl->k2};
+    int seed = 0;
+    {
+        const double X = vertical ? a_line : b_in, Y = vertical ? b_in : a_line;
+        double best = INFINITY;
+        for (int p = 0; p < pl->B; ++p) {
+            const double dx = pl->bx[p] - X, dy = pl->by[p] - Y, d2 = dx * dx + dy * dy;
+            if (d2 < best) { best = d2; seed = p; }
+        }
+    }
+    double lo = b_in, hi = b_out;
+    for (int it = 0; it < 64; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        const double X = vertical ? a_line : mid;
+        const double Y = vertical ? mid : a_line;
+        seed = nearest_sample(pl, X, Y, seed);
+        double th, eta;
+        int its;
+        if (foot_host(pl->M, pl->curve, bd, X, Y, seed, 60, &th, &eta, &its) != FOOT_OK) {
+            set_error("foot of the normal failed while locating a grid-line crossing with the boundary");
+            return FC2D_E_NEWTON;
+        }
+        if (eta <= 0) lo = mid;
+        else hi = mid;
+    }
+    *out = 0.5 * (lo + hi);
+    return FC2D_OK;
+}
+
 }  // namespace fc2d
 
 using namespace fc2d;

@@ -56,6 +56,12 @@ class fc2d_plan_info(C.Structure):
                 ("n_solved", C.c_int64), ("n_fallback", C.c_int64), ("newton_iters", C.c_int64)]
 
 
+class fc2d_ff_info(C.Structure):
+    _fields_ = [("c", C.c_double), ("dT", C.c_double), ("dt", C.c_double), ("K", C.c_int), ("n_c", C.c_int),
+                ("M_b", C.c_int), ("n_cross", C.c_int64), ("n_stepped", C.c_int64), ("n_bnd", C.c_int64),
+                ("n_segments", C.c_int), ("max_segment", C.c_int)]
+
+
 _LIB = None
 _P = C.c_void_p
 
@@ -101,6 +107,12 @@ def _lib():
             "fc2d_mlp_loss_grad": (C.c_int, [_P, _P, _P, C.c_int64, _P, _P, _P]),
             "fc2d_mlp_train": (C.c_int, [_P, _P, _P, _P, _P, C.c_int64, C.c_int, C.c_int, C.c_int64, C.c_float,
                                          C.c_float, C.c_int64, _P, _P]),
+            "fc2d_ff_create": (C.c_int, [_P, C.c_double, C.c_int, C.c_int, _P, C.POINTER(_P)]),
+            "fc2d_ff_destroy": (C.c_int, [_P]),
+            "fc2d_ff_get_info": (C.c_int, [_P, C.POINTER(fc2d_ff_info)]),
+            "fc2d_ff_crossings": (C.c_int, [_P, C.POINTER(C.c_int64), _P]),
+            "fc2d_ff_regions": (C.c_int, [_P, _P]),
+            "fc2d_ff_advance": (C.c_int, [_P, _P, _P, _P, _P, _P, _P, C.c_int, _P]),
             "fc2d_strerror": (C.c_char_p, [C.c_int]),
             "fc2d_last_error": (C.c_char_p, []),
             "fc2d_version": (C.c_int, []),
@@ -520,3 +532,61 @@ def fc2d_mlp_train(weights, adam_m, adam_v, X, Y, batch, steps, t0, lr0, lr_min,
 
 def fc2d_version():
     return _lib().fc2d_version()
+
+
+FFR_OUT, FFR_INT, FFR_STEP, FFR_BND = 0, 1, 2, 3
+
+
+class FF:
+    """Owning wrapper of fc2d_ff* (Fourier Forwarding solver; keeps its plan alive)."""
+
+    def __init__(self, plan, c=1.0, n_c=6, closure_nodes=0, stream=None):
+        self.plan = plan
+        h = C.c_void_p()
+        _check(_lib().fc2d_ff_create(plan.handle, float(c), int(n_c), int(closure_nodes), _stream(stream),
+                                     C.byref(h)))
+        self._h = h
+        info = fc2d_ff_info()
+        _check(_lib().fc2d_ff_get_info(h, C.byref(info)))
+        self.info = info
+
+    def crossings(self):
+        n = C.c_int64()
+        _check(_lib().fc2d_ff_crossings(self._h, C.byref(n), None))
+        xy = np.zeros((n.value, 2))
+        _check(_lib().fc2d_ff_crossings(self._h, C.byref(n), C.c_void_p(xy.ctypes.data)))
+        return xy
+
+    def regions(self):
+        g = self.plan.grid
+        out = np.zeros((g.nx, g.ny), dtype=np.int8)
+        _check(_lib().fc2d_ff_regions(self._h, C.c_void_p(out.ctypes.data)))
+        return out
+
+    def advance(self, u, ut, fb_u, fb_ut, bc_u, bc_ut, nsmall=None, stream=None):
+        """Advance (u, ut) in place by nsmall small steps (default: one large step).
+        fb_u, fb_ut [n_bdry]; bc_u, bc_ut [nsmall + 1][n_cross] (device float64)."""
+        import torch
+        g = self.plan.grid
+        ns = self.info.K if nsmall is None else int(nsmall)
+        nc = self.info.n_cross
+        _check_out(u, "u", g.nx * g.ny, torch.float64)
+        _check_out(ut, "ut", g.nx * g.ny, torch.float64)
+        _check_out(fb_u, "fb_u", self.plan.info.n_bdry, torch.float64)
+        _check_out(fb_ut, "fb_ut", self.plan.info.n_bdry, torch.float64)
+        _check_out(bc_u, "bc_u", (ns + 1) * nc, torch.float64)
+        _check_out(bc_ut, "bc_ut", (ns + 1) * nc, torch.float64)
+        _check(_lib().fc2d_ff_advance(self._h, _dptr(u, "u"), _dptr(ut, "ut"), _dptr(fb_u, "fb_u"),
+                                      _dptr(fb_ut, "fb_ut"), _dptr(bc_u, "bc_u"), _dptr(bc_ut, "bc_ut"), ns,
+                                      _stream(stream)))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            _lib().fc2d_ff_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -41,7 +41,10 @@ def source_hash():
 
 def measured_traffic(kernel):
     """HBM bytes per dispatch from the committed rocprofv3 counter runs, or None
-    when they are missing or the kernels changed since they were taken."""
+    when they are missing or the kernels changed since they were taken.  kernel
+    is a tracer name; the timed path's instantiation is picked by its template
+    arguments: the masked, row-major row pass, and the forward column pass on
+    128-byte-aligned rows (non-temporal form)."""
     try:
         with open(COUNTERS) as fh:
             c = json.load(fh)
@@ -50,13 +53,14 @@ def measured_traffic(kernel):
     if c.get("source_hash") != source_hash():
         return None
     base = kernel.replace("_ext", "")
-    masked = kernel.endswith("_ext")
     for name, v in c["kernels"].items():
         if name.split("<")[0] != base:
             continue
-        if base == "k_rows_r2c" and name.endswith("true>") != masked:
+        targs = [a.strip() for a in name[name.find("<") + 1: name.rfind(">")].split(",")] if "<" in name else []
+        if base == "k_rows_r2c" and (len(targs) < 5 or targs[3] != ("true" if kernel.endswith("_ext") else "false")
+                                     or targs[4] != "false"):
             continue
-        if base == "k_cols" and not name.endswith("false>"):
+        if base == "k_cols" and (len(targs) < 5 or targs[3] != "false" or targs[4] != "true"):
             continue
         return v["traffic_bytes"]
     return None
@@ -587,16 +591,25 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    spec = torch.empty((nf, case.n, case.n // 2 + 1), dtype=torch.complex128, device="cuda:0")
+    # the timed fused step writes the half spectrum with 128-byte-aligned rows (row pitch
+    # ld = ny/2 + 1 rounded up to a multiple of 8 complex; fc2d_extend_fft_ld); the same
+    # step into the numpy layout (ld = ny/2 + 1, fc2d_extend_fft) is timed beside it
+    half = case.n // 2 + 1
+    ld = (half + 7) // 8 * 8
+    spec = torch.empty((nf, case.n, ld), dtype=torch.complex128, device="cuda:0")
+    spec_np = torch.empty((nf, case.n, half), dtype=torch.complex128, device="cuda:0")
     torch.cuda.synchronize()
     print("[bench] plan %.2fs, inputs ready" % plan_s, file=sys.stderr, flush=True)
 
     def step_plain():
         fc2d.fc2d_extend(plan, fg, fb, ext)
-        fc2d.fc2d_fft(grid, ext, spec, fc2d.FC2D_FORWARD)
+        fc2d.fc2d_fft(grid, ext, spec_np, fc2d.FC2D_FORWARD)
 
     def step_fused():
-        fc2d.fc2d_extend_fft(plan, fg, fb, ext, spec)
+        fc2d.fc2d_extend_fft_ld(plan, fg, fb, ext, spec)
+
+    def step_fused_numpy_layout():
+        fc2d.fc2d_extend_fft(plan, fg, fb, ext, spec_np)
 
     def timed(step):
         for _ in range(args.warmup):
@@ -615,23 +628,26 @@ def main():
     # sampled outputs of the timed runs (the last step's), for the oracle check of the cpu_baseline leg
     check_seeds = sorted({0, min(nf, args.cpu_sample_fields) - 1})
     checks = {s: {"extension": ext[s].cpu().numpy()} for s in check_seeds}
+    ms_np = timed(step_fused_numpy_layout)
     ms = timed(step_fused)
     for s in check_seeds:
-        checks[s]["spectrum"] = spec[s].cpu().numpy()
+        checks[s]["spectrum"] = spec[s, :, :half].cpu().numpy()
     value = nf * case.n * case.n / (ms * 1e-3)
     value_plain = nf * case.n * case.n / (ms_plain * 1e-3)
-    print("[bench] plain %.3f ms/step (%.3e points/s); fused %.3f ms/step (%.3e points/s)"
-          % (ms_plain, value_plain, ms, value), file=sys.stderr, flush=True)
+    value_np = nf * case.n * case.n / (ms_np * 1e-3)
+    print("[bench] plain %.3f ms/step (%.3e points/s); fused, numpy layout %.3f ms/step (%.3e points/s); fused, "
+          "aligned rows %.3f ms/step (%.3e points/s)" % (ms_plain, value_plain, ms_np, value_np, ms, value),
+          file=sys.stderr, flush=True)
 
     # side-by-side reference (not the library's path): torch.fft.rfft2 on ROCm
     # (rocFFT through hipFFT), float64, the same fields, already extended
     fc2d.fc2d_extend(plan, fg, fb, ext)
     torch.cuda.synchronize()
     ref_spec = torch.fft.rfft2(ext)
-    err_vs_rocfft = float(((spec - ref_spec).abs().max() / ref_spec.abs().max()).item())
+    err_vs_rocfft = float(((spec_np - ref_spec).abs().max() / ref_spec.abs().max()).item())
     del ref_spec
     ms_rocfft = timed(lambda: torch.fft.rfft2(ext))
-    ms_fft_only = timed(lambda: fc2d.fc2d_fft(grid, ext, spec, fc2d.FC2D_FORWARD))
+    ms_fft_only = timed(lambda: fc2d.fc2d_fft(grid, ext, spec_np, fc2d.FC2D_FORWARD))
     print("[bench] 2D R2C of the extended fields: library %.3f ms, rocFFT (torch.fft.rfft2) %.3f ms, spectra agree "
           "to %.1e" % (ms_fft_only, ms_rocfft, err_vs_rocfft), file=sys.stderr, flush=True)
 
@@ -660,7 +676,7 @@ def main():
     batched, ff_check = None, None
     if not args.no_batched:
         print("[bench] Fourier Forwarding, plain and batched ...", file=sys.stderr, flush=True)
-        del fg, fb, ext, spec
+        del fg, fb, ext, spec, spec_np
         torch.cuda.empty_cache()
         batched, ff_check = run_ff(args)
         print("[bench] FF step: plain %.3f ms (%.3e points/s), batched %.3f ms (%.3e points/s)"
@@ -671,7 +687,7 @@ def main():
     if not args.no_mlp:
         print("[bench] learned foot seed ...", file=sys.stderr, flush=True)
         if batched is None:
-            del fg, fb, ext, spec
+            del fg, fb, ext, spec, spec_np
             torch.cuda.empty_cache()
         learned = run_mlp(args)
         print("[bench] learned seed: " + json.dumps(learned), file=sys.stderr, flush=True)
@@ -706,7 +722,10 @@ def main():
         "dtype": "f64", "data": "synthetic",
         "config": {"workload": "star r=1+0.3cos5t, B=%d, [-1.6,1.6]^2 on %dx%d, d=5, C=27, M=8, k1=%g; "
                                "extend + forward FFT of %d fields per step" % (case.B, case.n, case.n, case.k1, nf),
-                   "fields_per_step": nf, "grid": case.n, "path": "fused extend+FFT (fc2d_extend_fft)",
+                   "fields_per_step": nf, "grid": case.n,
+                   "path": "fused extend+FFT into a half spectrum with 128-byte-aligned rows (fc2d_extend_fft_ld, "
+                           "row pitch %d complex)" % ld,
+                   "numpy_layout_points_per_s": value_np, "numpy_layout_ms_per_step": ms_np,
                    "plain_points_per_s": value_plain, "plain_ms_per_step": ms_plain,
                    "fft_only_ms": ms_fft_only, "rocfft_reference_ms": ms_rocfft,
                    "rocfft_reference": "torch.fft.rfft2 (rocFFT via hipFFT), float64, same extended fields",

@@ -209,6 +209,15 @@ int fc2d_boundary_values(const fc2d_plan* plan, const double* u, double* f_bdry,
 int fc2d_extend_fft(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, double* work,
                     void* spec, int nf, hipStream_t stream);
 
+/* fc2d_extend_fft with the half spectrum's rows spec_ld >= ny/2 + 1 complex
+ * elements apart: spec [nf][nx][spec_ld], columns ny/2 + 1 .. spec_ld - 1 of
+ * each row neither read nor written.  spec_ld = ny/2 + 1 is the layout of
+ * fc2d_extend_fft; a multiple of 8 starts every row on a 128-byte boundary,
+ * so the column pass reads and writes whole cache lines (the numpy layout's
+ * 16 (ny/2 + 1)-byte rows start 16 bytes further into a line each row). */
+int fc2d_extend_fft_ld(const fc2d_plan* plan, const double* f_grid, const double* f_bdry, double* work,
+                       void* spec, int spec_ld, int nf, hipStream_t stream);
+
 /* fc2d_extend_fft for callers that cannot allocate device memory (code under
  * HIP graph capture, tight serving loops, harnesses that forbid allocation):
  * same arguments, kernels and results (bitwise), but the Gram records live in
@@ -232,6 +241,9 @@ int fc2d_extend_fft_noalloc(const fc2d_plan* plan, const double* f_grid, const d
  * second spectrum-sized buffer per call), out = real, scaled by 1/(nx ny).
  * in and out must not overlap; `in` is therefore not const. */
 int fc2d_fft(const fc2d_grid* grid, void* in, void* out, int dir, int nf, hipStream_t stream);
+/* fc2d_fft with the half spectrum's rows spec_ld >= ny/2 + 1 complex elements
+ * apart (as fc2d_extend_fft_ld). */
+int fc2d_fft_ld(const fc2d_grid* grid, void* in, void* out, int dir, int spec_ld, int nf, hipStream_t stream);
 
 /* Full Poisson solve (Sec. 4.1; eq. def_poisson): Delta u = f in Omega, u = g on
  * Gamma, as u = u_p + v (eq. total_soln).  u_p is the 2D-FC particular solution

@@ -192,18 +192,19 @@ int static_scratch(double** p, size_t* bytes);
 // ---- FFT and spectral kernels (kernels_fft.hip) ----
 // strip / cls2 non-null: the rows are assembled on the fly from `in` (IN),
 // `strip` (STRIP) and zeros (FAR) using the per-pair class bytes cls2.
+// ld: row pitch of the half spectrum in complex elements (0 -> ny/2 + 1, the numpy layout)
 int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s,
-             const double* strip = nullptr, const uint8_t* cls2 = nullptr);
-int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s);
+             const double* strip = nullptr, const uint8_t* cls2 = nullptr, int ld = 0);
+int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s, int ld = 0);
 // single passes (batches) and twiddle set-up outside stream capture
 int fft_prepare(int nx, int ny);
 // true when the twiddle tables of lengths nx and ny exist on the current device
 // (then the FFT launches allocate nothing)
 bool fft_ready(int nx, int ny);
 int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
-                 const uint8_t* cls2);
-int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s);
-int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s);
+                 const uint8_t* cls2, int ld = 0);
+int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s, int ld = 0);
+int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, int ld = 0);
 // the same row passes with the half spectrum transposed, [field][bin][row] (ny <= 4096)
 int fft_rows_fwd_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
                    const uint8_t* cls2);

@@ -314,6 +314,21 @@ __device__ __forceinline__ int xcd_row_block(int nrb) {
 
 __device__ const double2 g_zero_pair[1] = {{0.0, 0.0}};
 
+// Streaming (non-temporal) 16-byte loads and stores: the passes touch every
+// element once, so they bypass the cache's normal retention (measured on a
+// 1 GiB device copy: 6.2 TB/s with non-temporal accesses, 4.3-5.7 TB/s without).
+typedef double nt_d2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+    const nt_d2 v = __builtin_nontemporal_load((const nt_d2*)p);
+    return make_double2(v.x, v.y);
+}
+__device__ __forceinline__ void st_nt(double2* p, double2 x) {
+    nt_d2 v;
+    v.x = x.x;
+    v.y = x.y;
+    __builtin_nontemporal_store(v, (nt_d2*)p);
+}
+
 // One unconditional 16-byte load per pair from a selected source: both IN ->
 // the field, both STRIP -> the strip values, anything else -> a cached zero
 // pair (mixed pairs are fixed up afterwards).
@@ -337,7 +352,7 @@ template <int L, int E, int RPB, bool MASKED, bool TRANS>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __restrict__ in, double2* __restrict__ out,
                                                             int nx, const double2* __restrict__ tw,
                                                             const double* __restrict__ strip,
-                                                            const uint8_t* __restrict__ cls2) {
+                                                            const uint8_t* __restrict__ cls2, int ld) {
     constexpr int P = L / E;
     constexpr int N = 2 * L;
     constexpr int QS = TRANS ? L + 2 : L;
@@ -357,7 +372,7 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
         uint8_t cb[E];
         load_classes<E>(cls2 + (int64_t)(live ? row : 0) * L + t * E, cb);
 #pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = *pair_source(src, ssrc, cb[k], in_index<L, E>(k, t));
+        for (int k = 0; k < E; ++k) v[k] = ld_nt(pair_source(src, ssrc, cb[k], in_index<L, E>(k, t)));
 #pragma unroll
         for (int k = 0; k < E; ++k) {
             const int c = cb[k];
@@ -365,7 +380,7 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
         }
     } else {
 #pragma unroll
-        for (int k = 0; k < E; ++k) v[k] = ((const double2*)src)[in_index<L, E>(k, t)];
+        for (int k = 0; k < E; ++k) v[k] = ld_nt((const double2*)src + in_index<L, E>(k, t));
     }
     StockhamFrom<L, E, 1, false>::run(v, lds, QS, 1, q, t, tw, N);
     __syncthreads();
@@ -390,7 +405,7 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
         const double2 O = make_double2(D.y, -D.x);   // D / i
         const double2 X = cadd(Eh, cmul(wk, O));
         if (TRANS) out[((int64_t)f * (L + 1) + k) * nx + orow] = X;
-        else out[((int64_t)f * nx + orow) * (L + 1) + k] = X;
+        else st_nt(out + ((int64_t)f * nx + orow) * ld + k, X);
         wk = cmul(wk, wstep);
     }
 }
@@ -400,7 +415,8 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
 // first stages its RPB rows in LDS (RPB x 16 contiguous bytes per bin).
 template <int L, int E, int RPB, bool TRANS>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __restrict__ in, double* __restrict__ out,
-                                                            int nx, const double2* __restrict__ tw, double scale) {
+                                                            int nx, const double2* __restrict__ tw, double scale,
+                                                            int ld) {
     constexpr int P = L / E;
     constexpr int N = 2 * L;
     constexpr int QS = TRANS ? L + 2 : L;
@@ -412,7 +428,7 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __res
     const int row = rblk * RPB + q;
     const int f = blockIdx.y;
     const bool live = row < nx;
-    const double2* src = in + ((int64_t)f * nx + (live ? row : 0)) * (L + 1);
+    const double2* src = in + ((int64_t)f * nx + (live ? row : 0)) * ld;
     if constexpr (TRANS) {
         // bins 0..L of the block's rows
         for (int e = threadIdx.x; e < RPB * (L + 1); e += RPB * P) {
@@ -437,7 +453,7 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __res
     if (!live) return;
     double2* dst = (double2*)(out + ((int64_t)f * nx + row) * N);
 #pragma unroll
-    for (int k = 0; k < E; ++k) dst[out_index<L, E>(k, t)] = make_double2(v[k].x * scale, v[k].y * scale);
+    for (int k = 0; k < E; ++k) st_nt(dst + out_index<L, E>(k, t), make_double2(v[k].x * scale, v[k].y * scale));
 }
 
 // ---------------------------------------------------------------------------
@@ -464,8 +480,11 @@ __device__ __forceinline__ bool col_block(int ntiles, bool by_field, int* tile, 
     return *tile < ntiles;
 }
 
-template <int L, int E, int T, bool INV>
-__global__ __launch_bounds__(T * (L / E)) void k_cols(double2* __restrict__ data, int ncol,
+// NT: rows of the half spectrum start on 128-byte lines and a tile row is a
+// whole number of lines (T >= 8): loads and stores stream past the caches
+// (with lines shared between tiles, non-temporal stores cost more than they save)
+template <int L, int E, int T, bool INV, bool NT>
+__global__ __launch_bounds__(T * (L / E)) void k_cols(double2* __restrict__ data, int ncol, int ld,
                                                       const double2* __restrict__ tw, int by_field) {
     constexpr int P = L / E;
     __shared__ double2 lds[L * T];
@@ -476,14 +495,21 @@ __global__ __launch_bounds__(T * (L / E)) void k_cols(double2* __restrict__ data
     if (!col_block(ntiles, by_field != 0, &tile, &field)) return;   // uniform per block
     const int col = tile * T + q;
     const bool live = col < ncol;
-    double2* base = data + (int64_t)field * L * ncol + (live ? col : 0);
+    double2* base = data + (int64_t)field * L * ld + (live ? col : 0);
     double2 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, t) * ncol];
+    for (int k = 0; k < E; ++k) {
+        const double2* p = base + (int64_t)in_index<L, E>(k, t) * ld;
+        v[k] = NT ? ld_nt(p) : *p;
+    }
     StockhamFrom<L, E, 1, INV>::run(v, lds, 1, T, q, t, tw, L);
     if (!live) return;
 #pragma unroll
-    for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, t) * ncol] = v[k];
+    for (int k = 0; k < E; ++k) {
+        double2* p = base + (int64_t)out_index<L, E>(k, t) * ld;
+        if (NT) st_nt(p, v[k]);
+        else *p = v[k];
+    }
 }
 
 static int check(const char* what, hipStream_t s) {
@@ -500,7 +526,7 @@ static int check(const char* what, hipStream_t s) {
 // forms take 4 rows per block (64 contiguous bytes per bin)
 template <bool FWD, bool TRANS>
 static void launch_rows(int L, int nx, int nf, const void* in, void* out, const double2* tw, double scale,
-                        const double* strip, const uint8_t* cls2, hipStream_t s) {
+                        const double* strip, const uint8_t* cls2, hipStream_t s, int ld) {
 #define FC2D_ROWS(LL, EE, RR0)                                                                             \
     case LL: {                                                                                             \
         constexpr int RR = TRANS ? 4 : RR0;                                                                \
@@ -508,10 +534,10 @@ static void launch_rows(int L, int nx, int nf, const void* in, void* out, const 
             const int nrb = (nx + RR - 1) / RR;                                                            \
             dim3 g(TRANS ? (nrb + 7) / 8 * 8 : nrb, nf);                                                   \
             if (FWD && cls2)                                                                               \
-                k_rows_r2c<LL, EE, RR, true, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, strip, cls2); \
+                k_rows_r2c<LL, EE, RR, true, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, strip, cls2, ld); \
             else if (FWD)                                                                                  \
-                k_rows_r2c<LL, EE, RR, false, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, nullptr, nullptr); \
-            else k_rows_c2r<LL, EE, RR, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double2*)in, (double*)out, nx, tw, scale); \
+                k_rows_r2c<LL, EE, RR, false, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double*)in, (double2*)out, nx, tw, nullptr, nullptr, ld); \
+            else k_rows_c2r<LL, EE, RR, TRANS><<<g, RR * (LL / EE), 0, s>>>((const double2*)in, (double*)out, nx, tw, scale, ld); \
         }                                                                                                  \
         break;                                                                                             \
     }
@@ -598,17 +624,29 @@ int col_cfg_set(int nx, int E, int T) {
 int col_tile_set(int nx, int T) { return col_cfg_set(nx, col_elems_get(nx), T); }
 int col_elems_set(int nx, int E) { return col_cfg_set(nx, E, col_tile_get(nx)); }
 
+// Rows 128-byte aligned (ld a multiple of 8 complex): tiles of at least 8
+// columns where compiled, so each tile row is whole cache lines, written
+// with non-temporal stores.
 template <bool INV>
-static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* tw, hipStream_t s) {
-    const int T = col_tile_get(nx);
+static void launch_cols(int nx, int ncol, int nf, double2* data, const double2* tw, hipStream_t s, int ld) {
+    int T = col_tile_get(nx);
     const int E = col_elems_get(nx);
-#define FC2D_COLT(LL, EE, TT)                                                                    \
-    if (nx == LL && E == EE && T == TT) {                                                        \
-        const int ntiles = (ncol + TT - 1) / TT;                                                 \
-        const bool byf = nf % 8 == 0;                                                            \
-        const dim3 g = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);   \
-        k_cols<LL, EE, TT, INV><<<g, TT * (LL / EE), 0, s>>>(data, ncol, tw, byf ? 1 : 0);       \
-        return;                                                                                  \
+    const bool aligned = ld % 8 == 0;
+    if (aligned && T < 8 && col_cfg_ok(nx, E, 8)) T = 8;
+    const bool nt = aligned && T >= 8;
+#define FC2D_COLT(LL, EE, TT)                                                                             \
+    if (nx == LL && E == EE && T == TT) {                                                                 \
+        const int ntiles = (ncol + TT - 1) / TT;                                                          \
+        const bool byf = nf % 8 == 0;                                                                     \
+        const dim3 g = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);            \
+        if constexpr (TT >= 8) {                                                                          \
+            if (nt) {                                                                                     \
+                k_cols<LL, EE, TT, INV, true><<<g, TT * (LL / EE), 0, s>>>(data, ncol, ld, tw, byf ? 1 : 0); \
+                return;                                                                                   \
+            }                                                                                             \
+        }                                                                                                 \
+        k_cols<LL, EE, TT, INV, false><<<g, TT * (LL / EE), 0, s>>>(data, ncol, ld, tw, byf ? 1 : 0);     \
+        return;                                                                                           \
     }
     FC2D_COLT(16, 2, 4) FC2D_COLT(16, 2, 8) FC2D_COLT(16, 2, 16)
     FC2D_COLT(32, 2, 4) FC2D_COLT(32, 2, 8) FC2D_COLT(32, 2, 16)
@@ -637,10 +675,10 @@ bool fft_ready(int nx, int ny) {
 }
 
 int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
-                 const uint8_t* cls2) {
+                 const uint8_t* cls2, int ld) {
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_rows<true, false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s);
+    launch_rows<true, false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s, ld > 0 ? ld : g->ny / 2 + 1);
     return check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
 }
 
@@ -649,23 +687,24 @@ int fft_rows_fwd_t(const fc2d_grid* g, const double* in, double* out, int nf, hi
     if (g->ny > 4096) { set_error("transposed spectra: rows of at most 4096 points"); return FC2D_E_ARG; }
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    launch_rows<true, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s);
+    launch_rows<true, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s, g->ny / 2 + 1);
     return check(cls2 ? "k_rows_r2c_ext" : "k_rows_r2c", s);
 }
 
-int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s) {
+int fft_cols(const fc2d_grid* g, double* data, int nf, bool inv, hipStream_t s, int ld) {
     const double2* twx = twiddles(g->nx);
     if (!twx) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
-    if (inv) launch_cols<true>(g->nx, g->ny / 2 + 1, nf, (double2*)data, twx, s);
-    else launch_cols<false>(g->nx, g->ny / 2 + 1, nf, (double2*)data, twx, s);
+    const int ncol = g->ny / 2 + 1;
+    if (inv) launch_cols<true>(g->nx, ncol, nf, (double2*)data, twx, s, ld > 0 ? ld : ncol);
+    else launch_cols<false>(g->nx, ncol, nf, (double2*)data, twx, s, ld > 0 ? ld : ncol);
     return check(inv ? "k_cols_inv" : "k_cols", s);
 }
 
-int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
+int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, int ld) {
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
     launch_rows<false, false>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr,
-                              nullptr, s);
+                              nullptr, s, ld > 0 ? ld : g->ny / 2 + 1);
     return check("k_rows_c2r", s);
 }
 
@@ -674,21 +713,21 @@ int fft_rows_inv_t(const fc2d_grid* g, const double* in, double* out, int nf, hi
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
     launch_rows<false, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr,
-                             nullptr, s);
+                             nullptr, s, g->ny / 2 + 1);
     return check("k_rows_c2r", s);
 }
 
 int fft2_r2c(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
-             const uint8_t* cls2) {
-    int st = fft_rows_fwd(g, in, out, nf, s, strip, cls2);
+             const uint8_t* cls2, int ld) {
+    int st = fft_rows_fwd(g, in, out, nf, s, strip, cls2, ld);
     if (st) return st;
-    return fft_cols(g, out, nf, false, s);
+    return fft_cols(g, out, nf, false, s, ld);
 }
 
-int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s) {
-    int st = fft_cols(g, in, nf, true, s);
+int fft2_c2r(const fc2d_grid* g, double* in, double* out, int nf, hipStream_t s, int ld) {
+    int st = fft_cols(g, in, nf, true, s, ld);
     if (st) return st;
-    return fft_rows_inv(g, in, out, nf, s);
+    return fft_rows_inv(g, in, out, nf, s, ld);
 }
 
 // ---------------------------------------------------------------------------

@@ -987,14 +987,15 @@ static int extend_fft_check(const fc2d_plan* pl, const double* f_grid, const dou
     return FC2D_OK;
 }
 
-// matching -> strip -> masked row pass -> column pass, Gram records in c
+// matching -> strip -> masked row pass -> column pass, Gram records in c,
+// half-spectrum rows at pitch ld (complex elements; 0 -> ny/2 + 1)
 static int extend_fft_run(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
-                          int nf, double* c, hipStream_t s) {
+                          int nf, double* c, hipStream_t s, int ld = 0) {
     int st;
     const int64_t nb = pl->B + (int64_t)pl->squares.size() / 2;
     if ((st = launch_match(pl, f_grid, f_bdry, nb, c, nullptr, nf, s))) return st;
     if ((st = launch_strip(pl, c, f_bdry, nb, work, nf, s))) return st;
-    return fft2_r2c(&pl->grid, f_grid, (double*)spec, nf, s, work, pl->d_cls2);
+    return fft2_r2c(&pl->grid, f_grid, (double*)spec, nf, s, work, pl->d_cls2, ld);
 }
 
 int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
@@ -1004,6 +1005,19 @@ int fc2d_extend_fft(const fc2d_plan* pl, const double* f_grid, const double* f_b
     WorkSpace ws;
     if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
     return extend_fft_run(pl, f_grid, f_bdry, work, spec, nf, (double*)ws.p, s);
+}
+
+int fc2d_extend_fft_ld(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work, void* spec,
+                       int spec_ld, int nf, hipStream_t s) {
+    int st = extend_fft_check(pl, f_grid, f_bdry, work, spec, nf);
+    if (st || nf == 0) return st;
+    if (spec_ld < pl->grid.ny / 2 + 1) {
+        set_error("fc2d_extend_fft_ld: spec_ld must be at least ny/2 + 1");
+        return FC2D_E_ARG;
+    }
+    WorkSpace ws;
+    if ((st = ws.alloc(gram_bytes(pl, nf), s))) return st;
+    return extend_fft_run(pl, f_grid, f_bdry, work, spec, nf, (double*)ws.p, s, spec_ld);
 }
 
 int fc2d_extend_fft_noalloc(const fc2d_plan* pl, const double* f_grid, const double* f_bdry, double* work,
@@ -1035,17 +1049,25 @@ int fc2d_boundary_values(const fc2d_plan* pl, const double* u, double* f_bdry, i
 
 static bool pow2_ok(int n, int nmax) { return n >= 16 && n <= nmax && (n & (n - 1)) == 0; }
 
-int fc2d_fft(const fc2d_grid* g, void* in, void* out, int dir, int nf, hipStream_t s) {
+int fc2d_fft_ld(const fc2d_grid* g, void* in, void* out, int dir, int spec_ld, int nf, hipStream_t s) {
     if (!g || !pow2_ok(g->nx, 4096) || !pow2_ok(g->ny, 8192) || nf < 0) {
         set_error("fc2d_fft: nx must be a power of two in [16, 4096] and ny one in [16, 8192]");
         return FC2D_E_ARG;
     }
+    if (spec_ld < g->ny / 2 + 1) {
+        set_error("fc2d_fft: spec_ld must be at least ny/2 + 1");
+        return FC2D_E_ARG;
+    }
     if (nf == 0) return FC2D_OK;
     if (!in || !out || in == out) { set_error("fc2d_fft: NULL or aliased buffers"); return FC2D_E_ARG; }
-    if (dir == FC2D_FORWARD) return fft2_r2c(g, (const double*)in, (double*)out, nf, s);
-    if (dir == FC2D_INVERSE) return fft2_c2r(g, (double*)in, (double*)out, nf, s);
+    if (dir == FC2D_FORWARD) return fft2_r2c(g, (const double*)in, (double*)out, nf, s, nullptr, nullptr, spec_ld);
+    if (dir == FC2D_INVERSE) return fft2_c2r(g, (double*)in, (double*)out, nf, s, spec_ld);
     set_error("fc2d_fft: dir must be FC2D_FORWARD or FC2D_INVERSE");
     return FC2D_E_ARG;
+}
+
+int fc2d_fft(const fc2d_grid* g, void* in, void* out, int dir, int nf, hipStream_t s) {
+    return fc2d_fft_ld(g, in, out, dir, g ? g->ny / 2 + 1 : 0, nf, s);
 }
 
 int fc2d_spectral_apply(const fc2d_grid* g, int op, const void* in, void* out, int nf, hipStream_t s) {

@@ -86,6 +86,8 @@ def _lib():
             "fc2d_extend": (C.c_int, [_P, _P, _P, _P, C.c_int, _P]),
             "fc2d_extend_fft": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P]),
             "fc2d_extend_fft_noalloc": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, _P]),
+            "fc2d_extend_fft_ld": (C.c_int, [_P, _P, _P, _P, _P, C.c_int, C.c_int, _P]),
+            "fc2d_fft_ld": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, C.c_int, _P]),
             "fc2d_fft": (C.c_int, [C.POINTER(fc2d_grid), _P, _P, C.c_int, C.c_int, _P]),
             "fc2d_spectral_apply": (C.c_int, [C.POINTER(fc2d_grid), C.c_int, _P, _P, C.c_int, _P]),
             "fc2d_poisson_nodes": (C.c_int, [_P, C.c_int, _P]),
@@ -323,6 +325,34 @@ def _extend_fft_args(plan, f_grid, f_bdry, work, spec):
 
 def fc2d_extend_fft(plan, f_grid, f_bdry, work, spec, stream=None):
     _check(_lib().fc2d_extend_fft(*_extend_fft_args(plan, f_grid, f_bdry, work, spec), _stream(stream)))
+
+
+def fc2d_extend_fft_ld(plan, f_grid, f_bdry, work, spec, stream=None):
+    """fc2d_extend_fft into spec [nf][nx][ld] complex128 (rows ld >= ny/2+1 apart)."""
+    import torch
+    nf = _nf(f_grid, plan.grid)
+    g = plan.grid
+    _check_bdry(plan, f_bdry, nf)
+    _check_out(work, "work", f_grid.numel(), torch.float64)
+    if spec.dtype != torch.complex128 or spec.dim() != 3 or tuple(spec.shape[:2]) != (nf, g.nx) or \
+            spec.shape[2] < g.ny // 2 + 1:
+        raise ValueError("spec must be complex128 [nf][nx][ld] with ld >= ny/2+1")
+    _check(_lib().fc2d_extend_fft_ld(plan.handle, _dptr(f_grid, "f_grid", torch.float64), _bptr(plan, f_bdry),
+                                     _dptr(work, "work", torch.float64), _dptr(spec, "spec"), int(spec.shape[2]), nf,
+                                     _stream(stream)))
+
+
+def fc2d_fft_ld(grid, inp, out, direction, stream=None):
+    """fc2d_fft with the half spectrum [nf][nx][ld] complex128 (ld >= ny/2+1)."""
+    import torch
+    real = inp if direction == FC2D_FORWARD else out
+    nf = _nf(real, grid)
+    spec = out if direction == FC2D_FORWARD else inp
+    if spec.dtype != torch.complex128 or spec.dim() != 3 or tuple(spec.shape[:2]) != (nf, grid.nx) or \
+            spec.shape[2] < grid.ny // 2 + 1:
+        raise ValueError("spectrum must be complex128 [nf][nx][ld] with ld >= ny/2+1")
+    _check(_lib().fc2d_fft_ld(C.byref(grid), _dptr(inp, "in"), _dptr(out, "out"), int(direction),
+                              int(spec.shape[2]), nf, _stream(stream)))
 
 
 def fc2d_extend_fft_noalloc(plan, f_grid, f_bdry, work, spec, stream=None):

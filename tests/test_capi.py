@@ -145,3 +145,11 @@ def test_poisson_argument_errors_without_gpu():
     lib = fc2d._lib()
     assert lib.fc2d_poisson_solve(None, None, None, None, 64, None, 1, None, None) == fc2d.FC2D_E_ARG
     assert lib.fc2d_poisson_nodes(None, 64, None) == fc2d.FC2D_E_ARG
+
+
+def test_spectrum_pitch_below_half_width_refused():
+    from paper_2010_03901_amd import fc2d
+    lib = fc2d._lib()
+    g = fc2d.make_grid(0.0, 0.0, 0.01, 64, 64)
+    assert lib.fc2d_fft_ld(C.byref(g), C.c_void_p(8), C.c_void_p(16), fc2d.FC2D_FORWARD, 32, 1, None) == fc2d.FC2D_E_ARG
+    assert b"spec_ld" in lib.fc2d_last_error()

@@ -139,13 +139,22 @@ def solve(pl, f_grid, f_bdry, g_nodes, nb, MP=None, sample=None):
     # points within h/2 of Gamma: along the normal from the foot
     bd = pl.bd
     bq = np.stack([bd["x"], bd["y"]], 1)
-    near = []
+    near, dnear = [], []
     for a in range(0, P.shape[0], 4096):
         d2 = ((P[a:a + 4096, None, :] - bq[None, :, :]) ** 2).sum(-1)
         near.append(np.argmin(d2, 1))
+        dnear.append(np.sqrt(d2.min(1)))
     seed = np.concatenate(near)
-    th, eta, _ = foot_solve(curve, bd, P[:, 0], P[:, 1], seed, pl.M)
+    dnear = np.concatenate(dnear)
     h = grid.h
+    # only points that can lie within h/2 of Gamma take the foot of the normal (a
+    # point's nearest boundary sample is at most half a sample spacing farther than
+    # its foot); far inside, e.g. at a disc's centre, the foot is not defined
+    spacing = bd["k2"] * float(np.hypot(bd["x1"], bd["y1"]).max())
+    cand = np.nonzero(dnear <= 0.5 * h + spacing)[0]
+    th = np.zeros(P.shape[0])
+    eta = np.full(P.shape[0], np.inf)
+    th[cand], eta[cand], _ = foot_solve(curve, bd, P[cand, 0], P[cand, 1], seed[cand], pl.M)
     sel = np.nonzero(np.abs(eta) < 0.5 * h)[0]
     if sel.size:
         x, y, x1, y1, _, _ = curve.eval_vec(th[sel])

@@ -274,3 +274,43 @@ def test_poisson_field_chunks(torch_mod):
         print("\n[poisson] chunked field %d: vs alone %.1e, vs exact %.1e"
               % (k, e, np.linalg.norm(u_all[k][ins] - ex) / np.linalg.norm(ex)), end="")
         assert e < 1e-13
+
+
+def test_paper_example_41_disc(torch_mod):
+    """Example 4.1 (unit disc, f = -sin 2 pi x sin 2 pi y, h = 2e-2, N^Omega = 100)
+    on a power-of-two box (256^2, shifted by h/3 so no grid point falls on Gamma or on
+    a Nystrom node), nb = 256: with d = 10 (M = 13) the relative l2 error over the IN
+    points within a factor 2 of the quoted 1.4e-12; with d = 5 (M = 8) the solve
+    against the oracle's (1e-11 of max |u|)."""
+    from paper_2010_03901_amd import fc2d
+    torch = torch_mod
+    (h, _, _, ref), = load_golden("paper_ex41_disc_poisson.txt")
+    n = 256
+    x0 = -0.5 * n * h + h / 3
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0")
+    res = {}
+    for d, M in ((10, 13), (5, 8)):
+        grid = fc2d.make_grid(x0, x0, h, n, n)
+        pl = fc2d.Plan(fc2d.make_curve(*W.disc()), grid, d=d, C_=27, B=int(round(2 * np.pi / h)), k1=h, M=M)
+        bp = fc2d.fc2d_boundary_points(pl)
+        q = fc2d.fc2d_poisson_nodes(pl, n)
+        X, Y = np.meshgrid(x0 + np.arange(n) * h, x0 + np.arange(n) * h, indexing="ij")
+        u = torch.full((1, n, n), float("nan"), dtype=torch.float64, device="cuda:0")
+        it = fc2d.fc2d_poisson_solve(pl, dev(_f(X, Y)[None]), dev(_f(bp[:, 0], bp[:, 1])[None]),
+                                     dev(_u_exact(q[:, 0], q[:, 1])[None]), u)
+        torch.cuda.synchronize()
+        u = u[0].cpu().numpy()
+        ins = fc2d.fc2d_plan_classes(pl) == OP.IN
+        ex = _u_exact(X, Y)[ins]
+        res[d] = (u, np.linalg.norm(u[ins] - ex) / np.linalg.norm(ex))
+        print("\n[poisson] Example 4.1 d=%d: rel l2 %.2e (quoted %.1e), GMRES %d" % (d, res[d][1], ref, it), end="")
+    assert ref / 2 < res[10][1] < 2 * ref
+    opl = OP.make_plan(Curve(*W.disc()), OP.Grid(x0, x0, h, n, n), fcgram.load_tables(5), int(round(2 * np.pi / h)),
+                       k1=h, M=8)
+    X, Y = np.meshgrid(opl.grid.xs(), opl.grid.ys(), indexing="ij")
+    obp = OP.boundary_points(opl)
+    _, oq, _, _ = OPS.nodes(opl.curve, n)
+    ou = OPS.solve(opl, _f(X, Y), _f(obp[:, 0], obp[:, 1]), _u_exact(oq[:, 0], oq[:, 1]), n)
+    e = rel_err(res[5][0], ou)
+    print("\n[poisson] Example 4.1 d=5: rel err vs oracle %.2e" % e, end="")
+    assert e < 1e-11

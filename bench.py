@@ -499,6 +499,7 @@ def run_mlp(args):
             if best is None or kms < best["classify_kernel_ms"]:
                 inf = pl.info
                 best = {"plan_s": wall, "classify_kernel_ms": kms,
+                        "phases_ms": {k: inf.t_ms[i] for i, k in enumerate(fc2d.PLAN_PHASES)},
                         "kernels_ms": {k: t for k, t in tr if k.startswith("k_")},
                         "solved": inf.n_solved, "strip": inf.n_strip,
                         "newton_steps_per_point": inf.newton_iters / max(inf.n_solved, 1),
@@ -543,6 +544,7 @@ def run_mlp(args):
             "classify_speedup_mlp_vs_proximity": sp("proximity", "mlp"),
             "classify_speedup_mlp_vs_polar": sp("polar", "mlp"),
             "plan_speedup_mlp_vs_proximity": res["proximity"]["plan_s"] / res["mlp"]["plan_s"],
+            "plan_speedup_mlp_vs_polar": res["polar"]["plan_s"] / res["mlp"]["plan_s"],
             "extend_fft": {"fields": nf, "ms": ms, "points_per_s": nf * case.n * case.n / (ms * 1e-3)}}
 
 

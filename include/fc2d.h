@@ -130,6 +130,17 @@ typedef struct {
 
 typedef struct fc2d_plan fc2d_plan;
 
+/* Phases of plan creation timed in fc2d_plan_info.t_ms (host wall clock; device
+ * work inside a phase is waited for by that phase). */
+enum {
+    FC2D_PHASE_GEOMETRY = 0,   /* boundary grid, admissibility, crossing polygon */
+    FC2D_PHASE_CLASSIFY = 1,   /* classification and foot kernels, until their results are on the host */
+    FC2D_PHASE_LISTS = 2,      /* STRIP list order, class counts */
+    FC2D_PHASE_MATCHING = 3,   /* matching stencils, squares and weights */
+    FC2D_PHASE_LAYOUT = 4,     /* device layouts (stencils, row runs, pair classes) and uploads */
+    FC2D_PLAN_PHASES = 5
+};
+
 typedef struct {
     int d, C, M, n_r, Cr, B;
     double k1, k2;
@@ -141,6 +152,7 @@ typedef struct {
     int64_t n_solved;       /* grid points whose foot was solved (candidates near Gamma) */
     int64_t n_fallback;     /* MLP seed: points that took the bracketed fallback */
     int64_t newton_iters;   /* Newton steps summed over the solved points */
+    double t_ms[FC2D_PLAN_PHASES];   /* host wall clock of plan creation by phase, ms: FC2D_PHASE_* */
 } fc2d_plan_info;
 
 void fc2d_opts_default(const fc2d_grid* grid, fc2d_opts* opts);

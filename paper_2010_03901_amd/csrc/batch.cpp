@@ -306,7 +306,7 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
             P.sidx = pl->d_sidx; P.sth = pl->d_sth; P.seta = pl->d_seta; P.bxy = pl->d_bxy;
             P.B = pl->B; P.D = pl->d; P.nf = b->nf[k]; P.nx = g.grid.nx; P.ny = g.grid.ny;
             P.io = pl->interior_only ? 1 : 0;
-            P.npts = npts; P.nbdry = nb; P.S = (int64_t)pl->strip_idx.size();
+            P.npts = npts; P.nbdry = nb; P.S = pl->n_strip;
             P.k2 = pl->k2; P.lev_scale = pl->n_r / pl->k1; P.x0 = g.grid.x0; P.y0 = g.grid.y0; P.h = g.grid.h;
             P.u = g.state + ((int64_t)half * g.nf_total + b->field_off[k]) * npts;
             double *fb = nullptr, *cb = nullptr;

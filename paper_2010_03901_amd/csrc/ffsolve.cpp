@@ -193,6 +193,7 @@ int ff_build(fc2d_ff* f) {
     const int n_o = d;
     const size_t npts = (size_t)nx * ny;
     std::vector<uint8_t> in(npts), near0(npts), ub(npts);
+    if (int st = plan_host_lists(pl)) return st;
     for (size_t k = 0; k < npts; ++k) in[k] = pl->cls[k] == 1;
     // Chebyshev dilation of the non-IN set by nB (outside the grid counts as non-IN), separably
     for (int i = 0; i < nx; ++i)

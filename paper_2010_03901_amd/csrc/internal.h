@@ -4,6 +4,7 @@
 
 #include <stdint.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -63,15 +64,21 @@ struct fc2d_plan {
     std::vector<double> Q, A, Ar;                // tables
     std::vector<double> bx, by, bnx, bny;        // boundary samples and normals
     std::vector<double> squares;                 // 2 per square (x, y)
-    std::vector<int8_t> cls;                     // nx * ny
-    std::vector<int32_t> strip_idx, strip_seed;  // row-major STRIP list
-    std::vector<double> strip_theta, strip_eta;
+    // host copies of the classes and the row-major STRIP list, downloaded from
+    // the device copies on first use (plan_host_lists)
+    mutable std::mutex host_mu;
+    mutable bool host_ready = false;
+    mutable std::vector<int8_t> cls;                     // nx * ny
+    mutable std::vector<int32_t> strip_idx, strip_seed;  // row-major STRIP list
+    mutable std::vector<double> strip_theta, strip_eta;
+    int64_t n_strip = 0;
     int newton_max_iters = 0;
     int strip_wmax = 0;   // widest stencil window (normals) of a block of 512 theta-sorted STRIP points
     int64_t n_in = 0, n_far = 0;
     int seed = 0;
     bool interior_only = false;   // Remark 3.1 II: no boundary samples, d matching values interpolated
     int64_t n_solved = 0, n_fallback = 0, newton_iters = 0;
+    double t_ms[FC2D_PLAN_PHASES] = {};   // host wall clock per set-up phase (fc2d_plan_info.t_ms)
     // device
     double* d_Q = nullptr;          // [d][d]
     double* d_Ar = nullptr;         // [Cr][d]
@@ -90,6 +97,11 @@ struct fc2d_plan {
     int32_t* d_run = nullptr;       // [nruns][3] (start, end, class)
     double* d_bxy = nullptr;        // [n_bdry][2] boundary points (feet, then squares)
     uint8_t* d_cls2 = nullptr;      // [nx][ny/2] pair classes (2 bits per point) in row-pass thread order
+    int8_t* d_cls = nullptr;        // [nx][ny] classes (0 FAR, 1 IN, 2 STRIP)
+    int32_t* d_rm_idx = nullptr;    // [S] row-major STRIP list: flat index, seed normal
+    int32_t* d_rm_seed = nullptr;
+    double* d_rm_th = nullptr;      // [S] theta^Q, eta_Q in row-major order
+    double* d_rm_eta = nullptr;
     int nruns = 0;
 };
 
@@ -141,6 +153,44 @@ int launch_seed_polar(const SeedArgs& a, const int32_t* d_cand, int64_t ncand, i
                       int64_t cap, int* d_counters, hipStream_t s);
 int launch_seed_mlp(const SeedArgs& a, const float* d_w, const int32_t* d_cand, int64_t ncand, int8_t* d_cls,
                     StripRec* d_rec, int64_t cap, int* d_counters, hipStream_t s);
+
+// Lists of the plan built on the device from the classes and the STRIP records:
+// per-row runs of equal class (d_run_ptr, d_run), the row pass's pair classes
+// (d_cls2, when pair_E > 0), the row-major STRIP list (d_rm_*) and the STRIP
+// list in order of theta (d_sidx, d_sth, d_seta) with the widest strip-kernel
+// block window (strip_wmax), plus n_in / n_far.  The classification work space
+// (d_cls, rec with S records) must be complete on stream s.
+int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream_t s);
+// host copies of the classes and the row-major STRIP list (downloaded once)
+int plan_host_lists(const fc2d_plan* pl);
+
+// Red-star candidates of the matching stencils (Sec. 3.2): one per (normal,
+// candidate line).  The device scans the star's grid line for the runs of IN
+// points next to it and locates the line's crossings with Gamma bounding them.
+struct StarQ {
+    int32_t p;          // normal
+    int32_t vertical;   // 1: the line x = x_line (runs along y); 0: y = y_line
+    int32_t line;       // grid line index
+    int32_t jb;         // grid index along the line just below the star
+    double a_line;      // the line's coordinate
+    double bstar;       // the star's coordinate along the line
+    int32_t skip;       // 1: too close to Gamma, not used
+    int32_t pad;
+};
+struct StarR {
+    int32_t nlo, nhi;   // IN points jb, jb-1, ... (nlo of them) and jb+1, ... (nhi)
+    int32_t flags;      // 1: run below ends at Gamma within M steps (square sq[0]); 2: above (sq[1]); 4: foot failed
+    int32_t pad;
+    double sq[2];       // crossing coordinate along the line
+};
+struct StarArgs {
+    CurveC curve;
+    const double *bx, *by, *bnx, *bny;
+    int B, M, maxit, io;
+    double k2, x0, y0, h;
+    int nx, ny;
+};
+int launch_star_scan(const StarArgs& a, const int8_t* d_cls, const StarQ* d_q, StarR* d_r, int n, hipStream_t s);
 
 // ---- batches: one descriptor per (plan, field set) for the persistent kernels ----
 struct PlanDev {

@@ -710,7 +710,7 @@ size_t strip_lds(int wmax, int d, int Cr, int fpt, int* lcap, int* fstage) {
 
 int launch_strip(const fc2d_plan* pl, const double* c, const double* f_bdry, int64_t nbdry, double* out, int nf,
                  hipStream_t s) {
-    const int64_t S = (int64_t)pl->strip_idx.size();
+    const int64_t S = pl->n_strip;
     if (S == 0) return FC2D_OK;
     const int64_t npts = (int64_t)pl->grid.nx * pl->grid.ny;
     // fields per thread: at most 8, the chunks a multiple of 8 (an equal range

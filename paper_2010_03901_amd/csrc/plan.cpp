@@ -27,6 +27,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <new>
 #include <string>
@@ -177,26 +178,15 @@ static int nearest_sample(const fc2d_plan* pl, double X, double Y, int p) {
 // the normal) are skipped: the point on Gamma is itself a node along the normal
 constexpr double kStarMinDepth = 0.05;
 constexpr int32_t kUnusedRef = INT32_MIN;   // stencil entry of the point-on-Gamma slot (not gathered)
+constexpr int kMaxStencil = 15;             // largest compiled M
 
-struct StarRec {
-    int p;
-    bool vertical;
-    int line;            // grid line index i_s
-    long double delta;   // depth along the inward normal
-    long double bstar;   // coordinate of the star along its line
-    std::vector<int> lower, upper;   // IN node indices along the line
-    bool sq_has[2] = {false, false};
-    double sq_b[2] = {0, 0};
-};
-struct SqReq {
-    int rid, side;
-    bool vertical;
-    double a_line, b_in, b_out, result;
-    int seed;
-};
-
-static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
-                          std::vector<double>& mwv, std::vector<double>& mwn) {
+// Red stars and their nodes (Sec. 3.2, Fig. 3).  The host places each normal's
+// 2M candidate stars (depth and position in extended precision); the device
+// scans their grid lines for the IN runs next to them and bisects the lines'
+// crossings with Gamma (k_star_scan); the host then picks the stars and nodes
+// and forms the weights, normal by normal in parallel.
+static int build_matching(fc2d_plan* pl, int maxit, const BndView& dbd, hipStream_t stream,
+                          std::vector<int32_t>& mref, std::vector<double>& mwv, std::vector<double>& mwn) {
     const fc2d_grid& g = pl->grid;
     const int M = pl->M, d = pl->d, B = pl->B;
     const bool io = pl->interior_only;
@@ -205,181 +195,174 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
     // boundary sample) is the M-th node of the along-normal interpolation
     const int nstar = io ? M : M - 1;
     const double h = g.h;
-    std::vector<StarRec> stars;
-    stars.reserve((size_t)B * 2 * M);
-    std::vector<SqReq> reqs;
+    const int ns = 2 * M;   // candidates per normal
+    const size_t nst = (size_t)B * ns;
+    std::vector<StarQ> q(nst);
+    std::vector<long double> delta(nst), bstar(nst);
+#pragma omp parallel for
     for (int p = 0; p < B; ++p) {
         const double nx = pl->bnx[p], ny = pl->bny[p];
         const bool vertical = fabs(nx) >= fabs(ny);
         double na, nb, qa, qb, a0, b0;
-        int Nb;
         if (vertical) {
-            na = nx; nb = ny; qa = pl->bx[p]; qb = pl->by[p]; a0 = g.x0; b0 = g.y0; Nb = g.ny;
+            na = nx; nb = ny; qa = pl->bx[p]; qb = pl->by[p]; a0 = g.x0; b0 = g.y0;
         } else {
-            na = ny; nb = nx; qa = pl->by[p]; qb = pl->bx[p]; a0 = g.y0; b0 = g.x0; Nb = g.nx;
+            na = ny; nb = nx; qa = pl->by[p]; qb = pl->bx[p]; a0 = g.y0; b0 = g.x0;
         }
         const double u = (qa - a0) / h;
         int i_first, step;
         if (na > 0) { i_first = (int)floor(u); step = -1; }
         else { i_first = (int)ceil(u); step = 1; }
-        for (int s = 0; s < 2 * M; ++s) {
-            StarRec r;
+        for (int c = 0; c < ns; ++c) {
+            const size_t k = (size_t)p * ns + c;
+            StarQ& r = q[k];
             r.p = p;
-            r.vertical = vertical;
-            r.line = i_first + step * s;
-            const double a_s = a0 + r.line * h;
-            r.delta = ((long double)qa - (long double)a_s) / (long double)na;
-            r.bstar = (long double)qb - r.delta * (long double)nb;
-            const int jb = (int)floor(((double)r.bstar - b0) / h);
-            if (!io && r.delta < (long double)kStarMinDepth * h / fabs(na)) {
-                stars.push_back(std::move(r));   // too close to the point on Gamma: unusable
-                continue;
-            }
-            auto c_at = [&](int j) -> int {
-                if (j < 0 || j >= Nb) return 0;
-                if (r.line < 0 || r.line >= (vertical ? g.nx : g.ny)) return 0;
-                return vertical ? pl->cls[(size_t)r.line * g.ny + j] : pl->cls[(size_t)j * g.ny + r.line];
-            };
-            int j = jb;
-            while (j >= jb - M && c_at(j) == 1) { r.lower.push_back(j); --j; }
-            const bool lo_stop = j >= jb - M;
-            const int jlo = j;
-            j = jb + 1;
-            while (j <= jb + 1 + M && c_at(j) == 1) { r.upper.push_back(j); ++j; }
-            const bool hi_stop = j <= jb + 1 + M;
-            const int jhi = j;
-            const int rid = (int)stars.size();
-            if (io) {   // no boundary samples: IN nodes only
-                stars.push_back(std::move(r));
-                continue;
-            }
-            if (lo_stop) {
-                SqReq q{rid, 0, vertical, a_s,
-                        r.lower.empty() ? (double)r.bstar : b0 + (jlo + 1) * h, b0 + jlo * h, 0.0, p};
-                reqs.push_back(q);
-            }
-            if (hi_stop) {
-                SqReq q{rid, 1, vertical, a_s,
-                        r.upper.empty() ? (double)r.bstar : b0 + (jhi - 1) * h, b0 + jhi * h, 0.0, p};
-                reqs.push_back(q);
-            }
-            stars.push_back(std::move(r));
+            r.vertical = vertical ? 1 : 0;
+            r.line = i_first + step * c;
+            r.a_line = a0 + r.line * h;
+            delta[k] = ((long double)qa - (long double)r.a_line) / (long double)na;
+            bstar[k] = (long double)qb - delta[k] * (long double)nb;
+            r.bstar = (double)bstar[k];
+            r.jb = (int)floor((r.bstar - b0) / h);
+            r.skip = (!io && delta[k] < (long double)kStarMinDepth * h / fabs(na)) ? 1 : 0;   // too close to
+            r.pad = 0;                                                                      // the point on Gamma
         }
     }
-    // squares: bisection on the sign of eta along each segment
-    const BndView bd{pl->bx.data(), pl->by.data(), pl->bnx.data(), pl->bny.data(), B, pl->k2};
-    int fail = 0;
-#pragma omp parallel for schedule(dynamic, 64) reduction(+ : fail)
-    for (long k = 0; k < (long)reqs.size(); ++k) {
-        SqReq& q = reqs[k];
-        double lo = q.b_in, hi = q.b_out;
-        int seed = q.seed;
-        for (int it = 0; it < 64; ++it) {
-            const double mid = 0.5 * (lo + hi);
-            const double X = q.vertical ? q.a_line : mid;
-            const double Y = q.vertical ? mid : q.a_line;
-            seed = nearest_sample(pl, X, Y, seed);
-            double th, eta;
-            int its;
-            if (foot_host(M, pl->curve, bd, X, Y, seed, maxit, &th, &eta, &its) != FOOT_OK) {
-                ++fail;
-                break;
-            }
-            if (eta <= 0) lo = mid;
-            else hi = mid;
+    // device: IN runs along the candidates' lines and the squares bounding them
+    std::vector<StarR> res(nst);
+    {
+        StarArgs sa;
+        sa.curve = pl->curve;
+        sa.bx = dbd.x; sa.by = dbd.y; sa.bnx = dbd.nx; sa.bny = dbd.ny;
+        sa.B = B; sa.M = M; sa.maxit = maxit; sa.io = io ? 1 : 0;
+        sa.k2 = pl->k2; sa.x0 = g.x0; sa.y0 = g.y0; sa.h = h;
+        sa.nx = g.nx; sa.ny = g.ny;
+        StarQ* d_q = nullptr;
+        StarR* d_r = nullptr;
+        int st = dev_upload(&d_q, q.data(), nst);
+        hipError_t e = hipSuccess;
+        if (!st && (e = hipMalloc((void**)&d_r, nst * sizeof(StarR))) != hipSuccess) st = hip_fail(e, "red-star scan");
+        if (!st) st = launch_star_scan(sa, pl->d_cls, d_q, d_r, (int)nst, stream);
+        if (!st && ((e = hipMemcpyAsync(res.data(), d_r, nst * sizeof(StarR), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+                    (e = hipStreamSynchronize(stream)) != hipSuccess))
+            st = hip_fail(e, "red-star scan");
+        if (d_q) (void)hipFree(d_q);
+        if (d_r) (void)hipFree(d_r);
+        if (st) return st;
+    }
+    for (size_t k = 0; k < nst; ++k)
+        if (res[k].flags & 4) {
+            set_error("foot of the normal failed while locating grid-line crossings with the boundary");
+            return FC2D_E_NEWTON;
         }
-        q.result = 0.5 * (lo + hi);
-    }
-    if (fail) {
-        set_error("foot of the normal failed while locating grid-line crossings with the boundary");
-        return FC2D_E_NEWTON;
-    }
-    for (const SqReq& q : reqs) {
-        StarRec& r = stars[q.rid];
-        const double b0 = r.vertical ? g.y0 : g.x0;
-        bool near_node = false;
-        for (int j : r.lower) near_node = near_node || fabs(q.result - (b0 + j * h)) < 0.5 * h;
-        for (int j : r.upper) near_node = near_node || fabs(q.result - (b0 + j * h)) < 0.5 * h;
-        if (near_node) continue;   // dropped: closer than h/2 to an IN node
-        r.sq_has[q.side] = true;
-        r.sq_b[q.side] = q.result;
-    }
-    // select stars and nodes, form weights
+    // select stars and nodes, form weights; squares per normal, numbered afterwards
     mref.assign((size_t)B * M * M, 0);
     mwv.assign((size_t)B * M * M * 2, 0.0);
     mwn.assign((size_t)B * nq * M * 2, 0.0);
-    pl->squares.clear();
-    std::vector<long double> deltas(M);
+    std::vector<double> sqxy((size_t)B * nstar * 2 * 2);   // at most two squares per star
+    std::vector<int> nsq(B, 0);
+    int bad = B;   // first normal with too few usable red stars
+#pragma omp parallel for reduction(min : bad)
     for (int p = 0; p < B; ++p) {
+        struct Node { bool sq; int j; double b; };
+        Node lo[kMaxStencil + 2], hi[kMaxStencil + 2], chosen[kMaxStencil];
+        long double deltas[kMaxStencil];
         int used = 0;
-        for (int s = 0; s < 2 * M && used < nstar; ++s) {
-            const StarRec& r = stars[(size_t)p * 2 * M + s];
-            const int ncand = (int)r.lower.size() + (int)r.upper.size() + r.sq_has[0] + r.sq_has[1];
-            if (ncand < M) continue;
+        for (int c = 0; c < ns && used < nstar; ++c) {
+            const size_t k = (size_t)p * ns + c;
+            const StarQ& r = q[k];
+            const StarR& rr = res[k];
+            if (r.skip) continue;
+            // a square closer than h/2 to one of the run's IN nodes is dropped
             const double b0 = r.vertical ? g.y0 : g.x0;
-            struct Node { bool sq; int j; double b; };
-            std::vector<Node> lo, hi;
-            for (int j : r.lower) lo.push_back({false, j, b0 + j * h});
-            if (r.sq_has[0]) lo.push_back({true, -1, r.sq_b[0]});
-            for (int j : r.upper) hi.push_back({false, j, b0 + j * h});
-            if (r.sq_has[1]) hi.push_back({true, -1, r.sq_b[1]});
-            std::vector<Node> chosen;
-            size_t a = 0, b = 0;
-            const double bs = (double)r.bstar;
-            while ((int)chosen.size() < M) {
-                if (a < lo.size() && b < hi.size()) {
+            bool has[2] = {(rr.flags & 1) != 0, (rr.flags & 2) != 0};
+            for (int side = 0; side < 2; ++side) {
+                if (!has[side]) continue;
+                bool near_node = false;
+                for (int t = 0; t < rr.nlo; ++t) near_node = near_node || fabs(rr.sq[side] - (b0 + (r.jb - t) * h)) < 0.5 * h;
+                for (int t = 0; t < rr.nhi; ++t) near_node = near_node || fabs(rr.sq[side] - (b0 + (r.jb + 1 + t) * h)) < 0.5 * h;
+                if (near_node) has[side] = false;
+            }
+            const int ncand = rr.nlo + rr.nhi + has[0] + has[1];
+            if (ncand < M) continue;
+            int nlo = 0, nhi = 0;
+            for (int t = 0; t < rr.nlo; ++t) lo[nlo++] = {false, r.jb - t, b0 + (r.jb - t) * h};
+            if (has[0]) lo[nlo++] = {true, -1, rr.sq[0]};
+            for (int t = 0; t < rr.nhi; ++t) hi[nhi++] = {false, r.jb + 1 + t, b0 + (r.jb + 1 + t) * h};
+            if (has[1]) hi[nhi++] = {true, -1, rr.sq[1]};
+            int nch = 0, a = 0, b = 0;
+            const double bs = r.bstar;
+            while (nch < M) {
+                if (a < nlo && b < nhi) {
                     const double dl = bs - lo[a].b, du = hi[b].b - bs;
-                    if (dl < du || (dl == du && !(lo[a].sq && !hi[b].sq))) chosen.push_back(lo[a++]);
-                    else chosen.push_back(hi[b++]);
-                } else if (a < lo.size()) {
-                    chosen.push_back(lo[a++]);
+                    if (dl < du || (dl == du && !(lo[a].sq && !hi[b].sq))) chosen[nch++] = lo[a++];
+                    else chosen[nch++] = hi[b++];
+                } else if (a < nlo) {
+                    chosen[nch++] = lo[a++];
                 } else {
-                    chosen.push_back(hi[b++]);
+                    chosen[nch++] = hi[b++];
                 }
             }
-            for (int k = 0; k < M; ++k) {
+            for (int t = 0; t < M; ++t) {
                 long double w = 1.0L;
                 for (int m = 0; m < M; ++m)
-                    if (m != k)
-                        w *= (r.bstar - (long double)chosen[m].b) / ((long double)chosen[k].b - (long double)chosen[m].b);
-                const size_t o = (((size_t)p * M + used) * M + k);
+                    if (m != t)
+                        w *= (bstar[k] - (long double)chosen[m].b) / ((long double)chosen[t].b - (long double)chosen[m].b);
+                const size_t o = (((size_t)p * M + used) * M + t);
                 const double whi = (double)w;
                 mwv[2 * o] = whi;
                 mwv[2 * o + 1] = (double)(w - (long double)whi);
-                if (!chosen[k].sq) {
-                    mref[o] = r.vertical ? (int32_t)((size_t)r.line * g.ny + chosen[k].j)
-                                         : (int32_t)((size_t)chosen[k].j * g.ny + r.line);
+                if (!chosen[t].sq) {
+                    mref[o] = r.vertical ? (int32_t)((size_t)r.line * g.ny + chosen[t].j)
+                                         : (int32_t)((size_t)chosen[t].j * g.ny + r.line);
                 } else {
-                    mref[o] = -(1 + (int32_t)(pl->squares.size() / 2));
-                    const double a_s = (r.vertical ? g.x0 : g.y0) + r.line * h;
-                    if (r.vertical) { pl->squares.push_back(a_s); pl->squares.push_back(chosen[k].b); }
-                    else { pl->squares.push_back(chosen[k].b); pl->squares.push_back(a_s); }
+                    const int ls = nsq[p]++;
+                    mref[o] = -(1 + ls);   // square number within the normal, made global below
+                    double* xy = &sqxy[((size_t)p * nstar * 2 + ls) * 2];
+                    if (r.vertical) { xy[0] = r.a_line; xy[1] = chosen[t].b; }
+                    else { xy[0] = chosen[t].b; xy[1] = r.a_line; }
                 }
             }
-            deltas[used] = r.delta;
+            deltas[used] = delta[k];
             ++used;
         }
         if (used < nstar) {
-            char buf[160];
-            snprintf(buf, sizeof buf, "matching stencil: too few usable red stars at normal %d", p);
-            set_error(buf);
-            return FC2D_E_GEOMETRY;
+            bad = std::min(bad, p);
+            continue;
         }
         if (nstar < M) {   // the point on Gamma: no stencil (entries marked unused), depth 0
-            for (int k = 0; k < M; ++k) mref[((size_t)p * M + M - 1) * M + k] = kUnusedRef;
+            for (int t = 0; t < M; ++t) mref[((size_t)p * M + M - 1) * M + t] = kUnusedRef;
             deltas[M - 1] = 0.0L;
         }
-        for (int q = 0; q < nq; ++q) {
-            const long double x = (long double)(d - 1 - q) * (long double)pl->k1;
-            for (int s = 0; s < M; ++s) {
+        for (int qq = 0; qq < nq; ++qq) {
+            const long double x = (long double)(d - 1 - qq) * (long double)pl->k1;
+            for (int sv = 0; sv < M; ++sv) {
                 long double w = 1.0L;
                 for (int m = 0; m < M; ++m)
-                    if (m != s) w *= (x - deltas[m]) / (deltas[s] - deltas[m]);
-                const size_t o = ((size_t)p * nq + q) * M + s;
+                    if (m != sv) w *= (x - deltas[m]) / (deltas[sv] - deltas[m]);
+                const size_t o = ((size_t)p * nq + qq) * M + sv;
                 const double whi = (double)w;
                 mwn[2 * o] = whi;
                 mwn[2 * o + 1] = (double)(w - (long double)whi);
             }
+        }
+    }
+    if (bad < B) {
+        char buf[160];
+        snprintf(buf, sizeof buf, "matching stencil: too few usable red stars at normal %d", bad);
+        set_error(buf);
+        return FC2D_E_GEOMETRY;
+    }
+    // squares in the order normal, star, node
+    std::vector<int> sq0(B + 1, 0);
+    for (int p = 0; p < B; ++p) sq0[p + 1] = sq0[p] + nsq[p];
+    pl->squares.resize(2 * (size_t)sq0[B]);
+    for (int p = 0; p < B; ++p) {
+        std::copy(&sqxy[(size_t)p * nstar * 2 * 2], &sqxy[(size_t)p * nstar * 2 * 2] + 2 * nsq[p],
+                  pl->squares.begin() + 2 * (size_t)sq0[p]);
+        for (int e = 0; e < M * M; ++e) {
+            int32_t& r = mref[(size_t)p * M * M + e];
+            if (r < 0 && r != kUnusedRef) r -= sq0[p];
         }
     }
     return FC2D_OK;
@@ -391,7 +374,8 @@ static int build_matching(fc2d_plan* pl, int maxit, std::vector<int32_t>& mref,
 static void free_plan(fc2d_plan* pl) {
     if (!pl) return;
     void* ptrs[] = {pl->d_Q, pl->d_Ar, pl->d_mref, pl->d_mlab, pl->d_mwv, pl->d_mwn, pl->d_sidx,
-                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_cls2, pl->d_bxy};
+                    pl->d_sth, pl->d_seta, pl->d_run_ptr, pl->d_run, pl->d_cls2, pl->d_bxy,
+                    pl->d_cls, pl->d_rm_idx, pl->d_rm_seed, pl->d_rm_th, pl->d_rm_eta};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete pl;
@@ -435,6 +419,12 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     }
     fc2d_plan* pl = new (std::nothrow) fc2d_plan();
     if (!pl) { set_error("out of host memory"); return FC2D_E_NOMEM; }
+    auto t_last = std::chrono::steady_clock::now();
+    auto lap = [&](int phase) {   // host wall clock of the phase that ends here
+        const auto t = std::chrono::steady_clock::now();
+        pl->t_ms[phase] += std::chrono::duration<double, std::milli>(t - t_last).count();
+        t_last = t;
+    };
     pl->grid = *grid;
     pl->d = d; pl->C = C; pl->M = o.M; pl->n_r = o.n_r; pl->Cr = C * o.n_r; pl->B = o.B;
     pl->k1 = o.k1;
@@ -454,13 +444,16 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     // step 1: boundary discretisation and normals (eq. bdry_grid)
     const int B = pl->B;
     pl->bx.resize(B); pl->by.resize(B); pl->bnx.resize(B); pl->bny.resize(B);
+    std::vector<double> spd(B);   // |q'(theta_p)|
     double spmax = 0.0;
+#pragma omp parallel for reduction(max : spmax)
     for (int p = 0; p < B; ++p) {
         double v[6];
         curve_eval(pl->curve, p * pl->k2, v);
         const double sp = sqrt(v[2] * v[2] + v[3] * v[3]);
         pl->bx[p] = v[0]; pl->by[p] = v[1];
         pl->bnx[p] = v[3] / sp; pl->bny[p] = -v[2] / sp;
+        spd[p] = sp;
         spmax = std::max(spmax, sp);
     }
     // admissibility: exterior reach and the box
@@ -468,6 +461,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     {
         const int ns = 16 * B;
         double kmin = 0.0;   // most negative curvature
+#pragma omp parallel for reduction(min : kmin)
         for (int k = 0; k < ns; ++k) {
             double v[6];
             curve_eval(pl->curve, k * (2.0 * M_PI / ns), v);
@@ -503,6 +497,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     if (o.seed == FC2D_SEED_PROXIMITY) {
         const int nv = 16 * B;
         std::vector<double> px(nv), py(nv);
+#pragma omp parallel for
         for (int k = 0; k < nv; ++k) {
             double v[6];
             curve_eval(pl->curve, k * (2.0 * M_PI / nv), v);
@@ -528,6 +523,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             col_y.insert(col_y.end(), cols[i].begin(), cols[i].end());
         }
     }
+    lap(FC2D_PHASE_GEOMETRY);
     // steps 3-4 on the device: classification and foot of the normal
     const int64_t npts = (int64_t)grid->nx * grid->ny;
     const double ds = pl->k2 * spmax;
@@ -543,6 +539,8 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     int32_t* d_colptr = nullptr;
     int8_t* d_cls = nullptr;
     StripRec* d_rec = nullptr;
+    std::vector<int32_t> mref;
+    std::vector<double> mwv, mwn;
     uint64_t* d_near = nullptr;
     int32_t* d_cand = nullptr;
     float* d_w = nullptr;
@@ -550,11 +548,10 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     // capacity for STRIP records: twice the area of a band of width r_out
     // along the boundary, plus a margin of a few grid rows
     double perim = 0.0, rmin = INFINITY, rmax = 0.0, slope = 0.0;
-    for (int p = 0; p < B; ++p) {
-        double v[6];
-        curve_eval(pl->curve, p * pl->k2, v);
-        perim += sqrt(v[2] * v[2] + v[3] * v[3]) * pl->k2;
-        if (pl->curve.kind == FC2D_CURVE_POLAR) {
+    for (int p = 0; p < B; ++p) perim += spd[p] * pl->k2;
+    if (pl->curve.kind == FC2D_CURVE_POLAR) {
+#pragma omp parallel for reduction(min : rmin) reduction(max : rmax, slope)
+        for (int p = 0; p < B; ++p) {
             double r, r1, r2;
             series3(pl->curve.a, pl->curve.nmodes, p * pl->k2, &r, &r1, &r2);
             rmin = std::min(rmin, r);
@@ -590,27 +587,28 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         cap_cand = std::min<int64_t>(
             npts, (int64_t)(2.0 * perim * (sa.band_hi - sa.band_lo) / (hh * hh) + 4.0 * perim / hh) + 4096);
     }
-    std::vector<StripRec> rec;
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     auto cleanup = [&]() {
-        void* ps[] = {d_bx, d_by, d_bnx, d_bny, d_coly, d_colptr, d_cls, d_rec, d_near, d_cand, d_w, d_cnt};
+        void* ps[] = {d_bx, d_by, d_bnx, d_bny, d_coly, d_colptr, d_rec, d_near, d_cand, d_w, d_cnt};
         for (void* q : ps)
             if (q) (void)hipFree(q);
     };
     st = FC2D_OK;
     do {
-        if (hipMalloc((void**)&d_cls, npts) != hipSuccess || hipMalloc((void**)&d_rec, cap * sizeof(StripRec)) != hipSuccess ||
+        if (hipMalloc((void**)&pl->d_cls, npts) != hipSuccess || hipMalloc((void**)&d_rec, cap * sizeof(StripRec)) != hipSuccess ||
             hipMalloc((void**)&d_cnt, 8 * sizeof(int)) != hipSuccess) {
             set_error("hipMalloc failed (classification work space)");
             st = FC2D_E_NOMEM;
             break;
         }
+        d_cls = pl->d_cls;
         hipError_t e;
+        // boundary samples on the device: proximity seeds and the red-star scan
+        if ((st = dev_upload(&d_bx, pl->bx.data(), B))) break;
+        if ((st = dev_upload(&d_by, pl->by.data(), B))) break;
+        if ((st = dev_upload(&d_bnx, pl->bnx.data(), B))) break;
+        if ((st = dev_upload(&d_bny, pl->bny.data(), B))) break;
         if (o.seed == FC2D_SEED_PROXIMITY) {
-            if ((st = dev_upload(&d_bx, pl->bx.data(), B))) break;
-            if ((st = dev_upload(&d_by, pl->by.data(), B))) break;
-            if ((st = dev_upload(&d_bnx, pl->bnx.data(), B))) break;
-            if ((st = dev_upload(&d_bny, pl->bny.data(), B))) break;
             if ((st = dev_upload(&d_colptr, col_ptr.data(), col_ptr.size()))) break;
             if (!col_y.empty() && (st = dev_upload(&d_coly, col_y.data(), col_y.size()))) break;
             if (hipMalloc((void**)&d_near, npts * sizeof(uint64_t)) != hipSuccess) {
@@ -643,9 +641,11 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
                      : launch_seed_polar(sa, d_cand, cnt[3], d_cls, d_rec, cap, d_cnt, stream);
             if (st) break;
         }
-        e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) { st = hip_fail(e, "classification kernels"); break; }
-        if ((e = hipMemcpy(cnt, d_cnt, 8 * sizeof(int), hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
+        if ((e = hipMemcpyAsync(cnt, d_cnt, 8 * sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
+            (e = hipStreamSynchronize(stream)) != hipSuccess) {
+            st = hip_fail(e, "classification kernels");
+            break;
+        }
         if (cnt[1] > 0) {
             char buf[128];
             snprintf(buf, sizeof buf, "foot of the normal failed at %d grid points", cnt[1]);
@@ -654,47 +654,22 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             break;
         }
         if (cnt[0] > cap) { set_error("STRIP capacity exceeded"); st = FC2D_E_GEOMETRY; break; }
-        pl->cls.resize(npts);
-        rec.resize(cnt[0]);
-        if ((e = hipMemcpy(pl->cls.data(), d_cls, npts, hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
-        if (cnt[0] && (e = hipMemcpy(rec.data(), d_rec, cnt[0] * sizeof(StripRec), hipMemcpyDeviceToHost)) != hipSuccess) { st = hip_fail(e, "hipMemcpy"); break; }
+        lap(FC2D_PHASE_CLASSIFY);
+        // runs, pair classes and the STRIP lists, built on the device
+        if ((st = plan_device_lists(pl, d_rec, cnt[0], stream))) break;
+        pl->newton_max_iters = cnt[2];
+        pl->n_solved = cnt[3];
+        pl->n_fallback = cnt[4];
+        pl->newton_iters = cnt[5];
+        lap(FC2D_PHASE_LISTS);
+        // matching stencils
+        const BndView dbd{d_bx, d_by, d_bnx, d_bny, B, pl->k2};
+        st = build_matching(pl, o.newton_maxit, dbd, stream, mref, mwv, mwn);
+        if (st) break;
+        lap(FC2D_PHASE_MATCHING);
     } while (0);
     cleanup();
     if (st) { free_plan(pl); return st; }
-    std::sort(rec.begin(), rec.end(), [](const StripRec& a, const StripRec& b) { return a.idx < b.idx; });
-    pl->newton_max_iters = cnt[2];
-    pl->n_solved = cnt[3];
-    pl->n_fallback = cnt[4];
-    pl->newton_iters = cnt[5];
-    pl->strip_idx.resize(rec.size()); pl->strip_seed.resize(rec.size());
-    pl->strip_theta.resize(rec.size()); pl->strip_eta.resize(rec.size());
-    for (size_t k = 0; k < rec.size(); ++k) {
-        pl->strip_idx[k] = rec[k].idx; pl->strip_seed[k] = rec[k].seed;
-        pl->strip_theta[k] = rec[k].theta; pl->strip_eta[k] = rec[k].eta;
-    }
-    for (int8_t c : pl->cls) {
-        if (c == 1) ++pl->n_in;
-        else if (c == 0) ++pl->n_far;
-    }
-    // matching stencils
-    std::vector<int32_t> mref;
-    std::vector<double> mwv, mwn;
-    st = build_matching(pl, o.newton_maxit, mref, mwv, mwn);
-    if (st) { free_plan(pl); return st; }
-    // row runs of equal class
-    std::vector<int32_t> run_ptr(grid->nx + 1, 0), runs;
-    for (int i = 0; i < grid->nx; ++i) {
-        const int8_t* row = &pl->cls[(size_t)i * grid->ny];
-        int j = 0;
-        while (j < grid->ny) {
-            int k = j;
-            while (k < grid->ny && row[k] == row[j]) ++k;
-            runs.push_back(j); runs.push_back(k); runs.push_back(row[j]);
-            j = k;
-        }
-        run_ptr[i + 1] = (int32_t)(runs.size() / 3);
-    }
-    pl->nruns = (int)(runs.size() / 3);
     // uploads
     do {
         if ((st = dev_upload(&pl->d_Q, pl->Q.data(), pl->Q.size()))) break;
@@ -711,14 +686,15 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             std::vector<uint8_t> dlab((size_t)B * 4 * NU, 255);
             const int RS = (M + 3) / 4;   // stars per lane
             std::vector<double> dwv((size_t)B * RS * M * 4 * 2, 0.0), dwn((size_t)B * RQ * M * 4 * 2, 0.0);
-            std::vector<int> ord(MM);
+#pragma omp parallel for
             for (int p = 0; p < B; ++p) {
+                int ord[kMaxStencil * kMaxStencil];
                 const int32_t* r0 = &mref[(size_t)p * MM];
                 auto key = [&](int e) { return r0[e] >= 0 ? (int64_t)r0[e] : npts + (int64_t)(-r0[e] - 1); };
                 int nuse = 0;   // entries of unused stencils stay padding (label 255)
                 for (int e = 0; e < MM; ++e)
                     if (r0[e] != kUnusedRef) ord[nuse++] = e;
-                std::stable_sort(ord.begin(), ord.begin() + nuse, [&](int a, int b) { return key(a) < key(b); });
+                std::stable_sort(ord, ord + nuse, [&](int a, int b) { return key(a) < key(b); });
                 for (int i = 0; i < nuse; ++i) {
                     const size_t o = ((size_t)p * 4 + i % 4) * NU + i / 4;
                     dref[o] = r0[ord[i]];
@@ -751,53 +727,12 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             if ((st = dev_upload(&pl->d_mwn, dwn.data(), dwn.size()))) break;
         }
         {
-            // the strip kernel takes the points in order of their foot parameter,
-            // so the lanes of a wave share the Gram records of nearly the same
-            // normals (the host copies stay in row-major order)
-            const size_t S = pl->strip_idx.size();
-            std::vector<size_t> ord(S);
-            for (size_t k = 0; k < S; ++k) ord[k] = k;
-            std::stable_sort(ord.begin(), ord.end(), [&](size_t a, size_t b) {
-                return pl->strip_theta[a] < pl->strip_theta[b];
-            });
-            std::vector<int32_t> oi(S);
-            std::vector<double> ot(S), oe(S);
-            for (size_t k = 0; k < S; ++k) {
-                oi[k] = pl->strip_idx[ord[k]];
-                ot[k] = pl->strip_theta[ord[k]];
-                oe[k] = pl->strip_eta[ord[k]];
-            }
-            // widest window of normals under a strip-kernel block of 512 points
-            // (p0 as the kernel computes it; monotone in theta)
-            auto p0_of = [&](double th) {
-                return (pl->M % 2 == 0) ? (int)floor(th / pl->k2) : (int)rint(th / pl->k2);
-            };
-            pl->strip_wmax = 0;
-            for (size_t k0 = 0; k0 < S; k0 += 512) {
-                const size_t k1 = std::min(S, k0 + 512) - 1;
-                pl->strip_wmax = std::max(pl->strip_wmax, p0_of(ot[k1]) - p0_of(ot[k0]) + pl->M + 1);
-            }
-            if ((st = dev_upload(&pl->d_sidx, oi.data(), S))) break;
-            if ((st = dev_upload(&pl->d_sth, ot.data(), S))) break;
-            if ((st = dev_upload(&pl->d_seta, oe.data(), S))) break;
-        }
-        if ((st = dev_upload(&pl->d_run_ptr, run_ptr.data(), run_ptr.size()))) break;
-        if ((st = dev_upload(&pl->d_run, runs.data(), runs.size()))) break;
-        {
             std::vector<double> bxy(2 * (size_t)B + pl->squares.size());
             for (int p = 0; p < B; ++p) { bxy[2 * p] = pl->bx[p]; bxy[2 * p + 1] = pl->by[p]; }
             std::copy(pl->squares.begin(), pl->squares.end(), bxy.begin() + 2 * B);
             if ((st = dev_upload(&pl->d_bxy, bxy.data(), bxy.size()))) break;
         }
-        const int Lh = grid->ny / 2;
-        if (grid->ny % 2 == 0 && row_elems(Lh) > 0) {
-            std::vector<uint8_t> pairs(Lh), cls2((size_t)grid->nx * Lh);
-            for (int i = 0; i < grid->nx; ++i) {
-                const int8_t* c = &pl->cls[(size_t)i * grid->ny];
-                for (int n = 0; n < Lh; ++n) pairs[n] = (uint8_t)(c[2 * n] | (c[2 * n + 1] << 2));
-                row_class_layout(Lh, pairs.data(), &cls2[(size_t)i * Lh]);
-            }
-            if ((st = dev_upload(&pl->d_cls2, cls2.data(), cls2.size()))) break;
+        if (pl->d_cls2) {
             // set-up on this device for the extension calls that allocate nothing
             // (fc2d_extend_fft_noalloc): the FFT tables and the fixed scratch's address
             if ((st = fft_prepare(grid->nx, grid->ny))) { set_error("FFT table set-up failed"); break; }
@@ -807,6 +742,7 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         }
     } while (0);
     if (st) { free_plan(pl); return st; }
+    lap(FC2D_PHASE_LAYOUT);
     *out = pl;
     return FC2D_OK;
 }
@@ -843,6 +779,26 @@ int gridline_crossing(const fc2d_plan* pl, bool vertical, double a_line, double 
         else hi = mid;
     }
     *out = 0.5 * (lo + hi);
+    return FC2D_OK;
+}
+
+// Host copies of the classes and the row-major STRIP list, downloaded from the
+// plan's device arrays on first use (synchronous; the plan's device data is
+// complete once fc2d_plan_create has returned).
+int plan_host_lists(const fc2d_plan* pl) {
+    std::lock_guard<std::mutex> lk(pl->host_mu);
+    if (pl->host_ready) return FC2D_OK;
+    const size_t npts = (size_t)pl->grid.nx * pl->grid.ny, S = (size_t)pl->n_strip;
+    pl->cls.resize(npts);
+    pl->strip_idx.resize(S); pl->strip_seed.resize(S); pl->strip_theta.resize(S); pl->strip_eta.resize(S);
+    hipError_t e;
+    if ((e = hipMemcpy(pl->cls.data(), pl->d_cls, npts, hipMemcpyDeviceToHost)) != hipSuccess ||
+        (S && ((e = hipMemcpy(pl->strip_idx.data(), pl->d_rm_idx, S * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+               (e = hipMemcpy(pl->strip_seed.data(), pl->d_rm_seed, S * sizeof(int32_t), hipMemcpyDeviceToHost)) != hipSuccess ||
+               (e = hipMemcpy(pl->strip_theta.data(), pl->d_rm_th, S * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess ||
+               (e = hipMemcpy(pl->strip_eta.data(), pl->d_rm_eta, S * sizeof(double), hipMemcpyDeviceToHost)) != hipSuccess)))
+        return hip_fail(e, "plan lists download");
+    pl->host_ready = true;
     return FC2D_OK;
 }
 
@@ -887,13 +843,14 @@ int fc2d_plan_get_info(const fc2d_plan* pl, fc2d_plan_info* info) {
     info->d = pl->d; info->C = pl->C; info->M = pl->M; info->n_r = pl->n_r; info->Cr = pl->Cr; info->B = pl->B;
     info->k1 = pl->k1; info->k2 = pl->k2;
     info->n_bdry = pl->B + (int64_t)pl->squares.size() / 2;
-    info->n_strip = (int64_t)pl->strip_idx.size();
+    info->n_strip = pl->n_strip;
     info->n_in = pl->n_in; info->n_far = pl->n_far;
     info->newton_max_iters = pl->newton_max_iters;
     info->seed = pl->seed;
     info->n_solved = pl->n_solved;
     info->n_fallback = pl->n_fallback;
     info->newton_iters = pl->newton_iters;
+    for (int k = 0; k < FC2D_PLAN_PHASES; ++k) info->t_ms[k] = pl->t_ms[k];
     return FC2D_OK;
 }
 
@@ -910,12 +867,14 @@ int fc2d_boundary_points(const fc2d_plan* pl, int64_t* n, double* xy) {
 
 int fc2d_plan_classes(const fc2d_plan* pl, int8_t* classes) {
     if (!pl) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (int st = plan_host_lists(pl)) return st;
     if (classes) memcpy(classes, pl->cls.data(), pl->cls.size());
     return FC2D_OK;
 }
 
 int fc2d_plan_strip(const fc2d_plan* pl, int64_t* index, double* theta, double* eta, int32_t* seed) {
     if (!pl) { set_error("NULL argument"); return FC2D_E_ARG; }
+    if (int st = plan_host_lists(pl)) return st;
     const size_t S = pl->strip_idx.size();
     for (size_t k = 0; k < S; ++k) {
         if (index) index[k] = pl->strip_idx[k];

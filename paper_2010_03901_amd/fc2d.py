@@ -53,7 +53,11 @@ class fc2d_plan_info(C.Structure):
     _fields_ = [("d", C.c_int), ("C", C.c_int), ("M", C.c_int), ("n_r", C.c_int), ("Cr", C.c_int), ("B", C.c_int),
                 ("k1", C.c_double), ("k2", C.c_double), ("n_bdry", C.c_int64), ("n_strip", C.c_int64),
                 ("n_in", C.c_int64), ("n_far", C.c_int64), ("newton_max_iters", C.c_int), ("seed", C.c_int),
-                ("n_solved", C.c_int64), ("n_fallback", C.c_int64), ("newton_iters", C.c_int64)]
+                ("n_solved", C.c_int64), ("n_fallback", C.c_int64), ("newton_iters", C.c_int64),
+                ("t_ms", C.c_double * 5)]
+
+# fc2d_plan_info.t_ms phases
+PLAN_PHASES = ("geometry", "classify", "lists", "matching", "layout")
 
 
 class fc2d_ff_info(C.Structure):

@@ -83,7 +83,18 @@ def test_boundary_points_agree(both):
     o = OP.boundary_points(opl)
     assert g.shape == o.shape
     assert np.array_equal(g[: case.B], o[: case.B])          # feet: same formula, same libm
-    assert np.abs(g - o).max() < 1e-14
+    # Squares are crossings of grid lines with Gamma, bisected on both sides on the
+    # sign of a rounded eta.  A line meeting Gamma at a shallow angle turns that
+    # rounding into a shift along the line of rounding(eta) / |cos angle| (about
+    # 1e-14 on the star at 2048^2), so each square is held to lie on Gamma to
+    # rounding -- the oracle's own eta at the library's square, within 8 ulps of
+    # the coordinates (the oracle's squares give at most 6e-16) -- and near the
+    # oracle's square.
+    sq = g[case.B:]
+    assert np.abs(sq - o[case.B:]).max() < 1e-13
+    _, near = opl.tree.query(sq)
+    _, eta, _ = OP.foot_solve(opl.curve, opl.bd, sq[:, 0], sq[:, 1], near, opl.M)
+    assert np.abs(eta).max() < 2e-15
 
 
 def _device(torch, a):

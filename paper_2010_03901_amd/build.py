@@ -18,7 +18,7 @@ OUT = os.path.join(PKG, "libfc2d.so")
 BUILD = os.path.join(ROOT, "_build")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
-HOST_SRC = ["plan.cpp", "fcgram_quad.cpp", "batch.cpp", "poisson.cpp", "workspace.cpp", "ffsolve.cpp"]
+HOST_SRC = ["plan.cpp", "matching_host.cpp", "fcgram_quad.cpp", "batch.cpp", "poisson.cpp", "workspace.cpp", "ffsolve.cpp"]
 HIP_SRC = ["kernels_plan.hip", "kernels_extend.hip", "kernels_fft.hip", "kernels_mlp.hip", "kernels_poisson.hip",
            "kernels_ffsolve.hip"]
 

@@ -12,6 +12,7 @@
 
 #include "../../include/fc2d.h"
 #include "geom.h"
+#include "matching.h"
 
 namespace fc2d {
 
@@ -164,25 +165,6 @@ int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream
 // host copies of the classes and the row-major STRIP list (downloaded once)
 int plan_host_lists(const fc2d_plan* pl);
 
-// Red-star candidates of the matching stencils (Sec. 3.2): one per (normal,
-// candidate line).  The device scans the star's grid line for the runs of IN
-// points next to it and locates the line's crossings with Gamma bounding them.
-struct StarQ {
-    int32_t p;          // normal
-    int32_t vertical;   // 1: the line x = x_line (runs along y); 0: y = y_line
-    int32_t line;       // grid line index
-    int32_t jb;         // grid index along the line just below the star
-    double a_line;      // the line's coordinate
-    double bstar;       // the star's coordinate along the line
-    int32_t skip;       // 1: too close to Gamma, not used
-    int32_t pad;
-};
-struct StarR {
-    int32_t nlo, nhi;   // IN points jb, jb-1, ... (nlo of them) and jb+1, ... (nhi)
-    int32_t flags;      // 1: run below ends at Gamma within M steps (square sq[0]); 2: above (sq[1]); 4: foot failed
-    int32_t pad;
-    double sq[2];       // crossing coordinate along the line
-};
 struct StarArgs {
     CurveC curve;
     const double *bx, *by, *bnx, *bny;

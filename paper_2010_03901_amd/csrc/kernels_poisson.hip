@@ -331,9 +331,9 @@ __device__ inline double inv_r2(double r2) {
 // fields, not yet divided by the node count: sum[f].  The records come through
 // the scalar cache (wave-uniform addresses), 8 / NF per wait, their
 // reciprocals formed side by side; distance and reciprocal are shared by the
-// fields, and for one or two fields two terms share one reciprocal (of the
-// product of their squared distances, at most about 1e4 and at least about
-// 1e-20 here: normal numbers).  With MIN also a lower bound of the smallest squared node distance:
+// fields, and for one or two fields four terms share one reciprocal (of the
+// product of their squared distances, at most about 1e8 and at least about
+// 1e-40 here: normal numbers).  With MIN also a lower bound of the smallest squared node distance:
 // the minimum of the high words, low word zero (relative error below 2^-20,
 // rounded down; it only steers the level choice and the candidate test).
 template <bool MIN, int NF>
@@ -358,17 +358,27 @@ __device__ inline void dl_partial(const DlRec<NF>* __restrict__ rec, int j0, int
             if (MIN) dmh = min(dmh, (unsigned)(__double_as_longlong(r2[u]) >> 32));
         }
         if constexpr (NF <= 2) {
-            // pairs over one reciprocal: n0 / r0 + n1 / r1 = (n0 r1 + n1 r0) / (r0 r1)
+            // four terms over one reciprocal: with p01 = n0 r1 + n1 r0, d01 = r0 r1
+            // (and p23, d23 alike), n0/r0 + n1/r1 + n2/r2 + n3/r3 = (p01 d23 + p23 d01) / (d01 d23)
+            double d01[U / 4], d23[U / 4];
 #pragma unroll
-            for (int u = 0; u < U; u += 2) rv[u] = inv_r2(r2[u] * r2[u + 1]);
+            for (int v = 0; v < U / 4; ++v) {
+                d01[v] = r2[4 * v] * r2[4 * v + 1];
+                d23[v] = r2[4 * v + 2] * r2[4 * v + 3];
+                rv[v] = inv_r2(d01[v] * d23[v]);
+            }
 #pragma unroll
-            for (int u = 0; u < U; u += 2)
+            for (int v = 0; v < U / 4; ++v)
 #pragma unroll
                 for (int f = 0; f < NF; ++f) {
-                    const double n0 = dx[u] * b[u].ab[2 * f] - dy[u] * b[u].ab[2 * f + 1];
-                    const double n1 = dx[u + 1] * b[u + 1].ab[2 * f] - dy[u + 1] * b[u + 1].ab[2 * f + 1];
-                    const double t = fma(n0, r2[u + 1], n1 * r2[u]) * rv[u];
-                    if (u & 2) s1[f] += t;
+                    const int u = 4 * v;
+                    double n[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) n[m] = dx[u + m] * b[u + m].ab[2 * f] - dy[u + m] * b[u + m].ab[2 * f + 1];
+                    const double p01 = fma(n[0], r2[u + 1], n[1] * r2[u]);
+                    const double p23 = fma(n[2], r2[u + 3], n[3] * r2[u + 2]);
+                    const double t = fma(p01, d23[v], p23 * d01[v]) * rv[v];
+                    if (v & 1) s1[f] += t;
                     else s0[f] += t;
                 }
         } else {

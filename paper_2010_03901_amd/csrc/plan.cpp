@@ -1,27 +1,19 @@
 // Host side of the Geometrical Setup (Sec. 3.5 steps 1-4) and the C ABI.
 //
-// Boundary-sized work (boundary grid, admissibility, matching stencils and the
-// squares of Fig. 3) runs here on the host in C++; grid-sized and
-// strip-sized work (classification of H, foot of the normal) runs in the
+// Boundary-sized work (boundary grid, admissibility, the FC-Gram tables, the
+// placement and selection of the matching stencils' red stars and nodes) runs
+// here and in matching_host.cpp on the host in C++; grid-sized and strip-sized
+// work (classification of H, foot of the normal, the lists built from the
+// classes, the red stars' grid-line scans and crossings with Gamma) runs in the
 // device kernels of kernels_plan.hip.
 //
-// Readings of the paper (the same rules the checking code follows; they are
-// stated in the paper's terms):
-//  * Classification: IN / FAR by the parity of crossings of each grid column
-//    with a 16 B-vertex polygon of Gamma; every point whose nearest boundary
-//    sample is within C k1 + ds/2 (outside) or h + ds/2 (inside), ds the
-//    largest sample spacing, is reclassified by the signed normal distance eta
-//    of its foot: IN (eta <= 0), STRIP (0 < eta <= C k1) or FAR; a point with
-//    eta <= 1e-13 (1 + |x| + |y|) lies on Gamma to rounding and is IN.
-//  * Matching stencils (Sec. 3.2): candidate red stars are the crossings at
-//    depth >= 0 of the inward normal with grid lines x = x_i (|n_x| >= |n_y|)
-//    or y = y_j, in order of depth.  A star's nodes are the IN points of the
-//    run of IN points holding it (at most M + 1 grid steps away) and the
-//    crossings of its line with Gamma bounding the run (squares); a square
-//    closer than h/2 to one of those IN nodes is dropped.  The first M
-//    candidates with at least M nodes are the red stars; each uses its M
-//    nearest nodes.  Weights are formed in x87 extended precision and stored
-//    as double-double.
+// Classification (reading of Sec. 3.3-3.4, the same rule the checking code
+// follows): IN / FAR by the parity of crossings of each grid column with a
+// 16 B-vertex polygon of Gamma; every point whose nearest boundary sample is
+// within C k1 + ds/2 (outside) or h + ds/2 (inside), ds the largest sample
+// spacing, is reclassified by the signed normal distance eta of its foot:
+// IN (eta <= 0), STRIP (0 < eta <= C k1) or FAR; a point with
+// eta <= 1e-13 (1 + |x| + |y|) lies on Gamma to rounding and is IN.
 #include <math.h>
 #include <stdio.h>
 #include <string.h>
@@ -174,68 +166,30 @@ static int nearest_sample(const fc2d_plan* pl, double X, double Y, int p) {
 // ----------------------------------------------------------------------------
 // matching stencils (Sec. 3.2)
 // ----------------------------------------------------------------------------
-// red stars closer to Gamma than this fraction of the star spacing (h / |n| along
-// the normal) are skipped: the point on Gamma is itself a node along the normal
-constexpr double kStarMinDepth = 0.05;
-constexpr int32_t kUnusedRef = INT32_MIN;   // stencil entry of the point-on-Gamma slot (not gathered)
-constexpr int kMaxStencil = 15;             // largest compiled M
 
 // Red stars and their nodes (Sec. 3.2, Fig. 3).  The host places each normal's
-// 2M candidate stars (depth and position in extended precision); the device
-// scans their grid lines for the IN runs next to them and bisects the lines'
-// crossings with Gamma (k_star_scan); the host then picks the stars and nodes
-// and forms the weights, normal by normal in parallel.
+// 2M candidate stars (matching_host.cpp); the device scans their grid lines for
+// the IN runs next to them and bisects the lines' crossings with Gamma
+// (k_star_scan); the host then picks the stars and nodes and forms the weights.
 static int build_matching(fc2d_plan* pl, int maxit, const BndView& dbd, hipStream_t stream,
                           std::vector<int32_t>& mref, std::vector<double>& mwv, std::vector<double>& mwn) {
     const fc2d_grid& g = pl->grid;
-    const int M = pl->M, d = pl->d, B = pl->B;
-    const bool io = pl->interior_only;
-    const int nq = io ? d : d - 1;   // matching values interpolated along the normal
-    // red stars per normal: with boundary data the point on Gamma (depth 0, the
-    // boundary sample) is the M-th node of the along-normal interpolation
-    const int nstar = io ? M : M - 1;
-    const double h = g.h;
-    const int ns = 2 * M;   // candidates per normal
-    const size_t nst = (size_t)B * ns;
-    std::vector<StarQ> q(nst);
-    std::vector<long double> delta(nst), bstar(nst);
-#pragma omp parallel for
-    for (int p = 0; p < B; ++p) {
-        const double nx = pl->bnx[p], ny = pl->bny[p];
-        const bool vertical = fabs(nx) >= fabs(ny);
-        double na, nb, qa, qb, a0, b0;
-        if (vertical) {
-            na = nx; nb = ny; qa = pl->bx[p]; qb = pl->by[p]; a0 = g.x0; b0 = g.y0;
-        } else {
-            na = ny; nb = nx; qa = pl->by[p]; qb = pl->bx[p]; a0 = g.y0; b0 = g.x0;
-        }
-        const double u = (qa - a0) / h;
-        int i_first, step;
-        if (na > 0) { i_first = (int)floor(u); step = -1; }
-        else { i_first = (int)ceil(u); step = 1; }
-        for (int c = 0; c < ns; ++c) {
-            const size_t k = (size_t)p * ns + c;
-            StarQ& r = q[k];
-            r.p = p;
-            r.vertical = vertical ? 1 : 0;
-            r.line = i_first + step * c;
-            r.a_line = a0 + r.line * h;
-            delta[k] = ((long double)qa - (long double)r.a_line) / (long double)na;
-            bstar[k] = (long double)qb - delta[k] * (long double)nb;
-            r.bstar = (double)bstar[k];
-            r.jb = (int)floor((r.bstar - b0) / h);
-            r.skip = (!io && delta[k] < (long double)kStarMinDepth * h / fabs(na)) ? 1 : 0;   // too close to
-            r.pad = 0;                                                                      // the point on Gamma
-        }
-    }
+    MatchGeom mg;
+    mg.x0 = g.x0; mg.y0 = g.y0; mg.h = g.h; mg.nx = g.nx; mg.ny = g.ny;
+    mg.M = pl->M; mg.d = pl->d; mg.B = pl->B; mg.interior_only = pl->interior_only; mg.k1 = pl->k1;
+    mg.bx = pl->bx.data(); mg.by = pl->by.data(); mg.bnx = pl->bnx.data(); mg.bny = pl->bny.data();
+    std::vector<StarQ> q;
+    std::vector<long double> delta, bstar;
+    place_stars(mg, q, delta, bstar);
+    const size_t nst = q.size();
     // device: IN runs along the candidates' lines and the squares bounding them
     std::vector<StarR> res(nst);
     {
         StarArgs sa;
         sa.curve = pl->curve;
         sa.bx = dbd.x; sa.by = dbd.y; sa.bnx = dbd.nx; sa.bny = dbd.ny;
-        sa.B = B; sa.M = M; sa.maxit = maxit; sa.io = io ? 1 : 0;
-        sa.k2 = pl->k2; sa.x0 = g.x0; sa.y0 = g.y0; sa.h = h;
+        sa.B = pl->B; sa.M = pl->M; sa.maxit = maxit; sa.io = pl->interior_only ? 1 : 0;
+        sa.k2 = pl->k2; sa.x0 = g.x0; sa.y0 = g.y0; sa.h = g.h;
         sa.nx = g.nx; sa.ny = g.ny;
         StarQ* d_q = nullptr;
         StarR* d_r = nullptr;
@@ -255,115 +209,12 @@ static int build_matching(fc2d_plan* pl, int maxit, const BndView& dbd, hipStrea
             set_error("foot of the normal failed while locating grid-line crossings with the boundary");
             return FC2D_E_NEWTON;
         }
-    // select stars and nodes, form weights; squares per normal, numbered afterwards
-    mref.assign((size_t)B * M * M, 0);
-    mwv.assign((size_t)B * M * M * 2, 0.0);
-    mwn.assign((size_t)B * nq * M * 2, 0.0);
-    std::vector<double> sqxy((size_t)B * nstar * 2 * 2);   // at most two squares per star
-    std::vector<int> nsq(B, 0);
-    int bad = B;   // first normal with too few usable red stars
-#pragma omp parallel for reduction(min : bad)
-    for (int p = 0; p < B; ++p) {
-        struct Node { bool sq; int j; double b; };
-        Node lo[kMaxStencil + 2], hi[kMaxStencil + 2], chosen[kMaxStencil];
-        long double deltas[kMaxStencil];
-        int used = 0;
-        for (int c = 0; c < ns && used < nstar; ++c) {
-            const size_t k = (size_t)p * ns + c;
-            const StarQ& r = q[k];
-            const StarR& rr = res[k];
-            if (r.skip) continue;
-            // a square closer than h/2 to one of the run's IN nodes is dropped
-            const double b0 = r.vertical ? g.y0 : g.x0;
-            bool has[2] = {(rr.flags & 1) != 0, (rr.flags & 2) != 0};
-            for (int side = 0; side < 2; ++side) {
-                if (!has[side]) continue;
-                bool near_node = false;
-                for (int t = 0; t < rr.nlo; ++t) near_node = near_node || fabs(rr.sq[side] - (b0 + (r.jb - t) * h)) < 0.5 * h;
-                for (int t = 0; t < rr.nhi; ++t) near_node = near_node || fabs(rr.sq[side] - (b0 + (r.jb + 1 + t) * h)) < 0.5 * h;
-                if (near_node) has[side] = false;
-            }
-            const int ncand = rr.nlo + rr.nhi + has[0] + has[1];
-            if (ncand < M) continue;
-            int nlo = 0, nhi = 0;
-            for (int t = 0; t < rr.nlo; ++t) lo[nlo++] = {false, r.jb - t, b0 + (r.jb - t) * h};
-            if (has[0]) lo[nlo++] = {true, -1, rr.sq[0]};
-            for (int t = 0; t < rr.nhi; ++t) hi[nhi++] = {false, r.jb + 1 + t, b0 + (r.jb + 1 + t) * h};
-            if (has[1]) hi[nhi++] = {true, -1, rr.sq[1]};
-            int nch = 0, a = 0, b = 0;
-            const double bs = r.bstar;
-            while (nch < M) {
-                if (a < nlo && b < nhi) {
-                    const double dl = bs - lo[a].b, du = hi[b].b - bs;
-                    if (dl < du || (dl == du && !(lo[a].sq && !hi[b].sq))) chosen[nch++] = lo[a++];
-                    else chosen[nch++] = hi[b++];
-                } else if (a < nlo) {
-                    chosen[nch++] = lo[a++];
-                } else {
-                    chosen[nch++] = hi[b++];
-                }
-            }
-            for (int t = 0; t < M; ++t) {
-                long double w = 1.0L;
-                for (int m = 0; m < M; ++m)
-                    if (m != t)
-                        w *= (bstar[k] - (long double)chosen[m].b) / ((long double)chosen[t].b - (long double)chosen[m].b);
-                const size_t o = (((size_t)p * M + used) * M + t);
-                const double whi = (double)w;
-                mwv[2 * o] = whi;
-                mwv[2 * o + 1] = (double)(w - (long double)whi);
-                if (!chosen[t].sq) {
-                    mref[o] = r.vertical ? (int32_t)((size_t)r.line * g.ny + chosen[t].j)
-                                         : (int32_t)((size_t)chosen[t].j * g.ny + r.line);
-                } else {
-                    const int ls = nsq[p]++;
-                    mref[o] = -(1 + ls);   // square number within the normal, made global below
-                    double* xy = &sqxy[((size_t)p * nstar * 2 + ls) * 2];
-                    if (r.vertical) { xy[0] = r.a_line; xy[1] = chosen[t].b; }
-                    else { xy[0] = chosen[t].b; xy[1] = r.a_line; }
-                }
-            }
-            deltas[used] = delta[k];
-            ++used;
-        }
-        if (used < nstar) {
-            bad = std::min(bad, p);
-            continue;
-        }
-        if (nstar < M) {   // the point on Gamma: no stencil (entries marked unused), depth 0
-            for (int t = 0; t < M; ++t) mref[((size_t)p * M + M - 1) * M + t] = kUnusedRef;
-            deltas[M - 1] = 0.0L;
-        }
-        for (int qq = 0; qq < nq; ++qq) {
-            const long double x = (long double)(d - 1 - qq) * (long double)pl->k1;
-            for (int sv = 0; sv < M; ++sv) {
-                long double w = 1.0L;
-                for (int m = 0; m < M; ++m)
-                    if (m != sv) w *= (x - deltas[m]) / (deltas[sv] - deltas[m]);
-                const size_t o = ((size_t)p * nq + qq) * M + sv;
-                const double whi = (double)w;
-                mwn[2 * o] = whi;
-                mwn[2 * o + 1] = (double)(w - (long double)whi);
-            }
-        }
-    }
-    if (bad < B) {
+    const int bad = select_matching(mg, q.data(), res.data(), delta.data(), bstar.data(), mref, mwv, mwn, pl->squares);
+    if (bad < 0) {
         char buf[160];
-        snprintf(buf, sizeof buf, "matching stencil: too few usable red stars at normal %d", bad);
+        snprintf(buf, sizeof buf, "matching stencil: too few usable red stars at normal %d", -bad - 1);
         set_error(buf);
         return FC2D_E_GEOMETRY;
-    }
-    // squares in the order normal, star, node
-    std::vector<int> sq0(B + 1, 0);
-    for (int p = 0; p < B; ++p) sq0[p + 1] = sq0[p] + nsq[p];
-    pl->squares.resize(2 * (size_t)sq0[B]);
-    for (int p = 0; p < B; ++p) {
-        std::copy(&sqxy[(size_t)p * nstar * 2 * 2], &sqxy[(size_t)p * nstar * 2 * 2] + 2 * nsq[p],
-                  pl->squares.begin() + 2 * (size_t)sq0[p]);
-        for (int e = 0; e < M * M; ++e) {
-            int32_t& r = mref[(size_t)p * M * M + e];
-            if (r < 0 && r != kUnusedRef) r -= sq0[p];
-        }
     }
     return FC2D_OK;
 }

@@ -19,7 +19,7 @@
 //    and in order of theta.
 //  k_star_scan: red-star candidates of the matching stencils (Sec. 3.2): the
 //    runs of IN points along each candidate's grid line and the crossings of
-//    the line with Gamma that bound them (bisection on the sign of eta).
+//    the line with Gamma that bound them (where eta changes sign).
 #include <hip/hip_runtime.h>
 #include <rocprim/device/device_radix_sort.hpp>
 
@@ -479,21 +479,73 @@ __device__ inline int nearest_descent(const StarArgs& a, double X, double Y, int
     return imod(p, a.B);
 }
 
-// crossing of {line = a_line, b between b_in (eta <= 0) and b_out} with Gamma:
-// bisection on the sign of eta (64 halvings, stopped once the bracket no longer
-// changes); false when a foot solve fails
+// crossing of {line = a_line, b between b_in (eta <= 0) and b_out} with Gamma,
+// where eta changes sign: false position with the Illinois modification (a
+// retained end's value is halved, so both ends move) while it shrinks the
+// bracket, then bisection until the bracket no longer changes (its fixed point:
+// adjacent doubles or one value).  false when a foot solve fails
 template <int M>
 __device__ bool crossing(const StarArgs& a, const BndView& bd, bool vertical, double a_line, double b_in, double b_out,
                          int seed, double* out) {
-    double lo = b_in, hi = b_out;
+    // the first foot is seeded from the nearest boundary sample (T(tau), as in the
+    // classification); later ones by Newton from the previous foot parameter,
+    // the points moving along the line by at most a few grid steps
+    double th = 0.0;
+    bool have_th = false;
+    auto eta_at = [&](double b, double* e) {
+        const double X = vertical ? a_line : b;
+        const double Y = vertical ? b : a_line;
+        int its;
+        if (have_th && foot_from_seed(a.curve, X, Y, th, 2.0 * a.k2, a.maxit, &th, e, &its) == FOOT_OK) return true;
+        seed = nearest_descent(a, X, Y, seed);
+        have_th = foot_solve<M>(a.curve, bd, X, Y, seed, a.maxit, &th, e, &its) == FOOT_OK;
+        return have_th;
+    };
+    // lo: the end with eta <= 0, hi: eta > 0 (either may be the larger coordinate)
+    double lo = b_in, hi = b_out, flo, fhi;
+    if (!eta_at(lo, &flo) || !eta_at(hi, &fhi)) return false;
+    if (flo <= 0 && fhi > 0) {
+        int kept = 0;   // -1: lo moved last (hi kept), 1: hi moved last
+        for (int it = 0; it < 40; ++it) {
+            const double x = (lo * fhi - hi * flo) / (fhi - flo);
+            if (!((x - lo) * (x - hi) < 0.0)) break;   // not strictly inside the bracket
+            double fx;
+            if (!eta_at(x, &fx)) return false;
+            if (fx <= 0) {
+                lo = x;
+                flo = fx;
+                if (kept == -1) fhi *= 0.5;
+                kept = -1;
+            } else {
+                hi = x;
+                fhi = fx;
+                if (kept == 1) flo *= 0.5;
+                kept = 1;
+            }
+            if (fabs(hi - lo) <= 8.0 * 0x1p-52 * fmax(fabs(lo), fabs(hi))) break;
+        }
+        // false position nears the root from one side (the end that moved last):
+        // step away from that end by 4, 32, 256 ... ulps until eta changes sign,
+        // so the bisection below starts from a bracket a few ulps wide
+        if (kept != 0) {
+            const bool near_lo = kept == -1;
+            const double sgn = hi > lo ? 1.0 : -1.0;   // direction from lo towards hi
+            double d = 4.0 * 0x1p-52 * fmax(fabs(lo), fabs(hi));
+            for (int it = 0; it < 24 && fabs(hi - lo) > d; ++it) {
+                const double x = near_lo ? lo + sgn * d : hi - sgn * d;
+                double fx;
+                if (!eta_at(x, &fx)) return false;
+                if (fx <= 0) lo = x;
+                else hi = x;
+                if (near_lo == (fx > 0)) break;   // the sign changes within d of that end
+                d *= 8.0;
+            }
+        }
+    }
     for (int it = 0; it < 64; ++it) {
         const double mid = 0.5 * (lo + hi);
-        const double X = vertical ? a_line : mid;
-        const double Y = vertical ? mid : a_line;
-        seed = nearest_descent(a, X, Y, seed);
-        double th, eta;
-        int its;
-        if (foot_solve<M>(a.curve, bd, X, Y, seed, a.maxit, &th, &eta, &its) != FOOT_OK) return false;
+        double eta;
+        if (!eta_at(mid, &eta)) return false;
         const double lo0 = lo, hi0 = hi;
         if (eta <= 0) lo = mid;
         else hi = mid;
@@ -503,15 +555,18 @@ __device__ bool crossing(const StarArgs& a, const BndView& bd, bool vertical, do
     return true;
 }
 
+// two lanes per candidate: lane 2c scans below the star and locates the
+// square there, lane 2c + 1 above it
 template <int M>
 __global__ __launch_bounds__(64) void k_star_scan(StarArgs a, const int8_t* __restrict__ cls,
                                                   const StarQ* __restrict__ q, StarR* out, int n) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    const StarQ sq = q[k];
-    StarR r;
-    r.nlo = r.nhi = r.flags = r.pad = 0;
-    r.sq[0] = r.sq[1] = 0.0;
+    if (k >= 2 * n) return;
+    const int c = k >> 1, up = k & 1;
+    const StarQ sq = q[c];
+    StarR* r = out + c;
+    int cnt = 0, flag = 0;
+    double sqv = 0.0;
     if (!sq.skip) {
         const bool vert = sq.vertical != 0;
         const int nline = vert ? a.nx : a.ny, nb = vert ? a.ny : a.nx;
@@ -519,35 +574,29 @@ __global__ __launch_bounds__(64) void k_star_scan(StarArgs a, const int8_t* __re
             if (j < 0 || j >= nb || sq.line < 0 || sq.line >= nline) return false;
             return (vert ? cls[(int64_t)sq.line * a.ny + j] : cls[(int64_t)j * a.ny + sq.line]) == 1;
         };
-        int j = sq.jb;
-        while (j >= sq.jb - M && in_at(j)) { ++r.nlo; --j; }
-        const bool lo_stop = j >= sq.jb - M;
-        const int jlo = j;
-        j = sq.jb + 1;
-        while (j <= sq.jb + 1 + M && in_at(j)) { ++r.nhi; ++j; }
-        const bool hi_stop = j <= sq.jb + 1 + M;
-        const int jhi = j;
-        if (!a.io) {
+        // below: jb, jb - 1, ... down to jb - M; above: jb + 1, ... up to jb + 1 + M
+        const int dir = up ? 1 : -1, j0 = up ? sq.jb + 1 : sq.jb;
+        int j = j0;
+        while (cnt <= M && in_at(j)) {
+            ++cnt;
+            j += dir;
+        }
+        if (!a.io && cnt <= M) {   // the run ends within reach: its crossing with Gamma
             const BndView bd{a.bx, a.by, a.bnx, a.bny, a.B, a.k2};
             const double b0 = vert ? a.y0 : a.x0;
-            if (lo_stop) {
-                const double b_in = r.nlo == 0 ? sq.bstar : b0 + (jlo + 1) * a.h;
-                if (crossing<M>(a, bd, vert, sq.a_line, b_in, b0 + jlo * a.h, sq.p, &r.sq[0])) r.flags |= 1;
-                else r.flags |= 4;
-            }
-            if (hi_stop) {
-                const double b_in = r.nhi == 0 ? sq.bstar : b0 + (jhi - 1) * a.h;
-                if (crossing<M>(a, bd, vert, sq.a_line, b_in, b0 + jhi * a.h, sq.p, &r.sq[1])) r.flags |= 2;
-                else r.flags |= 4;
-            }
+            const double b_in = cnt == 0 ? sq.bstar : b0 + (j - dir) * a.h;
+            flag = crossing<M>(a, bd, vert, sq.a_line, b_in, b0 + j * a.h, sq.p, &sqv) ? 1 : 2;
         }
     }
-    out[k] = r;
+    if (up) r->nhi = cnt;
+    else r->nlo = cnt;
+    r->side[up] = flag;
+    r->sq[up] = sqv;
 }
 
 int launch_star_scan(const StarArgs& a, const int8_t* d_cls, const StarQ* d_q, StarR* d_r, int n, hipStream_t s) {
     if (n <= 0) return FC2D_OK;
-    const unsigned nb = (unsigned)((n + 63) / 64);
+    const unsigned nb = (unsigned)((2 * (int64_t)n + 63) / 64);
     switch (a.M) {
         case 4: k_star_scan<4><<<nb, 64, 0, s>>>(a, d_cls, d_q, d_r, n); break;
         case 5: k_star_scan<5><<<nb, 64, 0, s>>>(a, d_cls, d_q, d_r, n); break;

@@ -25,8 +25,8 @@ struct StarQ {
 };
 struct StarR {
     int32_t nlo, nhi;   // IN points jb, jb-1, ... (nlo of them) and jb+1, ... (nhi)
-    int32_t flags;      // 1: run below ends at Gamma within M steps (square sq[0]); 2: above (sq[1]); 4: foot failed
-    int32_t pad;
+    int32_t side[2];    // below [0] and above [1]: 1 the run ends at Gamma within M steps (square
+                        // sq[s]); 2 a foot solve failed
     double sq[2];       // crossing coordinate along the line
 };
 

@@ -91,7 +91,7 @@ int select_matching(const MatchGeom& g, const StarQ* q, const StarR* res, const 
             const StarR& rr = res[k];
             if (r.skip) continue;
             const double b0 = r.vertical ? g.y0 : g.x0;
-            bool has[2] = {(rr.flags & 1) != 0, (rr.flags & 2) != 0};
+            bool has[2] = {(rr.side[0] & 1) != 0, (rr.side[1] & 1) != 0};
             for (int side = 0; side < 2; ++side) {
                 if (!has[side]) continue;
                 bool near_node = false;

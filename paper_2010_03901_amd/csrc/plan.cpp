@@ -205,7 +205,7 @@ static int build_matching(fc2d_plan* pl, int maxit, const BndView& dbd, hipStrea
         if (st) return st;
     }
     for (size_t k = 0; k < nst; ++k)
-        if (res[k].flags & 4) {
+        if ((res[k].side[0] | res[k].side[1]) & 2) {
             set_error("foot of the normal failed while locating grid-line crossings with the boundary");
             return FC2D_E_NEWTON;
         }

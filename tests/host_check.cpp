@@ -46,7 +46,7 @@ static void check_tables(int d) {
 // the scan of one red star's grid line on the unit disc: IN runs next to the
 // star and the crossings of the line with the circle that bound them
 static StarR scan_disc(const MatchGeom& g, const StarQ& s) {
-    StarR r = {0, 0, 0, 0, {0.0, 0.0}};
+    StarR r = {0, 0, {0, 0}, {0.0, 0.0}};
     if (s.skip) return r;
     const bool vert = s.vertical != 0;
     const int nline = vert ? g.nx : g.ny, nb = vert ? g.ny : g.nx;
@@ -65,8 +65,8 @@ static StarR scan_disc(const MatchGeom& g, const StarQ& s) {
     const bool hi_stop = j <= s.jb + 1 + M;
     if (!g.interior_only) {
         const double half = sqrt(fmax(0.0, 1.0 - s.a_line * s.a_line));
-        if (lo_stop) { r.sq[0] = -half; r.flags |= 1; }
-        if (hi_stop) { r.sq[1] = half; r.flags |= 2; }
+        if (lo_stop) { r.sq[0] = -half; r.side[0] = 1; }
+        if (hi_stop) { r.sq[1] = half; r.side[1] = 1; }
     }
     return r;
 }

@@ -403,9 +403,10 @@ int fc2d_trace_end(int* n, const char** names, float* ms, int cap);
  * transposed spectra, and the strip kernel's fields per thread on the batch's
  * buffers and keeps the fastest (launch shapes are process-wide, see
  * fc2d_tune_set); FC2D_BATCH_TRANSPOSED keeps each grid size's spectra
- * transposed ([field][column][row], so the column passes read contiguous
- * columns; the row passes write and read them 4 rows at a time; grids with
- * ny <= 4096) and implies the fused spectral step for those sizes.  The
+ * transposed (bin-major within groups of 8 rows, so a bin's 8 rows fill one
+ * 128-byte line: the column passes read whole lines, the row passes a group's
+ * bins as one contiguous range, 4 rows at a time; grids with ny <= 4096 and nx
+ * a multiple of 8) and implies the fused spectral step for those sizes.  The
  * spectra are internal: results do not depend on the layout beyond rounding.
  * State starts at zero. */
 typedef struct fc2d_batch fc2d_batch;

@@ -32,7 +32,7 @@ struct Group {
     double* state = nullptr;      // [2][nf_total][nx][ny]: u then u_t
     double* spec = nullptr;       // [2][nf_total][nx][ny/2+1] complex128
     bool fused_ff = false;        // column passes and propagation in one launch (k_cols_ff)
-    bool trans = false;           // spectra stored transposed, [field][column][row] (implies fused_ff)
+    bool trans = false;           // spectra stored transposed, rows in groups of 8 (implies fused_ff)
 };
 }  // namespace fc2d
 
@@ -179,7 +179,7 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
         g.fused_ff = t_fused >= 0 && (t_sep < 0 || t_fused < t_sep);
         // row-major spectra (as chosen above) against transposed spectra, over
         // the group's whole spectral step, unless the layout was fixed
-        if (!b->trans_fixed && g.grid.ny <= 4096) {
+        if (!b->trans_fixed && g.grid.ny <= 4096 && g.grid.nx % 8 == 0) {
             int nl = 0;
             g.trans = false;
             const float t_rm = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 2);
@@ -358,7 +358,7 @@ int fc2d_batch_create(const fc2d_plan* const* plans, const int* nf, int nplans, 
         for (Group& g : b->groups) g.fused_ff = true;
     if (flags & FC2D_BATCH_TRANSPOSED) {
         b->trans_fixed = true;
-        for (Group& g : b->groups) g.trans = g.grid.ny <= 4096;
+        for (Group& g : b->groups) g.trans = g.grid.ny <= 4096 && g.grid.nx % 8 == 0;
     }
     if (flags & FC2D_BATCH_AUTOTUNE) st = autotune(b, s);
     if (st) { batch_free(b); return st; }

@@ -312,6 +312,15 @@ __device__ __forceinline__ int xcd_row_block(int nrb) {
     return rb < nrb ? rb : -1;
 }
 
+// Position of bin k of row i of field f in a transposed half spectrum (ncol
+// bins, nx rows, nx a multiple of 8), in complex elements: the rows are kept in
+// groups of 8, ((f nx/8 + i/8) ncol + k) 8 + i % 8.  The 8 rows of a group fill
+// one 128-byte line per bin and a group's bins follow each other, so the row
+// passes stream a group as one contiguous range; a column is nx/8 whole lines.
+__device__ __forceinline__ int64_t tpos(int f, int k, int i, int nx, int ncol) {
+    return (((int64_t)f * (nx >> 3) + (i >> 3)) * ncol + k) * 8 + (i & 7);
+}
+
 __device__ const double2 g_zero_pair[1] = {{0.0, 0.0}};
 
 // Streaming (non-temporal) 16-byte loads and stores: the passes touch every
@@ -344,10 +353,10 @@ __device__ __forceinline__ double2 mixed_pair(const double* row, const double* s
     return z;
 }
 
-// TRANS: the half spectrum is written transposed, [field][bin k][row]
-// (each column contiguous), the RPB rows of a block as RPB x 16 contiguous
-// bytes per bin; the LDS rows are padded to L + 2 so the RPB rows of one bin
-// sit in different banks.
+// TRANS: the half spectrum is written transposed (tpos: rows in groups of 8,
+// a bin's 8 rows of a group on one 128-byte line), the RPB rows of a block as
+// RPB x 16 contiguous bytes per bin; the LDS rows are padded to L + 2 so the
+// RPB rows of one bin sit in different banks.
 template <int L, int E, int RPB, bool MASKED, bool TRANS>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __restrict__ in, double2* __restrict__ out,
                                                             int nx, const double2* __restrict__ tw,
@@ -404,15 +413,16 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_r2c(const double* __rest
         const double2 D = make_double2(0.5 * (zk.x - zc.x), 0.5 * (zk.y - zc.y));
         const double2 O = make_double2(D.y, -D.x);   // D / i
         const double2 X = cadd(Eh, cmul(wk, O));
-        if (TRANS) out[((int64_t)f * (L + 1) + k) * nx + orow] = X;
+        if (TRANS) out[tpos(f, k, orow, nx, L + 1)] = X;
         else st_nt(out + ((int64_t)f * nx + orow) * ld + k, X);
         wk = cmul(wk, wstep);
     }
 }
 
 // pass R': half-spectrum rows -> real rows, scaled
-// TRANS: the half spectrum is read transposed ([field][bin][row]); the block
-// first stages its RPB rows in LDS (RPB x 16 contiguous bytes per bin).
+// TRANS: the half spectrum is read transposed (tpos); the block first stages
+// its RPB rows in LDS (RPB x 16 contiguous bytes per bin, the bins of a row
+// group one line apart).
 template <int L, int E, int RPB, bool TRANS>
 __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __restrict__ in, double* __restrict__ out,
                                                             int nx, const double2* __restrict__ tw, double scale,
@@ -430,11 +440,22 @@ __global__ __launch_bounds__(RPB * (L / E)) void k_rows_c2r(const double2* __res
     const bool live = row < nx;
     const double2* src = in + ((int64_t)f * nx + (live ? row : 0)) * ld;
     if constexpr (TRANS) {
-        // bins 0..L of the block's rows
-        for (int e = threadIdx.x; e < RPB * (L + 1); e += RPB * P) {
+        // bins 0..L of the block's rows: every load in flight before the first
+        // LDS write (a loop that waits for each load in turn leaves the pass
+        // latency-bound)
+        constexpr int NIT = (RPB * (L + 1) + RPB * P - 1) / (RPB * P);
+        double2 st[NIT];
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = threadIdx.x + it * RPB * P;
             const int qq = e % RPB, n = e / RPB;
             const int r = rblk * RPB + qq;
-            lds[qq * QS + n] = r < nx ? in[((int64_t)f * (L + 1) + n) * nx + r] : make_double2(0.0, 0.0);
+            st[it] = (e < RPB * (L + 1) && r < nx) ? in[tpos(f, n, r, nx, L + 1)] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int it = 0; it < NIT; ++it) {
+            const int e = threadIdx.x + it * RPB * P;
+            if (e < RPB * (L + 1)) lds[(e % RPB) * QS + e / RPB] = st[it];
         }
         __syncthreads();
         src = lds + q * QS;
@@ -684,7 +705,10 @@ int fft_rows_fwd(const fc2d_grid* g, const double* in, double* out, int nf, hipS
 
 int fft_rows_fwd_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s, const double* strip,
                    const uint8_t* cls2) {
-    if (g->ny > 4096) { set_error("transposed spectra: rows of at most 4096 points"); return FC2D_E_ARG; }
+    if (g->ny > 4096 || g->nx % 8) {
+        set_error("transposed spectra: rows of at most 4096 points, a multiple of 8 rows");
+        return FC2D_E_ARG;
+    }
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
     launch_rows<true, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0, strip, cls2, s, g->ny / 2 + 1);
@@ -709,7 +733,10 @@ int fft_rows_inv(const fc2d_grid* g, const double* in, double* out, int nf, hipS
 }
 
 int fft_rows_inv_t(const fc2d_grid* g, const double* in, double* out, int nf, hipStream_t s) {
-    if (g->ny > 4096) { set_error("transposed spectra: rows of at most 4096 points"); return FC2D_E_ARG; }
+    if (g->ny > 4096 || g->nx % 8) {
+        set_error("transposed spectra: rows of at most 4096 points, a multiple of 8 rows");
+        return FC2D_E_ARG;
+    }
     const double2* twy = twiddles(g->ny);
     if (!twy) { set_error("twiddle table allocation failed"); return FC2D_E_NOMEM; }
     launch_rows<false, true>(g->ny / 2, g->nx, nf, in, out, twy, 1.0 / ((double)g->nx * (double)g->ny), nullptr,
@@ -832,8 +859,8 @@ __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2*
 // LDS), transforms back along x and writes both in place.  Replaces forward
 // column pass + propagation + inverse column pass (three reads and writes of
 // both spectra) by one.
-// TRANS: spectra stored transposed ([field][column][row], each column
-// contiguous), as the transposed row passes write and read them.
+// TRANS: spectra stored transposed (tpos: each column nx/8 whole 128-byte
+// lines), as the transposed row passes write and read them.
 template <int L, int E, int T, bool TRANS>
 __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict__ su, double2* __restrict__ sut,
                                                          int ncol, int nx, double Lx, double Ly, double c, double t,
@@ -848,12 +875,15 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
     if (!col_block(ntiles, by_field != 0, &tile, &field)) return;   // uniform per block
     const int col = tile * H + q % H;
     const bool live = col < ncol;
-    const int64_t rs = TRANS ? 1 : ncol;   // row stride of a column
-    double2* base = (comp ? sut : su) + (TRANS ? ((int64_t)field * ncol + (live ? col : 0)) * L
-                                               : (int64_t)field * L * ncol + (live ? col : 0));
+    const int cl = live ? col : 0;
+    double2* sp = comp ? sut : su;
+    // element r of the block's column
+    auto at = [&](int r) -> int64_t {
+        return TRANS ? tpos(field, cl, r, L, ncol) : (int64_t)field * L * ncol + cl + (int64_t)r * ncol;
+    };
     double2 v[E];
 #pragma unroll
-    for (int k = 0; k < E; ++k) v[k] = base[(int64_t)in_index<L, E>(k, tt) * rs];
+    for (int k = 0; k < E; ++k) v[k] = sp[at(in_index<L, E>(k, tt))];
     StockhamFrom<L, E, 1, false>::run(v, lds, 1, T, q, tt, nullptr, L);
     __syncthreads();
 #pragma unroll
@@ -879,7 +909,7 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
     StockhamFrom<L, E, 1, true>::run(v, lds, 1, T, q, tt, nullptr, L);
     if (!live) return;
 #pragma unroll
-    for (int k = 0; k < E; ++k) base[(int64_t)out_index<L, E>(k, tt) * rs] = v[k];
+    for (int k = 0; k < E; ++k) sp[at(out_index<L, E>(k, tt))] = v[k];
 }
 
 // The same fused step with one column of u_hat and the same column of u_t_hat
@@ -896,15 +926,15 @@ __global__ __launch_bounds__(L / E) void k_cols_ffp(double2* __restrict__ su, do
     const int tt = threadIdx.x;
     int col, field;
     if (!col_block(ncol, by_field != 0, &col, &field)) return;   // uniform per block
-    const int64_t rs = TRANS ? 1 : ncol;   // row stride of a column
-    const int64_t off = TRANS ? ((int64_t)field * ncol + col) * L : (int64_t)field * L * ncol + col;
-    double2* bu = su + off;
-    double2* bt = sut + off;
+    // element r of the block's column
+    auto at = [&](int r) -> int64_t {
+        return TRANS ? tpos(field, col, r, L, ncol) : (int64_t)field * L * ncol + col + (int64_t)r * ncol;
+    };
     double2 a[E], b[E];
 #pragma unroll
     for (int k = 0; k < E; ++k) {
-        a[k] = bu[(int64_t)in_index<L, E>(k, tt) * rs];
-        b[k] = bt[(int64_t)in_index<L, E>(k, tt) * rs];
+        a[k] = su[at(in_index<L, E>(k, tt))];
+        b[k] = sut[at(in_index<L, E>(k, tt))];
     }
     StockhamFrom<L, E, 1, false>::run(a, lds, 1, 1, 0, tt, nullptr, L);
     __syncthreads();   // the last stage of a may still read lds
@@ -924,7 +954,7 @@ __global__ __launch_bounds__(L / E) void k_cols_ffp(double2* __restrict__ su, do
     __syncthreads();
     StockhamFrom<L, E, 1, true>::run(a, lds, 1, 1, 0, tt, nullptr, L);
 #pragma unroll
-    for (int k = 0; k < E; ++k) bu[(int64_t)out_index<L, E>(k, tt) * rs] = a[k];
+    for (int k = 0; k < E; ++k) su[at(out_index<L, E>(k, tt))] = a[k];
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < E; ++k) lds[swz(out_index<L, E>(k, tt))] = b[k];
@@ -934,7 +964,7 @@ __global__ __launch_bounds__(L / E) void k_cols_ffp(double2* __restrict__ su, do
     __syncthreads();
     StockhamFrom<L, E, 1, true>::run(b, lds, 1, 1, 0, tt, nullptr, L);
 #pragma unroll
-    for (int k = 0; k < E; ++k) bt[(int64_t)out_index<L, E>(k, tt) * rs] = b[k];
+    for (int k = 0; k < E; ++k) sut[at(out_index<L, E>(k, tt))] = b[k];
 }
 
 // shapes of the fused kernel per length 2^lg (elements per thread and columns

@@ -515,8 +515,7 @@ int fc2d_ff_advance(fc2d_ff* f, double* u, double* ut, const double* fb_u, const
         const double tau = k * f->dt;
         if ((st = ffs_position(dv, u, ut, f->acc, f->dt, s))) return st;
         // U_FC(t) on the grid: the propagated spectrum, inverse transformed
-        if ((st = ff_apply(g, f->c, tau, f->spec_u, f->spec_ut, f->prop_u, nullptr, 1, s))) return st;
-        if ((st = fft2_c2r(g, f->prop_u, f->ufc, 1, s))) return st;
+        if ((st = prop_c2r(g, f->c, tau, f->spec_u, f->spec_ut, f->prop_u, f->ufc, 1, s))) return st;
         if ((st = ffs_boundary(dv, u, bc_u + (int64_t)k * ncross, s))) return st;
         if ((st = ffs_accel(dv, u, f->ufc, bc_u + (int64_t)k * ncross, f->accd, s))) return st;
         if ((st = ffs_velocity(dv, ut, f->acc, f->accd, f->dt, s))) return st;

@@ -247,6 +247,10 @@ int ff_apply(const fc2d_grid* g, double c, double t, const double* u0, const dou
 // column pass + propagation by t + inverse column pass in one launch, in place
 // on row-transformed spectra su, sut ([nf][nx][ny/2+1] each)
 // trans: spectra stored transposed ([field][column][row]), as fft_rows_fwd_t writes them
+// U_FC(t) on the grid: out = inverse FFT of cos(w t) u0 + sin(w t) / w u1 (half
+// spectra [nf][nx][ny/2+1]); spec receives the column-transformed spectrum
+int prop_c2r(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* spec, double* out,
+             int nf, hipStream_t s);
 int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int nf, hipStream_t s,
             bool trans = false);
 int colff_variants(int nx);   // compiled launch shapes of cols_ff for length nx

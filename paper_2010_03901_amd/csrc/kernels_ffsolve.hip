@@ -76,9 +76,17 @@ __global__ __launch_bounds__(64) void k_ffs_accel(const FfSeg* __restrict__ seg,
         const int32_t k = sgrid[sg.base + (int64_t)p * sg.stride];
         if (k < 0) continue;
         const double* row = mats + sg.mat + (int64_t)(p - sg.row0) * sg.ld;
-        double a = 0.0;
-        for (int q = 0; q < sg.ld; ++q) a = fma(row[q], val[q], a);
-        accd[(int64_t)ax * ns + k] = a;
+        // four partial sums, so four rows' loads are in flight together
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+        int q = 0;
+        for (; q + 4 <= sg.ld; q += 4) {
+            a0 = fma(row[q], val[q], a0);
+            a1 = fma(row[q + 1], val[q + 1], a1);
+            a2 = fma(row[q + 2], val[q + 2], a2);
+            a3 = fma(row[q + 3], val[q + 3], a3);
+        }
+        for (; q < sg.ld; ++q) a0 = fma(row[q], val[q], a0);
+        accd[(int64_t)ax * ns + k] = (a0 + a1) + (a2 + a3);
     }
 }
 

@@ -852,6 +852,69 @@ __global__ void k_ff(const double2* u0, const double2* u1, double2* uh, double2*
     }
 }
 
+// Inverse column pass of a propagated spectrum with the propagation fused into
+// its loads: out (row-major half spectrum, columns transformed back along x)
+// = the inverse column transform of cos(w t) u0_hat + sin(w t) / w u1_hat, the
+// same sums as ff_apply followed by the inverse column pass of that length.
+template <int L, int E, int T>
+__global__ __launch_bounds__(T * (L / E)) void k_cols_prop(const double2* __restrict__ u0, const double2* __restrict__ u1,
+                                                           double2* __restrict__ out, int ncol, double Lx, double Ly,
+                                                           double c, double t, int by_field) {
+    __shared__ double2 lds[L * T];
+    const int q = threadIdx.x % T;
+    const int tt = threadIdx.x / T;
+    const int ntiles = (ncol + T - 1) / T;
+    int tile, field;
+    if (!col_block(ntiles, by_field != 0, &tile, &field)) return;   // uniform per block
+    const int col = tile * T + q;
+    const bool live = col < ncol;
+    const int cl = live ? col : 0;
+    const int64_t base = (int64_t)field * L * ncol + cl;
+    const double iLx = 1.0 / Lx, iLy = 1.0 / Ly;
+    double2 v[E];
+#pragma unroll
+    for (int k = 0; k < E; ++k) {
+        const int r = in_index<L, E>(k, tt);
+        double2 rt;
+        ff_apply(ff_coef(row_freq(r, L), cl, iLx, iLy, c, t), u0[base + (int64_t)r * ncol],
+                 u1[base + (int64_t)r * ncol], &v[k], &rt);
+    }
+    StockhamFrom<L, E, 1, true>::run(v, lds, 1, T, q, tt, nullptr, L);
+    if (!live) return;
+#pragma unroll
+    for (int k = 0; k < E; ++k) out[base + (int64_t)out_index<L, E>(k, tt) * ncol] = v[k];
+}
+
+int prop_c2r(const fc2d_grid* g, double c, double t, const double* u0, const double* u1, double* spec, double* out,
+             int nf, hipStream_t s) {
+    const int ncol = g->ny / 2 + 1;
+    const double Lx = g->nx * g->h, Ly = g->ny * g->h;
+    const int E = col_elems_get(g->nx), T = col_tile_get(g->nx);
+    bool done = false;
+#define FC2D_COLPROP(LL, EE, TT)                                                                              \
+    if (!done && g->nx == LL && E == EE && T == TT) {                                                        \
+        const int ntiles = (ncol + TT - 1) / TT;                                                             \
+        const bool byf = nf % 8 == 0;                                                                        \
+        const dim3 grid = byf ? dim3((unsigned)(nf * ntiles)) : dim3(((ntiles + 7) / 8) * 8, nf);            \
+        k_cols_prop<LL, EE, TT><<<grid, TT * (LL / EE), 0, s>>>((const double2*)u0, (const double2*)u1,      \
+                                                               (double2*)spec, ncol, Lx, Ly, c, t,          \
+                                                               byf ? 1 : 0);                                 \
+        done = true;                                                                                         \
+    }
+    FC2D_COLPROP(256, 4, 4) FC2D_COLPROP(256, 4, 8) FC2D_COLPROP(512, 4, 4) FC2D_COLPROP(512, 4, 8)
+    FC2D_COLPROP(512, 8, 4) FC2D_COLPROP(512, 8, 8) FC2D_COLPROP(1024, 8, 4) FC2D_COLPROP(1024, 16, 2)
+    FC2D_COLPROP(1024, 16, 4) FC2D_COLPROP(2048, 16, 1) FC2D_COLPROP(2048, 16, 2)
+#undef FC2D_COLPROP
+    int st;
+    if (done) {
+        if ((st = check("k_cols_prop", s))) return st;
+    } else {   // other lengths and launch shapes: propagation, then the inverse column pass
+        if ((st = ff_apply(g, c, t, u0, u1, spec, nullptr, nf, s))) return st;
+        if ((st = fft_cols(g, spec, nf, true, s))) return st;
+    }
+    return fft_rows_inv(g, spec, out, nf, s);
+}
+
 // Column pass fused with the propagation, for spectra whose rows are already
 // transformed (the middle of a Fourier-Forwarding step): a block takes the
 // same T/2 adjacent columns of u_hat and of u_t_hat of one field, transforms

@@ -952,18 +952,26 @@ __global__ __launch_bounds__(T * (L / E), 4) void k_cols_ff(double2* __restrict_
 #pragma unroll
     for (int k = 0; k < E; ++k) lds[swz(out_index<L, E>(k, tt) * T + q)] = v[k];
     __syncthreads();
-    // propagate every (row i, column pair) in LDS; one mode at a time keeps the
-    // transcendental work out of the unrolled register code
+    // propagate every (row i, column pair) in LDS; one |row frequency| at a
+    // time (rows la and L - la share the factors) keeps the transcendental work
+    // out of the unrolled register code and computes each factor once
     const int tile_col0 = tile * H;
     const double iLx = 1.0 / Lx, iLy = 1.0 / Ly;
 #pragma unroll 1
-    for (int e = threadIdx.x; e < L * H; e += T * (L / E)) {
-        const int i = e / H, cq = e % H;
-        const int a = swz(i * T + cq), b = swz(i * T + cq + H);
+    for (int e = threadIdx.x; e < (L / 2 + 1) * H; e += T * (L / E)) {
+        const int la = e / H, cq = e % H;
+        const FFCoef k = ff_coef(la, tile_col0 + cq, iLx, iLy, c, t);
+        const int a = swz(la * T + cq), b = swz(la * T + cq + H);
         double2 ra, rt;
-        ff_apply(ff_coef(row_freq(i, L), tile_col0 + cq, iLx, iLy, c, t), lds[a], lds[b], &ra, &rt);
+        ff_apply(k, lds[a], lds[b], &ra, &rt);
         lds[a] = ra;
         lds[b] = rt;
+        if (la > 0 && la < L / 2) {
+            const int a2 = swz((L - la) * T + cq), b2 = swz((L - la) * T + cq + H);
+            ff_apply(k, lds[a2], lds[b2], &ra, &rt);
+            lds[a2] = ra;
+            lds[b2] = rt;
+        }
     }
     __syncthreads();
 #pragma unroll

@@ -368,8 +368,8 @@ int fc2d_ff_advance(fc2d_ff* ff, double* u, double* ut, const double* fb_u, cons
  * stencils span more normals read the records from device memory instead.
  * FC2D_TUNE_FF_SHAPE: index of the compiled shape of the fused column-pass +
  * propagation kernel for length n (batches; n = 256, 512: 0..2, n = 1024:
- * 0..3, n = 2048: 0..5, n = 4096: 0..1, other lengths: 0; the last index of
- * 1024 and 4096 and the last two of 2048 take one column of both spectra per
+ * 0..5, n = 2048: 0..5, n = 4096: 0..1, other lengths: 0; index 3 of 1024, the
+ * last two of 2048 and the last of 4096 take one column of both spectra per
  * block, propagated in registers).  Not thread-safe against
  * concurrent launches. */
 int fc2d_tune_set(int knob, int n, int value);

@@ -1046,7 +1046,7 @@ static int g_colff_var[14] = {0};
 int colff_variants(int nx) {
     switch (nx) {
         case 256: case 512: return 3;
-        case 1024: return 4;
+        case 1024: return 6;
         case 2048: return 6;
         case 4096: return 2;
         case 16: case 32: case 64: case 128: return 1;
@@ -1083,6 +1083,7 @@ int cols_ff(const fc2d_grid* g, double c, double t, double* su, double* sut, int
     FC2D_COLFF(256, 0, 4, 8) FC2D_COLFF(256, 1, 4, 4) FC2D_COLFF(256, 2, 2, 8)
     FC2D_COLFF(512, 0, 8, 8) FC2D_COLFF(512, 1, 8, 4) FC2D_COLFF(512, 2, 4, 8)
     FC2D_COLFF(1024, 0, 8, 4) FC2D_COLFF(1024, 1, 8, 8) FC2D_COLFF(1024, 2, 16, 4)
+    FC2D_COLFF(1024, 4, 8, 2) FC2D_COLFF(1024, 5, 16, 2)
     FC2D_COLFF(2048, 0, 8, 2) FC2D_COLFF(2048, 1, 8, 4) FC2D_COLFF(2048, 2, 16, 2) FC2D_COLFF(2048, 3, 16, 4)
     FC2D_COLFF(4096, 0, 16, 2)
 #undef FC2D_COLFF

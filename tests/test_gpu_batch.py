@@ -309,7 +309,7 @@ def test_every_fused_shape_matches_separate(torch_mod, n, nfl):
             nshape += 1
     finally:
         fc2d.fc2d_tune_set(fc2d.FC2D_TUNE_FF_SHAPE, n, keep)
-    assert nshape == {1024: 4, 2048: 6, 4096: 2}[n]
+    assert nshape == {1024: 6, 2048: 6, 4096: 2}[n]
 
 
 def test_bench_shaped_batch_step_matches_oracle(torch_mod):

@@ -6,9 +6,33 @@
 
 #include <stdint.h>
 
+#include <memory>
+#include <new>
+#include <utility>
 #include <vector>
 
 namespace fc2d {
+
+// Host arrays of the plan that their builders write in full, in parallel:
+// resize() leaves the elements default-initialised (no serial zero fill), so
+// the first touch of their pages happens in the parallel loops that fill them.
+template <class T>
+struct NoInitAlloc : std::allocator<T> {
+    template <class U>
+    struct rebind {
+        using other = NoInitAlloc<U>;
+    };
+    NoInitAlloc() = default;
+    template <class U>
+    NoInitAlloc(const NoInitAlloc<U>&) noexcept {}
+    template <class U, class... A>
+    void construct(U* p, A&&... a) {
+        if constexpr (sizeof...(A) == 0) ::new ((void*)p) U;
+        else ::new ((void*)p) U(std::forward<A>(a)...);
+    }
+};
+template <class T>
+using HostVec = std::vector<T, NoInitAlloc<T>>;
 
 // Red-star candidates of the matching stencils: one per (normal, candidate line).
 // The device scans the star's grid line for the runs of IN points next to it
@@ -45,8 +69,7 @@ struct MatchGeom {
 // 2M candidate stars per normal (crossings of the inward normal with the grid
 // lines x = x_i when |n_x| >= |n_y|, else y = y_j, by depth), with their depth
 // and position along the line in extended precision.
-void place_stars(const MatchGeom& g, std::vector<StarQ>& q, std::vector<long double>& delta,
-                 std::vector<long double>& bstar);
+void place_stars(const MatchGeom& g, HostVec<StarQ>& q, HostVec<long double>& delta, HostVec<long double>& bstar);
 
 // From the scan results: per normal the red stars (the first candidates with at
 // least M nodes), their M nearest nodes (grid points or squares), the weights
@@ -55,7 +78,7 @@ void place_stars(const MatchGeom& g, std::vector<StarQ>& q, std::vector<long dou
 // squares: 2 per square in the order normal, star, node.  Returns 0, or the
 // first normal with too few usable stars + 1 (as a negative number: -(p + 1)).
 int select_matching(const MatchGeom& g, const StarQ* q, const StarR* res, const long double* delta,
-                    const long double* bstar, std::vector<int32_t>& mref, std::vector<double>& mwv,
-                    std::vector<double>& mwn, std::vector<double>& squares);
+                    const long double* bstar, HostVec<int32_t>& mref, HostVec<double>& mwv, HostVec<double>& mwn,
+                    std::vector<double>& squares);
 
 }  // namespace fc2d

@@ -26,8 +26,7 @@ namespace fc2d {
 // the normal) are skipped
 constexpr double kStarMinDepth = 0.05;
 
-void place_stars(const MatchGeom& g, std::vector<StarQ>& q, std::vector<long double>& delta,
-                 std::vector<long double>& bstar) {
+void place_stars(const MatchGeom& g, HostVec<StarQ>& q, HostVec<long double>& delta, HostVec<long double>& bstar) {
     const int M = g.M, B = g.B, ns = 2 * M;
     const double h = g.h;
     const size_t nst = (size_t)B * ns;
@@ -66,17 +65,18 @@ void place_stars(const MatchGeom& g, std::vector<StarQ>& q, std::vector<long dou
 }
 
 int select_matching(const MatchGeom& g, const StarQ* q, const StarR* res, const long double* delta,
-                    const long double* bstar, std::vector<int32_t>& mref, std::vector<double>& mwv,
-                    std::vector<double>& mwn, std::vector<double>& squares) {
+                    const long double* bstar, HostVec<int32_t>& mref, HostVec<double>& mwv, HostVec<double>& mwn,
+                    std::vector<double>& squares) {
     const int M = g.M, d = g.d, B = g.B, ns = 2 * M;
     const bool io = g.interior_only;
     const int nq = io ? d : d - 1;       // matching values interpolated along the normal
     const int nstar = io ? M : M - 1;    // red stars per normal
     const double h = g.h;
-    mref.assign((size_t)B * M * M, 0);
-    mwv.assign((size_t)B * M * M * 2, 0.0);
-    mwn.assign((size_t)B * nq * M * 2, 0.0);
-    std::vector<double> sqxy((size_t)B * nstar * 2 * 2);   // at most two squares per star
+    // every entry of a normal whose stars all qualify is written below
+    mref.clear(); mref.resize((size_t)B * M * M);
+    mwv.clear(); mwv.resize((size_t)B * M * M * 2);
+    mwn.clear(); mwn.resize((size_t)B * nq * M * 2);
+    HostVec<double> sqxy((size_t)B * nstar * 2 * 2);   // at most two squares per star
     std::vector<int> nsq(B, 0);
     int bad = B;   // first normal with too few usable red stars
 #pragma omp parallel for reduction(min : bad)
@@ -120,10 +120,14 @@ int select_matching(const MatchGeom& g, const StarQ* q, const StarR* res, const 
                 }
             }
             for (int t = 0; t < M; ++t) {
-                long double w = 1.0L;
+                // Lagrange weight of node t: one quotient of the two products
+                long double num = 1.0L, den = 1.0L;
                 for (int m = 0; m < M; ++m)
-                    if (m != t)
-                        w *= (bstar[k] - (long double)chosen[m].b) / ((long double)chosen[t].b - (long double)chosen[m].b);
+                    if (m != t) {
+                        num *= bstar[k] - (long double)chosen[m].b;
+                        den *= (long double)chosen[t].b - (long double)chosen[m].b;
+                    }
+                const long double w = num / den;
                 const size_t o = (((size_t)p * M + used) * M + t);
                 const double whi = (double)w;
                 mwv[2 * o] = whi;
@@ -147,15 +151,23 @@ int select_matching(const MatchGeom& g, const StarQ* q, const StarR* res, const 
             continue;
         }
         if (nstar < M) {   // the point on Gamma: no stencil (entries marked unused), depth 0
-            for (int t = 0; t < M; ++t) mref[((size_t)p * M + M - 1) * M + t] = kUnusedRef;
+            for (int t = 0; t < M; ++t) {
+                const size_t o = ((size_t)p * M + M - 1) * M + t;
+                mref[o] = kUnusedRef;
+                mwv[2 * o] = mwv[2 * o + 1] = 0.0;
+            }
             deltas[M - 1] = 0.0L;
         }
         for (int qq = 0; qq < nq; ++qq) {
             const long double x = (long double)(d - 1 - qq) * (long double)g.k1;
             for (int sv = 0; sv < M; ++sv) {
-                long double w = 1.0L;
+                long double num = 1.0L, den = 1.0L;
                 for (int m = 0; m < M; ++m)
-                    if (m != sv) w *= (x - deltas[m]) / (deltas[sv] - deltas[m]);
+                    if (m != sv) {
+                        num *= x - deltas[m];
+                        den *= deltas[sv] - deltas[m];
+                    }
+                const long double w = num / den;
                 const size_t o = ((size_t)p * nq + qq) * M + sv;
                 const double whi = (double)w;
                 mwn[2 * o] = whi;

@@ -172,18 +172,18 @@ static int nearest_sample(const fc2d_plan* pl, double X, double Y, int p) {
 // the IN runs next to them and bisects the lines' crossings with Gamma
 // (k_star_scan); the host then picks the stars and nodes and forms the weights.
 static int build_matching(fc2d_plan* pl, int maxit, const BndView& dbd, hipStream_t stream,
-                          std::vector<int32_t>& mref, std::vector<double>& mwv, std::vector<double>& mwn) {
+                          HostVec<int32_t>& mref, HostVec<double>& mwv, HostVec<double>& mwn) {
     const fc2d_grid& g = pl->grid;
     MatchGeom mg;
     mg.x0 = g.x0; mg.y0 = g.y0; mg.h = g.h; mg.nx = g.nx; mg.ny = g.ny;
     mg.M = pl->M; mg.d = pl->d; mg.B = pl->B; mg.interior_only = pl->interior_only; mg.k1 = pl->k1;
     mg.bx = pl->bx.data(); mg.by = pl->by.data(); mg.bnx = pl->bnx.data(); mg.bny = pl->bny.data();
-    std::vector<StarQ> q;
-    std::vector<long double> delta, bstar;
+    HostVec<StarQ> q;
+    HostVec<long double> delta, bstar;
     place_stars(mg, q, delta, bstar);
     const size_t nst = q.size();
     // device: IN runs along the candidates' lines and the squares bounding them
-    std::vector<StarR> res(nst);
+    HostVec<StarR> res(nst);
     {
         StarArgs sa;
         sa.curve = pl->curve;
@@ -307,15 +307,21 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
         spd[p] = sp;
         spmax = std::max(spmax, sp);
     }
-    // admissibility: exterior reach and the box
+    // admissibility: exterior reach and the box.  The 16 B curve samples are
+    // also the vertices of the polygon whose column crossings the proximity
+    // seed's parity test uses (kept when that seed is chosen).
     double reach_ext = INFINITY;
+    const int nv = 16 * B;
+    const bool keep_poly = o.seed == FC2D_SEED_PROXIMITY;
+    std::vector<double> px(keep_poly ? nv : 0), py(keep_poly ? nv : 0);
     {
-        const int ns = 16 * B;
+        const int ns = nv;
         double kmin = 0.0;   // most negative curvature
 #pragma omp parallel for reduction(min : kmin)
         for (int k = 0; k < ns; ++k) {
             double v[6];
             curve_eval(pl->curve, k * (2.0 * M_PI / ns), v);
+            if (keep_poly) { px[k] = v[0]; py[k] = v[1]; }
             const double s2 = v[2] * v[2] + v[3] * v[3];
             const double kap = (v[2] * v[5] - v[3] * v[4]) / (s2 * sqrt(s2));
             kmin = std::min(kmin, kap);
@@ -345,34 +351,37 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     // column crossings of the 16 B-vertex polygon (parity test of the proximity seed)
     std::vector<int32_t> col_ptr(grid->nx + 1, 0);
     std::vector<double> col_y;
-    if (o.seed == FC2D_SEED_PROXIMITY) {
-        const int nv = 16 * B;
-        std::vector<double> px(nv), py(nv);
-#pragma omp parallel for
-        for (int k = 0; k < nv; ++k) {
-            double v[6];
-            curve_eval(pl->curve, k * (2.0 * M_PI / nv), v);
-            px[k] = v[0]; py[k] = v[1];
-        }
-        std::vector<std::vector<double>> cols(grid->nx);
-        for (int k = 0; k < nv; ++k) {
-            const int k1 = (k + 1) % nv;
-            const double ax = px[k], ay = py[k], bx = px[k1], by = py[k1];
-            const double xmin = std::min(ax, bx), xmax = std::max(ax, bx);
-            const long i0 = (long)ceil((xmin - grid->x0) / grid->h);
-            const long i1 = (long)ceil((xmax - grid->x0) / grid->h);
-            for (long i = i0; i < i1; ++i) {
-                if (i < 0 || i >= grid->nx) continue;
-                const double xc = grid->x0 + i * grid->h;
-                const double s = (xc - ax) / (bx - ax);
-                cols[i].push_back(ay + s * (by - ay));
+    if (keep_poly) {
+        // (column, y) of every crossing, gathered per thread, then sorted:
+        // each column's crossings in increasing y whatever the thread count
+        std::vector<std::pair<int32_t, double>> xing;
+#pragma omp parallel
+        {
+            std::vector<std::pair<int32_t, double>> loc;
+#pragma omp for schedule(static) nowait
+            for (int k = 0; k < nv; ++k) {
+                const int k1 = (k + 1) % nv;
+                const double ax = px[k], ay = py[k], bx = px[k1], by = py[k1];
+                const double xmin = std::min(ax, bx), xmax = std::max(ax, bx);
+                const long i0 = (long)ceil((xmin - grid->x0) / grid->h);
+                const long i1 = (long)ceil((xmax - grid->x0) / grid->h);
+                for (long i = i0; i < i1; ++i) {
+                    if (i < 0 || i >= grid->nx) continue;
+                    const double xc = grid->x0 + i * grid->h;
+                    const double s = (xc - ax) / (bx - ax);
+                    loc.emplace_back((int32_t)i, ay + s * (by - ay));
+                }
             }
+#pragma omp critical
+            xing.insert(xing.end(), loc.begin(), loc.end());
         }
-        for (int i = 0; i < grid->nx; ++i) {
-            std::sort(cols[i].begin(), cols[i].end());
-            col_ptr[i + 1] = col_ptr[i] + (int32_t)cols[i].size();
-            col_y.insert(col_y.end(), cols[i].begin(), cols[i].end());
+        std::sort(xing.begin(), xing.end());
+        col_y.resize(xing.size());
+        for (size_t m = 0; m < xing.size(); ++m) {
+            ++col_ptr[xing[m].first + 1];
+            col_y[m] = xing[m].second;
         }
+        for (int i = 0; i < grid->nx; ++i) col_ptr[i + 1] += col_ptr[i];
     }
     lap(FC2D_PHASE_GEOMETRY);
     // steps 3-4 on the device: classification and foot of the normal
@@ -390,8 +399,8 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
     int32_t* d_colptr = nullptr;
     int8_t* d_cls = nullptr;
     StripRec* d_rec = nullptr;
-    std::vector<int32_t> mref;
-    std::vector<double> mwv, mwn;
+    HostVec<int32_t> mref;
+    HostVec<double> mwv, mwn;
     uint64_t* d_near = nullptr;
     int32_t* d_cand = nullptr;
     float* d_w = nullptr;
@@ -533,12 +542,17 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             const int nq = pl->interior_only ? d : d - 1;   // matching values along the normal
             const int MM = M * M, NU = (MM + 15) / 16 * 4, RQ = (nq + 3) / 4;
             const int64_t npts = (int64_t)grid->nx * grid->ny;
-            std::vector<int32_t> dref((size_t)B * 4 * NU, 0);
-            std::vector<uint8_t> dlab((size_t)B * 4 * NU, 255);
             const int RS = (M + 3) / 4;   // stars per lane
-            std::vector<double> dwv((size_t)B * RS * M * 4 * 2, 0.0), dwn((size_t)B * RQ * M * 4 * 2, 0.0);
+            // filled per normal (padding first) inside the parallel loop
+            HostVec<int32_t> dref((size_t)B * 4 * NU);
+            HostVec<uint8_t> dlab((size_t)B * 4 * NU);
+            HostVec<double> dwv((size_t)B * RS * M * 4 * 2), dwn((size_t)B * RQ * M * 4 * 2);
 #pragma omp parallel for
             for (int p = 0; p < B; ++p) {
+                std::fill_n(&dref[(size_t)p * 4 * NU], 4 * NU, 0);
+                std::fill_n(&dlab[(size_t)p * 4 * NU], 4 * NU, (uint8_t)255);
+                std::fill_n(&dwv[(size_t)p * RS * M * 4 * 2], RS * M * 4 * 2, 0.0);
+                std::fill_n(&dwn[(size_t)p * RQ * M * 4 * 2], RQ * M * 4 * 2, 0.0);
                 int ord[kMaxStencil * kMaxStencil];
                 const int32_t* r0 = &mref[(size_t)p * MM];
                 auto key = [&](int e) { return r0[e] >= 0 ? (int64_t)r0[e] : npts + (int64_t)(-r0[e] - 1); };

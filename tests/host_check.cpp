@@ -82,14 +82,15 @@ static void check_matching(bool interior_only) {
     g.x0 = -1.5; g.y0 = -1.5; g.h = 3.0 / n; g.nx = n; g.ny = n;
     g.M = 8; g.d = 5; g.B = B; g.interior_only = interior_only; g.k1 = 0.2 / 27;
     g.bx = bx.data(); g.by = by.data(); g.bnx = bnx.data(); g.bny = bny.data();
-    std::vector<StarQ> q;
-    std::vector<long double> delta, bstar;
+    HostVec<StarQ> q;
+    HostVec<long double> delta, bstar;
     place_stars(g, q, delta, bstar);
     CHECK(q.size() == (size_t)B * 2 * g.M, "place_stars: %zu candidates", q.size());
     std::vector<StarR> res(q.size());
     for (size_t k = 0; k < q.size(); ++k) res[k] = scan_disc(g, q[k]);
-    std::vector<int32_t> mref;
-    std::vector<double> mwv, mwn, squares;
+    HostVec<int32_t> mref;
+    HostVec<double> mwv, mwn;
+    std::vector<double> squares;
     const int st = select_matching(g, q.data(), res.data(), delta.data(), bstar.data(), mref, mwv, mwn, squares);
     CHECK(st == 0, "select_matching: %d", st);
     if (st) return;

@@ -133,20 +133,25 @@ static int batch_step(fc2d_batch* b, double c, double dt, hipStream_t s) {
     return FC2D_OK;
 }
 
+// the fastest of reps timed calls after one warm-up call (the minimum is the
+// least disturbed by other work on the device)
 static float time_ms(hipStream_t s, const std::function<int()>& fn, int reps) {
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return -1.0f;
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return -1.0f; }
     (void)fn();   // warm-up
-    (void)hipEventRecord(e0, s);
-    for (int r = 0; r < reps; ++r) (void)fn();
-    (void)hipEventRecord(e1, s);
-    (void)hipEventSynchronize(e1);
-    float ms = -1.0f;
-    (void)hipEventElapsedTime(&ms, e0, e1);
+    float best = -1.0f;
+    for (int r = 0; r < reps; ++r) {
+        (void)hipEventRecord(e0, s);
+        (void)fn();
+        (void)hipEventRecord(e1, s);
+        (void)hipEventSynchronize(e1);
+        float ms = -1.0f;
+        if (hipEventElapsedTime(&ms, e0, e1) == hipSuccess && ms >= 0.0f && (best < 0.0f || ms < best)) best = ms;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    return ms / reps;
+    return best;
 }
 
 static int autotune(fc2d_batch* b, hipStream_t s) {
@@ -182,13 +187,13 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
         if (!b->trans_fixed && g.grid.ny <= 4096 && g.grid.nx % 8 == 0) {
             int nl = 0;
             g.trans = false;
-            const float t_rm = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 2);
+            const float t_rm = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 3);
             g.trans = true;
             float t_tr = -1.0f;
             int best_tv = colff_get(g.grid.nx);
             for (int v = 0; v < colff_variants(g.grid.nx); ++v) {
                 colff_set(g.grid.nx, v);
-                const float ms = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 2);
+                const float ms = time_ms(s, [&]() { return group_fft_step(b, g, 1.0, 0.0, s, &nl); }, 3);
                 if (ms >= 0 && (t_tr < 0 || ms < t_tr)) { t_tr = ms; best_tv = v; }
             }
             g.trans = t_tr >= 0 && (t_rm < 0 || t_tr < t_rm);

@@ -488,7 +488,7 @@ def run_mlp(args):
     res, plans = {}, {}
     for name, kw in modes.items():
         best = None
-        for _ in range(3):
+        for _ in range(5):   # the fastest of five builds: host timings vary from build to build
             torch.cuda.synchronize()
             fc2d.fc2d_trace_begin()
             t0 = time.perf_counter()
@@ -496,7 +496,7 @@ def run_mlp(args):
             wall = time.perf_counter() - t0
             tr = fc2d.fc2d_trace_end()
             kms = sum(t for k, t in tr if k.startswith("k_"))
-            if best is None or kms < best["classify_kernel_ms"]:
+            if best is None or wall < best["plan_s"]:
                 inf = pl.info
                 best = {"plan_s": wall, "classify_kernel_ms": kms,
                         "phases_ms": {k: inf.t_ms[i] for i, k in enumerate(fc2d.PLAN_PHASES)},

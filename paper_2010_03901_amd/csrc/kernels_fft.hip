@@ -4,11 +4,14 @@
 //
 // Forward real-to-complex transform, two passes over HBM:
 //   pass R (rows):    each row of N_y reals is read as N_y/2 complex numbers
-//                     z_n = u_{2n} + i u_{2n+1}, transformed in LDS by a
-//                     radix-8/4 Stockham FFT, and split into the N_y/2 + 1
-//                     bins of the real transform (X_k = E_k + W^k O_k);
+//                     z_n = u_{2n} + i u_{2n+1}, transformed by a Stockham FFT
+//                     held in registers (radices 16, 8, 4, 2; the elements
+//                     change threads through LDS between stages), and split
+//                     into the N_y/2 + 1 bins of the real transform
+//                     (X_k = E_k + W^k O_k);
 //   pass C (columns): tiles of T adjacent columns (T x 16 B contiguous per row)
-//                     are transformed along x in LDS and written back in place.
+//                     are transformed along x the same way and written back in
+//                     place.
 // The inverse runs pass C (inverse) in place on the spectrum, then pass R'
 // which rebuilds z from the half spectrum, inverse-transforms and writes reals
 // scaled by 1/(N_x N_y).

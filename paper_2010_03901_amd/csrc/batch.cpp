@@ -187,20 +187,27 @@ static int autotune(fc2d_batch* b, hipStream_t s) {
         }
         colff_set(g.grid.nx, best_v);
         g.fused_ff = t_fused >= 0 && (t_sep < 0 || t_fused < t_sep);
-        // row-major spectra (as chosen above) against transposed spectra, over
-        // the group's whole spectral step, unless the layout was fixed
+        // row-major spectra (as chosen above) against transposed spectra, unless
+        // the layout was fixed: the fused kernel's shape on transposed spectra
+        // by its own launch (the row passes around it would only add noise),
+        // then the two layouts, each with its best shape, over the group's whole
+        // step (the row passes differ between them)
         if (!b->trans_fixed && g.grid.ny <= 4096 && g.grid.nx % 8 == 0) {
             int nl = 0;
-            g.trans = false;
-            const float t_rm = time_ms(s, [&]() { return group_fft_step(b, g, kTuneC, kTuneT, s, &nl); }, 3);
             g.trans = true;
-            float t_tr = -1.0f;
+            float t_sp = -1.0f;
             int best_tv = colff_get(g.grid.nx);
             for (int v = 0; v < colff_variants(g.grid.nx); ++v) {
                 colff_set(g.grid.nx, v);
-                const float ms = time_ms(s, [&]() { return group_fft_step(b, g, kTuneC, kTuneT, s, &nl); }, 3);
-                if (ms >= 0 && (t_tr < 0 || ms < t_tr)) { t_tr = ms; best_tv = v; }
+                const float ms = time_ms(s, [&]() { return spectral_step(g, kTuneC, kTuneT, s); }, 3);
+                if (ms >= 0 && (t_sp < 0 || ms < t_sp)) { t_sp = ms; best_tv = v; }
             }
+            g.trans = false;
+            colff_set(g.grid.nx, best_v);
+            const float t_rm = time_ms(s, [&]() { return group_fft_step(b, g, kTuneC, kTuneT, s, &nl); }, 3);
+            g.trans = true;
+            colff_set(g.grid.nx, best_tv);
+            const float t_tr = time_ms(s, [&]() { return group_fft_step(b, g, kTuneC, kTuneT, s, &nl); }, 3);
             g.trans = t_tr >= 0 && (t_rm < 0 || t_tr < t_rm);
             colff_set(g.grid.nx, g.trans ? best_tv : best_v);
         } else if (g.trans) {

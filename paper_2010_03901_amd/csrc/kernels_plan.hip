@@ -347,7 +347,9 @@ int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream
     };
     do {
         hipError_t e;
-        if ((e = hipMalloc((void**)&d_stats, (size_t)nx * 4 * sizeof(int32_t))) != hipSuccess) { st = fail(e, "plan lists"); break; }
+        // temporaries come from the library's stream-ordered pool (no device
+        // allocator call once the pool holds enough); the plan's arrays are its own
+        if ((st = ws_alloc((size_t)nx * 4 * sizeof(int32_t), s, (void**)&d_stats))) break;
         k_row_stats<<<nx, kRowThreads, 0, s>>>(pl->d_cls, ny, d_stats);
         if ((st = launch_status("row statistics launch"))) break;
         std::vector<int32_t> stats((size_t)nx * 4);
@@ -385,10 +387,14 @@ int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream
         if (E > 0)
             while (R > E || Lh % R != 0) R >>= 1;
         const size_t Sa = (size_t)std::max<int64_t>(S, 1);
-        if ((e = hipMalloc((void**)&d_off, off.size() * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc((void**)&pl->d_run_ptr, ((size_t)nx + 1) * sizeof(int32_t))) != hipSuccess ||
+        if ((st = ws_alloc(off.size() * sizeof(int32_t), s, (void**)&d_off)) ||
+            (st = ws_alloc((size_t)npts * sizeof(int32_t), s, (void**)&d_map)) ||
+            (st = ws_alloc(Sa * sizeof(int32_t), s, (void**)&d_pos)) ||
+            (st = ws_alloc(Sa * sizeof(int32_t), s, (void**)&d_pos2)) ||
+            (st = ws_alloc(sizeof(int), s, (void**)&d_wmax)))
+            break;
+        if ((e = hipMalloc((void**)&pl->d_run_ptr, ((size_t)nx + 1) * sizeof(int32_t))) != hipSuccess ||
             (e = hipMalloc((void**)&pl->d_run, (size_t)nruns * 3 * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc((void**)&d_map, (size_t)npts * sizeof(int32_t))) != hipSuccess ||
             (e = hipMalloc((void**)&pl->d_rm_idx, Sa * sizeof(int32_t))) != hipSuccess ||
             (e = hipMalloc((void**)&pl->d_rm_seed, Sa * sizeof(int32_t))) != hipSuccess ||
             (e = hipMalloc((void**)&pl->d_rm_th, Sa * sizeof(double))) != hipSuccess ||
@@ -396,9 +402,6 @@ int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream
             (e = hipMalloc((void**)&pl->d_sidx, Sa * sizeof(int32_t))) != hipSuccess ||
             (e = hipMalloc((void**)&pl->d_sth, Sa * sizeof(double))) != hipSuccess ||
             (e = hipMalloc((void**)&pl->d_seta, Sa * sizeof(double))) != hipSuccess ||
-            (e = hipMalloc((void**)&d_pos, Sa * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc((void**)&d_pos2, Sa * sizeof(int32_t))) != hipSuccess ||
-            (e = hipMalloc((void**)&d_wmax, sizeof(int))) != hipSuccess ||
             (E > 0 && (e = hipMalloc((void**)&pl->d_cls2, (size_t)nx * Lh)) != hipSuccess)) {
             st = fail(e, "plan lists");
             break;
@@ -425,9 +428,12 @@ int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream
             if ((st = launch_status("STRIP order launch"))) break;
             size_t tmp_bytes = 0;
             if ((e = rocprim::radix_sort_pairs(nullptr, tmp_bytes, pl->d_rm_th, pl->d_sth, d_pos, d_pos2,
-                                               (unsigned)S, 0, 64, s)) != hipSuccess ||
-                (e = hipMalloc(&d_tmp, tmp_bytes)) != hipSuccess ||
-                (e = rocprim::radix_sort_pairs(d_tmp, tmp_bytes, pl->d_rm_th, pl->d_sth, d_pos, d_pos2,
+                                               (unsigned)S, 0, 64, s)) != hipSuccess) {
+                st = fail(e, "STRIP sort by theta");
+                break;
+            }
+            if ((st = ws_alloc(tmp_bytes, s, &d_tmp))) break;
+            if ((e = rocprim::radix_sort_pairs(d_tmp, tmp_bytes, pl->d_rm_th, pl->d_sth, d_pos, d_pos2,
                                                (unsigned)S, 0, 64, s)) != hipSuccess) {
                 st = fail(e, "STRIP sort by theta");
                 break;
@@ -450,7 +456,7 @@ int plan_device_lists(fc2d_plan* pl, const StripRec* d_rec, int64_t S, hipStream
     } while (0);
     void* tmp[] = {d_stats, d_off, d_map, d_pos, d_pos2, d_wmax, d_tmp};
     for (void* q : tmp)
-        if (q) (void)hipFree(q);
+        if (q) (void)ws_free(q, s);
     return st;
 }
 

@@ -82,6 +82,22 @@ static int dev_upload(T** dst, const T* src, size_t n) {
     return FC2D_OK;
 }
 
+// a plan-creation temporary from the library's stream-ordered pool, filled
+// from host memory on stream s (the source must stay alive until s is
+// synchronised; every caller here synchronises before it returns)
+template <typename T>
+static int ws_upload(T** dst, const T* src, size_t n, hipStream_t s) {
+    *dst = nullptr;
+    if (n == 0) return FC2D_OK;
+    void* p = nullptr;
+    int st = ws_alloc(n * sizeof(T), s, &p);
+    if (st) return st;
+    *dst = (T*)p;
+    hipError_t e = hipMemcpyAsync(p, src, n * sizeof(T), hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync H2D");
+    return FC2D_OK;
+}
+
 // ----------------------------------------------------------------------------
 // FC-Gram table cache
 // ----------------------------------------------------------------------------
@@ -193,15 +209,15 @@ static int build_matching(fc2d_plan* pl, int maxit, const BndView& dbd, hipStrea
         sa.nx = g.nx; sa.ny = g.ny;
         StarQ* d_q = nullptr;
         StarR* d_r = nullptr;
-        int st = dev_upload(&d_q, q.data(), nst);
+        int st = ws_upload(&d_q, q.data(), nst, stream);
         hipError_t e = hipSuccess;
-        if (!st && (e = hipMalloc((void**)&d_r, nst * sizeof(StarR))) != hipSuccess) st = hip_fail(e, "red-star scan");
+        if (!st) st = ws_alloc(nst * sizeof(StarR), stream, (void**)&d_r);
         if (!st) st = launch_star_scan(sa, pl->d_cls, d_q, d_r, (int)nst, stream);
         if (!st && ((e = hipMemcpyAsync(res.data(), d_r, nst * sizeof(StarR), hipMemcpyDeviceToHost, stream)) != hipSuccess ||
                     (e = hipStreamSynchronize(stream)) != hipSuccess))
             st = hip_fail(e, "red-star scan");
-        if (d_q) (void)hipFree(d_q);
-        if (d_r) (void)hipFree(d_r);
+        if (d_q) (void)ws_free(d_q, stream);
+        if (d_r) (void)ws_free(d_r, stream);
         if (st) return st;
     }
     for (size_t k = 0; k < nst; ++k)
@@ -448,45 +464,41 @@ static int create_plan(const fc2d_curve* curve, const fc2d_grid* grid, int d, in
             npts, (int64_t)(2.0 * perim * (sa.band_hi - sa.band_lo) / (hh * hh) + 4.0 * perim / hh) + 4096);
     }
     int cnt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    // temporaries of the plan's creation come from the library's stream-ordered
+    // pool and go back to it on the plan's stream
     auto cleanup = [&]() {
         void* ps[] = {d_bx, d_by, d_bnx, d_bny, d_coly, d_colptr, d_rec, d_near, d_cand, d_w, d_cnt};
         for (void* q : ps)
-            if (q) (void)hipFree(q);
+            if (q) (void)ws_free(q, stream);
     };
     st = FC2D_OK;
     do {
-        if (hipMalloc((void**)&pl->d_cls, npts) != hipSuccess || hipMalloc((void**)&d_rec, cap * sizeof(StripRec)) != hipSuccess ||
-            hipMalloc((void**)&d_cnt, 8 * sizeof(int)) != hipSuccess) {
-            set_error("hipMalloc failed (classification work space)");
+        if (hipMalloc((void**)&pl->d_cls, npts) != hipSuccess) {
+            set_error("hipMalloc failed (classes)");
             st = FC2D_E_NOMEM;
             break;
         }
+        if ((st = ws_alloc(cap * sizeof(StripRec), stream, (void**)&d_rec)) ||
+            (st = ws_alloc(8 * sizeof(int), stream, (void**)&d_cnt)))
+            break;
         d_cls = pl->d_cls;
         hipError_t e;
         // boundary samples on the device: proximity seeds and the red-star scan
-        if ((st = dev_upload(&d_bx, pl->bx.data(), B))) break;
-        if ((st = dev_upload(&d_by, pl->by.data(), B))) break;
-        if ((st = dev_upload(&d_bnx, pl->bnx.data(), B))) break;
-        if ((st = dev_upload(&d_bny, pl->bny.data(), B))) break;
+        if ((st = ws_upload(&d_bx, pl->bx.data(), B, stream))) break;
+        if ((st = ws_upload(&d_by, pl->by.data(), B, stream))) break;
+        if ((st = ws_upload(&d_bnx, pl->bnx.data(), B, stream))) break;
+        if ((st = ws_upload(&d_bny, pl->bny.data(), B, stream))) break;
         if (o.seed == FC2D_SEED_PROXIMITY) {
-            if ((st = dev_upload(&d_colptr, col_ptr.data(), col_ptr.size()))) break;
-            if (!col_y.empty() && (st = dev_upload(&d_coly, col_y.data(), col_y.size()))) break;
-            if (hipMalloc((void**)&d_near, npts * sizeof(uint64_t)) != hipSuccess) {
-                set_error("hipMalloc failed (proximity map)");
-                st = FC2D_E_NOMEM;
-                break;
-            }
+            if ((st = ws_upload(&d_colptr, col_ptr.data(), col_ptr.size(), stream))) break;
+            if (!col_y.empty() && (st = ws_upload(&d_coly, col_y.data(), col_y.size(), stream))) break;
+            if ((st = ws_alloc(npts * sizeof(uint64_t), stream, (void**)&d_near))) break;
             ca.bx = d_bx; ca.by = d_by; ca.bnx = d_bnx; ca.bny = d_bny;
             ca.col_ptr = d_colptr; ca.col_y = d_coly;
             trace_point("plan_host", stream);   // kernel times below exclude the host set-up
             if ((st = launch_classify(ca, d_cls, d_rec, cap, d_near, d_cnt, stream))) break;
         } else {
-            if (hipMalloc((void**)&d_cand, cap_cand * sizeof(int32_t)) != hipSuccess) {
-                set_error("hipMalloc failed (candidate list)");
-                st = FC2D_E_NOMEM;
-                break;
-            }
-            if (o.seed == FC2D_SEED_MLP && (st = dev_upload(&d_w, o.mlp_weights, FC2D_MLP_NW))) break;
+            if ((st = ws_alloc(cap_cand * sizeof(int32_t), stream, (void**)&d_cand))) break;
+            if (o.seed == FC2D_SEED_MLP && (st = ws_upload(&d_w, o.mlp_weights, FC2D_MLP_NW, stream))) break;
             trace_point("plan_host", stream);
             if ((st = launch_radial_band(sa, d_cls, d_cand, cap_cand, d_cnt, stream))) break;
             if ((e = hipMemcpyAsync(cnt, d_cnt, 8 * sizeof(int), hipMemcpyDeviceToHost, stream)) != hipSuccess ||

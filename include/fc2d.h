@@ -24,6 +24,10 @@
  *    take it per call from a library-owned memory pool, ordered on the call's
  *    stream, and return it on that stream; so calls sharing one plan may run
  *    concurrently on different streams (and from different host threads).
+ *    Plan creation takes its temporaries from the same pool.  The pool (one
+ *    per device) keeps what it has held until the process ends, so later
+ *    calls reach no device allocator (at 4096^2 a plan's creation leaves about
+ *    0.3 GB in it).
  *    The exceptions are named where they occur: a batch (fc2d_batch_*) is
  *    advanced by one stream at a time, the tuning knobs are process-wide, and
  *    fc2d_extend_fft_noalloc shares one fixed scratch per device.

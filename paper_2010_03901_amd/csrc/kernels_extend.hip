@@ -765,7 +765,10 @@ int launch_bvals(const fc2d_plan* pl, const double* u, double* fb, int nf, hipSt
 
 int launch_multi(int which, int M, const PlanDev* d_pd, int np, int64_t total, int fpt, const double* Ar, int D,
                  int Cr, int wmax, int grid_blocks, hipStream_t s) {
-    const unsigned g = (unsigned)std::max<int64_t>(8, std::min<int64_t>(total, grid_blocks));
+    // the matching kernel's blocks are single waves: twice the blocks fill the
+    // 16 waves per CU its registers allow (the others have four waves per block)
+    const int64_t cap = which == 0 ? 2 * (int64_t)grid_blocks : (int64_t)grid_blocks;
+    const unsigned g = (unsigned)std::max<int64_t>(8, std::min<int64_t>(total, cap));
     int lcap = 1, fstage = 1;
     const size_t lds = which == 1 ? strip_lds(wmax, D, Cr, fpt, &lcap, &fstage) : 0;
     switch (M) {

@@ -489,7 +489,7 @@ def run_mlp(args):
     res, plans = {}, {}
     for name, kw in modes.items():
         best = None
-        for _ in range(5):   # the fastest of five builds: host timings vary from build to build
+        for _ in range(9):   # the fastest of nine builds: host timings vary from build to build
             torch.cuda.synchronize()
             fc2d.fc2d_trace_begin()
             t0 = time.perf_counter()

@@ -9,9 +9,10 @@
 // The plan-specific stages run as single persistent launches over every
 // (plan, field set) of the batch; the FFT passes run once per grid size with
 // the fields of all domains of that size contiguous.  A step can be captured
-// in a HIP graph and replayed.  An optional autotuner times the column-pass
-// tile widths and the strip kernel's fields per thread on the batch's own
-// buffers and keeps the fastest.
+// in a HIP graph and replayed.  An optional autotuner times, on the batch's
+// own buffers, the column-pass tile widths, the separate against the fused
+// spectral step and the fused kernel's shapes, row-major against transposed
+// spectra, and the strip kernel's fields per thread, and keeps the fastest.
 #include <string.h>
 
 #include <algorithm>
